@@ -1,0 +1,230 @@
+"""ctypes wrapper of the FP64 oracle (``gs_oracle.cpp``). Test infrastructure.
+
+Scenes and cameras are taken by duck typing (attributes ``means``, ``log_scales``,
+``quats``, ``opacity_logits``, ``sh``, ``sh_degree``; ``width``, ``height``, ``fx``,
+``fy``, ``cx``, ``cy``, ``R``, ``t``, ``near``, ``bg``), so this module imports
+nothing from the GPU package.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gs_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+__all__ = ["build", "load", "camera_array", "sh_basis", "preprocess", "render", "backward", "chain",
+           "morton", "cluster_bounds", "bin_instances", "count_instances", "variance", "l1_grad",
+           "l1_loss"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, no FMA contraction) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+                               "-ffp-contract=off", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        _lib = ctypes.CDLL(_LIB)
+        _lib.orc_count_instances.restype = ctypes.c_int64
+        _lib.orc_bin.restype = ctypes.c_int64
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _scene_args(scene):
+    arrs = [np.ascontiguousarray(x, dtype=np.float32) for x in
+            (scene.means, scene.log_scales, scene.quats, scene.opacity_logits, scene.sh)]
+    return arrs, [ctypes.c_int64(arrs[0].shape[0]), ctypes.c_int(int(scene.sh_degree))] + [_p(a) for a in arrs]
+
+
+def camera_array(cam) -> np.ndarray:
+    """22 doubles: W, H, fx, fy, cx, cy, R (9, row-major), t (3), near, bg (3). The
+    float fields are rounded to FP32 first, exactly as the GPU library receives them."""
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    R = np.asarray(cam.R, dtype=np.float32).reshape(9).astype(np.float64)
+    t = np.asarray(cam.t, dtype=np.float32).reshape(3).astype(np.float64)
+    bg = np.asarray(cam.bg, dtype=np.float32).reshape(3).astype(np.float64)
+    out = np.array([cam.width, cam.height, f32(cam.fx), f32(cam.fy), f32(cam.cx), f32(cam.cy)]
+                   + list(R) + list(t) + [f32(cam.near)] + list(bg), dtype=np.float64)
+    return out
+
+
+def sh_basis(deg: int, direction):
+    lib = load()
+    K = (deg + 1) ** 2
+    d = np.ascontiguousarray(direction, dtype=np.float64)
+    Y = np.zeros(K)
+    dY = np.zeros((K, 3))
+    lib.orc_sh_basis(ctypes.c_int(deg), _p(d), _p(Y), _p(dY))
+    return Y, dY
+
+
+def preprocess(scene, cam) -> dict:
+    lib = load()
+    arrs, args = _scene_args(scene)
+    n = arrs[0].shape[0]
+    f = np.zeros((n, 16))
+    iv = np.zeros((n, 8), dtype=np.int32)
+    db = np.zeros(n, dtype=np.uint32)
+    ca = camera_array(cam)
+    lib.orc_preprocess(*args, _p(ca), _p(f), _p(iv), _p(db))
+    return dict(u=f[:, 0], v=f[:, 1], conic=f[:, 2:5], cov=f[:, 5:8], opacity=f[:, 8], rgb=f[:, 9:12],
+                depth=f[:, 12], tcam=f[:, 13:16], valid=iv[:, 0].astype(bool), rect=iv[:, 1:5],
+                tiles=iv[:, 5], rect_fragile=iv[:, 6].astype(bool), depth_bits=db)
+
+
+def _window(cam, window):
+    if window is None:
+        return 0, cam.width, 0, cam.height
+    x0, x1, y0, y1 = window
+    return int(x0), int(x1), int(y0), int(y1)
+
+
+def render(scene, cam, mode: int = 1, window=None, threads: int = 0) -> dict:
+    """Forward render. mode 0 = brute force over all Gaussians, 1 = per-pixel
+    footprint filter, 2 = per-tile lists (list positions comparable to a tiled walk).
+    Returns image f64[3,H,W], T f64[H,W], n_contrib, n_blended i32[H,W], fragile bool."""
+    lib = load()
+    arrs, args = _scene_args(scene)
+    H, W = cam.height, cam.width
+    img = np.zeros((3, H, W))
+    T = np.ones((H, W))
+    nc = np.zeros((H, W), dtype=np.int32)
+    nb = np.zeros((H, W), dtype=np.int32)
+    fr = np.zeros((H, W), dtype=np.uint8)
+    ca = camera_array(cam)
+    x0, x1, y0, y1 = _window(cam, window)
+    lib.orc_render(*args, _p(ca), ctypes.c_int(mode), ctypes.c_int(x0), ctypes.c_int(x1), ctypes.c_int(y0),
+                   ctypes.c_int(y1), ctypes.c_int(threads), _p(img), _p(T), _p(nc), _p(nb), _p(fr))
+    return dict(image=img, T=T, n_contrib=nc, n_blended=nb, fragile=fr.astype(bool))
+
+
+def backward(scene, cam, dL_dI, mode: int = 1, window=None, threads: int = 0) -> dict:
+    """Analytic FP64 backward of render() for upstream gradient dL_dI [3,H,W]."""
+    lib = load()
+    arrs, args = _scene_args(scene)
+    n = arrs[0].shape[0]
+    K = (int(scene.sh_degree) + 1) ** 2
+    g = np.ascontiguousarray(dL_dI, dtype=np.float64)
+    assert g.shape == (3, cam.height, cam.width)
+    out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+               opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)), g2d=np.zeros((n, 9)),
+               S=np.zeros(n), M=np.zeros(n), C=np.zeros(n, dtype=np.int64), fragile=np.zeros(n, dtype=np.uint8))
+    ca = camera_array(cam)
+    x0, x1, y0, y1 = _window(cam, window)
+    lib.orc_backward(*args, _p(ca), ctypes.c_int(mode), ctypes.c_int(x0), ctypes.c_int(x1), ctypes.c_int(y0),
+                     ctypes.c_int(y1), ctypes.c_int(threads), _p(g), _p(out["means"]), _p(out["log_scales"]),
+                     _p(out["quats"]), _p(out["opacity_logits"]), _p(out["sh"]), _p(out["g2d"]), _p(out["S"]),
+                     _p(out["M"]), _p(out["C"]), _p(out["fragile"]))
+    out["fragile"] = out["fragile"].astype(bool)
+    return out
+
+
+def chain(scene, cam, g2d) -> dict:
+    """Chain screen-space gradients g2d f64[n,9] (u, v, a, b, c, o, r, g, b) to the parameters."""
+    lib = load()
+    arrs, args = _scene_args(scene)
+    n = arrs[0].shape[0]
+    K = (int(scene.sh_degree) + 1) ** 2
+    g = np.ascontiguousarray(g2d, dtype=np.float64)
+    out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
+               opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)))
+    ca = camera_array(cam)
+    lib.orc_chain(*args, _p(ca), _p(g), _p(out["means"]), _p(out["log_scales"]), _p(out["quats"]),
+                  _p(out["opacity_logits"]), _p(out["sh"]))
+    return out
+
+
+def morton(means):
+    lib = load()
+    m = np.ascontiguousarray(means, dtype=np.float32)
+    n = m.shape[0]
+    codes = np.zeros(n, dtype=np.uint64)
+    perm = np.zeros(n, dtype=np.int64)
+    lib.orc_morton(ctypes.c_int64(n), _p(m), _p(codes), _p(perm))
+    return codes, perm
+
+
+def cluster_bounds(means, log_scales, csize: int = 128):
+    lib = load()
+    m = np.ascontiguousarray(means, dtype=np.float32)
+    ls = np.ascontiguousarray(log_scales, dtype=np.float32)
+    n = m.shape[0]
+    nc = (n + csize - 1) // csize
+    out = np.zeros((nc, 8), dtype=np.float32)
+    lib.orc_cluster_bounds(ctypes.c_int64(n), ctypes.c_int(csize), _p(m), _p(ls), _p(out))
+    return out
+
+
+def _bin_inputs(views):
+    """views: list of (valid bool[n], rect i32[n,4] (x0,x1,y0,y1), depth_bits u32[n], tiles_x, tiles_y)."""
+    V = len(views)
+    n = views[0][0].shape[0]
+    rects = np.zeros((V * n, 5), dtype=np.int32)
+    depth = np.zeros(V * n, dtype=np.uint32)
+    base = np.zeros(V + 1, dtype=np.int64)
+    tx = np.zeros(V, dtype=np.int32)
+    for v, (valid, rect, db, tiles_x, tiles_y) in enumerate(views):
+        rects[v * n:(v + 1) * n, 0] = valid.astype(np.int32)
+        rects[v * n:(v + 1) * n, 1:] = rect
+        depth[v * n:(v + 1) * n] = db
+        base[v + 1] = base[v] + tiles_x * tiles_y
+        tx[v] = tiles_x
+    return V, n, rects, depth, base, tx
+
+
+def count_instances(views) -> int:
+    lib = load()
+    V, n, rects, depth, base, tx = _bin_inputs(views)
+    return int(lib.orc_count_instances(ctypes.c_int64(n), ctypes.c_int(V), _p(rects)))
+
+
+def bin_instances(views):
+    """Stable (tile, depth) binning. Returns keys u64[M], vals i64[M], ranges u32[T,2]."""
+    lib = load()
+    V, n, rects, depth, base, tx = _bin_inputs(views)
+    M = int(lib.orc_count_instances(ctypes.c_int64(n), ctypes.c_int(V), _p(rects)))
+    keys = np.zeros(max(M, 1), dtype=np.uint64)
+    vals = np.zeros(max(M, 1), dtype=np.int64)
+    ranges = np.zeros(2 * int(base[-1]), dtype=np.uint32)
+    m2 = lib.orc_bin(ctypes.c_int64(n), ctypes.c_int(V), _p(rects), _p(depth), _p(base), _p(tx), _p(keys),
+                     _p(vals), _p(ranges))
+    assert m2 == M
+    return keys[:M], vals[:M], ranges.reshape(-1, 2)
+
+
+def variance(S, M, C):
+    lib = load()
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    C = np.ascontiguousarray(C, dtype=np.int64)
+    out = np.zeros_like(S)
+    lib.orc_variance(ctypes.c_int64(S.shape[0]), _p(S), _p(M), _p(C), _p(out))
+    return out
+
+
+def l1_loss(image, w, gt) -> float:
+    """Random-weighted L1 loss sum w |I - gt| in FP64."""
+    return float(np.sum(np.asarray(w, np.float64) * np.abs(np.asarray(image, np.float64) - gt)))
+
+
+def l1_grad(image, w, gt):
+    """dL/dI of l1_loss: w * sign(I - gt)."""
+    return np.asarray(w, np.float64) * np.sign(np.asarray(image, np.float64) - np.asarray(gt, np.float64))

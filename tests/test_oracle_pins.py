@@ -1,0 +1,532 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+invariants, a library routine for a special case, brute force on tiny inputs, or
+finite differences. CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sps
+
+from paper_2503_01199_amd import scenes
+
+
+def _one_gaussian(mean, log_scale, quat, opacity, rgb, degree=0):
+    """Scene with the given Gaussians; colour set through the DC SH coefficient."""
+    mean = np.atleast_2d(np.asarray(mean, np.float64))
+    n = mean.shape[0]
+    K = (degree + 1) ** 2
+    sh = np.zeros((n, K, 3))
+    sh[:, 0, :] = (np.atleast_2d(rgb) - 0.5) * (2.0 * math.sqrt(math.pi))
+    op = np.atleast_1d(np.asarray(opacity, np.float64))
+    logit = np.log(op / (1 - op))
+    return scenes.Scene(*(np.ascontiguousarray(a, np.float32) for a in
+                          (mean, np.broadcast_to(log_scale, (n, 3)), np.broadcast_to(quat, (n, 4)), logit, sh)),
+                        degree)
+
+
+def _cam(W=64, H=48, f=64.0, cx=None, cy=None, bg=(0, 0, 0)):
+    return scenes.Camera(W, H, f, f, W / 2 if cx is None else cx, H / 2 if cy is None else cy,
+                         np.eye(3, dtype=np.float32), np.zeros(3, np.float32), 0.2, bg)
+
+
+# ------------------------------------------------------------------ spherical harmonics
+def _real_sh_scipy(l, m, theta, phi):
+    """Real SH from scipy's complex ones (which carry the Condon-Shortley phase)."""
+    if m > 0:
+        return math.sqrt(2) * (-1) ** m * np.real(sps.sph_harm_y(l, m, theta, phi))
+    if m < 0:
+        return math.sqrt(2) * (-1) ** m * np.imag(sps.sph_harm_y(l, -m, theta, phi))
+    return np.real(sps.sph_harm_y(l, 0, theta, phi))
+
+
+def test_sh_matches_scipy(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        theta = math.acos(d[2])
+        phi = math.atan2(d[1], d[0])
+        Y, _ = orc.sh_basis(3, d)
+        for l in range(4):
+            for m in range(-l, l + 1):
+                assert Y[l * l + l + m] == pytest.approx(_real_sh_scipy(l, m, theta, phi), abs=1e-13)
+
+
+def test_sh_orthonormal_by_quadrature(orc):
+    # Gauss-Legendre in cos(theta) x uniform in phi is exact for these polynomials.
+    xs, ws = np.polynomial.legendre.leggauss(12)
+    nphi = 16
+    G = np.zeros((16, 16))
+    for x, w in zip(xs, ws):
+        s = math.sqrt(1 - x * x)
+        for k in range(nphi):
+            phi = 2 * math.pi * k / nphi
+            d = np.array([s * math.cos(phi), s * math.sin(phi), x])
+            Y, _ = orc.sh_basis(3, d)
+            G += np.outer(Y, Y) * w * (2 * math.pi / nphi)
+    assert np.abs(G - np.eye(16)).max() < 1e-12
+
+
+def test_sh_gradient_by_central_differences(orc):
+    rng = np.random.default_rng(2)
+    for _ in range(10):
+        d = rng.standard_normal(3)
+        _, dY = orc.sh_basis(3, d)
+        h = 1e-6
+        for a in range(3):
+            e = np.zeros(3)
+            e[a] = h
+            fd = (orc.sh_basis(3, d + e)[0] - orc.sh_basis(3, d - e)[0]) / (2 * h)
+            assert np.abs(fd - dY[:, a]).max() < 1e-7
+
+
+def test_sh_low_degrees(orc):
+    Y0, _ = orc.sh_basis(0, np.array([0.0, 0.0, 1.0]))
+    assert Y0[0] == pytest.approx(1 / (2 * math.sqrt(math.pi)), abs=1e-15)
+    d = np.array([0.36, -0.48, 0.8])
+    Y1, _ = orc.sh_basis(1, d)
+    # degree 1 is proportional to the direction components (y, z, x)
+    ratio = Y1[1:] / np.array([d[1], d[2], d[0]])
+    assert np.allclose(ratio, math.sqrt(3 / (4 * math.pi)), atol=1e-14)
+
+
+# ------------------------------------------------------------------ P1: closed-form splats
+def test_single_isotropic_on_axis_closed_form(orc):
+    z, s, o, c = 3.0, 0.05, 0.8, np.array([0.9, 0.4, 0.2])
+    sc = _one_gaussian([0, 0, z], math.log(s), [1, 0, 0, 0], o, c)
+    cam = _cam()
+    out = orc.render(sc, cam, mode=0)
+    s32 = math.exp(float(sc.log_scales[0, 0]))
+    o32 = 1 / (1 + math.exp(-float(sc.opacity_logits[0])))
+    c32 = 0.5 + sc.sh[0, 0].astype(np.float64) / (2 * math.sqrt(math.pi))
+    sig2 = (64.0 * s32 / float(np.float32(z))) ** 2 + 0.3
+    py, px = np.mgrid[0:48, 0:64]
+    r2 = (px + 0.5 - 32) ** 2 + (py + 0.5 - 24) ** 2
+    a = o32 * np.exp(-r2 / (2 * sig2))
+    a = np.where(a >= 1 / 255, np.minimum(a, 0.99), 0.0)
+    exp_img = a[None] * c32[:, None, None]
+    assert np.abs(out["image"] - exp_img).max() < 1e-14
+    pp = orc.preprocess(sc, cam)
+    assert pp["cov"][0] == pytest.approx([sig2, 0, sig2], abs=1e-12)
+
+
+def test_single_anisotropic_and_off_axis_closed_form(orc):
+    # axis-aligned scales, off-axis in x: cov = [[s_x^2 f^2/z^2 (1 + X^2/z^2) + .3, 0], [0, s_y^2 f^2/z^2 + .3]]
+    X, z = 0.4, 2.5
+    sx, sy, sz = 0.03, 0.07, 0.05
+    sc = _one_gaussian([X, 0, z], [math.log(sx), math.log(sy), math.log(sz)], [1, 0, 0, 0], 0.7, [0.5, 0.5, 0.5])
+    cam = _cam(W=96, H=64, f=80.0)
+    pp = orc.preprocess(sc, cam)
+    Xf, zf = float(np.float32(X)), float(np.float32(z))
+    s = np.exp(sc.log_scales[0].astype(np.float64))
+    f = 80.0
+    # J = [[f/z, 0, -f X/z^2], [0, f/z, 0]], Sigma = diag(s^2)
+    J = np.array([[f / zf, 0, -f * Xf / zf ** 2], [0, f / zf, 0]])
+    cov = J @ np.diag(s ** 2) @ J.T + 0.3 * np.eye(2)
+    assert pp["cov"][0] == pytest.approx([cov[0, 0], cov[0, 1], cov[1, 1]], rel=1e-13)
+    assert pp["u"][0] == pytest.approx(f * Xf / zf + 48.0, rel=1e-14)
+    inv = np.linalg.inv(cov)
+    assert pp["conic"][0] == pytest.approx([inv[0, 0], inv[0, 1], inv[1, 1]], rel=1e-12)
+
+
+def test_rotated_gaussian_covariance(orc):
+    # 90 degrees about z swaps the x and y scales
+    q = [math.cos(math.pi / 4), 0, 0, math.sin(math.pi / 4)]
+    sc = _one_gaussian([0, 0, 2.0], [math.log(0.02), math.log(0.08), math.log(0.05)], q, 0.6, [0.5] * 3)
+    pp = orc.preprocess(sc, _cam())
+    s = np.exp(sc.log_scales[0].astype(np.float64))
+    f, z = 64.0, 2.0
+    assert pp["cov"][0, 0] == pytest.approx((f / z) ** 2 * s[1] ** 2 + 0.3, rel=1e-6)
+    assert pp["cov"][0, 2] == pytest.approx((f / z) ** 2 * s[0] ** 2 + 0.3, rel=1e-6)
+
+
+# ------------------------------------------------------------------ P2: compositing closed form
+def test_two_and_three_layer_compositing(orc):
+    cam = _cam(W=32, H=32, f=32.0, cx=16.5, cy=16.5, bg=(0.1, 0.2, 0.3))
+    cols = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    ops = np.array([0.6, 0.5, 0.3])
+    # huge flat Gaussians so that G ~ 1 at the centre pixel (16, 16), whose centre is on the axis
+    sc = _one_gaussian([[0, 0, 2.0], [0, 0, 3.0], [0, 0, 4.0]], math.log(3.0), [1, 0, 0, 0], ops, cols)
+    out = orc.render(sc, cam, mode=0)
+    o = 1 / (1 + np.exp(-sc.opacity_logits.astype(np.float64)))
+    # colour = max(0, Y00 f + 1/2); the FP32 coefficient of a 0 channel lands just below 0
+    c = np.maximum(0.0, 0.5 + sc.sh[:, 0, :].astype(np.float64) / (2 * math.sqrt(math.pi)))
+    bg = np.array(cam.bg, np.float32).astype(np.float64)
+    exp = o[0] * c[0] + (1 - o[0]) * o[1] * c[1] + (1 - o[0]) * (1 - o[1]) * o[2] * c[2] \
+        + (1 - o[0]) * (1 - o[1]) * (1 - o[2]) * bg
+    assert out["image"][:, 16, 16] == pytest.approx(exp, abs=1e-14)
+    assert out["T"][16, 16] == pytest.approx(np.prod(1 - o), abs=1e-15)
+    # reversing the depths reverses the order
+    sc2 = _one_gaussian([[0, 0, 4.0], [0, 0, 3.0], [0, 0, 2.0]], math.log(3.0), [1, 0, 0, 0], ops, cols)
+    out2 = orc.render(sc2, cam, mode=0)
+    exp2 = o[2] * c[2] + (1 - o[2]) * o[1] * c[1] + (1 - o[2]) * (1 - o[1]) * o[0] * c[0] \
+        + (1 - o[0]) * (1 - o[1]) * (1 - o[2]) * bg
+    assert out2["image"][:, 16, 16] == pytest.approx(exp2, abs=1e-14)
+
+
+# ------------------------------------------------------------------ P3: transmittance
+def test_stacked_alpha_095_blends_exactly_three(orc):
+    cam = _cam(W=32, H=32, f=32.0, cx=16.5, cy=16.5)
+    n = 5
+    sc = _one_gaussian([[0, 0, 2.0 + 0.1 * i] for i in range(n)], math.log(3.0), [1, 0, 0, 0],
+                       [0.95] * n, [[0.5, 0.5, 0.5]] * n)
+    out = orc.render(sc, cam, mode=0)
+    assert out["n_blended"][16, 16] == 3
+    o = 1 / (1 + np.exp(-np.float64(sc.opacity_logits[0])))
+    assert out["T"][16, 16] == pytest.approx((1 - o) ** 3, rel=1e-12)
+    assert out["T"][16, 16] == pytest.approx(1.25e-4, rel=1e-6)
+
+
+def test_transmittance_invariants_on_dense_scene(orc):
+    sc = scenes.tiny_scene(2048)
+    # push opacities up so the T stop is exercised
+    sc.opacity_logits[:] = sc.opacity_logits + 3.0
+    cam = scenes.tiny_camera()
+    out = orc.render(sc, cam, mode=2)
+    T = out["T"]
+    assert (T >= 1e-4).all() and (T <= 1).all()
+    assert (T < 1e-3).sum() > 100  # the stop rule is reached on many pixels
+    assert (out["n_contrib"] >= out["n_blended"]).all()
+    img = out["image"]
+    assert (img >= 0).all() and (img <= 1 + 1e-12).all()  # colours in [0,1] composite into [0,1]
+
+
+def test_alpha_skip_and_clamp(orc):
+    cam = _cam(W=32, H=32, f=32.0, cx=16.5, cy=16.5)
+    # opacity 0.999 is clamped to 0.99 at the centre
+    sc = _one_gaussian([0, 0, 2.0], math.log(3.0), [1, 0, 0, 0], 0.999, [1.0, 1.0, 1.0])
+    out = orc.render(sc, cam, mode=0)
+    c32 = 0.5 + float(sc.sh[0, 0, 0]) / (2 * math.sqrt(math.pi))
+    assert out["image"][0, 16, 16] == pytest.approx(0.99 * c32, abs=1e-14)
+    # opacity below 1/255 never contributes
+    sc = _one_gaussian([0, 0, 2.0], math.log(3.0), [1, 0, 0, 0], 0.9 / 255, [1.0, 1.0, 1.0])
+    out = orc.render(sc, cam, mode=0)
+    assert out["image"].max() == 0.0
+    assert not orc.preprocess(sc, cam)["valid"][0]
+
+
+# ------------------------------------------------------------------ P4: brute force = tiled
+@pytest.mark.parametrize("W,H,salt", [(128, 128, 0), (100, 75, 1), (37, 53, 2)])
+def test_brute_force_equals_footprint_and_tiled(orc, W, H, salt):
+    sc = scenes.tiny_scene(600, seed_salt=salt)
+    cam = scenes.tiny_camera(W, H)
+    r0 = orc.render(sc, cam, mode=0)
+    r1 = orc.render(sc, cam, mode=1)
+    r2 = orc.render(sc, cam, mode=2)
+    for k in ("image", "T", "n_blended"):
+        assert np.array_equal(r0[k], r1[k]) and np.array_equal(r0[k], r2[k]), k
+
+
+def test_footprint_contains_every_contributing_pixel(orc):
+    """alpha >= 1/255 (by direct evaluation) implies the pixel is inside the rect."""
+    sc = scenes.tiny_scene(300, seed_salt=5)
+    cam = scenes.tiny_camera(96, 80)
+    pp = orc.preprocess(sc, cam)
+    py, px = np.mgrid[0:80, 0:96]
+    for i in range(sc.n):
+        if pp["tcam"][i, 2] <= 0.2:
+            continue
+        a, b, c = pp["conic"][i]
+        dx = pp["u"][i] - (px + 0.5)
+        dy = pp["v"][i] - (py + 0.5)
+        al = pp["opacity"][i] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+        hit = al >= 1 / 255
+        if not hit.any():
+            continue
+        assert pp["valid"][i]
+        tx, ty = px[hit] // 16, py[hit] // 16
+        x0, x1, y0, y1 = pp["rect"][i]
+        assert tx.min() >= x0 and tx.max() <= x1 and ty.min() >= y0 and ty.max() <= y1
+
+
+# ------------------------------------------------------------------ P5: scanline algebra
+def test_scanline_identity():
+    """Basic + Linear j + Quad j^2 equals the exponent at (dx, dy - j) (App. A.2, Eq. (8)-(9))."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        A = rng.standard_normal((2, 2))
+        Q = A @ A.T + 0.1 * np.eye(2)
+        a, b, c = Q[0, 0], Q[0, 1], Q[1, 1]
+        dx, dy = rng.normal(0, 5, 2)
+        basic = -0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)
+        lin = b * dx + c * dy
+        quad = -0.5 * c
+        for j in range(4):
+            d = np.array([dx, dy - j])
+            assert basic + lin * j + quad * j * j == pytest.approx(-0.5 * d @ Q @ d, abs=1e-10)
+
+
+# ------------------------------------------------------------------ P6: finite differences
+def _small_scene(n, degree, salt):
+    rng = np.random.default_rng([77, salt])
+    means = np.stack([rng.uniform(-0.6, 0.6, n), rng.uniform(-0.5, 0.5, n), rng.uniform(2.0, 3.0, n)], 1)
+    ls = rng.normal(-2.6, 0.3, (n, 3))
+    q = rng.standard_normal((n, 4))
+    logits = rng.normal(0.5, 1.0, n)
+    K = (degree + 1) ** 2
+    sh = rng.normal(0, 0.3, (n, K, 3))
+    sc = scenes.Scene(*(np.ascontiguousarray(a, np.float32) for a in (means, ls, q, logits, sh)), degree)
+    R, t = scenes.look_at((0.3, -0.2, -0.5), (0.0, 0.0, 2.5))
+    cam = scenes.Camera(48, 40, 48.0, 48.0, 24.0, 20.0, R, t, 0.2, (0.2, 0.1, 0.0))
+    return sc, cam
+
+
+def _loss(orc, sc, cam, g):
+    out = orc.render(sc, cam, mode=0, threads=1)
+    return float(np.sum(out["image"] * g)), out["n_blended"]
+
+
+def _set(sc, field, idx, val):
+    arr = getattr(sc, field).copy()
+    arr.reshape(-1)[idx] = val
+    kw = {k: getattr(sc, k) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    kw[field] = arr
+    return scenes.Scene(kw["means"], kw["log_scales"], kw["quats"], kw["opacity_logits"], kw["sh"], sc.sh_degree)
+
+
+@pytest.mark.parametrize("degree", [0, 3])
+def test_gradients_by_central_differences(orc, degree):
+    """Analytic FP64 gradient vs central differences of L = sum g * I. The oracle
+    takes FP32 parameters, so each one is stepped to the neighbouring FP32 values
+    x +- h and the difference is divided by the exact step between them. Stencils
+    across which a discrete decision (a pixel's blended set) changes are skipped."""
+    sc, cam = _small_scene(24, degree, degree)
+    rng = np.random.default_rng(9)
+    g = rng.uniform(-1, 1, (3, cam.height, cam.width))
+    bw = orc.backward(sc, cam, g, mode=0, threads=1)
+    checked = 0
+    fields = ["means", "log_scales", "quats", "opacity_logits", "sh"]
+    for field in fields:
+        arr = getattr(sc, field).reshape(-1)
+        grad = bw[field].reshape(-1)
+        idxs = rng.choice(arr.size, size=min(arr.size, 24), replace=False)
+        for idx in idxs:
+            x = np.float32(arr[idx])
+            h = np.float32(max(1.0, abs(float(x))) * 3e-5)
+            xp, xm = np.float32(x + h), np.float32(x - h)
+            Lp, nbp = _loss(orc, _set(sc, field, idx, xp), cam, g)
+            Lm, nbm = _loss(orc, _set(sc, field, idx, xm), cam, g)
+            if not np.array_equal(nbp, nbm):
+                continue  # a discrete decision changed inside the stencil
+            fd = (Lp - Lm) / (float(xp) - float(xm))
+            an = grad[idx]
+            # the O(h^2) truncation error at h = 3e-5 is ~1e-7 relative
+            scale = max(abs(an), 1e-3 * np.abs(grad).max(), 1e-8)
+            assert abs(fd - an) <= 2e-5 * scale + 1e-10, (field, idx, fd, an)
+            checked += 1
+    assert checked > 60
+
+
+def test_chain_rule_by_central_differences(orc):
+    """orc.chain (screen-space gradients -> parameters) against central differences of
+    the projected quantities (u, v, conic, opacity, rgb) returned by preprocess."""
+    sc, cam = _small_scene(8, 3, 5)
+    rng = np.random.default_rng(11)
+    W = rng.standard_normal((sc.n, 9))
+
+    def proj_fn(s):
+        pp = orc.preprocess(s, cam)
+        Y = np.concatenate([pp["u"][:, None], pp["v"][:, None], pp["conic"], pp["opacity"][:, None], pp["rgb"]], 1)
+        return float(np.sum(Y * W))
+
+    an = orc.chain(sc, cam, W)
+    for field in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        arr = getattr(sc, field).reshape(-1)
+        for idx in rng.choice(arr.size, size=min(arr.size, 16), replace=False):
+            x = np.float32(arr[idx])
+            h = np.float32(max(1.0, abs(float(x))) * 3e-5)
+            xp, xm = np.float32(x + h), np.float32(x - h)
+            fd = (proj_fn(_set(sc, field, idx, xp)) - proj_fn(_set(sc, field, idx, xm))) / (float(xp) - float(xm))
+            a = an[field].reshape(-1)[idx]
+            scale = max(abs(a), 1e-3 * np.abs(an[field]).max(), 1e-9)
+            assert abs(fd - a) <= 2e-5 * scale, (field, idx, fd, a)
+
+
+# ------------------------------------------------------------------ P7: statistic
+def test_statistic_single_gaussian_closed_form(orc):
+    """One Gaussian, bg = 0, constant dL/dI = g: per-pixel dL/do = (g . c) G, so
+    S = (g.c)^2 sum G^2, M = (g.c) sum G, C = #pixels with o G >= 1/255 (o G < 0.99)."""
+    cam = _cam(W=40, H=40, f=40.0)
+    sc = _one_gaussian([0.05, -0.03, 2.0], [math.log(0.08), math.log(0.05), math.log(0.05)],
+                       [0.9, 0.1, 0.2, 0.3], 0.7, [0.8, 0.3, 0.6])
+    gI = np.array([0.3, -0.7, 0.5])
+    g = np.broadcast_to(gI[:, None, None], (3, 40, 40)).copy()
+    bw = orc.backward(sc, cam, g, mode=0)
+    pp = orc.preprocess(sc, cam)
+    a, b, c = pp["conic"][0]
+    py, px = np.mgrid[0:40, 0:40]
+    dx = pp["u"][0] - (px + 0.5)
+    dy = pp["v"][0] - (py + 0.5)
+    G = np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+    o = pp["opacity"][0]
+    hit = o * G >= 1 / 255
+    gc = float(gI @ pp["rgb"][0])
+    assert bw["C"][0] == hit.sum()
+    assert bw["M"][0] == pytest.approx(gc * G[hit].sum(), rel=1e-12)
+    assert bw["S"][0] == pytest.approx(gc * gc * (G[hit] ** 2).sum(), rel=1e-12)
+    V = orc.variance(bw["S"], bw["M"], bw["C"])
+    x = gc * G[hit]
+    assert V[0] == pytest.approx(x.size * np.var(x), rel=1e-9)
+
+
+def test_statistic_per_pixel_finite_differences(orc):
+    """S and M of a few Gaussians from per-pixel central differences of the image in
+    the opacity logit (dL_p/do = dL_p/dlogit / (o (1 - o)))."""
+    sc, cam = _small_scene(16, 0, 7)
+    rng = np.random.default_rng(13)
+    g = rng.uniform(-1, 1, (3, cam.height, cam.width))
+    bw = orc.backward(sc, cam, g, mode=0)
+    base = orc.render(sc, cam, mode=0)
+    tested = 0
+    for i in np.argsort(-bw["C"])[:5]:
+        x = np.float32(sc.opacity_logits[i])
+        h = np.float32(3e-5)
+        sp, sm = _set(sc, "opacity_logits", i, np.float32(x + h)), _set(sc, "opacity_logits", i, np.float32(x - h))
+        rp, rm = orc.render(sp, cam, mode=0), orc.render(sm, cam, mode=0)
+        if not (np.array_equal(rp["n_blended"], base["n_blended"]) and np.array_equal(rm["n_blended"], base["n_blended"])):
+            continue
+        step = float(np.float32(x + h)) - float(np.float32(x - h))
+        per_px = ((rp["image"] - rm["image"]) * g).sum(0) / step
+        o = 1 / (1 + math.exp(-float(x)))
+        g_o = per_px / (o * (1 - o))
+        assert bw["M"][i] == pytest.approx(g_o.sum(), rel=1e-5, abs=1e-9)
+        assert bw["S"][i] == pytest.approx((g_o ** 2).sum(), rel=1e-5, abs=1e-9)
+        tested += 1
+    assert tested >= 3
+
+
+def test_variance_closed_form(orc):
+    rng = np.random.default_rng(4)
+    xs = [rng.standard_normal(k) for k in (1, 5, 40)]
+    S = np.array([np.sum(x * x) for x in xs] + [0.0])
+    M = np.array([np.sum(x) for x in xs] + [0.0])
+    C = np.array([x.size for x in xs] + [0], dtype=np.int64)
+    V = orc.variance(S, M, C)
+    assert V[:3] == pytest.approx([x.size * np.var(x) for x in xs], abs=1e-12)
+    assert V[3] == 0.0
+
+
+# ------------------------------------------------------------------ P8: Morton
+def test_morton_hand_values(orc):
+    # the first two points pin the per-axis bounds to [0, 1]
+    pts = np.array([[0, 0, 0], [1, 1, 1], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0.5, 0, 0]], np.float32)
+    codes, _ = orc.morton(pts)
+    unit = sum(1 << (3 * k) for k in range(21))
+    assert int(codes[0]) == 0
+    assert int(codes[1]) == (1 << 63) - 1
+    assert int(codes[2]) == unit and int(codes[3]) == 2 * unit and int(codes[4]) == 4 * unit
+    # 0.5 * (2^21 - 1) truncates to 2^20 - 1
+    assert int(codes[5]) == sum(1 << (3 * k) for k in range(20))
+
+
+def _deinterleave(code):
+    c = int(code)
+    out = [0, 0, 0]
+    for k in range(21):
+        for a in range(3):
+            out[a] |= ((c >> (3 * k + a)) & 1) << k
+    return out
+
+
+def test_morton_decode_monotone_and_stable(orc):
+    rng = np.random.default_rng(6)
+    pts = rng.uniform(-3, 7, (2000, 3)).astype(np.float32)
+    pts[100:110] = pts[50]  # duplicates exercise the stable tie order
+    codes, perm = orc.morton(pts)
+    dec = np.array([_deinterleave(c) for c in codes], dtype=np.float64)
+    lo, hi = pts.min(0).astype(np.float64), pts.max(0).astype(np.float64)
+    u = (pts.astype(np.float64) - lo) / (hi - lo) * 2097151
+    assert np.all(np.abs(dec - u) <= 1.0)
+    for a in range(3):
+        o = np.argsort(pts[:, a], kind="stable")
+        assert np.all(np.diff(dec[o, a]) >= 0)
+    assert np.array_equal(perm, np.argsort(codes, kind="stable"))
+
+
+# ------------------------------------------------------------------ clusters and binning
+def test_cluster_bounds_brute_force(orc):
+    rng = np.random.default_rng(8)
+    n = 1000  # last cluster is ragged (1000 = 7 * 128 + 104)
+    m = rng.standard_normal((n, 3)).astype(np.float32)
+    ls = rng.normal(-3, 1, (n, 3)).astype(np.float32)
+    b = orc.cluster_bounds(m, ls, 128)
+    assert b.shape == (8, 8)
+    for c in range(8):
+        sl = slice(128 * c, min(n, 128 * (c + 1)))
+        assert np.array_equal(b[c, :3], m[sl].min(0)) and np.array_equal(b[c, 3:6], m[sl].max(0))
+        assert b[c, 6] == ls[sl].max()
+
+
+def test_binning_brute_force(orc):
+    sc = scenes.tiny_scene(300, seed_salt=3)
+    views = []
+    cams = [scenes.tiny_camera(128, 128), scenes.tiny_camera(72, 40)]
+    for cam in cams:
+        pp = orc.preprocess(sc, cam)
+        tx, ty = cam.tiles()
+        views.append((pp["valid"], pp["rect"], pp["depth_bits"], tx, ty))
+    keys, vals, ranges = orc.bin_instances(views)
+    # brute force with Python's sorted (stable) over explicitly listed pairs
+    pairs = []
+    base = 0
+    for v, (valid, rect, db, tx, ty) in enumerate(views):
+        for i in range(sc.n):
+            if not valid[i]:
+                continue
+            x0, x1, y0, y1 = rect[i]
+            for y in range(y0, y1 + 1):
+                for x in range(x0, x1 + 1):
+                    pairs.append((((base + y * tx + x) << 32) | int(db[i]), v * sc.n + i))
+        base += tx * ty
+    exp = sorted(pairs, key=lambda p: p[0])
+    assert [int(k) for k in keys] == [p[0] for p in exp]
+    assert [int(x) for x in vals] == [p[1] for p in exp]
+    assert orc.count_instances(views) == len(exp)
+    # ranges partition [0, M) and hold only their own tile
+    tile = (keys >> np.uint64(32)).astype(np.int64)
+    covered = 0
+    for t in range(ranges.shape[0]):
+        s, e = ranges[t]
+        assert np.all(tile[s:e] == t)
+        covered += e - s
+    assert covered == len(exp)
+    # depth order within a tile, ties by index
+    for t in range(ranges.shape[0]):
+        s, e = ranges[t]
+        d = (keys[s:e] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        assert np.all(np.diff(d) >= 0)
+
+
+def test_gradients_through_jacobian_clamp(orc):
+    """Large Gaussians beyond the 1.3 x half-FoV clamp (x/z = 0.8 > 0.65) whose
+    footprints still reach into the image: the clamped branch of the EWA Jacobian."""
+    cam = _cam(W=48, H=40, f=48.0, bg=(0.1, 0.1, 0.1))
+    means = [[1.6, 0.1, 2.0], [-1.7, -0.2, 2.1], [0.1, 1.3, 1.9]]
+    sc = _one_gaussian(means, [math.log(0.5), math.log(0.3), math.log(0.4)],
+                       [0.8, 0.3, -0.2, 0.4], [0.7, 0.8, 0.6], [[0.9, 0.2, 0.4], [0.1, 0.8, 0.3], [0.5, 0.5, 0.9]])
+    pp = orc.preprocess(sc, cam)
+    lim = 1.3 * 48 / (2 * 48.0)
+    assert np.sum(np.abs(pp["tcam"][:, 0] / pp["tcam"][:, 2]) > lim) == 2 and pp["valid"].all()
+    rng = np.random.default_rng(21)
+    g = rng.uniform(-1, 1, (3, cam.height, cam.width))
+    bw = orc.backward(sc, cam, g, mode=0, threads=1)
+    checked = 0
+    for field in ("means", "log_scales", "quats"):
+        arr = getattr(sc, field).reshape(-1)
+        for idx in range(arr.size):
+            x = np.float32(arr[idx])
+            h = np.float32(max(1.0, abs(float(x))) * 3e-5)
+            xp, xm = np.float32(x + h), np.float32(x - h)
+            Lp, nbp = _loss(orc, _set(sc, field, idx, xp), cam, g)
+            Lm, nbm = _loss(orc, _set(sc, field, idx, xm), cam, g)
+            if not np.array_equal(nbp, nbm):
+                continue
+            fd = (Lp - Lm) / (float(xp) - float(xm))
+            an = bw[field].reshape(-1)[idx]
+            scale = max(abs(an), 1e-3 * np.abs(bw[field]).max(), 1e-8)
+            assert abs(fd - an) <= 2e-5 * scale + 1e-10, (field, idx, fd, an)
+            checked += 1
+    assert checked >= 25
