@@ -1,0 +1,229 @@
+/* gsr.h - C ABI of the MI355X (gfx950) differentiable tile-based Gaussian rasterizer.
+ *
+ * The library implements the hot path of LiteGS (arXiv 2503.01199): projection of
+ * 3-D Gaussians to screen space with spherical-harmonic colour, Morton ordering
+ * with cluster-level culling and compaction (Sec. 3.2), (tile, depth) sorting and
+ * binning, front-to-back alpha compositing (Sec. 3, Eq. (1)-(2); App. A.2) and its
+ * backward pass (Eq. (3); App. A.1), with the opacity-gradient statistic of Sec. 3.3.
+ *
+ * Conventions for every call:
+ *  - Pointers typed `const float *` / `float *` inside gsr_scene, gsr_grads,
+ *    gsr_stats and the image arrays are DEVICE pointers owned by the caller. The
+ *    gsr_camera array and every struct passed by pointer are HOST memory, read
+ *    during the call only.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Every call enqueues
+ *    its work on that stream and returns; gsr_forward additionally waits once for
+ *    a 4-byte count (see below). Results are valid once the stream has reached
+ *    the call's work.
+ *  - The library never allocates device memory. Scratch space comes from a
+ *    caller-owned workspace whose size the *_workspace_size calls report.
+ *  - Every call returns a gsr_status. Host-side validation happens before any
+ *    work is enqueued, so on GSR_ERR_INVALID_ARG or GSR_ERR_WORKSPACE_TOO_SMALL
+ *    no output has been touched. gsr_last_error() describes the last failure.
+ *  - A context is a host object bound to one device. It is not thread-safe: use
+ *    one context per host thread. Separate workspaces on separate streams may
+ *    run concurrently.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GSR_OK = 0,
+  GSR_ERR_INVALID_ARG = 1,          /* a null pointer, bad size or option; nothing enqueued */
+  GSR_ERR_WORKSPACE_TOO_SMALL = 2,  /* gsr_required_workspace() gives the bytes needed */
+  GSR_ERR_DEVICE = 3,               /* a HIP runtime call failed */
+  GSR_ERR_UNSUPPORTED = 4
+} gsr_status;
+
+typedef enum {
+  GSR_FP32 = 0,        /* every raster quantity in FP32 */
+  GSR_FP16_BLEND = 1   /* exponent increments, exp and alpha in packed FP16 (Sec. 3.1.2); colour, T
+                          and all gradients accumulate in FP32 */
+} gsr_precision;
+
+#define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile */
+#define GSR_CLUSTER 128      /* primitives per cluster (Sec. 3.2.2) */
+#define GSR_MAX_VIEWS 64     /* views per gsr_forward / gsr_backward call */
+
+typedef struct gsr_context gsr_context;
+
+/* The scene G = {g_i} of Sec. 3: per Gaussian a mean, a covariance given as
+ * log-scales and a rotation quaternion, an opacity logit and SH colour
+ * coefficients. Structure of arrays, FP32, contiguous, device memory:
+ *   means [n,3] world; log_scales [n,3], Sigma = R diag(exp(2 s)) R^T;
+ *   quats [n,4] as (w, x, y, z), any non-zero norm (normalised inside);
+ *   opacity_logits [n], o = 1/(1 + exp(-l));
+ *   sh [n,K,3], K = (sh_degree+1)^2, real orthonormal SH without the
+ *   Condon-Shortley phase, colour = max(0, sum_k Y_k(dir) f_k + 1/2). */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  const float *means;
+  const float *log_scales;
+  const float *quats;
+  const float *opacity_logits;
+  const float *sh;
+} gsr_scene;
+
+/* A pinhole view pi_j (HOST memory). x_cam = R x_world + t with x right, y down,
+ * z forward; pixel (px, py) has its centre at (px + 1/2, py + 1/2) and a point
+ * projects to u = fx x/z + cx, v = fy y/z + cy. Gaussians with z <= near_plane
+ * are dropped. bg is composited behind the last blended Gaussian. */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R[9]; /* row-major */
+  float t[3];
+  float near_plane;
+  float bg[3];
+} gsr_camera;
+
+typedef struct {
+  int32_t precision;    /* gsr_precision */
+  int32_t cluster_cull; /* 1: cull clusters of GSR_CLUSTER consecutive Gaussians against the
+                           frusta and compact the visible ones (Sec. 3.2.2); 0: keep all */
+  int32_t stats;        /* 1: gsr_backward accumulates the statistic into gsr_stats */
+  int32_t reserved;     /* must be 0 */
+} gsr_options;
+
+/* Parameter gradients, device memory, the shapes of gsr_scene's arrays. Overwritten
+ * by gsr_backward (0 for Gaussians that no view sees). */
+typedef struct {
+  float *means;
+  float *log_scales;
+  float *quats;
+  float *opacity_logits;
+  float *sh;
+} gsr_grads;
+
+/* Opacity-gradient statistic of Sec. 3.3, device memory, [n] each, ACCUMULATED (+=)
+ * by gsr_backward over every (view, pixel) fragment in which the Gaussian is
+ * blended: S = sum (dL/do)^2, M = sum dL/do (o the activated opacity), C = count.
+ * The caller zeroes them at the start of a densification interval. */
+typedef struct {
+  float *S;
+  float *M;
+  uint32_t *C;
+} gsr_stats;
+
+/* Counters of the last forward on a workspace (host copy, filled by gsr_forward). */
+typedef struct {
+  int64_t n;               /* Gaussians in the scene */
+  int64_t n_visible_slots; /* compact slots = 128 x visible clusters (all when culling is off) */
+  int64_t instances;       /* (tile, Gaussian) pairs M */
+  int64_t tiles;           /* tiles over all views */
+  int64_t pixels;          /* pixels over all views */
+  int32_t views;
+  int32_t clusters;
+  int32_t visible_clusters;
+  int32_t reserved;
+} gsr_frame_info;
+
+/* Device pointers into a workspace after gsr_forward, for inspection and tests.
+ * Records are indexed r = slot * views + view, slot = compact position.
+ *   record      f32[R][12] : u_hi, v_hi, u_lo, v_lo, k1, r, k2, quad, o, red, green, blue
+ *                (screen mean as a float-float pair; exponent in log2 units
+ *                 E2 = k1 (dx + r dy)^2 + k2 dy^2, quad = E2's coefficient of j^2)
+ *   depth_key   u32[R]     : FP32 bits of the camera-space depth (0xffffffff: invalid)
+ *   tiles       u32[R]     : tiles touched
+ *   rect        u16[R][4]  : tile rect x0, x1, y0, y1 (inclusive)
+ *   compact2full u32[slots]: full Gaussian index of each compact slot (0xffffffff: none)
+ *   inst_tile   u32[M], inst_record u32[M]: instances sorted by (tile, depth, record)
+ *   ranges      u32[tiles][2]: [start, end) of each tile's instances
+ *   pixel_rgb   f32[pixels][3], pixel_T f32[pixels], pixel_last u32[pixels]
+ *                 (list position + 1 of the last blended instance)
+ *   grad2d      f32[R][12] (after gsr_backward): d/du, d/dv, d/da, d/db, d/dc, d/do,
+ *                 d/dred, d/dgreen, d/dblue, S, C, 0 of each record
+ *   cluster_bounds f32[clusters][8] : min xyz, max xyz, max log-scale, 0
+ *   cluster_visible u32[clusters] */
+typedef struct {
+  const float *record;
+  const uint32_t *depth_key;
+  const uint32_t *tiles;
+  const uint16_t *rect;
+  const uint32_t *compact2full;
+  const uint32_t *inst_tile;
+  const uint32_t *inst_record;
+  const uint32_t *ranges;
+  const float *pixel_rgb;
+  const float *pixel_T;
+  const uint32_t *pixel_last;
+  const float *grad2d;
+  const float *cluster_bounds;
+  const uint32_t *cluster_visible;
+  int64_t pixel_base[GSR_MAX_VIEWS]; /* first pixel of each view in the pixel arrays */
+  int64_t tile_base[GSR_MAX_VIEWS];  /* first global tile id of each view */
+} gsr_frame_buffers;
+
+/* Context on HIP device `device`. Returns GSR_ERR_DEVICE if the device cannot be used. */
+gsr_status gsr_context_create(int device, gsr_context **out);
+void gsr_context_destroy(gsr_context *ctx);
+/* Message of the last non-OK status on this context (never NULL). */
+const char *gsr_last_error(const gsr_context *ctx);
+/* Bytes that the last GSR_ERR_WORKSPACE_TOO_SMALL asked for. */
+size_t gsr_required_workspace(const gsr_context *ctx);
+
+/* Workspace bytes for one frame of V views whose instance count M is at most
+ * max_instances. Needs no device (ctx may be NULL) and validates its arguments
+ * exactly as gsr_forward does. M depends on the scene and is known only after projection:
+ * gsr_forward reports GSR_ERR_WORKSPACE_TOO_SMALL with the exact requirement when
+ * the workspace is too small for the actual M. */
+gsr_status gsr_workspace_size(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
+                              const gsr_options *opts, int64_t max_instances, size_t *bytes);
+
+/* Forward render of V views (Sec. 3, Eq. (1)): images[v] is a device pointer to
+ * f32 [3, height_v, width_v] (planar RGB), overwritten. The workspace keeps the
+ * frame state that gsr_backward needs; do not reuse it for another frame in
+ * between. Waits once on `stream` to read back the instance count M. */
+gsr_status gsr_forward(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
+                       const gsr_options *opts, void *workspace, size_t ws_bytes, float *const *images,
+                       void *stream);
+
+/* Backward of the last gsr_forward on `workspace` with the same scene, cameras and
+ * options (Sec. 3, Eq. (3); App. A.1-A.2). dL_dimages[v] is a device pointer to
+ * f32 [3, height_v, width_v]. grads are overwritten; stats (nullable; used when
+ * opts->stats = 1) are accumulated. Fully asynchronous. */
+gsr_status gsr_backward(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
+                        const gsr_options *opts, void *workspace, size_t ws_bytes,
+                        const float *const *dL_dimages, const gsr_grads *grads, const gsr_stats *stats,
+                        void *stream);
+
+/* Counters and buffer pointers of the last gsr_forward on `workspace`. */
+gsr_status gsr_frame_inspect(gsr_context *ctx, const void *workspace, gsr_frame_info *info,
+                             gsr_frame_buffers *bufs);
+
+/* Densification metric of Sec. 3.3, C * Var = S - M^2 / C (0 where C = 0),
+ * evaluated in FP64: out[n] f32, device memory. */
+gsr_status gsr_variance(gsr_context *ctx, const gsr_stats *stats, int64_t n, float *out, void *stream);
+
+/* Workspace bytes for gsr_morton_order on n Gaussians (ctx may be NULL). */
+gsr_status gsr_morton_workspace_size(gsr_context *ctx, int64_t n, size_t *bytes);
+
+/* Morton order (Sec. 3.2.1): per-axis min/max normalisation of means [n,3] to the
+ * unit cube, scaling by 2^21 - 1 with truncation, and interleaving bit k of x, y, z
+ * into bits 3k, 3k+1, 3k+2 of a 63-bit code (FP64 arithmetic on the FP32 means:
+ * q = trunc(clamp((p - lo)/(hi - lo), 0, 1) * 2097151), 0 on a degenerate axis).
+ * perm [n] (i64, device) receives the indices stably sorted by code; codes [n]
+ * (u64, device, nullable) the codes in the original order. */
+gsr_status gsr_morton_order(gsr_context *ctx, const float *means, int64_t n, void *workspace, size_t ws_bytes,
+                            int64_t *perm, uint64_t *codes, void *stream);
+
+/* Gathers rows: dst[a][i, :] = src[a][perm[i], :] for n_arrays arrays of n rows of
+ * row_floats[a] floats (device memory; dst and src must not overlap). Applies a
+ * Morton order to the parameters and to any optimiser state. */
+gsr_status gsr_apply_permutation(gsr_context *ctx, const int64_t *perm, int64_t n, int32_t n_arrays,
+                                 const float *const *src, float *const *dst, const int32_t *row_floats,
+                                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSR_H */

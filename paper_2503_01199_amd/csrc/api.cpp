@@ -1,0 +1,483 @@
+// Host runtime behind the C ABI of include/gsr.h: argument validation, the
+// workspace plan, launch sequencing and the per-workspace frame registry.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+
+#include "gsr_internal.h"
+
+using gsr::Frame;
+using gsr::ViewDev;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr size_t kPinnedBytes = 64 * 1024;
+
+struct FrameRecord {
+  Frame f;
+  gsr_frame_info info;
+  int64_t tile_base[GSR_MAX_VIEWS];
+  int64_t pixel_base[GSR_MAX_VIEWS];
+};
+
+}  // namespace
+
+struct gsr_context {
+  int device = 0;
+  std::string err;
+  size_t required = 0;
+  void* pinned = nullptr;
+  std::unordered_map<const void*, FrameRecord> frames;
+};
+
+namespace {
+
+gsr_status fail(gsr_context* ctx, gsr_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+gsr_status fail(gsr_context* ctx, gsr_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  return st;
+}
+
+gsr_status check_hip(gsr_context* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return GSR_OK;
+  return fail(ctx, GSR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes ctx's device current for the duration of a call and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+struct Planner {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) & ~(kAlign - 1);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int bits_for(int64_t count) {
+  int b = 0;
+  while (b < 63 && ((int64_t)1 << b) < count) ++b;
+  return b;
+}
+
+gsr_status validate_scene(gsr_context* ctx, const gsr_scene* sc) {
+  if (!sc) return fail(ctx, GSR_ERR_INVALID_ARG, "scene is NULL");
+  if (sc->n < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "scene n = %lld < 0", (long long)sc->n);
+  if (sc->n > (int64_t)0x7fffffff / 4) return fail(ctx, GSR_ERR_INVALID_ARG, "scene n = %lld too large", (long long)sc->n);
+  if (sc->sh_degree < 0 || sc->sh_degree > 3)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "sh_degree = %d not in [0, 3]", sc->sh_degree);
+  if (sc->n > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "a scene array pointer is NULL");
+  return GSR_OK;
+}
+
+gsr_status validate_views(gsr_context* ctx, const gsr_camera* cams, int32_t V) {
+  if (!cams) return fail(ctx, GSR_ERR_INVALID_ARG, "cameras are NULL");
+  if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_ERR_INVALID_ARG, "V = %d not in [1, %d]", V, GSR_MAX_VIEWS);
+  int64_t tiles = 0;
+  for (int v = 0; v < V; ++v) {
+    const gsr_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 65535 * GSR_TILE || c.height > 65535 * GSR_TILE)
+      return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: image %dx%d out of range", v, c.width, c.height);
+    if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy) ||
+        !std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: bad intrinsics", v);
+    if (!(c.near_plane > 0.0f)) return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: near_plane must be > 0", v);
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(c.R[k])) return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: R not finite", v);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(c.t[k]) || !std::isfinite(c.bg[k]))
+        return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: t or bg not finite", v);
+    tiles += (int64_t)((c.width + GSR_TILE - 1) / GSR_TILE) * ((c.height + GSR_TILE - 1) / GSR_TILE);
+  }
+  if (tiles >= ((int64_t)1 << 31)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles");
+  return GSR_OK;
+}
+
+gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
+  if (!o) return fail(ctx, GSR_ERR_INVALID_ARG, "options are NULL");
+  if (o->precision != GSR_FP32 && o->precision != GSR_FP16_BLEND)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+  if (o->precision == GSR_FP16_BLEND) return fail(ctx, GSR_ERR_UNSUPPORTED, "FP16 blending is not built yet");
+  if (o->cluster_cull != 0 && o->cluster_cull != 1)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "cluster_cull must be 0 or 1");
+  if (o->stats != 0 && o->stats != 1) return fail(ctx, GSR_ERR_INVALID_ARG, "stats must be 0 or 1");
+  if (o->reserved != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "reserved option field must be 0");
+  return GSR_OK;
+}
+
+// Lays out one frame in a workspace (or, with ws == nullptr, only sizes it).
+// Returns the bytes of the fixed part; the instance area of inst_cap entries
+// follows it.
+size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t inst_cap, void* ws, Frame& f,
+                  size_t* total) {
+  std::memset(&f, 0, sizeof(f));
+  f.n = sc->n;
+  f.V = V;
+  f.nclusters = (int32_t)((sc->n + GSR_CLUSTER - 1) / GSR_CLUSTER);
+  f.ncap = (int64_t)f.nclusters * GSR_CLUSTER;
+  f.nrec = f.ncap * V;
+  f.tiles = 0;
+  f.pixels = 0;
+  for (int v = 0; v < V; ++v) {
+    f.tiles += (int64_t)((cams[v].width + GSR_TILE - 1) / GSR_TILE) * ((cams[v].height + GSR_TILE - 1) / GSR_TILE);
+    f.pixels += (int64_t)cams[v].width * cams[v].height;
+  }
+  f.tile_bits = bits_for(f.tiles);
+  f.inst_cap = inst_cap;
+  Planner P{static_cast<char*>(ws)};
+  const size_t nr = (size_t)f.nrec, nc = (size_t)std::max(f.nclusters, 1);
+  f.header = P.take<uint32_t>(64);
+  f.views = P.take<ViewDev>(V);
+  f.cluster_bounds = P.take<float>(8 * nc);
+  f.cluster_visible = P.take<uint32_t>(nc);
+  f.cluster_offset = P.take<uint32_t>(nc);
+  f.cluster_list = P.take<uint32_t>(nc);
+  f.compact2full = P.take<uint32_t>(std::max<size_t>(f.ncap, 1));
+  f.rec = P.take<gsr::Record>(std::max<size_t>(nr, 1));
+  f.dkey = P.take<uint32_t>(nr + 1);
+  f.tiles_touched = P.take<uint32_t>(nr + 1);
+  f.rect = P.take<ushort4>(nr + 1);
+  f.skey[0] = P.take<uint32_t>(nr + 1);
+  f.skey[1] = P.take<uint32_t>(nr + 1);
+  f.sval[0] = P.take<uint32_t>(nr + 1);
+  f.sval[1] = P.take<uint32_t>(nr + 1);
+  f.sorted_tiles = P.take<uint32_t>(nr + 1);
+  f.offsets = P.take<uint32_t>(nr + 1);
+  f.ranges = P.take<uint32_t>(2 * (size_t)f.tiles);
+  f.pix_rgb = P.take<float>(3 * (size_t)f.pixels);
+  f.pix_T = P.take<float>((size_t)f.pixels);
+  f.pix_last = P.take<uint32_t>((size_t)f.pixels);
+  f.grad2d = P.take<float>(gsr::kGrad2D * std::max<size_t>(nr, 1));
+  f.temp_words = std::max(gsr::scan_temp_words(std::max<int64_t>(f.nrec, f.nclusters)), gsr::radix_temp_words());
+  f.temp = P.take<uint32_t>(f.temp_words);
+  const size_t fixed = (P.off + kAlign - 1) & ~(kAlign - 1);
+  for (int b = 0; b < 2; ++b) {
+    f.ikey[b] = P.take<uint32_t>((size_t)inst_cap);
+    f.ival[b] = P.take<uint32_t>((size_t)inst_cap);
+  }
+  if (total) *total = (P.off + kAlign - 1) & ~(kAlign - 1);
+  return fixed;
+}
+
+size_t bytes_for_instances(size_t fixed, int64_t m) { return fixed + 4 * (((size_t)m * 4 + kAlign - 1) & ~(kAlign - 1)) + 4 * kAlign; }
+
+int64_t instances_for_bytes(size_t fixed, size_t ws_bytes) {
+  if (ws_bytes < fixed + 8 * kAlign) return 0;
+  return (int64_t)((ws_bytes - fixed - 8 * kAlign) / 16);
+}
+
+void fill_views(const gsr_camera* cams, int32_t V, ViewDev* out) {
+  int64_t tile_base = 0, pixel_base = 0;
+  for (int v = 0; v < V; ++v) {
+    const gsr_camera& c = cams[v];
+    ViewDev& w = out[v];
+    std::memset(&w, 0, sizeof(w));
+    std::memcpy(w.R, c.R, sizeof(w.R));
+    std::memcpy(w.t, c.t, sizeof(w.t));
+    w.fx = c.fx;
+    w.fy = c.fy;
+    w.cx = c.cx;
+    w.cy = c.cy;
+    w.near_plane = c.near_plane;
+    std::memcpy(w.bg, c.bg, sizeof(w.bg));
+    w.limx = gsr::kFovClamp * (double)c.width / (2.0 * (double)c.fx);
+    w.limy = gsr::kFovClamp * (double)c.height / (2.0 * (double)c.fy);
+    const double R[9] = {c.R[0], c.R[1], c.R[2], c.R[3], c.R[4], c.R[5], c.R[6], c.R[7], c.R[8]};
+    const double t[3] = {c.t[0], c.t[1], c.t[2]};
+    w.campos[0] = -(R[0] * t[0] + R[3] * t[1] + R[6] * t[2]);
+    w.campos[1] = -(R[1] * t[0] + R[4] * t[1] + R[7] * t[2]);
+    w.campos[2] = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
+    w.width = c.width;
+    w.height = c.height;
+    w.tiles_x = (c.width + GSR_TILE - 1) / GSR_TILE;
+    w.tiles_y = (c.height + GSR_TILE - 1) / GSR_TILE;
+    w.tile_base = (int32_t)tile_base;
+    w.pixel_base = pixel_base;
+    tile_base += (int64_t)w.tiles_x * w.tiles_y;
+    pixel_base += (int64_t)c.width * c.height;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_context_create(int device, gsr_context** out) {
+  if (!out) return GSR_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSR_ERR_DEVICE;
+  gsr_context* ctx = new gsr_context();
+  ctx->device = device;
+  DeviceGuard g(device);
+  if (hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+    delete ctx;
+    return GSR_ERR_DEVICE;
+  }
+  *out = ctx;
+  return GSR_OK;
+}
+
+void gsr_context_destroy(gsr_context* ctx) {
+  if (!ctx) return;
+  if (ctx->pinned) {
+    DeviceGuard g(ctx->device);
+    (void)hipHostFree(ctx->pinned);
+  }
+  delete ctx;
+}
+
+const char* gsr_last_error(const gsr_context* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+size_t gsr_required_workspace(const gsr_context* ctx) { return ctx ? ctx->required : 0; }
+
+gsr_status gsr_workspace_size(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                              const gsr_options* opts, int64_t max_instances, size_t* bytes) {
+  if (!bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "NULL output");
+  gsr_status st;
+  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)))
+    return st;
+  if (max_instances < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances < 0");
+  Frame f;
+  const size_t fixed = plan_frame(scene, cams, V, 0, nullptr, f, nullptr);
+  *bytes = bytes_for_instances(fixed, max_instances);
+  return GSR_OK;
+}
+
+gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                       const gsr_options* opts, void* workspace, size_t ws_bytes, float* const* images,
+                       void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  gsr_status st;
+  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)))
+    return st;
+  if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
+  if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (!images) return fail(ctx, GSR_ERR_INVALID_ARG, "images is NULL");
+  for (int v = 0; v < V; ++v)
+    if (!images[v]) return fail(ctx, GSR_ERR_INVALID_ARG, "images[%d] is NULL", v);
+  Frame f;
+  const size_t fixed = plan_frame(scene, cams, V, 0, nullptr, f, nullptr);
+  if (ws_bytes < bytes_for_instances(fixed, 0)) {
+    ctx->required = bytes_for_instances(fixed, 16 * (int64_t)scene->n + 1024);
+    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes < %zu needed before instances", ws_bytes,
+                bytes_for_instances(fixed, 0));
+  }
+  const int64_t cap = instances_for_bytes(fixed, ws_bytes);
+  size_t total = 0;
+  plan_frame(scene, cams, V, cap, workspace, f, &total);
+  if (total > ws_bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: workspace plan exceeds its size");
+
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ViewDev* hv = static_cast<ViewDev*>(ctx->pinned);
+  uint32_t* hhdr = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->pinned) + kPinnedBytes - 256);
+  fill_views(cams, V, hv);
+  if ((st = check_hip(ctx, hipMemcpyAsync(f.views, hv, sizeof(ViewDev) * V, hipMemcpyHostToDevice, s), "upload views")))
+    return st;
+  gsr::fill_u32(f.header, 64, 0u, s);
+  // Cluster-Cull-Compact
+  if (opts->cluster_cull) {
+    gsr::launch_cluster_bounds(scene->means, scene->log_scales, scene->n, f.cluster_bounds, s);
+    gsr::launch_cluster_cull(f.cluster_bounds, f.nclusters, f.views, V, f.cluster_visible, s);
+  } else {
+    gsr::fill_u32(f.cluster_visible, f.nclusters, 1u, s);
+  }
+  gsr::scan_exclusive_u32(f.cluster_visible, f.cluster_offset, f.nclusters, f.header + 0, f.temp, s);
+  gsr::launch_cluster_list(f.cluster_visible, f.cluster_offset, f.nclusters, f.cluster_list, s);
+  // projection
+  gsr::launch_preprocess_fwd(*scene, f, s);
+  // depth order of the records, then instance offsets in that order
+  {
+    uint32_t* kb[2] = {f.skey[0], f.skey[1]};
+    uint32_t* vb[2] = {f.sval[0], f.sval[1]};
+    const int r = gsr::radix_sort_u32(f.dkey, nullptr, kb, vb, f.nrec, 32, f.temp, s);
+    const uint32_t* sorted_rec = vb[r];
+    gsr::launch_gather_tiles(f, sorted_rec, s);
+    gsr::scan_exclusive_u32(f.sorted_tiles, f.offsets, f.nrec, f.header + 1, f.temp, s);
+    if ((st = check_hip(ctx, hipGetLastError(), "projection and depth sort"))) return st;
+    if ((st = check_hip(ctx, hipMemcpyAsync(hhdr, f.header, 16, hipMemcpyDeviceToHost, s), "read counts"))) return st;
+    if ((st = check_hip(ctx, hipStreamSynchronize(s), "synchronise on counts"))) return st;
+    const int64_t M = hhdr[1];
+    const int64_t nvis = hhdr[0];
+    if (M > cap) {
+      ctx->required = bytes_for_instances(fixed, M + M / 8 + 1024);
+      return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
+                  (long long)cap);
+    }
+    gsr::launch_emit_instances(f, sorted_rec, s);
+    uint32_t* ik[2] = {f.ikey[1], f.ikey[0]};
+    uint32_t* iv[2] = {f.ival[1], f.ival[0]};
+    const int ri = gsr::radix_sort_u32(f.ikey[0], f.ival[0], ik, iv, M, f.tile_bits, f.temp, s);
+    f.inst_tile = ik[ri];
+    f.inst_rec = iv[ri];
+    gsr::launch_tile_ranges(f, f.inst_tile, M, s);
+    gsr::ImagePtrs ip;
+    std::memset(&ip, 0, sizeof(ip));
+    for (int v = 0; v < V; ++v) ip.p[v] = images[v];
+    gsr::launch_raster_fwd(f, ip, opts->precision, s);
+    if ((st = check_hip(ctx, hipGetLastError(), "binning and raster"))) return st;
+    FrameRecord& fr = ctx->frames[workspace];
+    fr.f = f;
+    std::memset(&fr.info, 0, sizeof(fr.info));
+    fr.info.n = scene->n;
+    fr.info.n_visible_slots = nvis * GSR_CLUSTER;
+    fr.info.instances = M;
+    fr.info.tiles = f.tiles;
+    fr.info.pixels = f.pixels;
+    fr.info.views = V;
+    fr.info.clusters = f.nclusters;
+    fr.info.visible_clusters = (int32_t)nvis;
+    for (int v = 0; v < V; ++v) {
+      fr.tile_base[v] = hv[v].tile_base;
+      fr.pixel_base[v] = hv[v].pixel_base;
+    }
+  }
+  return GSR_OK;
+}
+
+gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                        const gsr_options* opts, void* workspace, size_t ws_bytes, const float* const* dL_dimages,
+                        const gsr_grads* grads, const gsr_stats* stats, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  gsr_status st;
+  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)))
+    return st;
+  if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
+  auto it = ctx->frames.find(workspace);
+  if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "no forward was run on this workspace");
+  const Frame& f = it->second.f;
+  if (f.n != scene->n || f.V != V) return fail(ctx, GSR_ERR_INVALID_ARG, "scene or views differ from the forward");
+  {
+    Frame chk;
+    size_t total = 0;
+    plan_frame(scene, cams, V, f.inst_cap, workspace, chk, &total);
+    if (chk.tiles != f.tiles || chk.pixels != f.pixels || total > ws_bytes)
+      return fail(ctx, GSR_ERR_INVALID_ARG, "cameras or workspace differ from the forward");
+  }
+  if (!dL_dimages) return fail(ctx, GSR_ERR_INVALID_ARG, "dL_dimages is NULL");
+  for (int v = 0; v < V; ++v)
+    if (!dL_dimages[v]) return fail(ctx, GSR_ERR_INVALID_ARG, "dL_dimages[%d] is NULL", v);
+  if (!grads) return fail(ctx, GSR_ERR_INVALID_ARG, "grads is NULL");
+  if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "a gradient array pointer is NULL");
+  const bool use_stats = opts->stats && stats;
+  if (use_stats && scene->n > 0 && (!stats->S || !stats->M || !stats->C))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "a statistic array pointer is NULL");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gsr::fill_f32(f.grad2d, gsr::kGrad2D * f.nrec, 0.0f, s);
+  gsr::ConstImagePtrs dp;
+  std::memset(&dp, 0, sizeof(dp));
+  for (int v = 0; v < V; ++v) dp.p[v] = dL_dimages[v];
+  gsr::launch_raster_bwd(f, dp, opts->precision, s);
+  gsr::launch_preprocess_bwd(*scene, f, 1, *grads, use_stats ? stats : nullptr, s);
+  return check_hip(ctx, hipGetLastError(), "backward");
+}
+
+gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_info* info, gsr_frame_buffers* bufs) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  auto it = ctx->frames.find(workspace);
+  if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "no forward was run on this workspace");
+  const Frame& f = it->second.f;
+  if (info) *info = it->second.info;
+  if (bufs) {
+    std::memset(bufs, 0, sizeof(*bufs));
+    bufs->record = reinterpret_cast<const float*>(f.rec);
+    bufs->depth_key = f.dkey;
+    bufs->tiles = f.tiles_touched;
+    bufs->rect = reinterpret_cast<const uint16_t*>(f.rect);
+    bufs->compact2full = f.compact2full;
+    bufs->inst_tile = f.inst_tile;
+    bufs->inst_record = f.inst_rec;
+    bufs->ranges = f.ranges;
+    bufs->pixel_rgb = f.pix_rgb;
+    bufs->pixel_T = f.pix_T;
+    bufs->pixel_last = f.pix_last;
+    bufs->grad2d = f.grad2d;
+    bufs->cluster_bounds = f.cluster_bounds;
+    bufs->cluster_visible = f.cluster_visible;
+    for (int v = 0; v < f.V; ++v) {
+      bufs->tile_base[v] = it->second.tile_base[v];
+      bufs->pixel_base[v] = it->second.pixel_base[v];
+    }
+  }
+  return GSR_OK;
+}
+
+gsr_status gsr_variance(gsr_context* ctx, const gsr_stats* stats, int64_t n, float* out, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (!stats || n < 0 || (n > 0 && (!stats->S || !stats->M || !stats->C || !out)))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_variance");
+  DeviceGuard guard(ctx->device);
+  gsr::launch_variance(stats->S, stats->M, stats->C, n, out, static_cast<hipStream_t>(stream));
+  return check_hip(ctx, hipGetLastError(), "variance");
+}
+
+gsr_status gsr_morton_workspace_size(gsr_context* ctx, int64_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_morton_workspace_size");
+  *bytes = gsr::morton_temp_words(n) * 4 + 1024;
+  return GSR_OK;
+}
+
+gsr_status gsr_morton_order(gsr_context* ctx, const float* means, int64_t n, void* workspace, size_t ws_bytes,
+                            int64_t* perm, uint64_t* codes, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (n < 0 || n > 0x7fffffff || (n > 0 && (!means || !perm || !workspace)))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_morton_order");
+  const size_t need = gsr::morton_temp_words(n) * 4 + 1024;
+  if (ws_bytes < need) {
+    ctx->required = need;
+    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "morton workspace %zu < %zu", ws_bytes, need);
+  }
+  if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  DeviceGuard guard(ctx->device);
+  gsr::morton_order(means, n, static_cast<uint32_t*>(workspace), perm, codes, static_cast<hipStream_t>(stream));
+  return check_hip(ctx, hipGetLastError(), "morton order");
+}
+
+gsr_status gsr_apply_permutation(gsr_context* ctx, const int64_t* perm, int64_t n, int32_t n_arrays,
+                                 const float* const* src, float* const* dst, const int32_t* row_floats, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (n < 0 || n_arrays < 0 || (n > 0 && n_arrays > 0 && (!perm || !src || !dst || !row_floats)))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_apply_permutation");
+  for (int a = 0; a < n_arrays; ++a) {
+    if (row_floats[a] < 0 || (n > 0 && row_floats[a] > 0 && (!src[a] || !dst[a])))
+      return fail(ctx, GSR_ERR_INVALID_ARG, "array %d: bad pointer or row size", a);
+    if (src[a] == dst[a] && n > 0 && row_floats[a] > 0)
+      return fail(ctx, GSR_ERR_INVALID_ARG, "array %d: src and dst must not overlap", a);
+  }
+  DeviceGuard guard(ctx->device);
+  for (int a = 0; a < n_arrays; ++a)
+    gsr::launch_gather_rows(perm, n, src[a], dst[a], row_floats[a], static_cast<hipStream_t>(stream));
+  return check_hip(ctx, hipGetLastError(), "apply permutation");
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Binning: expand each depth-sorted record into one instance per covered tile and
+// delimit each tile's instances after the tile sort.
+//
+// The records are first stably sorted by depth key (ties keep record order); the
+// instances are then emitted in that order and stably sorted by global tile id.
+// The result is each tile's list in (depth, record) order, the same order as a
+// stable sort of 64-bit (tile << 32 | depth) keys emitted in record order, but it
+// moves 4-byte keys and sorts the instances on the tile bits only.
+#include "gsr_internal.h"
+
+namespace gsr {
+namespace {
+
+__global__ void k_gather_tiles(const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ tiles,
+                               uint32_t* __restrict__ out, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = tiles[sorted_rec[k]];
+}
+
+// One thread per sorted record; writes its instances at its scanned offset, tiles
+// in row-major order of its rect.
+__global__ void k_emit(const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ offsets,
+                       const uint32_t* __restrict__ tiles, const ushort4* __restrict__ rect,
+                       const ViewDev* __restrict__ views, int32_t V, int64_t n, int64_t cap,
+                       uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_rec) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const uint32_t r = sorted_rec[k];
+  const uint32_t cnt = tiles[r];
+  if (cnt == 0) return;
+  const ushort4 b = rect[r];
+  const int v = (int)(r % (uint32_t)V);
+  const int32_t base = views[v].tile_base;
+  const int32_t tx = views[v].tiles_x;
+  int64_t o = offsets[k];
+  if (o + cnt > cap) return;  // never taken: the host sized the buffers from the scan total
+  for (int y = b.z; y <= b.w; ++y)
+    for (int x = b.x; x <= b.y; ++x) {
+      inst_tile[o] = (uint32_t)(base + y * tx + x);
+      inst_rec[o] = r;
+      ++o;
+    }
+}
+
+__global__ void k_ranges(const uint32_t* __restrict__ inst_tile, int64_t M, uint32_t* __restrict__ ranges) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const uint32_t t = inst_tile[k];
+  if (k == 0 || inst_tile[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
+  if (k == M - 1 || inst_tile[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+}
+
+}  // namespace
+
+void launch_gather_tiles(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
+  if (f.nrec <= 0) return;
+  k_gather_tiles<<<(unsigned)((f.nrec + 255) / 256), 256, 0, s>>>(sorted_rec, f.tiles_touched, f.sorted_tiles,
+                                                                  f.nrec);
+}
+
+void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
+  if (f.nrec <= 0) return;
+  k_emit<<<(unsigned)((f.nrec + 127) / 128), 128, 0, s>>>(sorted_rec, f.offsets, f.tiles_touched, f.rect, f.views,
+                                                          f.V, f.nrec, f.inst_cap, f.ikey[0], f.ival[0]);
+}
+
+void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M, hipStream_t s) {
+  fill_u32(f.ranges, 2 * f.tiles, 0u, s);
+  if (M <= 0) return;
+  k_ranges<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(inst_tile, M, f.ranges);
+}
+
+}  // namespace gsr

@@ -1,0 +1,139 @@
+// Internal declarations shared by the HIP sources of libgsr (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsr.h"
+
+namespace gsr {
+
+// Thresholds of the compositing rule (Sec. 3, Eq. (1) with the alpha skip, clamp
+// and transmittance stop that the rasterizer applies).
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr double kDilation = 0.3;   // screen-space low-pass, px^2
+constexpr double kFovClamp = 1.3;   // EWA Jacobian evaluated within 1.3 x the half field of view
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+
+// Per-view constants, stored in the workspace (device memory).
+struct ViewDev {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float near_plane;
+  float bg[3];
+  double limx, limy;      // Jacobian clamp limits on x/z and y/z
+  double campos[3];       // camera centre -R^T t
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+  int32_t tile_base;      // first global tile id of the view
+  int32_t pad;
+  int64_t pixel_base;     // first pixel of the view in the per-pixel arrays
+};
+
+// Screen-space record of one (Gaussian, view), 48 bytes = 3 x float4:
+//   r0 = {u_hi, v_hi, u_lo, v_lo}    screen mean as a float-float pair
+//   r1 = {k1, r, k2, quad}           exponent in log2 units:
+//                                      E2(dx, dy) = k1 (dx + r dy)^2 + k2 dy^2,
+//                                      quad = coefficient of j^2 along a column
+//   r2 = {o, red, green, blue}
+struct alignas(16) Record {
+  float4 r0, r1, r2;
+};
+
+// Per-record screen-space gradient accumulated by the backward raster (12 floats):
+// d/du, d/dv, d/da, d/db, d/dc, d/do, d/dred, d/dgreen, d/dblue, S, count, 0, where
+// (a, b, c) is the conic of E = -1/2 (a dx^2 + 2 b dx dy + c dy^2) in natural units.
+constexpr int kGrad2D = 12;
+
+struct Frame {
+  // sizes (host)
+  int64_t n, ncap, nrec;    // Gaussians, compact slots (128 * clusters), records = ncap * V
+  int32_t V, nclusters;
+  int64_t tiles, pixels, inst_cap;
+  int32_t tile_bits;
+  // device pointers (all inside the workspace)
+  uint32_t* header;         // [0] visible clusters, [1] instance count, [2] record scan total
+  ViewDev* views;
+  float* cluster_bounds;    // [nclusters][8]
+  uint32_t* cluster_visible;
+  uint32_t* cluster_offset; // exclusive scan of visible
+  uint32_t* cluster_list;   // compact cluster -> cluster
+  uint32_t* compact2full;   // [ncap]
+  Record* rec;              // [nrec]
+  uint32_t* dkey;           // [nrec]
+  uint32_t* tiles_touched;  // [nrec]
+  ushort4* rect;            // [nrec]
+  uint32_t *skey[2], *sval[2];   // depth sort buffers [nrec]
+  uint32_t* sorted_tiles;   // [nrec]
+  uint32_t* offsets;        // [nrec]
+  uint32_t *ikey[2], *ival[2];   // instance buffers [inst_cap]
+  uint32_t* inst_tile;      // sorted instances (points into ikey/ival)
+  uint32_t* inst_rec;
+  uint32_t* ranges;         // [tiles][2]
+  float* pix_rgb;           // [pixels][3]
+  float* pix_T;             // [pixels]
+  uint32_t* pix_last;       // [pixels]
+  float* grad2d;            // [nrec][12]
+  uint32_t* temp;           // scan / sort scratch
+  size_t temp_words;
+};
+
+// ---------------------------------------------------------------- launchers
+// scan.hip
+size_t scan_temp_words(int64_t n);
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
+                        hipStream_t s);
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+void fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+// sort.hip: stable LSD radix sort of (key, value) pairs by key bits [0, bits), 8
+// bits per pass. The input is read-only; passes alternate between the buffer
+// pairs (kb[0], vb[0]) and (kb[1], vb[1]) and the return value is the index of the
+// pair that holds the result. vals_in == nullptr stands for the values 0..n-1.
+size_t radix_temp_words();
+int radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2], int64_t n,
+                   int bits, uint32_t* temp, hipStream_t s);
+int radix_sort_u64(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2], int64_t n,
+                   int bits, uint32_t* temp, hipStream_t s);
+
+// cluster.hip
+void launch_cluster_bounds(const float* means, const float* log_scales, int64_t n, float* bounds, hipStream_t s);
+void launch_cluster_cull(const float* bounds, int32_t nclusters, const ViewDev* views, int32_t V,
+                         uint32_t* visible, hipStream_t s);
+void launch_cluster_list(const uint32_t* visible, const uint32_t* offset, int32_t nclusters, uint32_t* list,
+                         hipStream_t s);
+
+// preprocess.hip
+void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s);
+void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
+                           const gsr_stats* stats, hipStream_t s);
+
+// binning.hip
+void launch_gather_tiles(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
+void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
+void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M, hipStream_t s);
+
+// raster_fwd.hip / raster_bwd.hip
+struct ImagePtrs {
+  float* p[GSR_MAX_VIEWS];
+};
+struct ConstImagePtrs {
+  const float* p[GSR_MAX_VIEWS];
+};
+void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s);
+void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s);
+
+// morton.hip
+size_t morton_temp_words(int64_t n);
+void morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, uint64_t* codes, hipStream_t s);
+void launch_gather_rows(const int64_t* perm, int64_t n, const float* src, float* dst, int32_t row_floats,
+                        hipStream_t s);
+
+// variance
+void launch_variance(const float* S, const float* M, const uint32_t* C, int64_t n, float* out, hipStream_t s);
+
+}  // namespace gsr

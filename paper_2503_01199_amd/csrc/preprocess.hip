@@ -1,0 +1,512 @@
+// Projection of 3-D Gaussians into screen-space records and its backward.
+//
+// Sec. 3: each primitive {p, Sigma, c, o} becomes {x, y, Sigma_screen, c, o} per
+// view. Sigma = R diag(exp(2 s)) R^T from a normalised quaternion; the screen
+// covariance is the EWA local-affine projection J W Sigma W^T J^T plus a 0.3 px^2
+// low-pass, with the Jacobian evaluated within 1.3x the half field of view; the
+// colour is a degree <= 3 real SH expansion at the camera-to-mean direction, plus
+// 1/2, clamped at 0; o = sigmoid(logit). The support is where alpha = o G >= 1/255,
+// i.e. the ellipse d^T Q d <= 2 ln(255 o); its bounding box gives the tile rect.
+//
+// This stage is memory-bound (236 B of parameters per Gaussian at SH degree 3), so
+// it runs in FP64: on gfx950 FP64 vector math costs half the FP32 rate, which is
+// free here, and it lets the records carry the screen mean as a float-float pair
+// and the conic in a cancellation-free factored form, which is what keeps the
+// FP32 raster within 1e-5 of an FP64 reference at 1600-pixel image widths.
+//
+// One thread per compact slot; a slot is projected into every view of the frame
+// (records r = slot * V + view), so its parameters are read once per frame.
+#include <math.h>
+
+#include "gsr_internal.h"
+
+namespace gsr {
+namespace {
+
+constexpr int kThreads = 128;
+
+struct GaussParams {
+  double m[3];
+  double s[3];     // scales
+  double q[4];     // normalised quaternion
+  double qn;       // norm of the input quaternion
+  double R[9];     // rotation of q, row-major
+  double Sig[6];   // 3-D covariance: xx, xy, xz, yy, yz, zz
+  double o;        // activated opacity
+};
+
+__device__ inline void load_gaussian(const gsr_scene& sc, int64_t i, GaussParams& g) {
+  for (int a = 0; a < 3; ++a) {
+    g.m[a] = (double)sc.means[3 * i + a];
+    g.s[a] = exp((double)sc.log_scales[3 * i + a]);
+  }
+  double q[4];
+  double nn = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    q[a] = (double)sc.quats[4 * i + a];
+    nn += q[a] * q[a];
+  }
+  g.qn = sqrt(nn);
+  for (int a = 0; a < 4; ++a) g.q[a] = q[a] / g.qn;
+  const double w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+  g.R[0] = 1 - 2 * (y * y + z * z); g.R[1] = 2 * (x * y - w * z);     g.R[2] = 2 * (x * z + w * y);
+  g.R[3] = 2 * (x * y + w * z);     g.R[4] = 1 - 2 * (x * x + z * z); g.R[5] = 2 * (y * z - w * x);
+  g.R[6] = 2 * (x * z - w * y);     g.R[7] = 2 * (y * z + w * x);     g.R[8] = 1 - 2 * (x * x + y * y);
+  double L[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) L[3 * r + k] = g.R[3 * r + k] * g.s[k];
+  int idx = 0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = r; c < 3; ++c) {
+      g.Sig[idx++] = L[3 * r + 0] * L[3 * c + 0] + L[3 * r + 1] * L[3 * c + 1] + L[3 * r + 2] * L[3 * c + 2];
+    }
+  g.o = 1.0 / (1.0 + exp(-(double)sc.opacity_logits[i]));
+}
+
+__device__ inline double sig(const GaussParams& g, int r, int c) {
+  // symmetric access into the packed upper triangle
+  if (r > c) {
+    const int t = r;
+    r = c;
+    c = t;
+  }
+  const int base[3] = {0, 3, 5};
+  return g.Sig[base[r] + (c - r)];
+}
+
+// Real SH basis of degree <= 3 (orthonormal, no Condon-Shortley phase) at the unit
+// direction (x, y, z), index l*l + l + m, and optionally its gradient in R^3.
+template <int deg>
+__device__ inline void sh_basis(double x, double y, double z, double* Y, double (*dY)[3]) {
+  const double pi = 3.14159265358979323846;
+  Y[0] = 0.5 * sqrt(1.0 / pi);
+  if (dY) dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
+  if constexpr (deg < 1) return;
+  const double c1 = sqrt(3.0 / (4.0 * pi));
+  Y[1] = c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = c1 * x;
+  if (dY) {
+    dY[1][0] = 0; dY[1][1] = c1; dY[1][2] = 0;
+    dY[2][0] = 0; dY[2][1] = 0;  dY[2][2] = c1;
+    dY[3][0] = c1; dY[3][1] = 0; dY[3][2] = 0;
+  }
+  if constexpr (deg < 2) return;
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double c2a = 0.5 * sqrt(15.0 / pi);   // xy, yz, xz
+  const double c2b = 0.25 * sqrt(5.0 / pi);   // 2z^2 - x^2 - y^2
+  const double c2c = 0.25 * sqrt(15.0 / pi);  // x^2 - y^2
+  Y[4] = c2a * x * y;
+  Y[5] = c2a * y * z;
+  Y[6] = c2b * (2 * zz - xx - yy);
+  Y[7] = c2a * x * z;
+  Y[8] = c2c * (xx - yy);
+  if (dY) {
+    dY[4][0] = c2a * y;      dY[4][1] = c2a * x;       dY[4][2] = 0;
+    dY[5][0] = 0;            dY[5][1] = c2a * z;       dY[5][2] = c2a * y;
+    dY[6][0] = -2 * c2b * x; dY[6][1] = -2 * c2b * y;  dY[6][2] = 4 * c2b * z;
+    dY[7][0] = c2a * z;      dY[7][1] = 0;             dY[7][2] = c2a * x;
+    dY[8][0] = 2 * c2c * x;  dY[8][1] = -2 * c2c * y;  dY[8][2] = 0;
+  }
+  if constexpr (deg < 3) return;
+  const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi));  // m = +-3
+  const double c3b = 0.5 * sqrt(105.0 / pi);          // m = -2
+  const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi));  // m = +-1
+  const double c3d = 0.25 * sqrt(7.0 / pi);           // m = 0
+  const double c3e = 0.25 * sqrt(105.0 / pi);         // m = 2
+  const double f1 = 4 * zz - xx - yy;
+  Y[9] = c3a * y * (3 * xx - yy);
+  Y[10] = c3b * x * y * z;
+  Y[11] = c3c * y * f1;
+  Y[12] = c3d * z * (2 * zz - 3 * xx - 3 * yy);
+  Y[13] = c3c * x * f1;
+  Y[14] = c3e * z * (xx - yy);
+  Y[15] = c3a * x * (xx - 3 * yy);
+  if (dY) {
+    dY[9][0] = c3a * 6 * x * y;           dY[9][1] = c3a * (3 * xx - 3 * yy);   dY[9][2] = 0;
+    dY[10][0] = c3b * y * z;              dY[10][1] = c3b * x * z;              dY[10][2] = c3b * x * y;
+    dY[11][0] = -2 * c3c * x * y;         dY[11][1] = c3c * (4 * zz - xx - 3 * yy); dY[11][2] = 8 * c3c * y * z;
+    dY[12][0] = -6 * c3d * x * z;         dY[12][1] = -6 * c3d * y * z;         dY[12][2] = c3d * (6 * zz - 3 * xx - 3 * yy);
+    dY[13][0] = c3c * (4 * zz - 3 * xx - yy); dY[13][1] = -2 * c3c * x * y;    dY[13][2] = 8 * c3c * x * z;
+    dY[14][0] = 2 * c3e * x * z;          dY[14][1] = -2 * c3e * y * z;         dY[14][2] = c3e * (xx - yy);
+    dY[15][0] = c3a * (3 * xx - 3 * yy);  dY[15][1] = -6 * c3a * x * y;        dY[15][2] = 0;
+  }
+}
+
+// Camera-side projection of one Gaussian into one view.
+struct ViewProj {
+  double tx, ty, tz;
+  double xt, yt;       // clamped tx/tz, ty/tz
+  bool clx, cly;
+  double J00, J02, J11, J12;
+  double M[6];         // J W
+  double cov[3];       // a', b', c' (dilated)
+  double det;
+  double u, v;
+  double dir[3], dist;
+};
+
+// Returns false when the Gaussian is dropped by the near plane or a degenerate
+// covariance. Camera-space coordinates are formed as ((r0 x + r1 y) + r2 z) + t
+// with no fused operations, so the FP32 depth key is a reproducible function of
+// the inputs.
+__device__ inline bool project_view(const GaussParams& g, const ViewDev& w, ViewProj& p) {
+  const double* m = g.m;
+  const double R0 = w.R[0], R1 = w.R[1], R2 = w.R[2], R3 = w.R[3], R4 = w.R[4], R5 = w.R[5];
+  const double R6 = w.R[6], R7 = w.R[7], R8 = w.R[8];
+  p.tx = ((R0 * m[0] + R1 * m[1]) + R2 * m[2]) + (double)w.t[0];
+  p.ty = ((R3 * m[0] + R4 * m[1]) + R5 * m[2]) + (double)w.t[1];
+  p.tz = ((R6 * m[0] + R7 * m[1]) + R8 * m[2]) + (double)w.t[2];
+  if (!(p.tz > (double)w.near_plane)) return false;
+  const double fx = w.fx, fy = w.fy;
+  const double xr = p.tx / p.tz, yr = p.ty / p.tz;
+  p.clx = (xr < -w.limx) || (xr > w.limx);
+  p.cly = (yr < -w.limy) || (yr > w.limy);
+  p.xt = fmin(fmax(xr, -w.limx), w.limx);
+  p.yt = fmin(fmax(yr, -w.limy), w.limy);
+  p.J00 = fx / p.tz;
+  p.J02 = -fx * p.xt / p.tz;
+  p.J11 = fy / p.tz;
+  p.J12 = -fy * p.yt / p.tz;
+  // M = J W (2x3)
+  p.M[0] = p.J00 * R0 + p.J02 * R6;
+  p.M[1] = p.J00 * R1 + p.J02 * R7;
+  p.M[2] = p.J00 * R2 + p.J02 * R8;
+  p.M[3] = p.J11 * R3 + p.J12 * R6;
+  p.M[4] = p.J11 * R4 + p.J12 * R7;
+  p.M[5] = p.J11 * R5 + p.J12 * R8;
+  double SM[2][3];  // Sigma M^T columns
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k)
+      SM[r][k] = sig(g, k, 0) * p.M[3 * r + 0] + sig(g, k, 1) * p.M[3 * r + 1] + sig(g, k, 2) * p.M[3 * r + 2];
+  const double c00 = p.M[0] * SM[0][0] + p.M[1] * SM[0][1] + p.M[2] * SM[0][2];
+  const double c01 = p.M[0] * SM[1][0] + p.M[1] * SM[1][1] + p.M[2] * SM[1][2];
+  const double c11 = p.M[3] * SM[1][0] + p.M[4] * SM[1][1] + p.M[5] * SM[1][2];
+  p.cov[0] = c00 + kDilation;
+  p.cov[1] = c01;
+  p.cov[2] = c11 + kDilation;
+  p.det = p.cov[0] * p.cov[2] - p.cov[1] * p.cov[1];
+  if (!(p.det > 0.0)) return false;
+  p.u = fx * p.tx / p.tz + (double)w.cx;
+  p.v = fy * p.ty / p.tz + (double)w.cy;
+  const double d0 = m[0] - w.campos[0], d1 = m[1] - w.campos[1], d2 = m[2] - w.campos[2];
+  p.dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  p.dir[0] = d0 / p.dist;
+  p.dir[1] = d1 / p.dist;
+  p.dir[2] = d2 / p.dist;
+  return true;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const ViewDev* __restrict__ views,
+                                                             int32_t V, int64_t ncap,
+                                                             const uint32_t* __restrict__ header,
+                                                             const uint32_t* __restrict__ cluster_list,
+                                                             uint32_t* __restrict__ compact2full,
+                                                             Record* __restrict__ rec, uint32_t* __restrict__ dkey,
+                                                             uint32_t* __restrict__ tiles,
+                                                             ushort4* __restrict__ rect) {
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (j >= ncap) return;
+  const uint32_t nvis = header[0];
+  const int64_t p = j / GSR_CLUSTER;
+  int64_t i = -1;
+  if (p < (int64_t)nvis) {
+    i = (int64_t)cluster_list[p] * GSR_CLUSTER + (j % GSR_CLUSTER);
+    if (i >= sc.n) i = -1;
+  }
+  compact2full[j] = i < 0 ? 0xffffffffu : (uint32_t)i;
+  if (i < 0) {
+    for (int v = 0; v < V; ++v) {
+      const int64_t r = j * V + v;
+      dkey[r] = 0xffffffffu;
+      tiles[r] = 0;
+      rect[r] = make_ushort4(0, 0, 0, 0);
+    }
+    return;
+  }
+  GaussParams g;
+  load_gaussian(sc, i, g);
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const float* shp = sc.sh + (int64_t)i * K * 3;
+  for (int v = 0; v < V; ++v) {
+    const int64_t r = j * V + v;
+    const ViewDev& w = views[v];
+    ViewProj pr;
+    bool ok = project_view(g, w, pr) && g.o >= (1.0 / 255.0);
+    int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
+    if (ok) {
+      // support box of d^T Q d <= 2 ln(255 o): half widths sqrt(K cov_xx), sqrt(K cov_yy);
+      // pixel px covers the centre px + 1/2
+      const double Kq = 2.0 * log(255.0 * g.o);
+      const double rx = sqrt(Kq * pr.cov[0]);
+      const double ry = sqrt(Kq * pr.cov[2]);
+      double fx0 = ceil((pr.u - rx) - 0.5), fx1 = floor((pr.u + rx) - 0.5);
+      double fy0 = ceil((pr.v - ry) - 0.5), fy1 = floor((pr.v + ry) - 0.5);
+      fx0 = fmax(fx0, 0.0);
+      fy0 = fmax(fy0, 0.0);
+      fx1 = fmin(fx1, (double)(w.width - 1));
+      fy1 = fmin(fy1, (double)(w.height - 1));
+      if (fx0 > fx1 || fy0 > fy1) {
+        ok = false;
+      } else {
+        x0 = (int)fx0 / GSR_TILE;
+        x1 = (int)fx1 / GSR_TILE;
+        y0 = (int)fy0 / GSR_TILE;
+        y1 = (int)fy1 / GSR_TILE;
+      }
+    }
+    if (!ok) {
+      dkey[r] = 0xffffffffu;
+      tiles[r] = 0;
+      rect[r] = make_ushort4(0, 0, 0, 0);
+      continue;
+    }
+    // colour
+    double Y[16];
+    sh_basis<DEG>(pr.dir[0], pr.dir[1], pr.dir[2], Y, nullptr);
+    double col[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      for (int ch = 0; ch < 3; ++ch) col[ch] += Y[k] * (double)shp[3 * k + ch];
+    // conic Q = cov^-1 = (a, b, c); factored exponent in log2 units:
+    //   -1/2 d^T Q d = -1/2 a (dx + (b/a) dy)^2 - 1/2 dy^2 / cov_yy
+    const double a = pr.cov[2] / pr.det;
+    const double c = pr.cov[0] / pr.det;
+    const double ratio = -pr.cov[1] / pr.cov[2];
+    Record out;
+    const float uh = (float)pr.u, vh = (float)pr.v;
+    out.r0 = make_float4(uh, vh, (float)(pr.u - (double)uh), (float)(pr.v - (double)vh));
+    out.r1 = make_float4((float)(-0.5 * a * kLog2e), (float)ratio, (float)(-0.5 / pr.cov[2] * kLog2e),
+                         (float)(-0.5 * c * kLog2e));
+    out.r2 = make_float4((float)g.o, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0), (float)fmax(col[2], 0.0));
+    rec[r] = out;
+    dkey[r] = __float_as_uint((float)pr.tz);
+    tiles[r] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+    rect[r] = make_ushort4((unsigned short)x0, (unsigned short)x1, (unsigned short)y0, (unsigned short)y1);
+  }
+}
+
+// Backward of the projection: screen-space gradients (grad2d, summed over the
+// views) to the parameter gradients. One thread per Gaussian in the caller's
+// order; Gaussians of culled clusters get zero.
+template <int DEG>
+__global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
+    gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, int cull, const uint32_t* __restrict__ visible,
+    const uint32_t* __restrict__ cluster_offset, const uint32_t* __restrict__ tiles,
+    const float* __restrict__ grad2d, gsr_grads gr, float* __restrict__ S, float* __restrict__ Mst,
+    uint32_t* __restrict__ Cst) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= sc.n) return;
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t c = i / GSR_CLUSTER;
+  bool vis = true;
+  int64_t j = i;
+  if (cull) {
+    vis = visible[c] != 0;
+    j = (int64_t)cluster_offset[c] * GSR_CLUSTER + (i % GSR_CLUSTER);
+  }
+  double dm[3] = {0, 0, 0};
+  double dlogit = 0.0;
+  double GS[6] = {0, 0, 0, 0, 0, 0};  // gradient w.r.t. Sigma (symmetric, packed as Sig)
+  float dsh[3 * K];
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.0f;
+  double sS = 0.0, sM = 0.0;
+  uint32_t sC = 0;
+  bool any = false;
+  GaussParams g;
+  if (vis) {
+    for (int v = 0; v < V; ++v) {
+      const int64_t r = j * V + v;
+      if (tiles[r] == 0) continue;
+      const float* gg = grad2d + r * kGrad2D;
+      const double du = gg[0], dv = gg[1], da = gg[2], db = gg[3], dc = gg[4], dop = gg[5];
+      const double dcol[3] = {gg[6], gg[7], gg[8]};
+      sS += gg[9];
+      sM += dop;
+      sC += (uint32_t)gg[10];
+      if (!any) {
+        load_gaussian(sc, i, g);
+        any = true;
+      }
+      const ViewDev& w = views[v];
+      ViewProj p;
+      if (!project_view(g, w, p)) continue;
+      // opacity: o = sigmoid(l)
+      dlogit += dop * g.o * (1.0 - g.o);
+      // colour = max(0, sum_k Y_k f_k + 1/2)
+      double Y[16], dY[16][3];
+      sh_basis<DEG>(p.dir[0], p.dir[1], p.dir[2], Y, dY);
+      const float* shp = sc.sh + i * K * 3;
+      double raw[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * (double)shp[3 * k + ch];
+      double ddir[3] = {0, 0, 0};
+      for (int ch = 0; ch < 3; ++ch) {
+        const double gc = raw[ch] < 0.0 ? 0.0 : dcol[ch];
+        if (gc == 0.0) continue;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          dsh[3 * k + ch] += (float)(gc * Y[k]);
+          const double f = (double)shp[3 * k + ch];
+          ddir[0] += gc * f * dY[k][0];
+          ddir[1] += gc * f * dY[k][1];
+          ddir[2] += gc * f * dY[k][2];
+        }
+      }
+      {
+        const double dd = p.dir[0] * ddir[0] + p.dir[1] * ddir[1] + p.dir[2] * ddir[2];
+        for (int a = 0; a < 3; ++a) dm[a] += (ddir[a] - p.dir[a] * dd) / p.dist;
+      }
+      // conic -> screen covariance: G_cov = -Q G_Q Q, G_Q = [[da, db/2], [db/2, dc]]
+      const double qa = p.cov[2] / p.det, qb = -p.cov[1] / p.det, qc = p.cov[0] / p.det;
+      const double h = 0.5 * db;
+      const double t00 = da * qa + h * qb, t01 = da * qb + h * qc;
+      const double t10 = h * qa + dc * qb, t11 = h * qb + dc * qc;
+      const double g00 = -(qa * t00 + qb * t10);
+      const double g01 = -(qa * t01 + qb * t11);
+      const double g11 = -(qb * t01 + qc * t11);
+      // cov = M Sigma M^T + 0.3 I: G_Sigma += M^T G_cov M, G_M = 2 G_cov M Sigma
+      const double* M = p.M;
+      double GM0[3], GM1[3];  // rows of G_cov M
+      for (int k = 0; k < 3; ++k) {
+        GM0[k] = g00 * M[k] + g01 * M[3 + k];
+        GM1[k] = g01 * M[k] + g11 * M[3 + k];
+      }
+      int idx = 0;
+      for (int r2 = 0; r2 < 3; ++r2)
+        for (int c2 = r2; c2 < 3; ++c2) GS[idx++] += M[r2] * GM0[c2] + M[3 + r2] * GM1[c2];
+      double GMf[6];  // 2 (G_cov M) Sigma
+      for (int k = 0; k < 3; ++k) {
+        GMf[k] = 2.0 * (GM0[0] * sig(g, 0, k) + GM0[1] * sig(g, 1, k) + GM0[2] * sig(g, 2, k));
+        GMf[3 + k] = 2.0 * (GM1[0] * sig(g, 0, k) + GM1[1] * sig(g, 1, k) + GM1[2] * sig(g, 2, k));
+      }
+      // M = J W: G_J = G_M W^T; only J00, J02, J11, J12 depend on t
+      const float* W = w.R;
+      const double gJ00 = GMf[0] * W[0] + GMf[1] * W[1] + GMf[2] * W[2];
+      const double gJ02 = GMf[0] * W[6] + GMf[1] * W[7] + GMf[2] * W[8];
+      const double gJ11 = GMf[3] * W[3] + GMf[4] * W[4] + GMf[5] * W[5];
+      const double gJ12 = GMf[3] * W[6] + GMf[4] * W[7] + GMf[5] * W[8];
+      const double fx = w.fx, fy = w.fy, tz = p.tz, tz2 = p.tz * p.tz;
+      double dt[3] = {0, 0, 0};
+      dt[2] += -gJ00 * fx / tz2 - gJ11 * fy / tz2;
+      if (p.clx) {
+        dt[2] += gJ02 * fx * p.xt / tz2;
+      } else {
+        dt[0] += -gJ02 * fx / tz2;
+        dt[2] += gJ02 * 2.0 * fx * p.tx / (tz2 * tz);
+      }
+      if (p.cly) {
+        dt[2] += gJ12 * fy * p.yt / tz2;
+      } else {
+        dt[1] += -gJ12 * fy / tz2;
+        dt[2] += gJ12 * 2.0 * fy * p.ty / (tz2 * tz);
+      }
+      // screen mean
+      dt[0] += du * fx / tz;
+      dt[1] += dv * fy / tz;
+      dt[2] += -du * fx * p.tx / tz2 - dv * fy * p.ty / tz2;
+      for (int a = 0; a < 3; ++a) dm[a] += (double)W[a] * dt[0] + (double)W[3 + a] * dt[1] + (double)W[6 + a] * dt[2];
+    }
+  }
+  float* om = gr.means + 3 * i;
+  float* ol = gr.log_scales + 3 * i;
+  float* oq = gr.quats + 4 * i;
+  float* osh = gr.sh + i * K * 3;
+  if (!any) {
+    for (int a = 0; a < 3; ++a) om[a] = 0.0f, ol[a] = 0.0f;
+    for (int a = 0; a < 4; ++a) oq[a] = 0.0f;
+    gr.opacity_logits[i] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) osh[k] = 0.0f;
+    return;
+  }
+  // Sigma = L L^T, L = R S: G_L = 2 G_Sigma L
+  double GL[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      double acc = 0.0;
+      for (int l = 0; l < 3; ++l) {
+        const int a = r < l ? r : l, b = r < l ? l : r;
+        const int base[3] = {0, 3, 5};
+        acc += GS[base[a] + (b - a)] * g.R[3 * l + k] * g.s[k];
+      }
+      GL[3 * r + k] = 2.0 * acc;
+    }
+  double GR[9];
+  for (int k = 0; k < 3; ++k) {
+    double ds = 0.0;
+    for (int r = 0; r < 3; ++r) ds += GL[3 * r + k] * g.R[3 * r + k];
+    ol[k] = (float)(ds * g.s[k]);
+    for (int r = 0; r < 3; ++r) GR[3 * r + k] = GL[3 * r + k] * g.s[k];
+  }
+  const double w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
+  double dq[4];
+  dq[0] = 2 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+  dq[1] = 2 * (y * GR[1] + z * GR[2] + y * GR[3] - 2 * x * GR[4] - w * GR[5] + z * GR[6] + w * GR[7] - 2 * x * GR[8]);
+  dq[2] = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] - 2 * y * GR[8]);
+  dq[3] = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] + x * GR[6] + y * GR[7]);
+  const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
+  for (int a = 0; a < 4; ++a) oq[a] = (float)((dq[a] - g.q[a] * qd) / g.qn);
+  for (int a = 0; a < 3; ++a) om[a] = (float)dm[a];
+  gr.opacity_logits[i] = (float)dlogit;
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) osh[k] = dsh[k];
+  if (S) {
+    S[i] += (float)sS;
+    Mst[i] += (float)sM;
+    Cst[i] += sC;
+  }
+}
+
+__global__ void k_variance(const float* __restrict__ S, const float* __restrict__ M, const uint32_t* __restrict__ C,
+                           int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double c = (double)C[i];
+  const double m = (double)M[i];
+  out[i] = c > 0.0 ? (float)((double)S[i] - m * m / c) : 0.0f;
+}
+
+}  // namespace
+
+void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
+  if (f.ncap <= 0) return;
+  const unsigned grid = (unsigned)((f.ncap + kThreads - 1) / kThreads);
+#define GSR_PRE_FWD(D)                                                                                          \
+  k_preprocess_fwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.ncap, f.header, f.cluster_list, f.compact2full, \
+                                                f.rec, f.dkey, f.tiles_touched, f.rect)
+  switch (sc.sh_degree) {
+    case 0: GSR_PRE_FWD(0); break;
+    case 1: GSR_PRE_FWD(1); break;
+    case 2: GSR_PRE_FWD(2); break;
+    default: GSR_PRE_FWD(3); break;
+  }
+#undef GSR_PRE_FWD
+}
+
+void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
+                           const gsr_stats* stats, hipStream_t s) {
+  if (sc.n <= 0) return;
+  const unsigned grid = (unsigned)((sc.n + kThreads - 1) / kThreads);
+#define GSR_PRE_BWD(D)                                                                                       \
+  k_preprocess_bwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, cull, f.cluster_visible, f.cluster_offset, \
+                                                f.tiles_touched, f.grad2d, g, stats ? stats->S : nullptr,    \
+                                                stats ? stats->M : nullptr, stats ? stats->C : nullptr)
+  switch (sc.sh_degree) {
+    case 0: GSR_PRE_BWD(0); break;
+    case 1: GSR_PRE_BWD(1); break;
+    case 2: GSR_PRE_BWD(2); break;
+    default: GSR_PRE_BWD(3); break;
+  }
+#undef GSR_PRE_BWD
+}
+
+void launch_variance(const float* S, const float* M, const uint32_t* C, int64_t n, float* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_variance<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(S, M, C, n, out);
+}
+
+}  // namespace gsr

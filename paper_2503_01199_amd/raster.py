@@ -1,0 +1,285 @@
+"""Torch-facing binding of libgsr: argument marshalling only.
+
+Every step of the rasterizer runs in the library's HIP kernels; this module turns
+torch tensors into device pointers, keeps the caller-owned workspace, and runs on
+torch's current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_ALIGN = 256
+
+
+def camera_struct(cam) -> L.GsrCamera:
+    c = L.GsrCamera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = np.asarray(cam.R, dtype=np.float32).reshape(9)
+    t = np.asarray(cam.t, dtype=np.float32).reshape(3)
+    bg = np.asarray(cam.bg, dtype=np.float32).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+        c.bg[k] = float(bg[k])
+    c.near_plane = float(cam.near)
+    return c
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+@dataclasses.dataclass
+class SceneTensors:
+    """The scene's parameter tensors on the device (FP32, contiguous)."""
+    means: torch.Tensor
+    log_scales: torch.Tensor
+    quats: torch.Tensor
+    opacity_logits: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_scene(scene, device="cuda") -> "SceneTensors":
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)  # noqa: E731
+        return SceneTensors(f(scene.means), f(scene.log_scales), f(scene.quats), f(scene.opacity_logits),
+                            f(scene.sh), int(scene.sh_degree))
+
+    def tensors(self):
+        return (self.means, self.log_scales, self.quats, self.opacity_logits, self.sh)
+
+    def struct(self) -> L.GsrScene:
+        for t in self.tensors():
+            if t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("scene tensors must be contiguous float32")
+        s = L.GsrScene()
+        s.n = self.n
+        s.sh_degree = self.sh_degree
+        s.means, s.log_scales, s.quats, s.opacity_logits, s.sh = (_ptr(t) for t in self.tensors())
+        return s
+
+
+class Workspace:
+    """A caller-owned device byte buffer, grown on demand, 256-byte aligned."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.buf = None
+        self.offset = 0
+        self.nbytes = 0
+
+    def ensure(self, nbytes: int):
+        if self.buf is not None and self.nbytes >= nbytes:
+            return
+        self.buf = torch.empty(int(nbytes) + _ALIGN, dtype=torch.uint8, device=self.device)
+        self.offset = (-self.buf.data_ptr()) % _ALIGN
+        self.nbytes = int(nbytes)
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr() + self.offset
+
+    def view(self, dev_ptr: int, count: int, dtype: torch.dtype) -> torch.Tensor:
+        """Tensor view of `count` elements at device pointer dev_ptr inside the workspace."""
+        start = dev_ptr - self.buf.data_ptr()
+        itemsize = torch.empty((), dtype=dtype).element_size()
+        assert 0 <= start and start + count * itemsize <= self.buf.numel(), "pointer outside the workspace"
+        return self.buf[start:start + count * itemsize].view(dtype)
+
+
+@dataclasses.dataclass
+class Frame:
+    """State of one forward: what gsr_backward needs to run on the same workspace."""
+    scene: SceneTensors
+    cameras: list
+    cam_structs: ctypes.Array
+    opts: L.GsrOptions
+    workspace: Workspace
+    images: list
+    info: dict
+
+
+class Rasterizer:
+    """One library context on one device (not thread-safe; one per host thread)."""
+
+    def __init__(self, device: int | str | torch.device = 0):
+        self.lib = L.load()
+        dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("the rasterizer runs on a HIP device")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
+        ctx = ctypes.c_void_p()
+        st = self.lib.gsr_context_create(self.device.index, ctypes.byref(ctx))
+        if st != L.GSR_OK:
+            raise L.GsrError(st, "gsr_context_create(%d)" % self.device.index)
+        self.ctx = ctx
+        self.default_workspace = Workspace(self.device)
+        self.morton_workspace = Workspace(self.device)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self.lib.gsr_context_destroy(ctx)
+            self.ctx = None
+
+    def _check(self, st: int, what: str):
+        if st != L.GSR_OK:
+            msg = self.lib.gsr_last_error(self.ctx)
+            raise L.GsrError(st, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    def _stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    @staticmethod
+    def options(precision=L.GSR_FP32, cluster_cull=True, stats=True) -> L.GsrOptions:
+        o = L.GsrOptions()
+        o.precision = int(precision)
+        o.cluster_cull = 1 if cluster_cull else 0
+        o.stats = 1 if stats else 0
+        o.reserved = 0
+        return o
+
+    # ------------------------------------------------------------------ forward / backward
+    def forward(self, scene: SceneTensors, cameras, precision=L.GSR_FP32, cluster_cull=True, stats=True,
+                workspace: Workspace | None = None, images=None) -> Frame:
+        V = len(cameras)
+        cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
+        opts = self.options(precision, cluster_cull, stats)
+        sc = scene.struct()
+        ws = workspace if workspace is not None else self.default_workspace
+        if images is None:
+            images = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device) for c in cameras]
+        img_ptrs = (ctypes.c_void_p * V)(*[t.data_ptr() for t in images])
+        if ws.buf is None:
+            nbytes = ctypes.c_size_t()
+            self._check(self.lib.gsr_workspace_size(self.ctx, ctypes.byref(sc), cams, V, ctypes.byref(opts),
+                                                    8 * scene.n + 4096, ctypes.byref(nbytes)), "gsr_workspace_size")
+            ws.ensure(nbytes.value)
+        for _ in range(4):
+            st = self.lib.gsr_forward(self.ctx, ctypes.byref(sc), cams, V, ctypes.byref(opts), ws.ptr, ws.nbytes,
+                                      img_ptrs, self._stream())
+            if st == L.GSR_ERR_WORKSPACE_TOO_SMALL:
+                ws.ensure(self.lib.gsr_required_workspace(self.ctx))
+                continue
+            break
+        self._check(st, "gsr_forward")
+        info = L.GsrFrameInfo()
+        self._check(self.lib.gsr_frame_inspect(self.ctx, ws.ptr, ctypes.byref(info), None), "gsr_frame_inspect")
+        info_d = {k: getattr(info, k) for k, _ in L.GsrFrameInfo._fields_ if k != "reserved"}
+        return Frame(scene, list(cameras), cams, opts, ws, images, info_d)
+
+    def backward(self, frame: Frame, dL_dimages, grads=None, stats=None):
+        """Returns the parameter gradients (a dict of tensors shaped like the scene's).
+        `stats` is None or a dict with tensors S, M (float32) and C (int32) that are
+        accumulated in place."""
+        V = len(frame.cameras)
+        sc = frame.scene.struct()
+        dl = [t.contiguous() for t in dL_dimages]
+        for t, c in zip(dl, frame.cameras):
+            if t.shape != (3, c.height, c.width) or t.dtype != torch.float32:
+                raise ValueError("dL/dimage must be float32 [3, H, W]")
+        dl_ptrs = (ctypes.c_void_p * V)(*[t.data_ptr() for t in dl])
+        if grads is None:
+            grads = {k: torch.empty_like(t) for k, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"),
+                                                            frame.scene.tensors())}
+        g = L.GsrGrads()
+        g.means, g.log_scales, g.quats, g.opacity_logits, g.sh = (
+            _ptr(grads[k]) for k in ("means", "log_scales", "quats", "opacity_logits", "sh"))
+        st_ptr = None
+        if stats is not None:
+            s = L.GsrStats()
+            s.S, s.M, s.C = _ptr(stats["S"]), _ptr(stats["M"]), _ptr(stats["C"])
+            st_ptr = ctypes.byref(s)
+        ws = frame.workspace
+        self._check(self.lib.gsr_backward(self.ctx, ctypes.byref(sc), frame.cam_structs, V, ctypes.byref(frame.opts),
+                                          ws.ptr, ws.nbytes, dl_ptrs, ctypes.byref(g), st_ptr, self._stream()),
+                    "gsr_backward")
+        return grads
+
+    # ------------------------------------------------------------------ inspection
+    def inspect(self, frame: Frame) -> dict:
+        """Tensor views (not copies) of the frame's intermediate buffers in the workspace."""
+        info = L.GsrFrameInfo()
+        b = L.GsrFrameBuffers()
+        ws = frame.workspace
+        self._check(self.lib.gsr_frame_inspect(self.ctx, ws.ptr, ctypes.byref(info), ctypes.byref(b)),
+                    "gsr_frame_inspect")
+        V = len(frame.cameras)
+        ncap = info.clusters * L.GSR_CLUSTER
+        R = ncap * V
+        M = info.instances
+        P = info.pixels
+        u32, f32, i16 = torch.int32, torch.float32, torch.int16
+        out = dict(
+            records=ws.view(b.record, 12 * R, f32).view(R, 12),
+            depth_key=ws.view(b.depth_key, R, u32),
+            tiles=ws.view(b.tiles, R, u32),
+            rect=ws.view(b.rect, 4 * R, i16).view(R, 4),
+            compact2full=ws.view(b.compact2full, ncap, u32),
+            inst_tile=ws.view(b.inst_tile, M, u32) if M > 0 else torch.zeros(0, dtype=u32, device=self.device),
+            inst_record=ws.view(b.inst_record, M, u32) if M > 0 else torch.zeros(0, dtype=u32, device=self.device),
+            ranges=ws.view(b.ranges, 2 * info.tiles, u32).view(-1, 2),
+            pixel_rgb=ws.view(b.pixel_rgb, 3 * P, f32).view(P, 3),
+            pixel_T=ws.view(b.pixel_T, P, f32),
+            pixel_last=ws.view(b.pixel_last, P, u32),
+            grad2d=ws.view(b.grad2d, 12 * R, f32).view(R, 12),
+            cluster_bounds=ws.view(b.cluster_bounds, 8 * max(info.clusters, 1), f32).view(-1, 8),
+            cluster_visible=ws.view(b.cluster_visible, max(info.clusters, 1), u32),
+            pixel_base=[b.pixel_base[v] for v in range(V)],
+            tile_base=[b.tile_base[v] for v in range(V)],
+            info={k: getattr(info, k) for k, _ in L.GsrFrameInfo._fields_ if k != "reserved"},
+        )
+        return out
+
+    # ------------------------------------------------------------------ Morton / permutation / variance
+    def morton_order(self, means: torch.Tensor):
+        """(perm i64[n], codes as i64[n] holding the 63-bit codes) of Sec. 3.2.1."""
+        n = int(means.shape[0])
+        means = means.contiguous()
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.gsr_morton_workspace_size(self.ctx, n, ctypes.byref(nbytes)), "gsr_morton_workspace_size")
+        self.morton_workspace.ensure(nbytes.value)
+        perm = torch.empty(n, dtype=torch.int64, device=self.device)
+        codes = torch.empty(n, dtype=torch.int64, device=self.device)
+        self._check(self.lib.gsr_morton_order(self.ctx, means.data_ptr(), n, self.morton_workspace.ptr,
+                                              self.morton_workspace.nbytes, perm.data_ptr(), codes.data_ptr(),
+                                              self._stream()), "gsr_morton_order")
+        return perm, codes
+
+    def apply_permutation(self, perm: torch.Tensor, arrays):
+        """New tensors dst[i] = src[perm[i]] for each array (rows along dim 0)."""
+        n = int(perm.shape[0])
+        srcs = [a.contiguous() for a in arrays]
+        dsts = [torch.empty_like(a) for a in srcs]
+        rows = (ctypes.c_int32 * len(srcs))(*[int(a[0].numel()) if a.shape[0] > 0 else 0 for a in srcs])
+        sp = (ctypes.c_void_p * len(srcs))(*[a.data_ptr() for a in srcs])
+        dp = (ctypes.c_void_p * len(srcs))(*[a.data_ptr() for a in dsts])
+        self._check(self.lib.gsr_apply_permutation(self.ctx, perm.contiguous().data_ptr(), n, len(srcs), sp, dp, rows,
+                                                   self._stream()), "gsr_apply_permutation")
+        return dsts
+
+    def variance(self, S: torch.Tensor, M: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
+        n = int(S.shape[0])
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        s = L.GsrStats()
+        s.S, s.M, s.C = S.data_ptr(), M.data_ptr(), C.data_ptr()
+        self._check(self.lib.gsr_variance(self.ctx, ctypes.byref(s), n, out.data_ptr(), self._stream()), "gsr_variance")
+        return out
+
+
+def new_stats(n: int, device) -> dict:
+    """Zeroed statistic accumulators S, M (float32) and C (int32 holding u32 counts)."""
+    return dict(S=torch.zeros(n, dtype=torch.float32, device=device), M=torch.zeros(n, dtype=torch.float32, device=device),
+                C=torch.zeros(n, dtype=torch.int32, device=device))

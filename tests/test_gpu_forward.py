@@ -1,0 +1,199 @@
+"""GPU forward path vs the FP64 oracle: records, binning, image, per-pixel state.
+
+Integer stages (depth keys, tile rects, sorted instances, tile ranges, list
+positions) must match bit for bit; images within 1e-5 relative (floor 1) on pixels
+that the oracle does not flag as fragile (a discrete decision within rounding of
+its threshold).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from helpers import IMAGE_TOL, decode_records, ensure_built, image_errors
+from paper_2503_01199_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rz():
+    ensure_built()
+    from paper_2503_01199_amd.raster import Rasterizer
+    return Rasterizer(0)
+
+
+def gpu_forward(rz, scene, cams, cull=True):
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    st = SceneTensors.from_scene(scene)
+    print("gpu_forward n=%d views=%s cull=%s" % (scene.n, [(c.width, c.height) for c in cams], cull), flush=True)
+    fr = rz.forward(st, cams, cluster_cull=cull, workspace=Workspace(rz.device))
+    torch.cuda.synchronize()
+    return fr
+
+
+def full_index_of_records(ins, V):
+    c2f = ins["compact2full"].cpu().numpy().view(np.uint32).astype(np.int64)
+    R = ins["records"].shape[0]
+    slots = np.arange(R) // V
+    views = np.arange(R) % V
+    full = np.where(c2f[slots] == 0xFFFFFFFF, -1, c2f[slots])
+    return full, views
+
+
+def check_image(fr, scene, cam, v=0, what=""):
+    ref = orc.render(scene, cam, mode=2)
+    img = fr.images[v].cpu().numpy()
+    mx, bad, nfrag = image_errors(img, ref["image"], ref["fragile"])
+    print("%s image max rel err %.3g, fragile pixels %d" % (what, mx, nfrag))
+    assert nfrag <= max(2, 2e-3 * cam.width * cam.height)
+    assert bad == 0, "%d pixels exceed %.0e (max %.3g)" % (bad, IMAGE_TOL, mx)
+    return ref
+
+
+@pytest.mark.parametrize("cull", [True, False])
+def test_tiny_scene_image(rz, cull):
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    fr = gpu_forward(rz, sc, [cam], cull)
+    check_image(fr, sc, cam, what="tiny cull=%s" % cull)
+
+
+def test_records_match_oracle_projection(rz):
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    fr = gpu_forward(rz, sc, [cam])
+    ins = rz.inspect(fr)
+    pp = orc.preprocess(sc, cam)
+    full, _ = full_index_of_records(ins, 1)
+    tiles = ins["tiles"].cpu().numpy().view(np.uint32)
+    valid_gpu = np.zeros(sc.n, bool)
+    has = full >= 0
+    valid_gpu[full[has]] = tiles[has] > 0
+    assert np.array_equal(valid_gpu, pp["valid"])
+    sel = has & (tiles > 0)
+    g = full[sel]
+    # depth key: FP32 bits of t_z, bit-exact
+    dk = ins["depth_key"].cpu().numpy().view(np.uint32)[sel]
+    assert np.array_equal(dk, pp["depth_bits"][g])
+    # tile rect: exact except where an edge is within 1e-9 px of a pixel-centre boundary
+    rect = ins["rect"].cpu().numpy().view(np.uint16).astype(np.int32)[sel]
+    ok = np.all(rect == pp["rect"][g], axis=1) | pp["rect_fragile"][g]
+    assert ok.all()
+    assert np.array_equal(tiles[sel], pp["tiles"][g])
+    u, v, conic, o, rgb = decode_records(ins["records"].cpu().numpy()[sel])
+    assert np.abs(u - pp["u"][g]).max() < 1e-9 * 128 and np.abs(v - pp["v"][g]).max() < 1e-9 * 128
+    rel = np.abs(conic - pp["conic"][g]) / np.abs(pp["conic"][g]).max(1, keepdims=True)
+    assert rel.max() < 4e-7
+    assert np.abs(o - pp["opacity"][g]).max() < 1e-7
+    assert np.abs(rgb - pp["rgb"][g]).max() < 2e-7
+
+
+def _oracle_bins(scene, cams):
+    views = []
+    for cam in cams:
+        pp = orc.preprocess(scene, cam)
+        tx, ty = cam.tiles()
+        views.append((pp["valid"], pp["rect"], pp["depth_bits"], tx, ty))
+        assert not pp["rect_fragile"].any()
+    return orc.bin_instances(views)
+
+
+@pytest.mark.parametrize("sizes", [[(128, 128)], [(100, 75)], [(128, 128), (72, 40)]])
+def test_binning_bit_exact(rz, sizes):
+    sc = scenes.tiny_scene(800, seed_salt=4)
+    cams = [scenes.tiny_camera(w, h) for w, h in sizes]
+    fr = gpu_forward(rz, sc, cams)
+    ins = rz.inspect(fr)
+    keys, vals, ranges = _oracle_bins(sc, cams)
+    V = len(cams)
+    M = ins["info"]["instances"]
+    assert M == len(keys)
+    full, view = full_index_of_records(ins, V)
+    it = ins["inst_tile"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    ir = ins["inst_record"].cpu().numpy().view(np.uint32).astype(np.int64)
+    dk = ins["depth_key"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    gkeys = (it << np.uint64(32)) | dk[ir]
+    gvals = view[ir] * sc.n + full[ir]
+    assert np.array_equal(gkeys, keys)
+    assert np.array_equal(gvals, vals)
+    gr = ins["ranges"].cpu().numpy().view(np.uint32)
+    # empty tiles are (0, 0) on the GPU and in the oracle
+    assert np.array_equal(gr, ranges)
+
+
+def test_pixel_state_matches_tiled_oracle(rz):
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    sc.opacity_logits[:] = sc.opacity_logits + 2.0  # reach the T stop on many pixels
+    fr = gpu_forward(rz, sc, [cam])
+    ref = check_image(fr, sc, cam, what="dense tiny")
+    ins = rz.inspect(fr)
+    keep = ~ref["fragile"].ravel()
+    last = ins["pixel_last"].cpu().numpy().view(np.uint32)
+    assert np.array_equal(last[keep], ref["n_contrib"].ravel()[keep])
+    T = ins["pixel_T"].cpu().numpy()
+    assert np.abs(T - ref["T"].ravel())[keep].max() < 1e-5
+    assert (T >= 1e-4).all() and (T <= 1).all()
+    assert (ref["T"] < 1e-3).sum() > 50
+
+
+def test_ragged_and_batched_views_equal_single(rz):
+    sc = scenes.tiny_scene(700, seed_salt=6)
+    cams = [scenes.tiny_camera(100, 75), scenes.tiny_camera(37, 53), scenes.tiny_camera(128, 128)]
+    fr = gpu_forward(rz, sc, cams)
+    for v, cam in enumerate(cams):
+        check_image(fr, sc, cam, v=v, what="view %d" % v)
+        single = gpu_forward(rz, sc, [cam])
+        assert torch.equal(single.images[0], fr.images[v])
+
+
+def test_empty_and_invisible_scenes_render_background(rz):
+    cam = scenes.tiny_camera(40, 24)
+    cam.bg = (0.25, 0.5, 0.75)
+    empty = scenes.tiny_scene(0)
+    fr = gpu_forward(rz, empty, [cam])
+    img = fr.images[0].cpu().numpy()
+    for ch in range(3):
+        assert np.all(img[ch] == np.float32(cam.bg[ch]))
+    behind = scenes.tiny_scene(300)
+    behind.means[:, 2] = -behind.means[:, 2]  # all behind the camera
+    fr = gpu_forward(rz, behind, [cam])
+    assert fr.info["instances"] == 0
+    assert np.all(fr.images[0].cpu().numpy()[2] == np.float32(0.75))
+
+
+def test_cluster_cull_is_neutral_and_conservative(rz):
+    sc = scenes.spheres_planes_scene(30_000, seed_salt=1)
+    # Morton order makes clusters compact so the cull has something to remove
+    codes, perm = orc.morton(sc.means)
+    sc = sc.permuted(perm)
+    cam = scenes.spheres_planes_camera()
+    on = gpu_forward(rz, sc, [cam], cull=True)
+    off = gpu_forward(rz, sc, [cam], cull=False)
+    assert torch.equal(on.images[0], off.images[0])
+    ins = rz.inspect(on)
+    vis = ins["cluster_visible"].cpu().numpy()[: on.info["clusters"]]
+    print("visible clusters %d of %d" % (vis.sum(), vis.size))
+    assert vis.sum() < vis.size  # something was culled
+    pp = orc.preprocess(sc, cam)
+    for c in np.nonzero(vis == 0)[0]:
+        assert pp["tiles"][c * 128:(c + 1) * 128].sum() == 0
+    check_image(on, sc, cam, what="spheres 30k")
+
+
+def test_spheres_scene_full_size(rz):
+    """200k Gaussians, SH degree 3, 800x800, Morton-ordered, cull on: image and binning."""
+    sc = scenes.spheres_planes_scene()
+    _, perm = orc.morton(sc.means)
+    sc = sc.permuted(perm)
+    cam = scenes.spheres_planes_camera()
+    fr = gpu_forward(rz, sc, [cam])
+    check_image(fr, sc, cam, what="spheres 200k")
+    ins = rz.inspect(fr)
+    keys, vals, ranges = _oracle_bins(sc, [cam])
+    assert ins["info"]["instances"] == len(keys)
+    full, _ = full_index_of_records(ins, 1)
+    it = ins["inst_tile"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    ir = ins["inst_record"].cpu().numpy().view(np.uint32).astype(np.int64)
+    dk = ins["depth_key"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal((it << np.uint64(32)) | dk[ir], keys)
+    assert np.array_equal(full[ir], vals)
+    assert np.array_equal(ins["ranges"].cpu().numpy().view(np.uint32), ranges)
