@@ -308,8 +308,8 @@ struct PixelResult {
   double T;
   int n_contrib;    // position of the last blended entry + 1 (0 if none)
   int n_blended;
-  int fragile;
   std::vector<Frag> blended;
+  std::vector<int64_t> fragile_at;  // Gaussians whose decision here is within rounding
 };
 
 bool depth_less(const std::vector<Proj>& P, int64_t a, int64_t b) {
@@ -329,22 +329,24 @@ void composite(const std::vector<Proj>& P, const std::vector<int64_t>& list, int
   r.T = 1.0;
   r.n_contrib = 0;
   r.n_blended = 0;
-  r.fragile = 0;
   r.blended.clear();
+  r.fragile_at.clear();
   for (int pos = 0; pos < (int)list.size(); ++pos) {
     const Proj& p = P[list[pos]];
     double dx, dy;
     const double E = exponent(p, px, py, dx, dy);
     const double G = std::exp(E);
     const double araw = p.o * G;
-    if (E > 0) continue;  // non-PD numerics guard (never taken for a valid conic)
-    const double la = std::log(255.0 * araw);
-    if (std::fabs(la) < kFragAlpha) r.fragile = 1;
-    if (araw < kAlphaMin) continue;
-    if (std::fabs(araw / kAlphaMax - 1.0) < kFragClamp) r.fragile = 1;
+    bool frag = std::fabs(std::log(255.0 * araw)) < kFragAlpha;
+    if (araw < kAlphaMin) {
+      if (frag) r.fragile_at.push_back(list[pos]);
+      continue;
+    }
+    frag = frag || std::fabs(araw / kAlphaMax - 1.0) < kFragClamp;
     const double alpha = araw <= kAlphaMax ? araw : kAlphaMax;
     const double Tn = r.T * (1.0 - alpha);
-    if (std::fabs(Tn / kTMin - 1.0) < kFragT) r.fragile = 1;
+    frag = frag || std::fabs(Tn / kTMin - 1.0) < kFragT;
+    if (frag) r.fragile_at.push_back(list[pos]);
     if (Tn < kTMin) break;
     if (keep) r.blended.push_back(Frag{list[pos], pos, G, araw, alpha, r.T, dx, dy});
     for (int ch = 0; ch < 3; ++ch) r.rgb[ch] += r.T * alpha * p.rgb[ch];
@@ -633,7 +635,7 @@ void orc_render(int64_t n, int deg, const float* means, const float* ls, const f
       T[o] = r.T;
       n_contrib[o] = r.n_contrib;
       n_blended[o] = r.n_blended;
-      fragile[o] = (uint8_t)r.fragile;
+      fragile[o] = (uint8_t)!r.fragile_at.empty();
     }
   });
 }
@@ -668,8 +670,11 @@ void orc_backward(int64_t n, int deg, const float* means, const float* ls, const
       pixel_list(P, L, px, py, list);
       composite(P, list, px, py, cam, true, r);
       const size_t o = (size_t)py * W + px;
-      if (r.fragile) {
-        for (int64_t g : list) fr[t][g] = 1;
+      // A decision within rounding of its threshold can change the gradients of the
+      // Gaussian it concerns and of every Gaussian blended at this pixel.
+      if (!r.fragile_at.empty()) {
+        for (int64_t g : r.fragile_at) fr[t][g] = 1;
+        for (const Frag& f : r.blended) fr[t][f.g] = 1;
       }
       const double gI[3] = {dL_dI[o], dL_dI[(size_t)H * W + o], dL_dI[(size_t)2 * H * W + o]};
       const int nb = (int)r.blended.size();

@@ -1,0 +1,177 @@
+"""GPU backward path vs the FP64 oracle's analytic backward.
+
+Compositing is per pixel, so a discrete decision within rounding of its threshold
+(a fragile pixel) can only change that pixel's terms. The upstream gradient is
+set to zero on the oracle's fragile pixels for both sides; then every gradient
+and the statistic's S and M are compared on all Gaussians: per parameter group
+within 1e-3 relative (floor 1e-3 of the group's largest magnitude). The fragment
+count C, which counts blended pairs whatever their gradient, must match exactly
+on Gaussians that no fragile pixel blends.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from helpers import GRAD_TOL, ensure_built, grad_errors, normwise
+from paper_2503_01199_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.fixture(scope="module")
+def rz():
+    ensure_built()
+    from paper_2503_01199_amd.raster import Rasterizer
+    return Rasterizer(0)
+
+
+def upstream(scene, cams, salt=0):
+    """dL/dI of the random-weighted L1 loss, from the oracle's image (so both sides
+    receive identical upstream gradients)."""
+    gs = []
+    for v, cam in enumerate(cams):
+        ref = orc.render(scene, cam, mode=1)
+        w, gt = scenes.l1_weights((3, cam.height, cam.width), config=0, salt=salt + v)
+        g = orc.l1_grad(ref["image"], w, gt).astype(np.float32)
+        g[:, ref["fragile"]] = 0.0
+        gs.append(g)
+    return gs
+
+
+def run_gpu(rz, scene, cams, gI, cull=True, stats=None):
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace, new_stats
+    print("backward n=%d views=%d cull=%s" % (scene.n, len(cams), cull), flush=True)
+    st = SceneTensors.from_scene(scene)
+    fr = rz.forward(st, cams, cluster_cull=cull, workspace=Workspace(rz.device))
+    stats = stats if stats is not None else new_stats(scene.n, rz.device)
+    grads = rz.backward(fr, [torch.as_tensor(g, device=rz.device) for g in gI], stats=stats)
+    torch.cuda.synchronize()
+    return fr, {k: v.cpu().numpy() for k, v in grads.items()}, {k: v.cpu().numpy() for k, v in stats.items()}
+
+
+def oracle_sum(scene, cams, gI):
+    out = None
+    for cam, g in zip(cams, gI):
+        b = orc.backward(scene, cam, g.astype(np.float64), mode=1)
+        if out is None:
+            out = b
+        else:
+            for k in out:
+                out[k] = out[k] | b[k] if k == "fragile" else out[k] + b[k]
+    return out
+
+
+def compare(grads, stats, ref, what):
+    none = np.zeros(ref["C"].shape, bool)
+    for k in GROUPS:
+        e = grad_errors(grads[k], ref[k], none)
+        print("  %-15s max rel %.3g  normwise %.3g" % (k, e, normwise(grads[k], ref[k])))
+        assert e <= GRAD_TOL, k
+    assert grad_errors(stats["M"], ref["M"], none) <= GRAD_TOL
+    assert grad_errors(stats["S"], ref["S"], none) <= GRAD_TOL
+    skip = ref["fragile"]
+    print("%s: fragment counts compared on %d of %d Gaussians" % (what, (~skip).sum(), skip.size))
+    assert skip.mean() < 0.1
+    keep = ~skip
+    assert np.array_equal(stats["C"].astype(np.int64)[keep], ref["C"][keep])
+    # M is dL/do summed over fragments, so M o (1 - o) = dL/dlogit
+    o = 1 / (1 + np.exp(-ref["_logits"].astype(np.float64)))
+    assert grad_errors(stats["M"] * o * (1 - o), grads["opacity_logits"], none) <= 2 * GRAD_TOL
+
+
+@pytest.mark.parametrize("cull", [True, False])
+def test_tiny_scene_gradients(rz, cull):
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    gI = upstream(sc, [cam])
+    fr, grads, stats = run_gpu(rz, sc, [cam], gI, cull=cull)
+    ref = oracle_sum(sc, [cam], gI)
+    ref["_logits"] = sc.opacity_logits
+    compare(grads, stats, ref, "tiny cull=%s" % cull)
+
+
+def test_screen_space_gradients_match(rz):
+    """grad2d rows (d/du, d/dv, d/da, d/db, d/dc, d/do, d/drgb) vs the oracle's."""
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    gI = upstream(sc, [cam], salt=3)
+    fr, grads, stats = run_gpu(rz, sc, [cam], gI)
+    ins = rz.inspect(fr)
+    ref = oracle_sum(sc, [cam], gI)
+    c2f = ins["compact2full"].cpu().numpy().view(np.uint32).astype(np.int64)
+    g2 = ins["grad2d"].cpu().numpy()
+    ok = c2f != 0xFFFFFFFF
+    full = c2f[ok]
+    gpu2d = np.zeros((sc.n, 9))
+    gpu2d[full] = g2[ok][:, :9]
+    for k, name in enumerate(["u", "v", "a", "b", "c", "o", "r", "g", "b"]):
+        e = grad_errors(gpu2d[:, k], ref["g2d"][:, k], np.zeros(sc.n, bool))
+        print("  d/d%s max rel %.3g" % (name, e))
+        assert e <= GRAD_TOL, name
+
+
+def test_sh3_scene_gradients(rz):
+    sc = scenes.spheres_planes_scene(20_000, seed_salt=2)
+    _, perm = orc.morton(sc.means)
+    sc = sc.permuted(perm)
+    cam = scenes.spheres_planes_camera()
+    cam.width, cam.height, cam.cx, cam.cy = 320, 240, 160.0, 120.0
+    cam.fx = cam.fy = float(np.float32(cam.fx * 0.4))
+    gI = upstream(sc, [cam], salt=5)
+    fr, grads, stats = run_gpu(rz, sc, [cam], gI)
+    ref = oracle_sum(sc, [cam], gI)
+    ref["_logits"] = sc.opacity_logits
+    compare(grads, stats, ref, "spheres 20k SH3")
+
+
+def test_multi_view_gradients_sum_over_views(rz):
+    sc = scenes.tiny_scene(900, seed_salt=8)
+    cams = [scenes.tiny_camera(128, 128), scenes.tiny_camera(100, 75)]
+    cams[1].R = np.array([[0.98, 0, 0.2], [0, 1, 0], [-0.2, 0, 0.98]], np.float32)
+    cams[1].R /= np.linalg.norm(cams[1].R, axis=1, keepdims=True)
+    cams[1].t = np.array([0.1, -0.05, 0.2], np.float32)
+    gI = upstream(sc, cams, salt=9)
+    fr, grads, stats = run_gpu(rz, sc, cams, gI)
+    ref = oracle_sum(sc, cams, gI)
+    ref["_logits"] = sc.opacity_logits
+    compare(grads, stats, ref, "two views")
+
+
+def test_culled_gaussians_get_zero_and_stats_accumulate(rz):
+    from paper_2503_01199_amd.raster import new_stats
+    sc = scenes.spheres_planes_scene(30_000, seed_salt=1)
+    _, perm = orc.morton(sc.means)
+    sc = sc.permuted(perm)
+    cam = scenes.spheres_planes_camera()
+    gI = upstream(sc, [cam], salt=11)
+    stats = new_stats(sc.n, rz.device)
+    fr, g_on, s1 = run_gpu(rz, sc, [cam], gI, cull=True, stats=stats)
+    s1 = {k: v.copy() for k, v in s1.items()}
+    _, g_off, s2 = run_gpu(rz, sc, [cam], gI, cull=False, stats=stats)
+    ins = rz.inspect(fr)
+    vis = ins["cluster_visible"].cpu().numpy()[: fr.info["clusters"]]
+    culled = np.repeat(vis == 0, 128)[: sc.n]
+    assert culled.any()
+    for k in GROUPS:
+        assert np.all(g_on[k][culled] == 0)
+        # the same gradients up to atomic summation order
+        assert np.abs(g_on[k] - g_off[k]).max() <= 1e-4 * max(np.abs(g_off[k]).max(), 1e-12)
+    # the statistic accumulates: the second backward doubled it
+    assert np.array_equal(s2["C"], 2 * s1["C"])
+    assert np.allclose(s2["M"], 2 * s1["M"], rtol=1e-5, atol=1e-6 * np.abs(s1["M"]).max())
+
+
+def test_variance_finalise(rz):
+    rng = np.random.default_rng(3)
+    n = 10_000
+    C = rng.integers(0, 50, n).astype(np.int32)
+    x = rng.standard_normal(n).astype(np.float32)
+    M = (x * C).astype(np.float32)
+    S = (x * x * C + rng.uniform(0, 1, n) * C).astype(np.float32)
+    dev = rz.device
+    V = rz.variance(torch.as_tensor(S, device=dev), torch.as_tensor(M, device=dev), torch.as_tensor(C, device=dev))
+    ref = orc.variance(S.astype(np.float64), M.astype(np.float64), C.astype(np.int64))
+    got = V.cpu().numpy()
+    assert np.all(got[C == 0] == 0)
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
