@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Training-step benchmark of the MI355X differentiable Gaussian rasterizer.
+
+One step is the hot path of a 3DGS training iteration on one view: cluster cull
+and compaction, projection, depth sort, binning, tile sort, forward raster, the
+weighted-L1 loss gradient, the backward raster with the opacity-gradient
+statistic and the projection backward, all in the library's HIP kernels. The
+scene is the synthetic 1M-Gaussian SH3 room at 1600x1064 (Morton-ordered once
+beforehand, as a trainer does every few epochs; that reorder is timed separately).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+prints one JSON line: ms per step (mean over K timed steps, p50/p99), per-stage
+times, the roofline of the dominant kernel measured with HIP events on the
+stream it runs on, and the FP64 CPU reference timed on a band of rows of the
+same view, scaled to the full image.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd raster ms/iter at 1M Gaussians 1600×1064; p50/p99 render latency"
+# MI355X peaks: HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s (256 CUs x 4 SIMD x 16 lanes x
+# 2.4 GHz x 2 flops per FMA x 2 for packed FP32).
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic FLOPs of the raster per (pixel, Gaussian) evaluation up to the pixel's
+# last blend (exponent 2 FMA, exp, alpha = min(0.99, o G)) and per blended fragment
+# (forward: 1 - alpha, T', weight, 3 colour FMAs; backward: weight, 3 colour-gradient
+# FMAs, 3 behind-colour FMAs, two 3-term dot products, 1 - alpha, reciprocal,
+# dL/dalpha, g_o, dL/dE, the three scanline moments, the opacity sum, its square
+# sum, the count and the transmittance update).
+FWD_FLOP_EVAL = 7
+FWD_FLOP_FRAG = 9
+BWD_FLOP_EVAL = 7
+BWD_FLOP_FRAG = 41
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, p):
+    s = sorted(xs)
+    k = (len(s) - 1) * p / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def build_workload(name, n_override=None):
+    from paper_2503_01199_amd import scenes
+    if name == "room":
+        sc = scenes.room_scene(n_override or 1_000_000)
+        cams = [scenes.room_camera()]
+        desc = "room-%dk-SH3-1600x1064" % (sc.n // 1000)
+    elif name == "spheres":
+        sc = scenes.spheres_planes_scene(n_override or 200_000)
+        cams = [scenes.spheres_planes_camera()]
+        desc = "spheres-%dk-SH3-800x800" % (sc.n // 1000)
+    elif name == "tiny":
+        sc = scenes.tiny_scene(n_override or 1024)
+        cams = [scenes.tiny_camera()]
+        desc = "tiny-%d-SH0-128x128" % sc.n
+    else:
+        raise SystemExit("unknown workload %s" % name)
+    return sc, cams, desc
+
+
+def cpu_baseline(scene, cam, rows, threads):
+    """The FP64 oracle's forward + backward on full-width row bands, extrapolated
+    linearly in the number of rows to the whole image: t(H) = t(1) + (H - 1) slope,
+    slope = (t(R) - t(1)) / (R - 1)."""
+    import numpy as np
+    import oracle
+    from paper_2503_01199_amd import scenes
+    oracle.load()
+    H, W = cam.height, cam.width
+    w, gt = scenes.l1_weights((3, H, W), config=2)
+    y0 = max(0, H // 2 - rows // 2)
+
+    def run(nrows):
+        win = (0, W, y0, y0 + nrows)
+        t = time.perf_counter()
+        r = oracle.render(scene, cam, mode=1, window=win, threads=threads)
+        g = oracle.l1_grad(r["image"], w, gt)
+        g[:, :y0] = 0.0
+        g[:, y0 + nrows:] = 0.0
+        oracle.backward(scene, cam, g, mode=1, window=win, threads=threads)
+        return time.perf_counter() - t
+
+    t1 = run(1)
+    tr = run(rows)
+    slope = max(tr - t1, 0.0) / max(rows - 1, 1)
+    full_s = t1 + (H - 1) * slope
+    return {"value": round(full_s * 1e3, 1), "unit": "ms/iter", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle fwd+bwd on %d full-width rows (and on 1 row) of the same 1600x1064 view, "
+                      "%.1f s + %.1f s measured, extrapolated linearly in rows to %d rows" % (rows, tr, t1, H)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="room", choices=["room", "spheres", "tiny"])
+    ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
+    ap.add_argument("--no-cull", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=160)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2503_01199_amd import scenes
+    from paper_2503_01199_amd.raster import Rasterizer, SceneTensors, Workspace, new_stats
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+    log("generating workload %s" % args.workload)
+    scene, cams, desc = build_workload(args.workload, args.n)
+    cam = cams[0]
+    rz = Rasterizer(0)
+    dev = rz.device
+    st = SceneTensors.from_scene(scene, dev)
+
+    # Morton reorder (Sec. 3.2.1), amortised over epochs: timed on its own
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    perm, _ = rz.morton_order(st.means)
+    arrays = rz.apply_permutation(perm, list(st.tensors()))
+    t1.record()
+    torch.cuda.synchronize()
+    morton_ms = t0.elapsed_time(t1)
+    st = SceneTensors(*arrays, st.sh_degree)
+    scene_sorted = scene.permuted(perm.cpu().numpy())
+
+    w_np, gt_np = scenes.l1_weights((3, cam.height, cam.width), config=2)
+    w = torch.as_tensor(w_np, device=dev)
+    gt = torch.as_tensor(gt_np, device=dev)
+    ws = Workspace(dev)
+    stats = new_stats(st.n, dev)
+    dl = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=dev)
+    grads = {k: torch.empty_like(t) for k, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"),
+                                                     st.tensors())}
+    cull = not args.no_cull
+
+    def step():
+        fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws)
+        rz.l1_grad(fr.images[0], w, gt, out=dl)
+        rz.backward(fr, [dl], grads=grads, stats=stats)
+        return fr
+
+    log("warmup %d steps" % args.warmup)
+    for _ in range(max(args.warmup, 1)):
+        fr = step()
+    torch.cuda.synchronize()
+
+    # algorithmic work of one step, from the frame state (outside the timed region)
+    ins = rz.inspect(fr)
+    E = int(ins["pixel_last"].to(torch.int64).sum().item())
+    stats1 = new_stats(st.n, dev)
+    rz.backward(fr, [dl], grads=grads, stats=stats1)
+    torch.cuda.synchronize()
+    F = int(stats1["C"].to(torch.int64).sum().item())
+    info = dict(fr.info)
+
+    log("timing %d steps" % args.steps)
+    rz.set_profiling(True)
+    times, stage_acc = [], {}
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+        for k, v in rz.stage_times().items():
+            if v >= 0:
+                stage_acc.setdefault(k, []).append(v)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    rz.set_profiling(False)
+    ms_per_step = wall * 1e3 / args.steps
+    stages = {k: round(sum(v) / len(v), 4) for k, v in stage_acc.items()}
+
+    # roofline of the dominant kernel (each stage below is one kernel launch)
+    dom = max(("raster_bwd", "raster_fwd", "preprocess_bwd", "preprocess"), key=lambda k: stages.get(k, 0.0))
+    dur_s = stages[dom] * 1e-3
+    if dom == "raster_bwd":
+        work = BWD_FLOP_EVAL * E + BWD_FLOP_FRAG * F
+        roof = {"bound": "alu", "achieved": round(work / dur_s / 1e12, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif dom == "raster_fwd":
+        work = FWD_FLOP_EVAL * E + FWD_FLOP_FRAG * F
+        roof = {"bound": "alu", "achieved": round(work / dur_s / 1e12, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        K = (st.sh_degree + 1) ** 2
+        pbytes = 4 * (3 + 3 + 4 + 1 + 3 * K)
+        nvis = info["n_visible_slots"]
+        if dom == "preprocess_bwd":
+            work = st.n * pbytes + nvis * (pbytes + 48 + 4) + st.n * 12
+        else:
+            work = nvis * (pbytes + 48 + 4 + 4 + 8 + 4)
+        roof = {"bound": "hbm", "achieved": round(work / dur_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = {"raster_bwd": "k_raster_bwd", "raster_fwd": "k_raster_fwd",
+                      "preprocess_bwd": "k_preprocess_bwd", "preprocess": "k_preprocess_fwd"}[dom]
+    roof["launch_ms"] = stages[dom]
+    roof["work_per_launch"] = work
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log("timing the FP64 oracle on %d rows with %d threads" % (args.cpu_rows, threads))
+        cpu = cpu_baseline(scene_sorted, cam, args.cpu_rows, threads)
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 4),
+        "unit": "ms/iter",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "gaussians": st.n, "sh_degree": st.sh_degree, "views": 1,
+                   "width": cam.width, "height": cam.height, "precision": "fp32", "cluster_cull": cull,
+                   "morton_ordered": True},
+        "p50_ms": round(percentile(times, 50), 4),
+        "p99_ms": round(percentile(times, 99), 4),
+        "stages_ms": stages,
+        "morton_reorder_ms": round(morton_ms, 3),
+        "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
+                  "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

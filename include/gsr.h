@@ -222,6 +222,35 @@ gsr_status gsr_apply_permutation(gsr_context *ctx, const int64_t *perm, int64_t 
                                  const float *const *src, float *const *dst, const int32_t *row_floats,
                                  void *stream);
 
+/* Gradient of the weighted L1 loss L = sum w |I - gt| (the loss of the training
+ * step the paper accelerates; the rasterizer itself only sees dL/dI):
+ * out[i] = w[i] * sign(image[i] - gt[i]) over `count` floats, device memory. */
+gsr_status gsr_l1_grad(gsr_context *ctx, const float *image, const float *w, const float *gt, int64_t count,
+                       float *out, void *stream);
+
+/* Stages of gsr_forward and gsr_backward, in launch order. */
+typedef enum {
+  GSR_STAGE_CLUSTER = 0,     /* cluster bounds, frustum cull, compaction list */
+  GSR_STAGE_PREPROCESS,      /* projection to screen-space records */
+  GSR_STAGE_DEPTH_SORT,      /* stable radix sort of the records by depth */
+  GSR_STAGE_OFFSETS,         /* tiles touched in depth order and their prefix sum */
+  GSR_STAGE_EMIT,            /* one instance per (record, covered tile) */
+  GSR_STAGE_TILE_SORT,       /* stable radix sort of the instances by tile */
+  GSR_STAGE_RANGES,          /* per-tile [start, end) */
+  GSR_STAGE_RASTER_FWD,      /* alpha compositing */
+  GSR_STAGE_ZERO_GRAD,       /* clear the screen-space gradient rows */
+  GSR_STAGE_RASTER_BWD,      /* backward compositing with the statistic */
+  GSR_STAGE_PREPROCESS_BWD,  /* chain to the parameter gradients */
+  GSR_STAGE_COUNT
+} gsr_stage;
+
+/* With profiling on, gsr_forward and gsr_backward record a HIP event pair around
+ * each stage on the caller's stream (no extra synchronisation). */
+gsr_status gsr_set_profiling(gsr_context *ctx, int enable);
+/* Milliseconds of each stage of the last profiled gsr_forward / gsr_backward
+ * (ms[GSR_STAGE_COUNT]; -1 for a stage that has not run). Waits for the events. */
+gsr_status gsr_stage_times(gsr_context *ctx, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

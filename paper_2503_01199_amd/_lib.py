@@ -85,7 +85,13 @@ EXPORTS = {
     "gsr_morton_order": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
     "gsr_apply_permutation": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(c_void_p),
                                         ctypes.POINTER(c_void_p), ctypes.POINTER(c_int32), c_void_p]),
+    "gsr_l1_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "gsr_set_profiling": (c_int32, [c_void_p, c_int32]),
+    "gsr_stage_times": (c_int32, [c_void_p, ctypes.POINTER(c_float)]),
 }
+
+STAGES = ["cluster", "preprocess", "depth_sort", "offsets", "emit", "tile_sort", "ranges", "raster_fwd",
+          "zero_grad", "raster_bwd", "preprocess_bwd"]
 
 _lib = None
 

@@ -35,6 +35,10 @@ struct gsr_context {
   size_t required = 0;
   void* pinned = nullptr;
   std::unordered_map<const void*, FrameRecord> frames;
+  bool profiling = false;
+  bool events_ready = false;
+  hipEvent_t ev[2 * GSR_STAGE_COUNT];
+  bool recorded[GSR_STAGE_COUNT] = {};
 };
 
 namespace {
@@ -193,6 +197,22 @@ int64_t instances_for_bytes(size_t fixed, size_t ws_bytes) {
   return (int64_t)((ws_bytes - fixed - 8 * kAlign) / 16);
 }
 
+// Event pair around one stage when the context profiles; a no-op otherwise.
+struct StageScope {
+  gsr_context* ctx;
+  int stage;
+  hipStream_t s;
+  StageScope(gsr_context* c, int st, hipStream_t stream) : ctx(c), stage(st), s(stream) {
+    if (ctx->profiling) (void)hipEventRecord(ctx->ev[2 * stage], s);
+  }
+  ~StageScope() {
+    if (ctx->profiling) {
+      (void)hipEventRecord(ctx->ev[2 * stage + 1], s);
+      ctx->recorded[stage] = true;
+    }
+  }
+};
+
 void fill_views(const gsr_camera* cams, int32_t V, ViewDev* out) {
   int64_t tile_base = 0, pixel_base = 0;
   for (int v = 0; v < V; ++v) {
@@ -247,9 +267,11 @@ gsr_status gsr_context_create(int device, gsr_context** out) {
 
 void gsr_context_destroy(gsr_context* ctx) {
   if (!ctx) return;
-  if (ctx->pinned) {
+  {
     DeviceGuard g(ctx->device);
-    (void)hipHostFree(ctx->pinned);
+    if (ctx->events_ready)
+      for (int k = 0; k < 2 * GSR_STAGE_COUNT; ++k) (void)hipEventDestroy(ctx->ev[k]);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   }
   delete ctx;
 }
@@ -302,26 +324,39 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
   fill_views(cams, V, hv);
   if ((st = check_hip(ctx, hipMemcpyAsync(f.views, hv, sizeof(ViewDev) * V, hipMemcpyHostToDevice, s), "upload views")))
     return st;
-  gsr::fill_u32(f.header, 64, 0u, s);
-  // Cluster-Cull-Compact
-  if (opts->cluster_cull) {
-    gsr::launch_cluster_bounds(scene->means, scene->log_scales, scene->n, f.cluster_bounds, s);
-    gsr::launch_cluster_cull(f.cluster_bounds, f.nclusters, f.views, V, f.cluster_visible, s);
-  } else {
-    gsr::fill_u32(f.cluster_visible, f.nclusters, 1u, s);
+  for (int k = 0; k < GSR_STAGE_COUNT; ++k) ctx->recorded[k] = false;
+  {
+    // Cluster-Cull-Compact
+    StageScope sc_(ctx, GSR_STAGE_CLUSTER, s);
+    gsr::fill_u32(f.header, 64, 0u, s);
+    if (opts->cluster_cull) {
+      gsr::launch_cluster_bounds(scene->means, scene->log_scales, scene->n, f.cluster_bounds, s);
+      gsr::launch_cluster_cull(f.cluster_bounds, f.nclusters, f.views, V, f.cluster_visible, s);
+    } else {
+      gsr::fill_u32(f.cluster_visible, f.nclusters, 1u, s);
+    }
+    gsr::scan_exclusive_u32(f.cluster_visible, f.cluster_offset, f.nclusters, f.header + 0, f.temp, s);
+    gsr::launch_cluster_list(f.cluster_visible, f.cluster_offset, f.nclusters, f.cluster_list, s);
   }
-  gsr::scan_exclusive_u32(f.cluster_visible, f.cluster_offset, f.nclusters, f.header + 0, f.temp, s);
-  gsr::launch_cluster_list(f.cluster_visible, f.cluster_offset, f.nclusters, f.cluster_list, s);
-  // projection
-  gsr::launch_preprocess_fwd(*scene, f, s);
+  {
+    StageScope sc_(ctx, GSR_STAGE_PREPROCESS, s);
+    gsr::launch_preprocess_fwd(*scene, f, s);
+  }
   // depth order of the records, then instance offsets in that order
   {
     uint32_t* kb[2] = {f.skey[0], f.skey[1]};
     uint32_t* vb[2] = {f.sval[0], f.sval[1]};
-    const int r = gsr::radix_sort_u32(f.dkey, nullptr, kb, vb, f.nrec, 32, f.temp, s);
+    int r;
+    {
+      StageScope sc_(ctx, GSR_STAGE_DEPTH_SORT, s);
+      r = gsr::radix_sort_u32(f.dkey, nullptr, kb, vb, f.nrec, 32, f.temp, s);
+    }
     const uint32_t* sorted_rec = vb[r];
-    gsr::launch_gather_tiles(f, sorted_rec, s);
-    gsr::scan_exclusive_u32(f.sorted_tiles, f.offsets, f.nrec, f.header + 1, f.temp, s);
+    {
+      StageScope sc_(ctx, GSR_STAGE_OFFSETS, s);
+      gsr::launch_gather_tiles(f, sorted_rec, s);
+      gsr::scan_exclusive_u32(f.sorted_tiles, f.offsets, f.nrec, f.header + 1, f.temp, s);
+    }
     if ((st = check_hip(ctx, hipGetLastError(), "projection and depth sort"))) return st;
     if ((st = check_hip(ctx, hipMemcpyAsync(hhdr, f.header, 16, hipMemcpyDeviceToHost, s), "read counts"))) return st;
     if ((st = check_hip(ctx, hipStreamSynchronize(s), "synchronise on counts"))) return st;
@@ -332,17 +367,29 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
       return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
                   (long long)cap);
     }
-    gsr::launch_emit_instances(f, sorted_rec, s);
+    {
+      StageScope sc_(ctx, GSR_STAGE_EMIT, s);
+      gsr::launch_emit_instances(f, sorted_rec, s);
+    }
     uint32_t* ik[2] = {f.ikey[1], f.ikey[0]};
     uint32_t* iv[2] = {f.ival[1], f.ival[0]};
-    const int ri = gsr::radix_sort_u32(f.ikey[0], f.ival[0], ik, iv, M, f.tile_bits, f.temp, s);
-    f.inst_tile = ik[ri];
-    f.inst_rec = iv[ri];
-    gsr::launch_tile_ranges(f, f.inst_tile, M, s);
+    {
+      StageScope sc_(ctx, GSR_STAGE_TILE_SORT, s);
+      const int ri = gsr::radix_sort_u32(f.ikey[0], f.ival[0], ik, iv, M, f.tile_bits, f.temp, s);
+      f.inst_tile = ik[ri];
+      f.inst_rec = iv[ri];
+    }
+    {
+      StageScope sc_(ctx, GSR_STAGE_RANGES, s);
+      gsr::launch_tile_ranges(f, f.inst_tile, M, s);
+    }
     gsr::ImagePtrs ip;
     std::memset(&ip, 0, sizeof(ip));
     for (int v = 0; v < V; ++v) ip.p[v] = images[v];
-    gsr::launch_raster_fwd(f, ip, opts->precision, s);
+    {
+      StageScope sc_(ctx, GSR_STAGE_RASTER_FWD, s);
+      gsr::launch_raster_fwd(f, ip, opts->precision, s);
+    }
     if ((st = check_hip(ctx, hipGetLastError(), "binning and raster"))) return st;
     FrameRecord& fr = ctx->frames[workspace];
     fr.f = f;
@@ -393,12 +440,22 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
     return fail(ctx, GSR_ERR_INVALID_ARG, "a statistic array pointer is NULL");
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  gsr::fill_f32(f.grad2d, gsr::kGrad2D * f.nrec, 0.0f, s);
+  for (int k = GSR_STAGE_ZERO_GRAD; k < GSR_STAGE_COUNT; ++k) ctx->recorded[k] = false;
+  {
+    StageScope sc_(ctx, GSR_STAGE_ZERO_GRAD, s);
+    gsr::fill_f32(f.grad2d, gsr::kGrad2D * f.nrec, 0.0f, s);
+  }
   gsr::ConstImagePtrs dp;
   std::memset(&dp, 0, sizeof(dp));
   for (int v = 0; v < V; ++v) dp.p[v] = dL_dimages[v];
-  gsr::launch_raster_bwd(f, dp, opts->precision, s);
-  gsr::launch_preprocess_bwd(*scene, f, 1, *grads, use_stats ? stats : nullptr, s);
+  {
+    StageScope sc_(ctx, GSR_STAGE_RASTER_BWD, s);
+    gsr::launch_raster_bwd(f, dp, opts->precision, s);
+  }
+  {
+    StageScope sc_(ctx, GSR_STAGE_PREPROCESS_BWD, s);
+    gsr::launch_preprocess_bwd(*scene, f, 1, *grads, use_stats ? stats : nullptr, s);
+  }
   return check_hip(ctx, hipGetLastError(), "backward");
 }
 
@@ -439,6 +496,43 @@ gsr_status gsr_variance(gsr_context* ctx, const gsr_stats* stats, int64_t n, flo
   DeviceGuard guard(ctx->device);
   gsr::launch_variance(stats->S, stats->M, stats->C, n, out, static_cast<hipStream_t>(stream));
   return check_hip(ctx, hipGetLastError(), "variance");
+}
+
+gsr_status gsr_l1_grad(gsr_context* ctx, const float* image, const float* w, const float* gt, int64_t count,
+                       float* out, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (count < 0 || (count > 0 && (!image || !w || !gt || !out)))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_l1_grad");
+  DeviceGuard guard(ctx->device);
+  gsr::launch_l1_grad(image, w, gt, count, out, static_cast<hipStream_t>(stream));
+  return check_hip(ctx, hipGetLastError(), "l1 grad");
+}
+
+gsr_status gsr_set_profiling(gsr_context* ctx, int enable) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  DeviceGuard guard(ctx->device);
+  if (enable && !ctx->events_ready) {
+    for (int k = 0; k < 2 * GSR_STAGE_COUNT; ++k) {
+      gsr_status st = check_hip(ctx, hipEventCreate(&ctx->ev[k]), "create profiling events");
+      if (st) return st;
+    }
+    ctx->events_ready = true;
+  }
+  ctx->profiling = enable != 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_stage_times(gsr_context* ctx, float* ms) {
+  if (!ctx || !ms) return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_stage_times");
+  DeviceGuard guard(ctx->device);
+  for (int k = 0; k < GSR_STAGE_COUNT; ++k) {
+    ms[k] = -1.0f;
+    if (!ctx->events_ready || !ctx->recorded[k]) continue;
+    gsr_status st = check_hip(ctx, hipEventSynchronize(ctx->ev[2 * k + 1]), "wait for stage events");
+    if (st) return st;
+    if ((st = check_hip(ctx, hipEventElapsedTime(&ms[k], ctx->ev[2 * k], ctx->ev[2 * k + 1]), "stage time"))) return st;
+  }
+  return GSR_OK;
 }
 
 gsr_status gsr_morton_workspace_size(gsr_context* ctx, int64_t n, size_t* bytes) {

@@ -133,7 +133,8 @@ void morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, 
 void launch_gather_rows(const int64_t* perm, int64_t n, const float* src, float* dst, int32_t row_floats,
                         hipStream_t s);
 
-// variance
+// variance and loss
 void launch_variance(const float* S, const float* M, const uint32_t* C, int64_t n, float* out, hipStream_t s);
+void launch_l1_grad(const float* image, const float* w, const float* gt, int64_t n, float* out, hipStream_t s);
 
 }  // namespace gsr

@@ -470,7 +470,44 @@ __global__ void k_variance(const float* __restrict__ S, const float* __restrict_
   out[i] = c > 0.0 ? (float)((double)S[i] - m * m / c) : 0.0f;
 }
 
+__global__ void k_l1_grad(const float4* __restrict__ img, const float4* __restrict__ w,
+                          const float4* __restrict__ gt, int64_t n4, float4* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    const float4 a = img[i], b = w[i], c = gt[i];
+    float4 r;
+    r.x = a.x > c.x ? b.x : (a.x < c.x ? -b.x : 0.0f);
+    r.y = a.y > c.y ? b.y : (a.y < c.y ? -b.y : 0.0f);
+    r.z = a.z > c.z ? b.z : (a.z < c.z ? -b.z : 0.0f);
+    r.w = a.w > c.w ? b.w : (a.w < c.w ? -b.w : 0.0f);
+    out[i] = r;
+  }
+}
+
+__global__ void k_l1_grad_tail(const float* __restrict__ img, const float* __restrict__ w,
+                               const float* __restrict__ gt, int64_t beg, int64_t n, float* __restrict__ out) {
+  for (int64_t i = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = img[i] > gt[i] ? w[i] : (img[i] < gt[i] ? -w[i] : 0.0f);
+}
+
 }  // namespace
+
+void launch_l1_grad(const float* image, const float* w, const float* gt, int64_t n, float* out, hipStream_t s) {
+  if (n <= 0) return;
+  const bool aligned = (((uintptr_t)image | (uintptr_t)w | (uintptr_t)gt | (uintptr_t)out) & 15) == 0;
+  const int64_t n4 = aligned ? n / 4 : 0;
+  if (n4 > 0) {
+    int64_t g = (n4 + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_l1_grad<<<(unsigned)g, 256, 0, s>>>(reinterpret_cast<const float4*>(image), reinterpret_cast<const float4*>(w),
+                                          reinterpret_cast<const float4*>(gt), n4, reinterpret_cast<float4*>(out));
+  }
+  const int64_t rest = n - 4 * n4;
+  if (rest > 0) {
+    int64_t g = (rest + 255) / 256;
+    if (g > 8192) g = 8192;
+    k_l1_grad_tail<<<(unsigned)g, 256, 0, s>>>(image, w, gt, 4 * n4, n, out);
+  }
+}
 
 void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
   if (f.ncap <= 0) return;

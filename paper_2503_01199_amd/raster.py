@@ -270,6 +270,22 @@ class Rasterizer:
                                                    self._stream()), "gsr_apply_permutation")
         return dsts
 
+    def l1_grad(self, image: torch.Tensor, w: torch.Tensor, gt: torch.Tensor, out: torch.Tensor | None = None):
+        """dL/dI of L = sum w |I - gt| computed by the library's kernel."""
+        out = torch.empty_like(image) if out is None else out
+        self._check(self.lib.gsr_l1_grad(self.ctx, image.data_ptr(), w.data_ptr(), gt.data_ptr(), image.numel(),
+                                         out.data_ptr(), self._stream()), "gsr_l1_grad")
+        return out
+
+    def set_profiling(self, enable: bool):
+        self._check(self.lib.gsr_set_profiling(self.ctx, 1 if enable else 0), "gsr_set_profiling")
+
+    def stage_times(self) -> dict:
+        """Milliseconds per stage of the last profiled forward / backward (waits for them)."""
+        ms = (ctypes.c_float * len(L.STAGES))()
+        self._check(self.lib.gsr_stage_times(self.ctx, ms), "gsr_stage_times")
+        return {name: float(ms[k]) for k, name in enumerate(L.STAGES)}
+
     def variance(self, S: torch.Tensor, M: torch.Tensor, C: torch.Tensor) -> torch.Tensor:
         n = int(S.shape[0])
         out = torch.empty(n, dtype=torch.float32, device=self.device)
