@@ -175,6 +175,7 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.sorted_tiles = P.take<uint32_t>(nr + 1);
   f.offsets = P.take<uint32_t>(nr + 1);
   f.ranges = P.take<uint32_t>(2 * (size_t)f.tiles);
+  f.tile_order = P.take<uint32_t>((size_t)f.tiles);
   f.pix_rgb = P.take<float>(3 * (size_t)f.pixels);
   f.pix_T = P.take<float>((size_t)f.pixels);
   f.pix_last = P.take<uint32_t>((size_t)f.pixels);
@@ -382,6 +383,7 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
     {
       StageScope sc_(ctx, GSR_STAGE_RANGES, s);
       gsr::launch_tile_ranges(f, f.inst_tile, M, s);
+      gsr::launch_tile_order(f, s);
     }
     gsr::ImagePtrs ip;
     std::memset(&ip, 0, sizeof(ip));

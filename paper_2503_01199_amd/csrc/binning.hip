@@ -50,7 +50,59 @@ __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, int64_t M, uint
   if (k == M - 1 || inst_tile[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
 }
 
+// Longest-list-first schedule for the raster (tiles are independent, so the order
+// changes no result): one block buckets the list lengths (clamped to 4095) in LDS in
+// descending order, scans the buckets and scatters the tile ids.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 4096;
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges, int64_t T,
+                                                              uint32_t* __restrict__ order) {
+  __shared__ uint32_t h[kOrderBuckets];
+  __shared__ uint32_t wsum[kOrderThreads / 64];
+  const int t = threadIdx.x;
+  for (int b = t; b < kOrderBuckets; b += kOrderThreads) h[b] = 0;
+  __syncthreads();
+  for (int64_t i = t; i < T; i += kOrderThreads) {
+    const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
+    atomicAdd(&h[kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1))], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the buckets, 4 per thread
+  uint32_t v[4], sum = 0;
+  for (int q = 0; q < 4; ++q) {
+    v[q] = h[4 * t + q];
+    sum += v[q];
+  }
+  uint32_t incl = sum;
+  const int lane = t & 63;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[t >> 6] = incl;
+  __syncthreads();
+  uint32_t off = incl - sum;
+  for (int w = 0; w < (t >> 6); ++w) off += wsum[w];
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    h[4 * t + q] = off;
+    off += v[q];
+  }
+  __syncthreads();
+  for (int64_t i = t; i < T; i += kOrderThreads) {
+    const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
+    const uint32_t pos = atomicAdd(&h[kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1))], 1u);
+    order[pos] = (uint32_t)i;
+  }
+}
+
 }  // namespace
+
+void launch_tile_order(const Frame& f, hipStream_t s) {
+  if (f.tiles <= 0) return;
+  k_tile_order<<<1, kOrderThreads, 0, s>>>(f.ranges, f.tiles, f.tile_order);
+}
 
 void launch_gather_tiles(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
   if (f.nrec <= 0) return;

@@ -74,6 +74,7 @@ struct Frame {
   uint32_t* inst_tile;      // sorted instances (points into ikey/ival)
   uint32_t* inst_rec;
   uint32_t* ranges;         // [tiles][2]
+  uint32_t* tile_order;     // [tiles] raster schedule: tiles by descending list length
   float* pix_rgb;           // [pixels][3]
   float* pix_T;             // [pixels]
   uint32_t* pix_last;       // [pixels]
@@ -116,6 +117,7 @@ void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const 
 void launch_gather_tiles(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
 void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M, hipStream_t s);
+void launch_tile_order(const Frame& f, hipStream_t s);
 
 // raster_fwd.hip / raster_bwd.hip
 struct ImagePtrs {

@@ -21,25 +21,56 @@
 namespace gsr {
 namespace {
 
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_move(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true));
+template <int CTRL>
+__device__ __forceinline__ float dpp_row_shr(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
 }
 
-// Sum over the wave; the total lands in lane 63.
-__device__ __forceinline__ float wave_sum_to_last(float x) {
-  x += dpp_move<0x111, 0xf>(x);  // row_shr:1
-  x += dpp_move<0x112, 0xf>(x);  // row_shr:2
-  x += dpp_move<0x114, 0xf>(x);  // row_shr:4
-  x += dpp_move<0x118, 0xf>(x);  // row_shr:8  -> lane 15 of each row holds the row sum
-  x += dpp_move<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-  x += dpp_move<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3 -> lane 63 holds the total
-  return x;
+// v_permlane32_swap / v_permlane16_swap (gfx950): exchange the upper 32 lanes of the
+// first operand with the lower 32 lanes of the second, resp. the odd 16-lane rows
+// of the first with the even rows of the second.
+__device__ __forceinline__ void swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ float lane63(float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63)); }
+// Transposed wave reduction of 12 per-lane values v[0..11]. Two swap-and-add
+// stages halve the registers while halving the lanes each value spans (so each
+// add reduces two values at once), then a 4-step DPP row reduction finishes the
+// 16-lane rows. On return w[i] holds, in lanes 15, 31, 47 and 63, the wave totals
+// of values 4i, 4i+2, 4i+1 and 4i+3.
+__device__ __forceinline__ void wave_reduce12(float v[12], float w[3]) {
+  float u[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    float a = v[2 * i], b = v[2 * i + 1];
+    swap32(a, b);
+    u[i] = a + b;  // lanes 0-31: value 2i, lanes 32-63: value 2i+1
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float a = u[2 * i], b = u[2 * i + 1];
+    swap16(a, b);
+    w[i] = a + b;  // rows 0, 1, 2, 3: values 4i, 4i+2, 4i+1, 4i+3
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] += dpp_row_shr<0x111>(w[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] += dpp_row_shr<0x112>(w[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] += dpp_row_shr<0x114>(w[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) w[i] += dpp_row_shr<0x118>(w[i]);
+}
 
 __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ views, int32_t V,
+                                                   const uint32_t* __restrict__ tile_order,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
                                                    const Record* __restrict__ rec, ConstImagePtrs dL,
@@ -48,7 +79,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    float* __restrict__ grad2d) {
   __shared__ Record batch[64];
   __shared__ uint32_t brec[64];
-  const uint32_t gt = blockIdx.x;
+  const uint32_t gt = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
   const int W = w.width, H = w.height;
@@ -62,15 +93,20 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
   const int64_t plane = (int64_t)W * H;
   const float* g_img = dL.p[v];
 
-  float gI[4][3], Rb[4][3], T[4];
+  // Per pixel: upstream gradient g, g . I_final, g . (colour composited so far), T
+  // and the list position after its last blend. The colour behind entry k is
+  // I_final - C_{<=k}, so g . (colour behind) = gIf - gC.
+  float gI[4][3], gIf[4], gC[4], T[4];
   uint32_t last[4];
   uint32_t mymax = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     T[j] = 1.0f;
+    gC[j] = 0.0f;
+    gIf[j] = 0.0f;
     last[j] = 0;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) gI[j][ch] = Rb[j][ch] = 0.0f;
+    for (int ch = 0; ch < 3; ++ch) gI[j][ch] = 0.0f;
     if (px < W && py0 + j < H) {
       const int64_t o = (int64_t)(py0 + j) * W + px;
       const int64_t pp = w.pixel_base + o;
@@ -78,7 +114,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         gI[j][ch] = g_img[ch * plane + o];
-        Rb[j][ch] = pix_rgb[3 * pp + ch];
+        gIf[j] = __builtin_fmaf(gI[j][ch], pix_rgb[3 * pp + ch], gIf[j]);
       }
       mymax = max(mymax, last[j]);
     }
@@ -87,15 +123,21 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
   for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = min(ranges[2 * gt + 1], s + mymax);
+
+  // Record gathers are pipelined: ids two batches ahead, records one batch ahead.
+  uint32_t r_cur = (s + lane < e) ? inst_rec[s + lane] : 0u;
+  Record g_cur = {};
+  if (s + lane < e) g_cur = rec[r_cur];
+  uint32_t r_next = (s + 64 + lane < e) ? inst_rec[s + 64 + lane] : 0u;
+
   for (uint32_t b0 = s; b0 < e; b0 += 64) {
-    const uint32_t idx = b0 + lane;
     __syncthreads();
-    if (idx < e) {
-      const uint32_t r = inst_rec[idx];
-      brec[lane] = r;
-      batch[lane] = rec[r];
-    }
+    batch[lane] = g_cur;
+    brec[lane] = r_cur;
     __syncthreads();
+    r_cur = r_next;
+    if (b0 + 64 + lane < e) g_cur = rec[r_cur];
+    r_next = (b0 + 128 + lane < e) ? inst_rec[b0 + 128 + lane] : 0u;
     const int cnt = (int)min(64u, e - b0);
     for (int k = 0; k < cnt; ++k) {
       const Record g = batch[k];
@@ -104,38 +146,38 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
       const uint32_t pos = b0 - s + (uint32_t)k;
       const float o = g.r2.x;
       float S0 = 0.f, S1 = 0.f, S2 = 0.f, dcr = 0.f, dcg = 0.f, dcb = 0.f, dop = 0.f, ss = 0.f, nfrag = 0.f;
-      bool any = false;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float G, araw;
         const float a = alpha_of(o, ev[j], G, araw);
         const bool blend = (pos < last[j]) && (a >= kAlphaMin);
         if (blend) {
+          nfrag += 1.0f;
           const float wt = a * T[j];
+          const float gc = __builtin_fmaf(gI[j][2], g.r2.w, __builtin_fmaf(gI[j][1], g.r2.z, gI[j][0] * g.r2.y));
           dcr = __builtin_fmaf(wt, gI[j][0], dcr);
           dcg = __builtin_fmaf(wt, gI[j][1], dcg);
           dcb = __builtin_fmaf(wt, gI[j][2], dcb);
-          Rb[j][0] = __builtin_fmaf(-wt, g.r2.y, Rb[j][0]);
-          Rb[j][1] = __builtin_fmaf(-wt, g.r2.z, Rb[j][1]);
-          Rb[j][2] = __builtin_fmaf(-wt, g.r2.w, Rb[j][2]);
-          const float gc = __builtin_fmaf(gI[j][2], g.r2.w, __builtin_fmaf(gI[j][1], g.r2.z, gI[j][0] * g.r2.y));
-          const float gR = __builtin_fmaf(gI[j][2], Rb[j][2], __builtin_fmaf(gI[j][1], Rb[j][1], gI[j][0] * Rb[j][0]));
+          gC[j] = __builtin_fmaf(wt, gc, gC[j]);
           const float one_m_a = 1.0f - a;
-          const float dA = __builtin_fmaf(T[j], gc, -gR * __builtin_amdgcn_rcpf(one_m_a));
-          const float dAr = (araw <= kAlphaMax) ? dA : 0.0f;
-          const float go = dAr * G;
+          // dL/dalpha = T (g . c) - (g . colour behind) / (1 - alpha)
+          const float dA = __builtin_fmaf(T[j], gc, -(gIf[j] - gC[j]) * __builtin_amdgcn_rcpf(one_m_a));
+          const float go = (araw <= kAlphaMax) ? dA * G : 0.0f;
           const float dE = go * o;
           S0 += dE;
-          S1 = __builtin_fmaf((float)j, dE, S1);
-          S2 = __builtin_fmaf((float)(j * j), dE, S2);
+          if (j == 1) {
+            S1 += dE;
+            S2 += dE;
+          } else if (j > 1) {
+            S1 = __builtin_fmaf((float)j, dE, S1);
+            S2 = __builtin_fmaf((float)(j * j), dE, S2);
+          }
           dop += go;
           ss = __builtin_fmaf(go, go, ss);
-          nfrag += 1.0f;
           T[j] *= one_m_a;
-          any = true;
         }
       }
-      if (!__any(any)) continue;
+      if (!__any(nfrag > 0.0f)) continue;  // nobody blended this entry
       // exponent -> conic (a, b, c) and mean (u, v) gradients at the strip start:
       //   E_j = -1/2 (a dx^2 + 2 b dx (dy - j) + c (dy - j)^2), d = mean - pixel
       const float ca = -2.0f * (float)kLn2 * g.r1.x;
@@ -146,14 +188,18 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
       const float ga = -0.5f * dx * dx * S0;
       const float gb = __builtin_fmaf(dx, S1, -dx * dy * S0);
       const float gcn = __builtin_fmaf(dy, S1, __builtin_fmaf(-0.5f * dy * dy, S0, -0.5f * S2));
-      float vals[11] = {gu, gv, ga, gb, gcn, dop, dcr, dcg, dcb, ss, nfrag};
-      float mine = 0.0f;
-#pragma unroll
-      for (int q = 0; q < 11; ++q) {
-        const float tot = lane63(wave_sum_to_last(vals[q]));
-        mine = (lane == q) ? tot : mine;
+      float vals[12] = {gu, gv, ga, gb, gcn, dop, dcr, dcg, dcb, ss, nfrag, 0.0f};
+      float tot[3];
+      wave_reduce12(vals, tot);
+      // lanes 15, 31, 47, 63 of tot[i] hold slots 4i, 4i+2, 4i+1, 4i+3 (slot 11 is padding)
+      if ((lane & 15) == 15) {
+        const int row = lane >> 4;
+        const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+        float* dst = grad2d + (int64_t)brec[k] * kGrad2D + sub;
+        unsafeAtomicAdd(dst, tot[0]);
+        unsafeAtomicAdd(dst + 4, tot[1]);
+        if (sub != 3) unsafeAtomicAdd(dst + 8, tot[2]);
       }
-      if (lane < 11) unsafeAtomicAdd(grad2d + (int64_t)brec[k] * kGrad2D + lane, mine);
     }
   }
 }
@@ -163,8 +209,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s) {
   (void)precision;
   if (f.tiles <= 0) return;
-  k_raster_bwd<<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.ranges, f.inst_rec, f.rec, dL, f.pix_rgb,
-                                                f.pix_last, f.grad2d);
+  k_raster_bwd<<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec, dL,
+                                                f.pix_rgb, f.pix_last, f.grad2d);
 }
 
 }  // namespace gsr

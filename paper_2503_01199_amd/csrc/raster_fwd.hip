@@ -17,13 +17,14 @@ namespace gsr {
 namespace {
 
 __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ views, int32_t V,
+                                                   const uint32_t* __restrict__ tile_order,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
                                                    const Record* __restrict__ rec, ImagePtrs images,
                                                    float* __restrict__ pix_rgb, float* __restrict__ pix_T,
                                                    uint32_t* __restrict__ pix_last) {
   __shared__ Record batch[64];
-  const uint32_t gt = blockIdx.x;
+  const uint32_t gt = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
   const int W = w.width, H = w.height;
@@ -35,24 +36,30 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
   const float pxc = (float)px + 0.5f;
   const float pyc = (float)py0 + 0.5f;
 
-  bool act[4];
-  float T[4], cr[4], cg[4], cb[4];
+  // A pixel blends an entry when alpha >= amin; amin is 1/255 while the pixel is
+  // live and 2 (unreachable) once it has stopped or lies outside the image.
+  float amin[4], T[4], cr[4], cg[4], cb[4];
   uint32_t last[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    act[j] = (px < W) && (py0 + j < H);
+    amin[j] = ((px < W) && (py0 + j < H)) ? kAlphaMin : 2.0f;
     T[j] = 1.0f;
     cr[j] = cg[j] = cb[j] = 0.0f;
     last[j] = 0;
   }
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = ranges[2 * gt + 1];
-  bool live = __any(act[0] | act[1] | act[2] | act[3]);
+  bool live = __any(fminf(fminf(amin[0], amin[1]), fminf(amin[2], amin[3])) < 1.0f);
+  // Record gathers are pipelined: ids two batches ahead, records one batch ahead.
+  uint32_t r_next = (s + 64 + lane < e) ? inst_rec[s + 64 + lane] : 0u;
+  Record g_cur = {};
+  if (s + lane < e) g_cur = rec[inst_rec[s + lane]];
   for (uint32_t b0 = s; b0 < e && live; b0 += 64) {
-    const uint32_t idx = b0 + lane;
     __syncthreads();
-    if (idx < e) batch[lane] = rec[inst_rec[idx]];
+    batch[lane] = g_cur;
     __syncthreads();
+    if (b0 + 64 + lane < e) g_cur = rec[r_next];
+    r_next = (b0 + 128 + lane < e) ? inst_rec[b0 + 128 + lane] : 0u;
     const int cnt = (int)min(64u, e - b0);
     for (int k = 0; k < cnt; ++k) {
       const Record g = batch[k];
@@ -63,21 +70,19 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
       for (int j = 0; j < 4; ++j) {
         float G, araw;
         const float a = alpha_of(g.r2.x, ev[j], G, araw);
-        const bool ok = act[j] && (a >= kAlphaMin);
+        const bool ok = a >= amin[j];
         const float Tn = T[j] * (1.0f - a);
         const bool stop = ok && (Tn < kTMin);
         const bool blend = ok && !stop;
-        const float wt = a * T[j];
-        if (blend) {
-          cr[j] = __builtin_fmaf(wt, g.r2.y, cr[j]);
-          cg[j] = __builtin_fmaf(wt, g.r2.z, cg[j]);
-          cb[j] = __builtin_fmaf(wt, g.r2.w, cb[j]);
-          T[j] = Tn;
-          last[j] = pos1;
-        }
-        if (stop) act[j] = false;
+        const float wt = blend ? a * T[j] : 0.0f;
+        cr[j] = __builtin_fmaf(wt, g.r2.y, cr[j]);
+        cg[j] = __builtin_fmaf(wt, g.r2.z, cg[j]);
+        cb[j] = __builtin_fmaf(wt, g.r2.w, cb[j]);
+        T[j] = blend ? Tn : T[j];
+        last[j] = blend ? pos1 : last[j];
+        amin[j] = stop ? 2.0f : amin[j];
       }
-      if (!__any(act[0] | act[1] | act[2] | act[3])) {
+      if (!__any(fminf(fminf(amin[0], amin[1]), fminf(amin[2], amin[3])) < 1.0f)) {
         live = false;
         break;
       }
@@ -111,7 +116,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
 void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s) {
   (void)precision;
   if (f.tiles <= 0) return;
-  k_raster_fwd<<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.ranges, f.inst_rec, f.rec, images,
+  k_raster_fwd<<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec, images,
                                                 f.pix_rgb, f.pix_T, f.pix_last);
 }
 
