@@ -76,13 +76,12 @@ __device__ inline double sig(const GaussParams& g, int r, int c) {
 
 // Real SH basis of degree <= 3 (orthonormal, no Condon-Shortley phase) at the unit
 // direction (x, y, z), index l*l + l + m, and optionally its gradient in R^3.
-template <int deg>
-__device__ inline void sh_basis(double x, double y, double z, double* Y, double (*dY)[3]) {
-  const double pi = 3.14159265358979323846;
-  Y[0] = 0.5 * sqrt(1.0 / pi);
+template <int deg, typename R = double>
+__device__ inline void sh_basis(R x, R y, R z, R* Y, R (*dY)[3]) {
+  Y[0] = (R)(0.5 * sqrt(1.0 / 3.14159265358979323846));
   if (dY) dY[0][0] = dY[0][1] = dY[0][2] = 0.0;
   if constexpr (deg < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * pi));
+  const R c1 = (R)sqrt(3.0 / (4.0 * 3.14159265358979323846));
   Y[1] = c1 * y;
   Y[2] = c1 * z;
   Y[3] = c1 * x;
@@ -92,10 +91,10 @@ __device__ inline void sh_basis(double x, double y, double z, double* Y, double 
     dY[3][0] = c1; dY[3][1] = 0; dY[3][2] = 0;
   }
   if constexpr (deg < 2) return;
-  const double xx = x * x, yy = y * y, zz = z * z;
-  const double c2a = 0.5 * sqrt(15.0 / pi);   // xy, yz, xz
-  const double c2b = 0.25 * sqrt(5.0 / pi);   // 2z^2 - x^2 - y^2
-  const double c2c = 0.25 * sqrt(15.0 / pi);  // x^2 - y^2
+  const R xx = x * x, yy = y * y, zz = z * z;
+  const R c2a = (R)(0.5 * sqrt(15.0 / 3.14159265358979323846));   // xy, yz, xz
+  const R c2b = (R)(0.25 * sqrt(5.0 / 3.14159265358979323846));   // 2z^2 - x^2 - y^2
+  const R c2c = (R)(0.25 * sqrt(15.0 / 3.14159265358979323846));  // x^2 - y^2
   Y[4] = c2a * x * y;
   Y[5] = c2a * y * z;
   Y[6] = c2b * (2 * zz - xx - yy);
@@ -109,12 +108,12 @@ __device__ inline void sh_basis(double x, double y, double z, double* Y, double 
     dY[8][0] = 2 * c2c * x;  dY[8][1] = -2 * c2c * y;  dY[8][2] = 0;
   }
   if constexpr (deg < 3) return;
-  const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi));  // m = +-3
-  const double c3b = 0.5 * sqrt(105.0 / pi);          // m = -2
-  const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi));  // m = +-1
-  const double c3d = 0.25 * sqrt(7.0 / pi);           // m = 0
-  const double c3e = 0.25 * sqrt(105.0 / pi);         // m = 2
-  const double f1 = 4 * zz - xx - yy;
+  const R c3a = (R)(0.25 * sqrt(35.0 / (2.0 * 3.14159265358979323846)));  // m = +-3
+  const R c3b = (R)(0.5 * sqrt(105.0 / 3.14159265358979323846));          // m = -2
+  const R c3c = (R)(0.25 * sqrt(21.0 / (2.0 * 3.14159265358979323846)));  // m = +-1
+  const R c3d = (R)(0.25 * sqrt(7.0 / 3.14159265358979323846));           // m = 0
+  const R c3e = (R)(0.25 * sqrt(105.0 / 3.14159265358979323846));         // m = 2
+  const R f1 = 4 * zz - xx - yy;
   Y[9] = c3a * y * (3 * xx - yy);
   Y[10] = c3b * x * y * z;
   Y[11] = c3c * y * f1;
@@ -131,6 +130,42 @@ __device__ inline void sh_basis(double x, double y, double z, double* Y, double 
     dY[14][0] = 2 * c3e * x * z;          dY[14][1] = -2 * c3e * y * z;         dY[14][2] = c3e * (xx - yy);
     dY[15][0] = c3a * (3 * xx - 3 * yy);  dY[15][1] = -6 * c3a * x * y;        dY[15][2] = 0;
   }
+}
+
+// Gradient on R^3 of P(x, y, z) = sum_k w_k Y_k(x, y, z) for the basis above,
+// accumulated term by term (no table of basis gradients is kept).
+template <int deg>
+__device__ __forceinline__ void sh_weighted_grad(float x, float y, float z, const float* w, float g[3]) {
+  g[0] = g[1] = g[2] = 0.0f;
+  if constexpr (deg < 1) return;
+  const float c1 = (float)sqrt(3.0 / (4.0 * 3.14159265358979323846));
+  g[0] += c1 * w[3];
+  g[1] += c1 * w[1];
+  g[2] += c1 * w[2];
+  if constexpr (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float c2a = (float)(0.5 * sqrt(15.0 / 3.14159265358979323846));
+  const float c2b = (float)(0.25 * sqrt(5.0 / 3.14159265358979323846));
+  const float c2c = (float)(0.25 * sqrt(15.0 / 3.14159265358979323846));
+  float t;
+  t = c2a * w[4]; g[0] += t * y; g[1] += t * x;
+  t = c2a * w[5]; g[1] += t * z; g[2] += t * y;
+  t = c2b * w[6]; g[0] -= 2 * t * x; g[1] -= 2 * t * y; g[2] += 4 * t * z;
+  t = c2a * w[7]; g[0] += t * z; g[2] += t * x;
+  t = c2c * w[8]; g[0] += 2 * t * x; g[1] -= 2 * t * y;
+  if constexpr (deg < 3) return;
+  const float c3a = (float)(0.25 * sqrt(35.0 / (2.0 * 3.14159265358979323846)));
+  const float c3b = (float)(0.5 * sqrt(105.0 / 3.14159265358979323846));
+  const float c3c = (float)(0.25 * sqrt(21.0 / (2.0 * 3.14159265358979323846)));
+  const float c3d = (float)(0.25 * sqrt(7.0 / 3.14159265358979323846));
+  const float c3e = (float)(0.25 * sqrt(105.0 / 3.14159265358979323846));
+  t = c3a * w[9];  g[0] += t * 6 * x * y; g[1] += t * (3 * xx - 3 * yy);
+  t = c3b * w[10]; g[0] += t * y * z; g[1] += t * x * z; g[2] += t * x * y;
+  t = c3c * w[11]; g[0] -= t * 2 * x * y; g[1] += t * (4 * zz - xx - 3 * yy); g[2] += t * 8 * y * z;
+  t = c3d * w[12]; g[0] -= t * 6 * x * z; g[1] -= t * 6 * y * z; g[2] += t * (6 * zz - 3 * xx - 3 * yy);
+  t = c3c * w[13]; g[0] += t * (4 * zz - 3 * xx - yy); g[1] -= t * 2 * x * y; g[2] += t * 8 * x * z;
+  t = c3e * w[14]; g[0] += t * 2 * x * z; g[1] -= t * 2 * y * z; g[2] += t * (xx - yy);
+  t = c3a * w[15]; g[0] += t * (3 * xx - 3 * yy); g[1] -= t * 6 * x * y;
 }
 
 // Camera-side projection of one Gaussian into one view.
@@ -264,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
     }
     // colour
     double Y[16];
-    sh_basis<DEG>(pr.dir[0], pr.dir[1], pr.dir[2], Y, nullptr);
+    sh_basis<DEG, double>(pr.dir[0], pr.dir[1], pr.dir[2], Y, nullptr);
     double col[3] = {0.5, 0.5, 0.5};
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -287,31 +322,24 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
   }
 }
 
-// Backward of the projection: screen-space gradients (grad2d, summed over the
-// views) to the parameter gradients. One thread per Gaussian in the caller's
-// order; Gaussians of culled clusters get zero.
-template <int DEG>
-__global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
-    gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, int cull, const uint32_t* __restrict__ visible,
+// Backward of the projection, geometric part: screen-space gradients (grad2d of
+// every view) to the mean, log-scale, quaternion and opacity-logit gradients, in
+// FP64. One thread per Gaussian in the caller's order; Gaussians that no view
+// blends (including those of culled clusters) get zero. The SH coefficients and the
+// colour's dependence on the mean through the view direction follow in k_sh_bwd.
+__global__ __launch_bounds__(kThreads) void k_project_bwd(
+    gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, const uint32_t* __restrict__ visible,
     const uint32_t* __restrict__ cluster_offset, const uint32_t* __restrict__ tiles,
     const float* __restrict__ grad2d, gsr_grads gr, float* __restrict__ S, float* __restrict__ Mst,
     uint32_t* __restrict__ Cst) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= sc.n) return;
-  constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t c = i / GSR_CLUSTER;
-  bool vis = true;
-  int64_t j = i;
-  if (cull) {
-    vis = visible[c] != 0;
-    j = (int64_t)cluster_offset[c] * GSR_CLUSTER + (i % GSR_CLUSTER);
-  }
+  const bool vis = visible[c] != 0;
+  const int64_t j = (int64_t)cluster_offset[c] * GSR_CLUSTER + (i % GSR_CLUSTER);
   double dm[3] = {0, 0, 0};
   double dlogit = 0.0;
-  double GS[6] = {0, 0, 0, 0, 0, 0};  // gradient w.r.t. Sigma (symmetric, packed as Sig)
-  float dsh[3 * K];
-#pragma unroll
-  for (int k = 0; k < 3 * K; ++k) dsh[k] = 0.0f;
+  double GS[6] = {0, 0, 0, 0, 0, 0};  // gradient w.r.t. Sigma (packed like Sig)
   double sS = 0.0, sM = 0.0;
   uint32_t sC = 0;
   bool any = false;
@@ -320,12 +348,12 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
     for (int v = 0; v < V; ++v) {
       const int64_t r = j * V + v;
       if (tiles[r] == 0) continue;
-      const float* gg = grad2d + r * kGrad2D;
-      const double du = gg[0], dv = gg[1], da = gg[2], db = gg[3], dc = gg[4], dop = gg[5];
-      const double dcol[3] = {gg[6], gg[7], gg[8]};
-      sS += gg[9];
+      const float4* gg4 = reinterpret_cast<const float4*>(grad2d + r * kGrad2D);
+      const float4 q0 = gg4[0], q1 = gg4[1], q2 = gg4[2];
+      const double du = q0.x, dv = q0.y, da = q0.z, db = q0.w, dc = q1.x, dop = q1.y;
+      sS += q2.y;
       sM += dop;
-      sC += (uint32_t)gg[10];
+      sC += (uint32_t)q2.z;
       if (!any) {
         load_gaussian(sc, i, g);
         any = true;
@@ -333,33 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
       const ViewDev& w = views[v];
       ViewProj p;
       if (!project_view(g, w, p)) continue;
-      // opacity: o = sigmoid(l)
       dlogit += dop * g.o * (1.0 - g.o);
-      // colour = max(0, sum_k Y_k f_k + 1/2)
-      double Y[16], dY[16][3];
-      sh_basis<DEG>(p.dir[0], p.dir[1], p.dir[2], Y, dY);
-      const float* shp = sc.sh + i * K * 3;
-      double raw[3] = {0.5, 0.5, 0.5};
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * (double)shp[3 * k + ch];
-      double ddir[3] = {0, 0, 0};
-      for (int ch = 0; ch < 3; ++ch) {
-        const double gc = raw[ch] < 0.0 ? 0.0 : dcol[ch];
-        if (gc == 0.0) continue;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          dsh[3 * k + ch] += (float)(gc * Y[k]);
-          const double f = (double)shp[3 * k + ch];
-          ddir[0] += gc * f * dY[k][0];
-          ddir[1] += gc * f * dY[k][1];
-          ddir[2] += gc * f * dY[k][2];
-        }
-      }
-      {
-        const double dd = p.dir[0] * ddir[0] + p.dir[1] * ddir[1] + p.dir[2] * ddir[2];
-        for (int a = 0; a < 3; ++a) dm[a] += (ddir[a] - p.dir[a] * dd) / p.dist;
-      }
       // conic -> screen covariance: G_cov = -Q G_Q Q, G_Q = [[da, db/2], [db/2, dc]]
       const double qa = p.cov[2] / p.det, qb = -p.cov[1] / p.det, qc = p.cov[0] / p.det;
       const double h = 0.5 * db;
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
       const double g11 = -(qb * t01 + qc * t11);
       // cov = M Sigma M^T + 0.3 I: G_Sigma += M^T G_cov M, G_M = 2 G_cov M Sigma
       const double* M = p.M;
-      double GM0[3], GM1[3];  // rows of G_cov M
+      double GM0[3], GM1[3];
       for (int k = 0; k < 3; ++k) {
         GM0[k] = g00 * M[k] + g01 * M[3 + k];
         GM1[k] = g01 * M[k] + g11 * M[3 + k];
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
       int idx = 0;
       for (int r2 = 0; r2 < 3; ++r2)
         for (int c2 = r2; c2 < 3; ++c2) GS[idx++] += M[r2] * GM0[c2] + M[3 + r2] * GM1[c2];
-      double GMf[6];  // 2 (G_cov M) Sigma
+      double GMf[6];
       for (int k = 0; k < 3; ++k) {
         GMf[k] = 2.0 * (GM0[0] * sig(g, 0, k) + GM0[1] * sig(g, 1, k) + GM0[2] * sig(g, 2, k));
         GMf[3 + k] = 2.0 * (GM1[0] * sig(g, 0, k) + GM1[1] * sig(g, 1, k) + GM1[2] * sig(g, 2, k));
@@ -414,13 +416,10 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
   float* om = gr.means + 3 * i;
   float* ol = gr.log_scales + 3 * i;
   float* oq = gr.quats + 4 * i;
-  float* osh = gr.sh + i * K * 3;
   if (!any) {
     for (int a = 0; a < 3; ++a) om[a] = 0.0f, ol[a] = 0.0f;
     for (int a = 0; a < 4; ++a) oq[a] = 0.0f;
     gr.opacity_logits[i] = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 3 * K; ++k) osh[k] = 0.0f;
     return;
   }
   // Sigma = L L^T, L = R S: G_L = 2 G_Sigma L
@@ -452,12 +451,126 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_bwd(
   for (int a = 0; a < 4; ++a) oq[a] = (float)((dq[a] - g.q[a] * qd) / g.qn);
   for (int a = 0; a < 3; ++a) om[a] = (float)dm[a];
   gr.opacity_logits[i] = (float)dlogit;
-#pragma unroll
-  for (int k = 0; k < 3 * K; ++k) osh[k] = dsh[k];
   if (S) {
     S[i] += (float)sS;
     Mst[i] += (float)sM;
     Cst[i] += sC;
+  }
+}
+
+// Backward of the SH colour: colour = max(0, sum_k Y_k(dir) f_k + 1/2) per channel,
+// dir = (mean - camera centre)/|mean - camera centre|. Writes the coefficient
+// gradients and adds the direction term to the mean gradient that k_project_bwd
+// wrote. The clamp decision is taken in FP64 like the projection's; the gradients
+// accumulate in FP32.
+template <int DEG>
+__global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev* __restrict__ views, int32_t V,
+                                                     const uint32_t* __restrict__ visible,
+                                                     const uint32_t* __restrict__ cluster_offset,
+                                                     const uint32_t* __restrict__ tiles,
+                                                     const float* __restrict__ grad2d, gsr_grads gr) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr bool kVec = (3 * K) % 4 == 0;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= sc.n) return;
+  const int64_t c = i / GSR_CLUSTER;
+  const bool vis = visible[c] != 0;
+  const int64_t j = (int64_t)cluster_offset[c] * GSR_CLUSTER + (i % GSR_CLUSTER);
+  float f[3 * K];
+  const float* shp = sc.sh + i * (3 * K);
+  if constexpr (kVec) {
+    const float4* s4 = reinterpret_cast<const float4*>(shp);
+#pragma unroll
+    for (int q = 0; q < 3 * K / 4; ++q) {
+      const float4 t = s4[q];
+      f[4 * q] = t.x, f[4 * q + 1] = t.y, f[4 * q + 2] = t.z, f[4 * q + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 3 * K; ++q) f[q] = shp[q];
+  }
+  float* osh = gr.sh + i * (3 * K);
+  float dmu[3] = {0.f, 0.f, 0.f};
+  bool written = false;
+  const double m0 = sc.means[3 * i], m1 = sc.means[3 * i + 1], m2 = sc.means[3 * i + 2];
+  if (vis) {
+    for (int v = 0; v < V; ++v) {
+      const int64_t r = j * V + v;
+      if (tiles[r] == 0) continue;
+      const float4* gg4 = reinterpret_cast<const float4*>(grad2d + r * kGrad2D);
+      const float4 q1 = gg4[1], q2 = gg4[2];
+      const float dcol[3] = {q1.z, q1.w, q2.x};
+      const ViewDev& w = views[v];
+      const double d0 = m0 - w.campos[0], d1 = m1 - w.campos[1], d2 = m2 - w.campos[2];
+      const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double x = d0 / dist, y = d1 / dist, z = d2 / dist;
+      float gc[3];
+      {
+        double Y[16];
+        sh_basis<DEG, double>(x, y, z, Y, nullptr);
+        double raw[3] = {0.5, 0.5, 0.5};
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) raw[ch] += Y[k] * (double)f[3 * k + ch];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gc[ch] = raw[ch] < 0.0 ? 0.0f : dcol[ch];
+      }
+      const float xf = (float)x, yf = (float)y, zf = (float)z;
+      float Yf[16];
+      sh_basis<DEG, float>(xf, yf, zf, Yf, nullptr);
+      // d colour / d f_k = Y_k, written per view (the row belongs to this thread)
+      if constexpr (kVec) {
+        float4* o4 = reinterpret_cast<float4*>(osh);
+#pragma unroll
+        for (int q = 0; q < 3 * K / 4; ++q) {
+          float4 t;
+          t.x = gc[(4 * q) % 3] * Yf[(4 * q) / 3];
+          t.y = gc[(4 * q + 1) % 3] * Yf[(4 * q + 1) / 3];
+          t.z = gc[(4 * q + 2) % 3] * Yf[(4 * q + 2) / 3];
+          t.w = gc[(4 * q + 3) % 3] * Yf[(4 * q + 3) / 3];
+          if (written) {
+            const float4 o = o4[q];
+            t.x += o.x, t.y += o.y, t.z += o.z, t.w += o.w;
+          }
+          o4[q] = t;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 3 * K; ++q) osh[q] = gc[q % 3] * Yf[q / 3] + (written ? osh[q] : 0.0f);
+      }
+      written = true;
+      if constexpr (DEG > 0) {
+        // d colour / d dir = grad of sum_k (sum_ch gc_ch f_k,ch) Y_k
+        float wk[16];
+#pragma unroll
+        for (int k = 0; k < K; ++k) wk[k] = gc[0] * f[3 * k] + gc[1] * f[3 * k + 1] + gc[2] * f[3 * k + 2];
+        float ddir[3];
+        sh_weighted_grad<DEG>(xf, yf, zf, wk, ddir);
+        const float dd = xf * ddir[0] + yf * ddir[1] + zf * ddir[2];
+        const float inv = (float)(1.0 / dist);
+        dmu[0] += (ddir[0] - xf * dd) * inv;
+        dmu[1] += (ddir[1] - yf * dd) * inv;
+        dmu[2] += (ddir[2] - zf * dd) * inv;
+      }
+    }
+  }
+  if (!written) {
+    if constexpr (kVec) {
+      float4* o4 = reinterpret_cast<float4*>(osh);
+#pragma unroll
+      for (int q = 0; q < 3 * K / 4; ++q) o4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 3 * K; ++q) osh[q] = 0.0f;
+    }
+    return;
+  }
+  if (DEG > 0) {
+    float* om = gr.means + 3 * i;
+    om[0] += dmu[0];
+    om[1] += dmu[1];
+    om[2] += dmu[2];
   }
 }
 
@@ -526,19 +639,22 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
 
 void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
                            const gsr_stats* stats, hipStream_t s) {
+  (void)cull;
   if (sc.n <= 0) return;
   const unsigned grid = (unsigned)((sc.n + kThreads - 1) / kThreads);
-#define GSR_PRE_BWD(D)                                                                                       \
-  k_preprocess_bwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, cull, f.cluster_visible, f.cluster_offset, \
-                                                f.tiles_touched, f.grad2d, g, stats ? stats->S : nullptr,    \
-                                                stats ? stats->M : nullptr, stats ? stats->C : nullptr)
+  k_project_bwd<<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset, f.tiles_touched,
+                                          f.grad2d, g, stats ? stats->S : nullptr, stats ? stats->M : nullptr,
+                                          stats ? stats->C : nullptr);
+#define GSR_SH_BWD(D)                                                                                      \
+  k_sh_bwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset, f.tiles_touched, \
+                                        f.grad2d, g)
   switch (sc.sh_degree) {
-    case 0: GSR_PRE_BWD(0); break;
-    case 1: GSR_PRE_BWD(1); break;
-    case 2: GSR_PRE_BWD(2); break;
-    default: GSR_PRE_BWD(3); break;
+    case 0: GSR_SH_BWD(0); break;
+    case 1: GSR_SH_BWD(1); break;
+    case 2: GSR_SH_BWD(2); break;
+    default: GSR_SH_BWD(3); break;
   }
-#undef GSR_PRE_BWD
+#undef GSR_SH_BWD
 }
 
 void launch_variance(const float* S, const float* M, const uint32_t* C, int64_t n, float* out, hipStream_t s) {
