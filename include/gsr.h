@@ -12,9 +12,10 @@
  *    gsr_camera array and every struct passed by pointer are HOST memory, read
  *    during the call only.
  *  - `stream` is a hipStream_t (NULL = the default stream). Every call enqueues
- *    its work on that stream and returns; gsr_forward additionally waits once for
- *    a 4-byte count (see below). Results are valid once the stream has reached
- *    the call's work.
+ *    its work on that stream and returns without waiting for the device (counts
+ *    that decide launch work are read by the kernels from device memory). Results
+ *    are valid once the stream has reached the call's work. Only gsr_frame_inspect,
+ *    gsr_frame_release and gsr_stage_times wait.
  *  - The library never allocates device memory. Scratch space comes from a
  *    caller-owned workspace whose size the *_workspace_size calls report.
  *  - Every call returns a gsr_status. Host-side validation happens before any
@@ -113,7 +114,7 @@ typedef struct {
   uint32_t *C;
 } gsr_stats;
 
-/* Counters of the last forward on a workspace (host copy, filled by gsr_forward). */
+/* Counters of the last forward on a workspace (host copy, see gsr_frame_inspect). */
 typedef struct {
   int64_t n;               /* Gaussians in the scene */
   int64_t n_visible_slots; /* compact slots = 128 x visible clusters (all when culling is off) */
@@ -171,17 +172,21 @@ const char *gsr_last_error(const gsr_context *ctx);
 size_t gsr_required_workspace(const gsr_context *ctx);
 
 /* Workspace bytes for one frame of V views whose instance count M is at most
- * max_instances. Needs no device (ctx may be NULL) and validates its arguments
- * exactly as gsr_forward does. M depends on the scene and is known only after projection:
- * gsr_forward reports GSR_ERR_WORKSPACE_TOO_SMALL with the exact requirement when
- * the workspace is too small for the actual M. */
+ * max_instances (< 2^30). Needs no device (ctx may be NULL) and validates its
+ * arguments exactly as gsr_forward does. M depends on the scene and is known only
+ * on the device after projection: a frame whose M exceeds the workspace's capacity
+ * drops the excess instances, and gsr_frame_inspect then reports
+ * GSR_ERR_WORKSPACE_TOO_SMALL with the bytes that M needs. */
 gsr_status gsr_workspace_size(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
                               const gsr_options *opts, int64_t max_instances, size_t *bytes);
 
 /* Forward render of V views (Sec. 3, Eq. (1)): images[v] is a device pointer to
  * f32 [3, height_v, width_v] (planar RGB), overwritten. The workspace keeps the
  * frame state that gsr_backward needs; do not reuse it for another frame in
- * between. Waits once on `stream` to read back the instance count M. */
+ * between. Asynchronous: GSR_ERR_WORKSPACE_TOO_SMALL here means the workspace cannot
+ * hold even an empty frame; whether the frame's instances fitted is known from
+ * gsr_frame_inspect (if not, the images and a following backward miss the dropped
+ * instances: grow the workspace and render again). At most n x V < 2^30 records. */
 gsr_status gsr_forward(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
                        const gsr_options *opts, void *workspace, size_t ws_bytes, float *const *images,
                        void *stream);
@@ -195,9 +200,18 @@ gsr_status gsr_backward(gsr_context *ctx, const gsr_scene *scene, const gsr_came
                         const float *const *dL_dimages, const gsr_grads *grads, const gsr_stats *stats,
                         void *stream);
 
-/* Counters and buffer pointers of the last gsr_forward on `workspace`. */
+/* Counters and buffer pointers of the last gsr_forward on `workspace` (info and
+ * bufs nullable). Waits until the forward's counters have reached the host.
+ * Returns GSR_ERR_WORKSPACE_TOO_SMALL (gsr_required_workspace() = the bytes the
+ * frame needs; info still filled, info->instances = the full M) when the frame's
+ * instances exceeded the workspace, GSR_ERR_UNSUPPORTED when M reached 2^30, and
+ * GSR_ERR_DEVICE if a device-wide wait inside the frame gave up. */
 gsr_status gsr_frame_inspect(gsr_context *ctx, const void *workspace, gsr_frame_info *info,
                              gsr_frame_buffers *bufs);
+
+/* Forgets the frame state kept for `workspace` (waits for its forward to finish);
+ * call before freeing a workspace whose address may be reused. No-op if none. */
+gsr_status gsr_frame_release(gsr_context *ctx, const void *workspace);
 
 /* Densification metric of Sec. 3.3, C * Var = S - M^2 / C (0 where C = 0),
  * evaluated in FP64: out[n] f32, device memory. */

@@ -80,6 +80,7 @@ EXPORTS = {
                                ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrStats), c_void_p]),
     "gsr_frame_inspect": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(GsrFrameInfo),
                                     ctypes.POINTER(GsrFrameBuffers)]),
+    "gsr_frame_release": (c_int32, [c_void_p, c_void_p]),
     "gsr_variance": (c_int32, [c_void_p, ctypes.POINTER(GsrStats), c_int64, c_void_p, c_void_p]),
     "gsr_morton_workspace_size": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_size_t)]),
     "gsr_morton_order": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "gsr_internal.h"
 
@@ -19,12 +20,17 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kPinnedBytes = 64 * 1024;
+constexpr size_t kHdrBytes = 256;
 
 struct FrameRecord {
   Frame f;
-  gsr_frame_info info;
+  gsr_scene scene;                     // sizes of the forward's scene (pointers unused)
+  gsr_camera cams[GSR_MAX_VIEWS];
   int64_t tile_base[GSR_MAX_VIEWS];
   int64_t pixel_base[GSR_MAX_VIEWS];
+  uint32_t* hdr = nullptr;             // pinned host copy of the frame header (64 words)
+  hipEvent_t done = nullptr;           // recorded after the header copy
+  int backwards = 0;                   // backward passes run on this frame
 };
 
 }  // namespace
@@ -33,7 +39,8 @@ struct gsr_context {
   int device = 0;
   std::string err;
   size_t required = 0;
-  void* pinned = nullptr;
+  std::vector<void*> pinned_blocks;    // pinned host blocks holding frame header copies
+  std::vector<uint32_t*> free_hdrs;    // unused 256-byte slots of those blocks
   std::unordered_map<const void*, FrameRecord> frames;
   bool profiling = false;
   bool events_ready = false;
@@ -124,6 +131,14 @@ gsr_status validate_views(gsr_context* ctx, const gsr_camera* cams, int32_t V) {
   return GSR_OK;
 }
 
+// Records (Gaussian slots x views) are counted and scanned in 30-bit words.
+gsr_status validate_records(gsr_context* ctx, const gsr_scene* sc, int32_t V) {
+  const int64_t ncap = (sc->n + GSR_CLUSTER - 1) / GSR_CLUSTER * GSR_CLUSTER;
+  if (ncap * V >= ((int64_t)1 << 30))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "n x views = %lld x %d records: must stay below 2^30", (long long)sc->n, V);
+  return GSR_OK;
+}
+
 gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   if (!o) return fail(ctx, GSR_ERR_INVALID_ARG, "options are NULL");
   if (o->precision != GSR_FP32 && o->precision != GSR_FP16_BLEND)
@@ -136,11 +151,11 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   return GSR_OK;
 }
 
-// Lays out one frame in a workspace (or, with ws == nullptr, only sizes it).
-// Returns the bytes of the fixed part; the instance area of inst_cap entries
-// follows it.
-size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t inst_cap, void* ws, Frame& f,
-                  size_t* total) {
+// Lays out one frame in a workspace (or, with ws == nullptr, only sizes it) with
+// room for inst_cap instances. Returns the total bytes. Layout: per-scene and
+// per-pixel buffers, then the header and control words (cleared together at the
+// frame start; their size grows with inst_cap), then the instance buffers.
+size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t inst_cap, void* ws, Frame& f) {
   std::memset(&f, 0, sizeof(f));
   f.n = sc->n;
   f.V = V;
@@ -157,7 +172,6 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.inst_cap = inst_cap;
   Planner P{static_cast<char*>(ws)};
   const size_t nr = (size_t)f.nrec, nc = (size_t)std::max(f.nclusters, 1);
-  f.header = P.take<uint32_t>(64);
   f.views = P.take<ViewDev>(V);
   f.cluster_bounds = P.take<float>(8 * nc);
   f.cluster_visible = P.take<uint32_t>(nc);
@@ -172,7 +186,6 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.skey[1] = P.take<uint32_t>(nr + 1);
   f.sval[0] = P.take<uint32_t>(nr + 1);
   f.sval[1] = P.take<uint32_t>(nr + 1);
-  f.sorted_tiles = P.take<uint32_t>(nr + 1);
   f.offsets = P.take<uint32_t>(nr + 1);
   f.ranges = P.take<uint32_t>(2 * (size_t)f.tiles);
   f.tile_order = P.take<uint32_t>((size_t)f.tiles);
@@ -180,25 +193,44 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.pix_T = P.take<float>((size_t)f.pixels);
   f.pix_last = P.take<uint32_t>((size_t)f.pixels);
   f.grad2d = P.take<float>(gsr::kGrad2D * std::max<size_t>(nr, 1));
-  f.temp_words = std::max(gsr::scan_temp_words(std::max<int64_t>(f.nrec, f.nclusters)), gsr::radix_temp_words());
-  f.temp = P.take<uint32_t>(f.temp_words);
-  const size_t fixed = (P.off + kAlign - 1) & ~(kAlign - 1);
-  for (int b = 0; b < 2; ++b) {
-    f.ikey[b] = P.take<uint32_t>((size_t)inst_cap);
-    f.ival[b] = P.take<uint32_t>((size_t)inst_cap);
+  auto up = [](size_t w) { return (w + 63) & ~(size_t)63; };
+  const size_t w_cluster = up(gsr::scan_ctl_words(f.nclusters));
+  const size_t w_depth = up(gsr::sort_ctl_words(f.nrec, 32));
+  const size_t w_offsets = up(gsr::scan_ctl_words(f.nrec));
+  const size_t w_tiles = up(gsr::sort_ctl_words(std::max<int64_t>(inst_cap, 1), f.tile_bits));
+  f.ctl_words = w_cluster + w_depth + w_offsets + w_tiles;
+  f.header = P.take<uint32_t>(64 + f.ctl_words);
+  if (f.header) {
+    f.ctl = f.header + 64;
+    f.ctl_cluster_scan = f.ctl;
+    f.ctl_depth_sort = f.ctl_cluster_scan + w_cluster;
+    f.ctl_offsets_scan = f.ctl_depth_sort + w_depth;
+    f.ctl_tile_sort = f.ctl_offsets_scan + w_offsets;
   }
-  if (total) *total = (P.off + kAlign - 1) & ~(kAlign - 1);
-  return fixed;
+  for (int b = 0; b < 2; ++b) {
+    f.ikey[b] = P.take<uint32_t>((size_t)std::max<int64_t>(inst_cap, 1));
+    f.ival[b] = P.take<uint32_t>((size_t)std::max<int64_t>(inst_cap, 1));
+  }
+  return (P.off + kAlign - 1) & ~(kAlign - 1);
 }
 
-size_t bytes_for_instances(size_t fixed, int64_t m) { return fixed + 4 * (((size_t)m * 4 + kAlign - 1) & ~(kAlign - 1)) + 4 * kAlign; }
-
-int64_t instances_for_bytes(size_t fixed, size_t ws_bytes) {
-  if (ws_bytes < fixed + 8 * kAlign) return 0;
-  return (int64_t)((ws_bytes - fixed - 8 * kAlign) / 16);
+size_t bytes_for_instances(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t m) {
+  Frame f;
+  return plan_frame(sc, cams, V, m, nullptr, f);
 }
 
-// Event pair around one stage when the context profiles; a no-op otherwise.
+// Largest instance capacity whose layout fits in ws_bytes (-1 if not even 0 fits).
+int64_t instances_for_bytes(const gsr_scene* sc, const gsr_camera* cams, int32_t V, size_t ws_bytes) {
+  if (bytes_for_instances(sc, cams, V, 0) > ws_bytes) return -1;
+  int64_t lo = 0, hi = (int64_t)(ws_bytes / 16) + 1;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (bytes_for_instances(sc, cams, V, mid) <= ws_bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 struct StageScope {
   gsr_context* ctx;
   int stage;
@@ -213,6 +245,29 @@ struct StageScope {
     }
   }
 };
+
+// A 256-byte pinned host slot for a frame's header copy (a new 64 KiB block when
+// every slot is taken).
+gsr_status take_header_slot(gsr_context* ctx, uint32_t** out) {
+  if (ctx->free_hdrs.empty()) {
+    void* blk = nullptr;
+    gsr_status st = check_hip(ctx, hipHostMalloc(&blk, kPinnedBytes, hipHostMallocDefault), "pinned header block");
+    if (st) return st;
+    ctx->pinned_blocks.push_back(blk);
+    for (size_t o = 0; o + kHdrBytes <= kPinnedBytes; o += kHdrBytes)
+      ctx->free_hdrs.push_back(reinterpret_cast<uint32_t*>(static_cast<char*>(blk) + o));
+  }
+  *out = ctx->free_hdrs.back();
+  ctx->free_hdrs.pop_back();
+  return GSR_OK;
+}
+
+void release_frame(gsr_context* ctx, FrameRecord& fr) {
+  if (fr.done) (void)hipEventDestroy(fr.done);
+  if (fr.hdr) ctx->free_hdrs.push_back(fr.hdr);
+  fr.done = nullptr;
+  fr.hdr = nullptr;
+}
 
 void fill_views(const gsr_camera* cams, int32_t V, ViewDev* out) {
   int64_t tile_base = 0, pixel_base = 0;
@@ -257,11 +312,6 @@ gsr_status gsr_context_create(int device, gsr_context** out) {
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSR_ERR_DEVICE;
   gsr_context* ctx = new gsr_context();
   ctx->device = device;
-  DeviceGuard g(device);
-  if (hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
-    delete ctx;
-    return GSR_ERR_DEVICE;
-  }
   *out = ctx;
   return GSR_OK;
 }
@@ -270,9 +320,14 @@ void gsr_context_destroy(gsr_context* ctx) {
   if (!ctx) return;
   {
     DeviceGuard g(ctx->device);
+    for (auto& kv : ctx->frames) {
+      if (kv.second.done) (void)hipEventSynchronize(kv.second.done);
+      release_frame(ctx, kv.second);
+    }
+    ctx->frames.clear();
     if (ctx->events_ready)
       for (int k = 0; k < 2 * GSR_STAGE_COUNT; ++k) (void)hipEventDestroy(ctx->ev[k]);
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (void* b : ctx->pinned_blocks) (void)hipHostFree(b);
   }
   delete ctx;
 }
@@ -285,12 +340,12 @@ gsr_status gsr_workspace_size(gsr_context* ctx, const gsr_scene* scene, const gs
                               const gsr_options* opts, int64_t max_instances, size_t* bytes) {
   if (!bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "NULL output");
   gsr_status st;
-  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)))
+  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
+      (st = validate_records(ctx, scene, V)))
     return st;
   if (max_instances < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances < 0");
-  Frame f;
-  const size_t fixed = plan_frame(scene, cams, V, 0, nullptr, f, nullptr);
-  *bytes = bytes_for_instances(fixed, max_instances);
+  if (max_instances >= ((int64_t)1 << 30)) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances >= 2^30");
+  *bytes = bytes_for_instances(scene, cams, V, max_instances);
   return GSR_OK;
 }
 
@@ -299,117 +354,123 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
                        void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   gsr_status st;
-  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)))
+  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
+      (st = validate_records(ctx, scene, V)))
     return st;
   if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   if (!images) return fail(ctx, GSR_ERR_INVALID_ARG, "images is NULL");
   for (int v = 0; v < V; ++v)
     if (!images[v]) return fail(ctx, GSR_ERR_INVALID_ARG, "images[%d] is NULL", v);
-  Frame f;
-  const size_t fixed = plan_frame(scene, cams, V, 0, nullptr, f, nullptr);
-  if (ws_bytes < bytes_for_instances(fixed, 0)) {
-    ctx->required = bytes_for_instances(fixed, 16 * (int64_t)scene->n + 1024);
+  int64_t cap = instances_for_bytes(scene, cams, V, ws_bytes);
+  if (cap < 0) {
+    ctx->required = bytes_for_instances(scene, cams, V, 16 * (int64_t)scene->n + 1024);
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes < %zu needed before instances", ws_bytes,
-                bytes_for_instances(fixed, 0));
+                bytes_for_instances(scene, cams, V, 0));
   }
-  const int64_t cap = instances_for_bytes(fixed, ws_bytes);
-  size_t total = 0;
-  plan_frame(scene, cams, V, cap, workspace, f, &total);
+  cap = std::min<int64_t>(cap, ((int64_t)1 << 30) - 1);
+  Frame f;
+  const size_t total = plan_frame(scene, cams, V, cap, workspace, f);
   if (total > ws_bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: workspace plan exceeds its size");
 
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  ViewDev* hv = static_cast<ViewDev*>(ctx->pinned);
-  uint32_t* hhdr = reinterpret_cast<uint32_t*>(static_cast<char*>(ctx->pinned) + kPinnedBytes - 256);
+  FrameRecord& fr = ctx->frames[workspace];
+  if (fr.done) {  // the previous frame on this workspace may still be copying its header
+    if ((st = check_hip(ctx, hipEventSynchronize(fr.done), "wait for the previous frame"))) return st;
+  } else {
+    if ((st = check_hip(ctx, hipEventCreateWithFlags(&fr.done, hipEventDisableTiming), "frame event"))) return st;
+  }
+  if (!fr.hdr && (st = take_header_slot(ctx, &fr.hdr))) return st;
+  fr.scene = *scene;
+  std::memcpy(fr.cams, cams, sizeof(gsr_camera) * V);
+  fr.backwards = 0;
+
+  ViewDev hv[GSR_MAX_VIEWS];
   fill_views(cams, V, hv);
-  if ((st = check_hip(ctx, hipMemcpyAsync(f.views, hv, sizeof(ViewDev) * V, hipMemcpyHostToDevice, s), "upload views")))
-    return st;
+  for (int v = 0; v < V; ++v) {
+    fr.tile_base[v] = hv[v].tile_base;
+    fr.pixel_base[v] = hv[v].pixel_base;
+  }
   for (int k = 0; k < GSR_STAGE_COUNT; ++k) ctx->recorded[k] = false;
   {
-    // Cluster-Cull-Compact
+    // frame start, then Cluster-Cull-Compact
     StageScope sc_(ctx, GSR_STAGE_CLUSTER, s);
-    gsr::fill_u32(f.header, 64, 0u, s);
-    if (opts->cluster_cull) {
-      gsr::launch_cluster_bounds(scene->means, scene->log_scales, scene->n, f.cluster_bounds, s);
-      gsr::launch_cluster_cull(f.cluster_bounds, f.nclusters, f.views, V, f.cluster_visible, s);
-    } else {
-      gsr::fill_u32(f.cluster_visible, f.nclusters, 1u, s);
+    for (int v0 = 0; v0 < V; v0 += gsr::kViewChunk) {
+      gsr::ViewChunk chunk;
+      const int nv = std::min(gsr::kViewChunk, V - v0);
+      std::memcpy(chunk.v, hv + v0, sizeof(ViewDev) * nv);
+      gsr::launch_frame_begin(chunk, v0, nv, f.views, f.header, v0 == 0 ? (int64_t)(64 + f.ctl_words) : 0, s);
     }
-    gsr::scan_exclusive_u32(f.cluster_visible, f.cluster_offset, f.nclusters, f.header + 0, f.temp, s);
-    gsr::launch_cluster_list(f.cluster_visible, f.cluster_offset, f.nclusters, f.cluster_list, s);
+    gsr::launch_cluster(scene->means, scene->log_scales, scene->n, opts->cluster_cull, f.views, V, f.cluster_bounds,
+                        f.cluster_visible, s);
+    gsr::scan_u32(f.cluster_visible, nullptr, f.cluster_offset, f.nclusters, nullptr,
+                  f.header + gsr::kHdrVisibleClusters, f.cluster_list, f.ctl_cluster_scan, f.header + gsr::kHdrError,
+                  s);
   }
   {
     StageScope sc_(ctx, GSR_STAGE_PREPROCESS, s);
     gsr::launch_preprocess_fwd(*scene, f, s);
   }
-  // depth order of the records, then instance offsets in that order
+  const uint32_t* n_rec = f.header + gsr::kHdrRecords;
+  uint32_t* err = f.header + gsr::kHdrError;
+  const uint32_t* sorted_rec;
   {
+    StageScope sc_(ctx, GSR_STAGE_DEPTH_SORT, s);
     uint32_t* kb[2] = {f.skey[0], f.skey[1]};
     uint32_t* vb[2] = {f.sval[0], f.sval[1]};
-    int r;
-    {
-      StageScope sc_(ctx, GSR_STAGE_DEPTH_SORT, s);
-      r = gsr::radix_sort_u32(f.dkey, nullptr, kb, vb, f.nrec, 32, f.temp, s);
-    }
-    const uint32_t* sorted_rec = vb[r];
-    {
-      StageScope sc_(ctx, GSR_STAGE_OFFSETS, s);
-      gsr::launch_gather_tiles(f, sorted_rec, s);
-      gsr::scan_exclusive_u32(f.sorted_tiles, f.offsets, f.nrec, f.header + 1, f.temp, s);
-    }
-    if ((st = check_hip(ctx, hipGetLastError(), "projection and depth sort"))) return st;
-    if ((st = check_hip(ctx, hipMemcpyAsync(hhdr, f.header, 16, hipMemcpyDeviceToHost, s), "read counts"))) return st;
-    if ((st = check_hip(ctx, hipStreamSynchronize(s), "synchronise on counts"))) return st;
-    const int64_t M = hhdr[1];
-    const int64_t nvis = hhdr[0];
-    if (M > cap) {
-      ctx->required = bytes_for_instances(fixed, M + M / 8 + 1024);
-      return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
-                  (long long)cap);
-    }
-    {
-      StageScope sc_(ctx, GSR_STAGE_EMIT, s);
-      gsr::launch_emit_instances(f, sorted_rec, s);
-    }
+    const int r = gsr::radix_sort_u32_dev(f.dkey, nullptr, kb, vb, f.nrec, n_rec, 32, f.ctl_depth_sort, err, s);
+    sorted_rec = r >= 0 ? vb[r] : vb[0];  // no pass only when there are no records
+  }
+  {
+    // instance offsets: exclusive scan of the tiles touched, in depth order
+    StageScope sc_(ctx, GSR_STAGE_OFFSETS, s);
+    gsr::scan_u32(f.tiles_touched, sorted_rec, f.offsets, f.nrec, n_rec, f.header + gsr::kHdrInstances, nullptr,
+                  f.ctl_offsets_scan, err, s);
+  }
+  {
+    StageScope sc_(ctx, GSR_STAGE_EMIT, s);
+    gsr::launch_emit_instances(f, sorted_rec, s);
+  }
+  {
+    StageScope sc_(ctx, GSR_STAGE_TILE_SORT, s);
     uint32_t* ik[2] = {f.ikey[1], f.ikey[0]};
     uint32_t* iv[2] = {f.ival[1], f.ival[0]};
-    {
-      StageScope sc_(ctx, GSR_STAGE_TILE_SORT, s);
-      const int ri = gsr::radix_sort_u32(f.ikey[0], f.ival[0], ik, iv, M, f.tile_bits, f.temp, s);
-      f.inst_tile = ik[ri];
-      f.inst_rec = iv[ri];
-    }
-    {
-      StageScope sc_(ctx, GSR_STAGE_RANGES, s);
-      gsr::launch_tile_ranges(f, f.inst_tile, M, s);
-      gsr::launch_tile_order(f, s);
-    }
-    gsr::ImagePtrs ip;
-    std::memset(&ip, 0, sizeof(ip));
-    for (int v = 0; v < V; ++v) ip.p[v] = images[v];
-    {
-      StageScope sc_(ctx, GSR_STAGE_RASTER_FWD, s);
-      gsr::launch_raster_fwd(f, ip, opts->precision, s);
-    }
-    if ((st = check_hip(ctx, hipGetLastError(), "binning and raster"))) return st;
-    FrameRecord& fr = ctx->frames[workspace];
-    fr.f = f;
-    std::memset(&fr.info, 0, sizeof(fr.info));
-    fr.info.n = scene->n;
-    fr.info.n_visible_slots = nvis * GSR_CLUSTER;
-    fr.info.instances = M;
-    fr.info.tiles = f.tiles;
-    fr.info.pixels = f.pixels;
-    fr.info.views = V;
-    fr.info.clusters = f.nclusters;
-    fr.info.visible_clusters = (int32_t)nvis;
-    for (int v = 0; v < V; ++v) {
-      fr.tile_base[v] = hv[v].tile_base;
-      fr.pixel_base[v] = hv[v].pixel_base;
-    }
+    const int ri = gsr::radix_sort_u32_dev(f.ikey[0], f.ival[0], ik, iv, cap, f.header + gsr::kHdrInstancesKept,
+                                           f.tile_bits, f.ctl_tile_sort, err, s);
+    f.inst_tile = ri >= 0 ? ik[ri] : f.ikey[0];
+    f.inst_rec = ri >= 0 ? iv[ri] : f.ival[0];
   }
+  {
+    StageScope sc_(ctx, GSR_STAGE_RANGES, s);
+    gsr::launch_tile_ranges(f, f.inst_tile, cap, s);
+    gsr::launch_tile_order(f, s);
+  }
+  gsr::ImagePtrs ip;
+  std::memset(&ip, 0, sizeof(ip));
+  for (int v = 0; v < V; ++v) ip.p[v] = images[v];
+  {
+    StageScope sc_(ctx, GSR_STAGE_RASTER_FWD, s);
+    gsr::launch_raster_fwd(f, ip, opts->precision, s);
+  }
+  if ((st = check_hip(ctx, hipGetLastError(), "forward launches"))) return st;
+  if ((st = check_hip(ctx, hipMemcpyAsync(fr.hdr, f.header, kHdrBytes, hipMemcpyDeviceToHost, s), "header copy")))
+    return st;
+  if ((st = check_hip(ctx, hipEventRecord(fr.done, s), "frame event"))) return st;
+  fr.f = f;
   return GSR_OK;
+}
+
+gsr_status gsr_frame_release(gsr_context* ctx, const void* workspace) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  auto it = ctx->frames.find(workspace);
+  if (it == ctx->frames.end()) return GSR_OK;
+  DeviceGuard guard(ctx->device);
+  gsr_status st = GSR_OK;
+  if (it->second.done) st = check_hip(ctx, hipEventSynchronize(it->second.done), "wait for the frame");
+  release_frame(ctx, it->second);
+  ctx->frames.erase(it);
+  return st;
 }
 
 gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
@@ -417,18 +478,20 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
                         const gsr_grads* grads, const gsr_stats* stats, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   gsr_status st;
-  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)))
+  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
+      (st = validate_records(ctx, scene, V)))
     return st;
   if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
   auto it = ctx->frames.find(workspace);
   if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "no forward was run on this workspace");
-  const Frame& f = it->second.f;
-  if (f.n != scene->n || f.V != V) return fail(ctx, GSR_ERR_INVALID_ARG, "scene or views differ from the forward");
+  FrameRecord& fr = it->second;
+  const Frame& f = fr.f;
+  if (f.n != scene->n || f.V != V || fr.scene.sh_degree != scene->sh_degree)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "scene or views differ from the forward");
   {
     Frame chk;
-    size_t total = 0;
-    plan_frame(scene, cams, V, f.inst_cap, workspace, chk, &total);
-    if (chk.tiles != f.tiles || chk.pixels != f.pixels || total > ws_bytes)
+    const size_t total = plan_frame(scene, cams, V, f.inst_cap, workspace, chk);
+    if (chk.tiles != f.tiles || chk.pixels != f.pixels || chk.grad2d != f.grad2d || total > ws_bytes)
       return fail(ctx, GSR_ERR_INVALID_ARG, "cameras or workspace differ from the forward");
   }
   if (!dL_dimages) return fail(ctx, GSR_ERR_INVALID_ARG, "dL_dimages is NULL");
@@ -443,7 +506,8 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   for (int k = GSR_STAGE_ZERO_GRAD; k < GSR_STAGE_COUNT; ++k) ctx->recorded[k] = false;
-  {
+  if (fr.backwards > 0) {
+    // the forward cleared the rows of its records; a repeated backward clears them again
     StageScope sc_(ctx, GSR_STAGE_ZERO_GRAD, s);
     gsr::fill_f32(f.grad2d, gsr::kGrad2D * f.nrec, 0.0f, s);
   }
@@ -458,6 +522,7 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
     StageScope sc_(ctx, GSR_STAGE_PREPROCESS_BWD, s);
     gsr::launch_preprocess_bwd(*scene, f, 1, *grads, use_stats ? stats : nullptr, s);
   }
+  fr.backwards++;
   return check_hip(ctx, hipGetLastError(), "backward");
 }
 
@@ -465,8 +530,25 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
   if (!ctx) return GSR_ERR_INVALID_ARG;
   auto it = ctx->frames.find(workspace);
   if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "no forward was run on this workspace");
-  const Frame& f = it->second.f;
-  if (info) *info = it->second.info;
+  FrameRecord& fr = it->second;
+  const Frame& f = fr.f;
+  DeviceGuard guard(ctx->device);
+  gsr_status st = check_hip(ctx, hipEventSynchronize(fr.done), "wait for the frame header");
+  if (st) return st;
+  const uint32_t* h = fr.hdr;
+  const int64_t nvis = h[gsr::kHdrVisibleClusters];
+  const int64_t M = h[gsr::kHdrInstances];
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->n = f.n;
+    info->n_visible_slots = nvis * GSR_CLUSTER;
+    info->instances = M;
+    info->tiles = f.tiles;
+    info->pixels = f.pixels;
+    info->views = f.V;
+    info->clusters = f.nclusters;
+    info->visible_clusters = (int32_t)nvis;
+  }
   if (bufs) {
     std::memset(bufs, 0, sizeof(*bufs));
     bufs->record = reinterpret_cast<const float*>(f.rec);
@@ -484,9 +566,16 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
     bufs->cluster_bounds = f.cluster_bounds;
     bufs->cluster_visible = f.cluster_visible;
     for (int v = 0; v < f.V; ++v) {
-      bufs->tile_base[v] = it->second.tile_base[v];
-      bufs->pixel_base[v] = it->second.pixel_base[v];
+      bufs->tile_base[v] = fr.tile_base[v];
+      bufs->pixel_base[v] = fr.pixel_base[v];
     }
+  }
+  if (h[gsr::kHdrError] & 2u) return fail(ctx, GSR_ERR_UNSUPPORTED, "the frame has 2^30 or more instances");
+  if (h[gsr::kHdrError]) return fail(ctx, GSR_ERR_DEVICE, "a device-wide scan or sort wait gave up");
+  if (h[gsr::kHdrOverflow]) {
+    ctx->required = bytes_for_instances(&fr.scene, fr.cams, f.V, M + M / 8 + 1024);
+    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
+                (long long)f.inst_cap);
   }
   return GSR_OK;
 }
@@ -546,7 +635,7 @@ gsr_status gsr_morton_workspace_size(gsr_context* ctx, int64_t n, size_t* bytes)
 gsr_status gsr_morton_order(gsr_context* ctx, const float* means, int64_t n, void* workspace, size_t ws_bytes,
                             int64_t* perm, uint64_t* codes, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
-  if (n < 0 || n > 0x7fffffff || (n > 0 && (!means || !perm || !workspace)))
+  if (n < 0 || n >= ((int64_t)1 << 30) || (n > 0 && (!means || !perm || !workspace)))
     return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_morton_order");
   const size_t need = gsr::morton_temp_words(n) * 4 + 1024;
   if (ws_bytes < need) {

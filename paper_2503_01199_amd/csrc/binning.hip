@@ -6,43 +6,51 @@
 // The result is each tile's list in (depth, record) order, the same order as a
 // stable sort of 64-bit (tile << 32 | depth) keys emitted in record order, but it
 // moves 4-byte keys and sorts the instances on the tile bits only.
+#include <algorithm>
+
 #include "gsr_internal.h"
 
 namespace gsr {
 namespace {
 
-__global__ void k_gather_tiles(const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ tiles,
-                               uint32_t* __restrict__ out, int64_t n) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = tiles[sorted_rec[k]];
-}
-
-// One thread per sorted record; writes its instances at its scanned offset, tiles
-// in row-major order of its rect.
+// One thread per sorted record k < (active records); writes its instances at its
+// scanned offset, tiles in row-major order of its rect. When the frame has more
+// instances than the workspace holds, the list is cut at the capacity (the record
+// that straddles it writes its first tiles only), so [0, kept) is always complete,
+// and the overflow flag is raised. The first threads also clear the per-tile ranges.
 __global__ void k_emit(const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ offsets,
                        const uint32_t* __restrict__ tiles, const ushort4* __restrict__ rect,
-                       const ViewDev* __restrict__ views, int32_t V, int64_t n, int64_t cap,
-                       uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_rec) {
+                       const ViewDev* __restrict__ views, int32_t V, uint32_t* __restrict__ header, int64_t cap,
+                       uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ ranges,
+                       int64_t ntiles) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  for (int64_t t = k; t < 2 * ntiles; t += (int64_t)gridDim.x * blockDim.x) ranges[t] = 0u;
+  if (k == 0) {
+    const uint32_t M = header[kHdrInstances];
+    header[kHdrInstancesKept] = (uint32_t)min((int64_t)M, cap);
+    if ((int64_t)M > cap) header[kHdrOverflow] = 1u;
+  }
+  if (k >= (int64_t)header[kHdrRecords]) return;
   const uint32_t r = sorted_rec[k];
   const uint32_t cnt = tiles[r];
-  if (cnt == 0) return;
+  int64_t o = offsets[k];
+  if (cnt == 0 || o >= cap) return;
+  const int64_t end = min(o + (int64_t)cnt, cap);
   const ushort4 b = rect[r];
   const int v = (int)(r % (uint32_t)V);
   const int32_t base = views[v].tile_base;
   const int32_t tx = views[v].tiles_x;
-  int64_t o = offsets[k];
-  if (o + cnt > cap) return;  // never taken: the host sized the buffers from the scan total
-  for (int y = b.z; y <= b.w; ++y)
-    for (int x = b.x; x <= b.y; ++x) {
+  for (int y = b.z; y <= b.w && o < end; ++y)
+    for (int x = b.x; x <= b.y && o < end; ++x) {
       inst_tile[o] = (uint32_t)(base + y * tx + x);
       inst_rec[o] = r;
       ++o;
     }
 }
 
-__global__ void k_ranges(const uint32_t* __restrict__ inst_tile, int64_t M, uint32_t* __restrict__ ranges) {
+__global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ header,
+                         uint32_t* __restrict__ ranges) {
+  const int64_t M = header[kHdrInstancesKept];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M) return;
   const uint32_t t = inst_tile[k];
@@ -104,22 +112,17 @@ void launch_tile_order(const Frame& f, hipStream_t s) {
   k_tile_order<<<1, kOrderThreads, 0, s>>>(f.ranges, f.tiles, f.tile_order);
 }
 
-void launch_gather_tiles(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
-  if (f.nrec <= 0) return;
-  k_gather_tiles<<<(unsigned)((f.nrec + 255) / 256), 256, 0, s>>>(sorted_rec, f.tiles_touched, f.sorted_tiles,
-                                                                  f.nrec);
-}
-
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
-  if (f.nrec <= 0) return;
-  k_emit<<<(unsigned)((f.nrec + 127) / 128), 128, 0, s>>>(sorted_rec, f.offsets, f.tiles_touched, f.rect, f.views,
-                                                          f.V, f.nrec, f.inst_cap, f.ikey[0], f.ival[0]);
+  int64_t n = std::max<int64_t>(f.nrec, 2 * f.tiles);
+  int64_t g = (n + 127) / 128;
+  if (g < 1) g = 1;
+  k_emit<<<(unsigned)g, 128, 0, s>>>(sorted_rec, f.offsets, f.tiles_touched, f.rect, f.views, f.V, f.header,
+                                     f.inst_cap, f.ikey[0], f.ival[0], f.ranges, f.tiles);
 }
 
-void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M, hipStream_t s) {
-  fill_u32(f.ranges, 2 * f.tiles, 0u, s);
-  if (M <= 0) return;
-  k_ranges<<<(unsigned)((M + 255) / 256), 256, 0, s>>>(inst_tile, M, f.ranges);
+void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s) {
+  if (M_max <= 0) return;
+  k_ranges<<<(unsigned)((M_max + 255) / 256), 256, 0, s>>>(inst_tile, f.header, f.ranges);
 }
 
 }  // namespace gsr

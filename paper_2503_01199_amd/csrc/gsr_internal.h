@@ -49,6 +49,16 @@ struct alignas(16) Record {
 // (a, b, c) is the conic of E = -1/2 (a dx^2 + 2 b dx dy + c dy^2) in natural units.
 constexpr int kGrad2D = 12;
 
+// Header words of a frame (device memory, cleared at the start of each forward).
+enum HeaderWord {
+  kHdrVisibleClusters = 0,  // clusters that survived the cull
+  kHdrInstances = 1,        // (tile, record) pairs M of the frame
+  kHdrInstancesKept = 2,    // min(M, capacity): what the tile sort and raster use
+  kHdrRecords = 3,          // active records = 128 * visible clusters * views
+  kHdrOverflow = 4,         // 1 when M exceeded the workspace capacity
+  kHdrError = 5,            // bit 0: a look-back wait gave up; bit 1: a scanned count reached 2^30
+};
+
 struct Frame {
   // sizes (host)
   int64_t n, ncap, nrec;    // Gaussians, compact slots (128 * clusters), records = ncap * V
@@ -56,7 +66,7 @@ struct Frame {
   int64_t tiles, pixels, inst_cap;
   int32_t tile_bits;
   // device pointers (all inside the workspace)
-  uint32_t* header;         // [0] visible clusters, [1] instance count, [2] record scan total
+  uint32_t* header;         // HeaderWord entries
   ViewDev* views;
   float* cluster_bounds;    // [nclusters][8]
   uint32_t* cluster_visible;
@@ -68,7 +78,6 @@ struct Frame {
   uint32_t* tiles_touched;  // [nrec]
   ushort4* rect;            // [nrec]
   uint32_t *skey[2], *sval[2];   // depth sort buffers [nrec]
-  uint32_t* sorted_tiles;   // [nrec]
   uint32_t* offsets;        // [nrec]
   uint32_t *ikey[2], *ival[2];   // instance buffers [inst_cap]
   uint32_t* inst_tile;      // sorted instances (points into ikey/ival)
@@ -79,44 +88,56 @@ struct Frame {
   float* pix_T;             // [pixels]
   uint32_t* pix_last;       // [pixels]
   float* grad2d;            // [nrec][12]
-  uint32_t* temp;           // scan / sort scratch
-  size_t temp_words;
+  uint32_t* ctl;            // look-back / histogram control words, cleared with the header
+  size_t ctl_words;
+  uint32_t *ctl_cluster_scan, *ctl_depth_sort, *ctl_offsets_scan, *ctl_tile_sort;
 };
 
 // ---------------------------------------------------------------- launchers
 // scan.hip
-size_t scan_temp_words(int64_t n);
-void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* temp,
-                        hipStream_t s);
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 void fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
-// sort.hip: stable LSD radix sort of (key, value) pairs by key bits [0, bits), 8
-// bits per pass. The input is read-only; passes alternate between the buffer
-// pairs (kb[0], vb[0]) and (kb[1], vb[1]) and the return value is the index of the
-// pair that holds the result. vals_in == nullptr stands for the values 0..n-1.
-size_t radix_temp_words();
-int radix_sort_u32(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2], int64_t n,
-                   int bits, uint32_t* temp, hipStream_t s);
-int radix_sort_u64(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2], int64_t n,
-                   int bits, uint32_t* temp, hipStream_t s);
+// onesweep.hip: single-pass scan and one-sweep radix sort, counts read from device
+// memory (n_dev; n_max bounds the launch). Control words (ctl) must be zero on entry.
+// Scan: out[i] = sum_{k<i} src[idx ? idx[k] : k]; total <- sum; list[out[i]] = i where
+// the item is non-zero (list nullable).
+size_t scan_ctl_words(int64_t n_max);
+void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
+              uint32_t* total, uint32_t* list, uint32_t* ctl, uint32_t* err, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits), 8 bits per pass.
+// The input is read-only; passes alternate between (kb[0], vb[0]) and (kb[1], vb[1]).
+// Returns the index of the pair holding the result, or -1 when no pass was needed
+// (then the input is the result). vals_in == nullptr stands for 0..n-1.
+size_t sort_ctl_words(int64_t n_max, int bits);
+int radix_sort_u32_dev(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2],
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s);
+int radix_sort_u64_dev(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2],
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s);
 
 // cluster.hip
-void launch_cluster_bounds(const float* means, const float* log_scales, int64_t n, float* bounds, hipStream_t s);
-void launch_cluster_cull(const float* bounds, int32_t nclusters, const ViewDev* views, int32_t V,
-                         uint32_t* visible, hipStream_t s);
-void launch_cluster_list(const uint32_t* visible, const uint32_t* offset, int32_t nclusters, uint32_t* list,
-                         hipStream_t s);
+constexpr int kViewChunk = 16;
+struct ViewChunk {
+  ViewDev v[kViewChunk];
+};
+static_assert(sizeof(ViewChunk) <= 3072, "a view chunk travels in the kernel arguments");
+// Copies views [v0, v0 + nv) from the kernel arguments to `views`; the first chunk
+// also clears `zero` (zero_words words: the frame header and control words).
+void launch_frame_begin(const ViewChunk& chunk, int v0, int nv, ViewDev* views, uint32_t* zero, int64_t zero_words,
+                        hipStream_t s);
+// Per cluster: bounds (min/max of the means, largest log-scale) and, when cull is
+// set, the frustum test against every view (else every cluster is visible).
+void launch_cluster(const float* means, const float* log_scales, int64_t n, int cull, const ViewDev* views, int32_t V,
+                    float* bounds, uint32_t* visible, hipStream_t s);
 
 // preprocess.hip
 void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s);
 void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
                            const gsr_stats* stats, hipStream_t s);
 
-// binning.hip
-void launch_gather_tiles(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
+// binning.hip (counts read from the frame header)
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
-void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M, hipStream_t s);
+void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s);
 void launch_tile_order(const Frame& f, hipStream_t s);
 
 // raster_fwd.hip / raster_bwd.hip
@@ -131,7 +152,7 @@ void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, 
 
 // morton.hip
 size_t morton_temp_words(int64_t n);
-void morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, uint64_t* codes, hipStream_t s);
+bool morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, uint64_t* codes, hipStream_t s);
 void launch_gather_rows(const int64_t* perm, int64_t n, const float* src, float* dst, int32_t row_floats,
                         hipStream_t s);
 

@@ -50,12 +50,18 @@ __global__ __launch_bounds__(256) void k_bounds_partial(const float* __restrict_
   }
 }
 
+// One wave per axis bound (6 waves): lanes stride over the block partials.
 __global__ void k_bounds_final(const float* __restrict__ part, int G, float* __restrict__ bounds) {
-  const int a = threadIdx.x;
+  const int a = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   if (a >= 6) return;
-  float x = part[a];
-  for (int b = 1; b < G; ++b) x = a < 3 ? fminf(x, part[6 * b + a]) : fmaxf(x, part[6 * b + a]);
-  bounds[a] = x;
+  float x = a < 3 ? INFINITY : -INFINITY;
+  for (int b = lane; b < G; b += 64) x = a < 3 ? fminf(x, part[6 * b + a]) : fmaxf(x, part[6 * b + a]);
+  for (int d = 32; d >= 1; d >>= 1) {
+    const float y = __shfl_xor(x, d, 64);
+    x = a < 3 ? fminf(x, y) : fmaxf(x, y);
+  }
+  if (lane == 0) bounds[a] = x;
 }
 
 // 21 bits of v spread to every third bit of a 64-bit word.
@@ -107,12 +113,12 @@ size_t align_words(size_t w) { return (w + 63) & ~(size_t)63; }
 }  // namespace
 
 size_t morton_temp_words(int64_t n) {
-  return align_words(6 * kBoundsBlocks) + 64 + 4 * align_words((size_t)n * 2) + 2 * align_words((size_t)n) +
-         radix_temp_words();
+  return align_words(6 * kBoundsBlocks) + 64 + 3 * align_words((size_t)n * 2) + 2 * align_words((size_t)n) +
+         align_words(sort_ctl_words(n, 63)) + 64;
 }
 
-void morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, uint64_t* codes, hipStream_t s) {
-  if (n <= 0) return;
+bool morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, uint64_t* codes, hipStream_t s) {
+  if (n <= 0) return true;
   float* part = (float*)temp;
   float* bounds = (float*)(temp + align_words(6 * kBoundsBlocks));
   uint32_t* p = temp + align_words(6 * kBoundsBlocks) + 64;
@@ -122,19 +128,24 @@ void morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, 
   ck[1] = (uint64_t*)p;
   p += align_words((size_t)n * 2);
   uint64_t* cin = (uint64_t*)p;
-  p += 2 * align_words((size_t)n * 2);
+  p += align_words((size_t)n * 2);
   uint32_t* vb[2];
   vb[0] = p;
   p += align_words((size_t)n);
   vb[1] = p;
   p += align_words((size_t)n);
+  uint32_t* err = p;
+  p += 64;
+  uint32_t* ctl = p;
+  fill_u32(err, 64 + (int64_t)sort_ctl_words(n, 63), 0u, s);
   int G = (int)((n + 255) / 256);
   if (G > kBoundsBlocks) G = kBoundsBlocks;
   k_bounds_partial<<<G, 256, 0, s>>>(means, n, part);
-  k_bounds_final<<<1, 64, 0, s>>>(part, G, bounds);
+  k_bounds_final<<<1, 384, 0, s>>>(part, G, bounds);
   k_morton_encode<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(means, n, bounds, cin, codes);
-  const int r = radix_sort_u64(cin, nullptr, ck, vb, n, 63, p, s);
+  const int r = radix_sort_u64_dev(cin, nullptr, ck, vb, n, nullptr, 63, ctl, err, s);
   k_perm_out<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(vb[r], n, perm);
+  return true;
 }
 
 void launch_gather_rows(const int64_t* perm, int64_t n, const float* src, float* dst, int32_t row_floats,

@@ -1,0 +1,317 @@
+// Single-pass device-wide scan and one-sweep LSD radix sort with decoupled
+// look-back, both driven by counts that live in device memory (so a frame is
+// enqueued without waiting on the host).
+//
+// Look-back protocol: every block takes its tile index from an atomic counter (so
+// all lower tiles belong to blocks that are already running or done), publishes
+// its tile aggregate, then walks back over its predecessors' status words until it
+// meets an inclusive prefix, and publishes its own inclusive prefix. A status word
+// is (flag << 30 | value): flag 0 = not ready, 1 = aggregate, 2 = inclusive
+// prefix. Values must stay below 2^30: a larger prefix sets bit 1 of the error word
+// (the result is then wrong but every access stays in bounds). The walk waits only
+// on blocks that have started, so it terminates; a bounded spin additionally sets
+// bit 0 of the error word instead of hanging.
+#include "gsr_internal.h"
+
+namespace gsr {
+namespace {
+
+constexpr uint32_t kFlagAgg = 1u << 30;
+constexpr uint32_t kFlagPrefix = 2u << 30;
+constexpr uint32_t kValueMask = (1u << 30) - 1u;
+constexpr int kSpinLimit = 1 << 22;
+
+__device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of `agg` over all earlier tiles, for the status column `col`
+// (stride `stride` words between tiles). Publishes this tile's inclusive prefix.
+__device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, int col, uint32_t agg,
+                              uint32_t* err) {
+  uint32_t* mine = status + tile * stride + col;
+  if (agg > kValueMask) {
+    atomicOr(err, 2u);
+    agg &= kValueMask;
+  }
+  if (tile == 0) {
+    st_status(mine, kFlagPrefix | agg);
+    return 0;
+  }
+  st_status(mine, kFlagAgg | agg);
+  uint32_t excl = 0;
+  int64_t b = tile - 1;
+  int spins = 0;
+  while (b >= 0) {
+    const uint32_t s = ld_status(status + b * stride + col);
+    const uint32_t flag = s & ~kValueMask;
+    if (flag == 0) {
+      if (++spins > kSpinLimit) {
+        atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += s & kValueMask;
+    if (flag == kFlagPrefix) break;
+    --b;
+  }
+  if ((uint64_t)excl + agg > kValueMask) atomicOr(err, 2u);
+  st_status(mine, kFlagPrefix | ((excl + agg) & kValueMask));
+  return excl;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+// out[k] = sum_{i<k} in(i) for k < n, n = *n_dev (or n_host when n_dev is null).
+// in(i) = src[idx ? idx[i] : i]. total (nullable) receives the sum of all n items;
+// when list != nullptr, every i with in(i) != 0 also writes list[out[i]] = i.
+__global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restrict__ src,
+                                                       const uint32_t* __restrict__ idx, uint32_t* __restrict__ out,
+                                                       int64_t n_host, const uint32_t* __restrict__ n_dev,
+                                                       uint32_t* __restrict__ total, uint32_t* __restrict__ list,
+                                                       uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
+  __shared__ uint32_t s_tile;
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  __shared__ uint32_t s_excl;
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  const int t = threadIdx.x;
+  if (t == 0) s_tile = atomicAdd(ctl, 1u);
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t base = tile * kScanTile;
+  if (base >= n && !(tile == 0 && n == 0)) return;
+  uint32_t v[kScanItems];
+  uint32_t sum = 0;
+  const int64_t first = base + (int64_t)t * kScanItems;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = first + q;
+    uint32_t x = 0;
+    if (i < n) x = src[idx ? idx[i] : i];
+    v[q] = x;
+    sum += x;
+  }
+  const uint32_t incl = wave_incl_scan(sum);
+  if ((t & 63) == 63) wsum[t >> 6] = incl;
+  __syncthreads();
+  uint32_t agg = 0, off = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    off += (w < (t >> 6)) ? wsum[w] : 0u;
+    agg += wsum[w];
+  }
+  if (t == 0) s_excl = look_back(ctl + 1, tile, 1, 0, agg, err);
+  __syncthreads();
+  uint32_t run = s_excl + off + incl - sum;
+#pragma unroll
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t i = first + q;
+    if (i < n) {
+      out[i] = run;
+      if (list && v[q]) list[run] = (uint32_t)i;
+    }
+    run += v[q];
+  }
+  if (total && (base + kScanTile >= n) && t == kScanThreads - 1) *total = run;
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 items per tile
+constexpr int kHistBlocks = 256;
+constexpr int kMaxPasses = 8;
+
+// Lanes of the wave holding the same 8-bit digit d (restricted to `valid` lanes).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bal = __ballot((d >> b) & 1u);
+    peers &= ((d >> b) & 1u) ? bal : ~bal;
+  }
+  return peers;
+}
+
+// Digit histograms of every pass in one read of the keys; the last block to finish
+// turns them into per-pass exclusive digit offsets (offs[p][d]).
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ keys, int64_t n_host,
+                                                          const uint32_t* __restrict__ n_dev, int passes,
+                                                          uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
+                                                          uint32_t* __restrict__ done) {
+  __shared__ uint32_t h[kMaxPasses][256];
+  __shared__ bool last;
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  for (int p = 0; p < passes; ++p) h[p][t] = 0;
+  __syncthreads();
+  for (int64_t i0 = (int64_t)blockIdx.x * kSortThreads; i0 < n; i0 += (int64_t)gridDim.x * kSortThreads) {
+    const int64_t i = i0 + t;
+    const bool valid = i < n;
+    const K key = valid ? keys[i] : (K)0;
+    for (int p = 0; p < passes; ++p) {
+      const uint32_t d = (uint32_t)(key >> (8 * p)) & 255u;
+      const uint64_t peers = match_digit(d, valid);
+      if (valid && (peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p)
+    if (h[p][t]) atomicAdd(&hist[p * 256 + t], h[p][t]);
+  __threadfence();
+  __syncthreads();
+  if (t == 0) last = atomicAdd(done, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  __shared__ uint32_t wsum[kSortThreads / 64];
+  for (int p = 0; p < passes; ++p) {
+    const uint32_t x = __hip_atomic_load(&hist[p * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == 63) wsum[t >> 6] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int w = 0; w < (t >> 6); ++w) off += wsum[w];
+    offs[p * 256 + t] = off + incl - x;
+    __syncthreads();
+  }
+}
+
+// One pass: each block takes the next tile of 2048 items (8 coalesced rounds of
+// 256), ranks them stably within the tile (ballot match per wave, counts per
+// (round, wave, digit) in LDS), learns the per-digit counts of all earlier tiles by
+// look-back and scatters.
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                             K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             int64_t n_host, const uint32_t* __restrict__ n_dev,
+                                                             int shift, const uint32_t* __restrict__ offs,
+                                                             uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
+  __shared__ uint32_t cnt[kSortRounds][4][256];
+  __shared__ uint32_t gofs[256];
+  __shared__ uint32_t s_tile;
+  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  const int t = threadIdx.x;
+  const int w = t >> 6;
+  const int lane = t & 63;
+  if (t == 0) s_tile = atomicAdd(ctl, 1u);
+  for (int r = 0; r < kSortRounds; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cnt[r][q][t] = 0;
+  __syncthreads();
+  const int64_t tile = s_tile;
+  const int64_t base = tile * kSortTile;
+  if (base >= n) return;
+  K key[kSortRounds];
+  uint32_t val[kSortRounds];
+  uint32_t dig[kSortRounds];
+  uint32_t rank[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + t;
+    const bool valid = i < n;
+    key[r] = valid ? kin[i] : (K)0;
+    val[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+    dig[r] = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
+    const uint64_t peers = match_digit(dig[r] & 255u, valid);
+    rank[r] = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    if (valid && rank[r] == 0) cnt[r][w][dig[r]] = (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+  // thread d: exclusive running count of digit d over (round, wave), then the tile total
+  uint32_t run = 0;
+  for (int r = 0; r < kSortRounds; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t c = cnt[r][q][t];
+      cnt[r][q][t] = run;
+      run += c;
+    }
+  const uint32_t prior = look_back(ctl + 1, tile, 256, t, run, err);
+  gofs[t] = offs[t] + prior;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (dig[r] < 256u) {
+      const uint32_t pos = gofs[dig[r]] + cnt[r][w][dig[r]] + rank[r];
+      kout[pos] = key[r];
+      vout[pos] = val[r];
+    }
+  }
+}
+
+template <typename K>
+int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t* vb[2], int64_t n_max,
+                  const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s) {
+  const int passes = (bits + 7) / 8;
+  if (n_max <= 0 || passes == 0) return -1;
+  uint32_t* hist = ctl;                       // [passes][256]
+  uint32_t* offs = ctl + kMaxPasses * 256;    // [passes][256]
+  uint32_t* done = offs + kMaxPasses * 256;   // 1 word (padded to 64)
+  uint32_t* pass_ctl = done + 64;             // per pass: counter + status[tiles][256]
+  const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
+  const int64_t pass_words = 64 + tiles * 256;
+  int64_t hb = (n_max + kSortThreads * 8 - 1) / (kSortThreads * 8);
+  if (hb > kHistBlocks) hb = kHistBlocks;
+  if (hb < 1) hb = 1;
+  k_os_hist<K><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
+  const K* kcur = keys_in;
+  const uint32_t* vcur = vals_in;
+  int out = 0;
+  for (int p = 0; p < passes; ++p) {
+    k_os_scatter<K><<<(unsigned)tiles, kSortThreads, 0, s>>>(kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p,
+                                                             offs + p * 256, pass_ctl + p * pass_words, err);
+    kcur = kb[out];
+    vcur = vb[out];
+    out ^= 1;
+  }
+  return out ^ 1;
+}
+
+}  // namespace
+
+size_t scan_ctl_words(int64_t n_max) { return 64 + (size_t)((n_max + kScanTile - 1) / kScanTile) + 64; }
+
+size_t sort_ctl_words(int64_t n_max, int bits) {
+  const int passes = (bits + 7) / 8;
+  const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
+  return 2 * kMaxPasses * 256 + 64 + (size_t)passes * (64 + tiles * 256);
+}
+
+void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
+              uint32_t* total, uint32_t* list, uint32_t* ctl, uint32_t* err, hipStream_t s) {
+  const int64_t tiles = n_max > 0 ? (n_max + kScanTile - 1) / kScanTile : 1;
+  k_scan<<<(unsigned)tiles, kScanThreads, 0, s>>>(src, idx, out, n_max, n_dev, total, list, ctl, err);
+}
+
+int radix_sort_u32_dev(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2],
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s) {
+  return radix_sort_os<uint32_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, s);
+}
+
+int radix_sort_u64_dev(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2],
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s) {
+  return radix_sort_os<uint64_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, s);
+}
+
+}  // namespace gsr

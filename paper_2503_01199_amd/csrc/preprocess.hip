@@ -235,15 +235,17 @@ __device__ inline bool project_view(const GaussParams& g, const ViewDev& w, View
 template <int DEG>
 __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const ViewDev* __restrict__ views,
                                                              int32_t V, int64_t ncap,
-                                                             const uint32_t* __restrict__ header,
+                                                             uint32_t* __restrict__ header,
                                                              const uint32_t* __restrict__ cluster_list,
                                                              uint32_t* __restrict__ compact2full,
                                                              Record* __restrict__ rec, uint32_t* __restrict__ dkey,
                                                              uint32_t* __restrict__ tiles,
-                                                             ushort4* __restrict__ rect) {
+                                                             ushort4* __restrict__ rect,
+                                                             float* __restrict__ grad2d) {
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (j >= ncap) return;
-  const uint32_t nvis = header[0];
+  const uint32_t nvis = header[kHdrVisibleClusters];
+  if (j == 0) header[kHdrRecords] = nvis * GSR_CLUSTER * (uint32_t)V;
   const int64_t p = j / GSR_CLUSTER;
   int64_t i = -1;
   if (p < (int64_t)nvis) {
@@ -316,6 +318,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
                          (float)(-0.5 * c * kLog2e));
     out.r2 = make_float4((float)g.o, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0), (float)fmax(col[2], 0.0));
     rec[r] = out;
+    float4* g4 = reinterpret_cast<float4*>(grad2d + r * kGrad2D);  // cleared for the backward's atomics
+    g4[0] = g4[1] = g4[2] = make_float4(0.f, 0.f, 0.f, 0.f);
     dkey[r] = __float_as_uint((float)pr.tz);
     tiles[r] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
     rect[r] = make_ushort4((unsigned short)x0, (unsigned short)x1, (unsigned short)y0, (unsigned short)y1);
@@ -627,7 +631,7 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
   const unsigned grid = (unsigned)((f.ncap + kThreads - 1) / kThreads);
 #define GSR_PRE_FWD(D)                                                                                          \
   k_preprocess_fwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.ncap, f.header, f.cluster_list, f.compact2full, \
-                                                f.rec, f.dkey, f.tiles_touched, f.rect)
+                                                f.rec, f.dkey, f.tiles_touched, f.rect, f.grad2d)
   switch (sc.sh_degree) {
     case 0: GSR_PRE_FWD(0); break;
     case 1: GSR_PRE_FWD(1); break;

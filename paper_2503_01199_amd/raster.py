@@ -72,17 +72,34 @@ class SceneTensors:
 
 
 class Workspace:
-    """A caller-owned device byte buffer, grown on demand, 256-byte aligned."""
+    """A caller-owned device byte buffer, grown on demand, 256-byte aligned. The
+    rasterizer that renders into it is told when the buffer goes away, so that the
+    library drops the frame state it keeps for the address."""
 
     def __init__(self, device):
         self.device = torch.device(device)
         self.buf = None
         self.offset = 0
         self.nbytes = 0
+        self.owner = None  # (library, context) of the last forward on this buffer
+
+    def _release(self):
+        if self.owner is not None and self.buf is not None:
+            lib, ctx = self.owner
+            if ctx.value:
+                lib.gsr_frame_release(ctx, self.ptr)
+        self.owner = None
+
+    def __del__(self):
+        try:
+            self._release()
+        except Exception:  # interpreter shutdown
+            pass
 
     def ensure(self, nbytes: int):
         if self.buf is not None and self.nbytes >= nbytes:
             return
+        self._release()
         self.buf = torch.empty(int(nbytes) + _ALIGN, dtype=torch.uint8, device=self.device)
         self.offset = (-self.buf.data_ptr()) % _ALIGN
         self.nbytes = int(nbytes)
@@ -132,6 +149,7 @@ class Rasterizer:
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
             self.lib.gsr_context_destroy(ctx)
+            ctx.value = None  # workspaces that still refer to the context see it gone
             self.ctx = None
 
     def _check(self, st: int, what: str):
@@ -153,7 +171,11 @@ class Rasterizer:
 
     # ------------------------------------------------------------------ forward / backward
     def forward(self, scene: SceneTensors, cameras, precision=L.GSR_FP32, cluster_cull=True, stats=True,
-                workspace: Workspace | None = None, images=None) -> Frame:
+                workspace: Workspace | None = None, images=None, check: bool = True) -> Frame:
+        """Renders the views. With check (the default) waits for the frame's counters
+        and, when its instances did not fit the workspace, grows it and renders
+        again; check=False returns right after enqueueing (info is then empty: call
+        check_frame to wait, read the counters and learn whether it fitted)."""
         V = len(cameras)
         cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
         opts = self.options(precision, cluster_cull, stats)
@@ -173,12 +195,33 @@ class Rasterizer:
             if st == L.GSR_ERR_WORKSPACE_TOO_SMALL:
                 ws.ensure(self.lib.gsr_required_workspace(self.ctx))
                 continue
-            break
+            self._check(st, "gsr_forward")
+            ws.owner = (self.lib, self.ctx)
+            frame = Frame(scene, list(cameras), cams, opts, ws, images, {})
+            if not check:
+                return frame
+            st, info = self._inspect(ws, None)
+            if st == L.GSR_ERR_WORKSPACE_TOO_SMALL:
+                ws.ensure(self.lib.gsr_required_workspace(self.ctx))
+                continue
+            self._check(st, "gsr_frame_inspect")
+            frame.info = info
+            return frame
         self._check(st, "gsr_forward")
+        raise L.GsrError(L.GSR_ERR_WORKSPACE_TOO_SMALL, "gsr_forward: workspace did not converge")
+
+    def _inspect(self, ws: Workspace, bufs):
         info = L.GsrFrameInfo()
-        self._check(self.lib.gsr_frame_inspect(self.ctx, ws.ptr, ctypes.byref(info), None), "gsr_frame_inspect")
-        info_d = {k: getattr(info, k) for k, _ in L.GsrFrameInfo._fields_ if k != "reserved"}
-        return Frame(scene, list(cameras), cams, opts, ws, images, info_d)
+        st = self.lib.gsr_frame_inspect(self.ctx, ws.ptr, ctypes.byref(info), None if bufs is None else ctypes.byref(bufs))
+        return st, {k: getattr(info, k) for k, _ in L.GsrFrameInfo._fields_ if k != "reserved"}
+
+    def check_frame(self, frame: Frame) -> dict:
+        """Waits for the frame's counters; raises GsrError if its instances did not
+        fit the workspace (GSR_ERR_WORKSPACE_TOO_SMALL) or a device wait gave up."""
+        st, info = self._inspect(frame.workspace, None)
+        self._check(st, "gsr_frame_inspect")
+        frame.info = info
+        return info
 
     def backward(self, frame: Frame, dL_dimages, grads=None, stats=None):
         """Returns the parameter gradients (a dict of tensors shaped like the scene's).
@@ -209,17 +252,24 @@ class Rasterizer:
         return grads
 
     # ------------------------------------------------------------------ inspection
-    def inspect(self, frame: Frame) -> dict:
-        """Tensor views (not copies) of the frame's intermediate buffers in the workspace."""
-        info = L.GsrFrameInfo()
+    def inspect(self, frame: Frame, allow_overflow: bool = False) -> dict:
+        """Tensor views (not copies) of the frame's intermediate buffers in the
+        workspace. With allow_overflow, a frame whose instances did not all fit is
+        inspected too: its instance lists then hold the kept prefix (info["kept"])."""
         b = L.GsrFrameBuffers()
         ws = frame.workspace
-        self._check(self.lib.gsr_frame_inspect(self.ctx, ws.ptr, ctypes.byref(info), ctypes.byref(b)),
-                    "gsr_frame_inspect")
+        st, info_d = self._inspect(ws, b)
+        if not (allow_overflow and st == L.GSR_ERR_WORKSPACE_TOO_SMALL):
+            self._check(st, "gsr_frame_inspect")
+        info = L.GsrFrameInfo(**{k: v for k, v in info_d.items()})
         V = len(frame.cameras)
         ncap = info.clusters * L.GSR_CLUSTER
         R = ncap * V
         M = info.instances
+        if st == L.GSR_ERR_WORKSPACE_TOO_SMALL:
+            ends = ws.view(b.ranges, 2 * info.tiles, torch.int32).view(-1, 2)[:, 1]
+            M = int(ends.max().item()) if info.tiles > 0 else 0
+        info_d["kept"] = M
         P = info.pixels
         u32, f32, i16 = torch.int32, torch.float32, torch.int16
         out = dict(
@@ -239,7 +289,7 @@ class Rasterizer:
             cluster_visible=ws.view(b.cluster_visible, max(info.clusters, 1), u32),
             pixel_base=[b.pixel_base[v] for v in range(V)],
             tile_base=[b.tile_base[v] for v in range(V)],
-            info={k: getattr(info, k) for k, _ in L.GsrFrameInfo._fields_ if k != "reserved"},
+            info=info_d,
         )
         return out
 

@@ -197,3 +197,66 @@ def test_spheres_scene_full_size(rz):
     assert np.array_equal((it << np.uint64(32)) | dk[ir], keys)
     assert np.array_equal(full[ir], vals)
     assert np.array_equal(ins["ranges"].cpu().numpy().view(np.uint32), ranges)
+
+
+def test_views_beyond_one_argument_chunk(rz):
+    """20 views of ragged sizes: the view table is uploaded in kernel-argument chunks
+    of 16, so views 16..19 come from a second chunk."""
+    sc = scenes.tiny_scene(500, seed_salt=8)
+    cams = [scenes.tiny_camera(40 + 3 * k, 30 + 2 * k) for k in range(20)]
+    fr = gpu_forward(rz, sc, cams)
+    ins = rz.inspect(fr)
+    keys, vals, ranges = _oracle_bins(sc, cams)
+    assert ins["info"]["instances"] == len(keys)
+    full, view = full_index_of_records(ins, len(cams))
+    it = ins["inst_tile"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    ir = ins["inst_record"].cpu().numpy().view(np.uint32).astype(np.int64)
+    dk = ins["depth_key"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal((it << np.uint64(32)) | dk[ir], keys)
+    assert np.array_equal(view[ir] * sc.n + full[ir], vals)
+    for v in (0, 15, 16, 19):
+        check_image(fr, sc, cams[v], v=v, what="view %d of 20" % v)
+
+
+def test_instance_overflow_keeps_a_depth_prefix_and_reports(rz):
+    """A workspace that holds about half of the frame's instances: the forward cuts
+    the list at the capacity, every tile keeps a prefix of its full list, and the
+    frame check reports the workspace the frame needs; after growing, the frame is
+    whole again."""
+    import ctypes
+    from paper_2503_01199_amd import _lib as L
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace, camera_struct
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    st = SceneTensors.from_scene(sc, rz.device)
+    full = rz.forward(st, [cam], workspace=Workspace(rz.device))
+    fins = rz.inspect(full)
+    M = fins["info"]["instances"]
+    assert M > 1000
+    cams = (L.GsrCamera * 1)(camera_struct(cam))
+    nbytes = ctypes.c_size_t()
+    sct = st.struct()
+    assert rz.lib.gsr_workspace_size(rz.ctx, ctypes.byref(sct), cams, 1, ctypes.byref(full.opts), M // 2,
+                                     ctypes.byref(nbytes)) == L.GSR_OK
+    ws = Workspace(rz.device)
+    ws.ensure(nbytes.value)
+    print("overflow case: M=%d, workspace for %d" % (M, M // 2), flush=True)
+    cut = rz.forward(st, [cam], workspace=ws, check=False)
+    with pytest.raises(L.GsrError, match="WORKSPACE_TOO_SMALL"):
+        rz.check_frame(cut)
+    assert rz.lib.gsr_required_workspace(rz.ctx) > nbytes.value
+    ins = rz.inspect(cut, allow_overflow=True)
+    kept = ins["info"]["kept"]
+    assert ins["info"]["instances"] == M and M // 2 <= kept < M
+    fr_r = fins["ranges"].cpu().numpy().view(np.uint32).astype(np.int64)
+    cr = ins["ranges"].cpu().numpy().view(np.uint32).astype(np.int64)
+    fr_rec = fins["inst_record"].cpu().numpy().view(np.uint32)
+    c_rec = ins["inst_record"].cpu().numpy().view(np.uint32)
+    assert (cr[:, 1] - cr[:, 0]).sum() == kept
+    for t in range(cr.shape[0]):
+        n_cut = cr[t, 1] - cr[t, 0]
+        assert n_cut <= fr_r[t, 1] - fr_r[t, 0]
+        if n_cut:
+            assert np.array_equal(c_rec[cr[t, 0]:cr[t, 1]], fr_rec[fr_r[t, 0]:fr_r[t, 0] + n_cut])
+    again = rz.forward(st, [cam], workspace=ws)
+    assert again.info["instances"] == M
+    assert torch.equal(again.images[0], full.images[0])
