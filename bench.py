@@ -157,8 +157,10 @@ def main():
                                                      st.tensors())}
     cull = not args.no_cull
 
-    def step(check=False):
-        fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check)
+    from paper_2503_01199_amd import _lib as L
+
+    def step(check=False, precision=L.GSR_FP32):
+        fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision)
         rz.l1_grad(fr.images[0], w, gt, out=dl)
         rz.backward(fr, [dl], grads=grads, stats=stats)
         return fr
@@ -207,6 +209,29 @@ def main():
                 stage_acc.setdefault(k, []).append(v)
     rz.set_profiling(False)
     stages = {k: round(sum(v) / len(v), 4) for k, v in stage_acc.items()}
+
+    # the packed-FP16 blend variant (Sec. 3.1.2) on the same workload and protocol
+    log("timing %d FP16-blend steps" % args.steps)
+    for _ in range(max(args.warmup, 1)):
+        step(precision=L.GSR_FP16_BLEND)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        fr16 = step(precision=L.GSR_FP16_BLEND)
+    torch.cuda.synchronize()
+    fp16_ms = (time.perf_counter() - wall0) * 1e3 / args.steps
+    rz.check_frame(fr16)
+    rz.set_profiling(True)
+    acc16 = {}
+    for _ in range(args.steps):
+        step(precision=L.GSR_FP16_BLEND)
+        for k, v in rz.stage_times().items():
+            if v >= 0:
+                acc16.setdefault(k, []).append(v)
+    rz.set_profiling(False)
+    st16 = {k: round(sum(v) / len(v), 4) for k, v in acc16.items()}
+    fp16 = {"ms_per_step": round(fp16_ms, 4), "raster_fwd_ms": st16.get("raster_fwd"),
+            "raster_bwd_ms": st16.get("raster_bwd")}
 
     # roofline of the dominant kernel (each stage below is one kernel launch)
     dom = max(("raster_bwd", "raster_fwd", "preprocess_bwd", "preprocess"), key=lambda k: stages.get(k, 0.0))
@@ -263,6 +288,7 @@ def main():
         "morton_reorder_ms": round(morton_ms, 3),
         "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
+        "fp16_blend": fp16,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

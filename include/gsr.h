@@ -45,8 +45,10 @@ typedef enum {
 
 typedef enum {
   GSR_FP32 = 0,        /* every raster quantity in FP32 */
-  GSR_FP16_BLEND = 1   /* exponent increments, exp and alpha in packed FP16 (Sec. 3.1.2); colour, T
-                          and all gradients accumulate in FP32 */
+  GSR_FP16_BLEND = 1   /* packed-FP16 blend (Sec. 3.1.2): exponents computed in FP32 and rounded
+                          toward zero to FP16; G = 2^e and alpha = min(0.99, o G) in packed FP16
+                          (clamp point 0.99 rounded to FP16); T, colour and all gradients FP32.
+                          An approximation: its error against FP32 is measured, not bounded. */
 } gsr_precision;
 
 #define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile */

@@ -19,7 +19,6 @@ using gsr::ViewDev;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kPinnedBytes = 64 * 1024;
 constexpr size_t kHdrBytes = 256;
 
 struct FrameRecord {
@@ -28,8 +27,7 @@ struct FrameRecord {
   gsr_camera cams[GSR_MAX_VIEWS];
   int64_t tile_base[GSR_MAX_VIEWS];
   int64_t pixel_base[GSR_MAX_VIEWS];
-  uint32_t* hdr = nullptr;             // pinned host copy of the frame header (64 words)
-  hipEvent_t done = nullptr;           // recorded after the header copy
+  hipEvent_t done = nullptr;           // recorded after the frame's last kernel
   int backwards = 0;                   // backward passes run on this frame
 };
 
@@ -39,8 +37,6 @@ struct gsr_context {
   int device = 0;
   std::string err;
   size_t required = 0;
-  std::vector<void*> pinned_blocks;    // pinned host blocks holding frame header copies
-  std::vector<uint32_t*> free_hdrs;    // unused 256-byte slots of those blocks
   std::unordered_map<const void*, FrameRecord> frames;
   bool profiling = false;
   bool events_ready = false;
@@ -143,7 +139,6 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   if (!o) return fail(ctx, GSR_ERR_INVALID_ARG, "options are NULL");
   if (o->precision != GSR_FP32 && o->precision != GSR_FP16_BLEND)
     return fail(ctx, GSR_ERR_INVALID_ARG, "unknown precision %d", o->precision);
-  if (o->precision == GSR_FP16_BLEND) return fail(ctx, GSR_ERR_UNSUPPORTED, "FP16 blending is not built yet");
   if (o->cluster_cull != 0 && o->cluster_cull != 1)
     return fail(ctx, GSR_ERR_INVALID_ARG, "cluster_cull must be 0 or 1");
   if (o->stats != 0 && o->stats != 1) return fail(ctx, GSR_ERR_INVALID_ARG, "stats must be 0 or 1");
@@ -246,27 +241,9 @@ struct StageScope {
   }
 };
 
-// A 256-byte pinned host slot for a frame's header copy (a new 64 KiB block when
-// every slot is taken).
-gsr_status take_header_slot(gsr_context* ctx, uint32_t** out) {
-  if (ctx->free_hdrs.empty()) {
-    void* blk = nullptr;
-    gsr_status st = check_hip(ctx, hipHostMalloc(&blk, kPinnedBytes, hipHostMallocDefault), "pinned header block");
-    if (st) return st;
-    ctx->pinned_blocks.push_back(blk);
-    for (size_t o = 0; o + kHdrBytes <= kPinnedBytes; o += kHdrBytes)
-      ctx->free_hdrs.push_back(reinterpret_cast<uint32_t*>(static_cast<char*>(blk) + o));
-  }
-  *out = ctx->free_hdrs.back();
-  ctx->free_hdrs.pop_back();
-  return GSR_OK;
-}
-
-void release_frame(gsr_context* ctx, FrameRecord& fr) {
+void release_frame(FrameRecord& fr) {
   if (fr.done) (void)hipEventDestroy(fr.done);
-  if (fr.hdr) ctx->free_hdrs.push_back(fr.hdr);
   fr.done = nullptr;
-  fr.hdr = nullptr;
 }
 
 void fill_views(const gsr_camera* cams, int32_t V, ViewDev* out) {
@@ -322,12 +299,11 @@ void gsr_context_destroy(gsr_context* ctx) {
     DeviceGuard g(ctx->device);
     for (auto& kv : ctx->frames) {
       if (kv.second.done) (void)hipEventSynchronize(kv.second.done);
-      release_frame(ctx, kv.second);
+      release_frame(kv.second);
     }
     ctx->frames.clear();
     if (ctx->events_ready)
       for (int k = 0; k < 2 * GSR_STAGE_COUNT; ++k) (void)hipEventDestroy(ctx->ev[k]);
-    for (void* b : ctx->pinned_blocks) (void)hipHostFree(b);
   }
   delete ctx;
 }
@@ -376,12 +352,8 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   FrameRecord& fr = ctx->frames[workspace];
-  if (fr.done) {  // the previous frame on this workspace may still be copying its header
-    if ((st = check_hip(ctx, hipEventSynchronize(fr.done), "wait for the previous frame"))) return st;
-  } else {
-    if ((st = check_hip(ctx, hipEventCreateWithFlags(&fr.done, hipEventDisableTiming), "frame event"))) return st;
-  }
-  if (!fr.hdr && (st = take_header_slot(ctx, &fr.hdr))) return st;
+  if (!fr.done && (st = check_hip(ctx, hipEventCreateWithFlags(&fr.done, hipEventDisableTiming), "frame event")))
+    return st;
   fr.scene = *scene;
   std::memcpy(fr.cams, cams, sizeof(gsr_camera) * V);
   fr.backwards = 0;
@@ -454,8 +426,6 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
     gsr::launch_raster_fwd(f, ip, opts->precision, s);
   }
   if ((st = check_hip(ctx, hipGetLastError(), "forward launches"))) return st;
-  if ((st = check_hip(ctx, hipMemcpyAsync(fr.hdr, f.header, kHdrBytes, hipMemcpyDeviceToHost, s), "header copy")))
-    return st;
   if ((st = check_hip(ctx, hipEventRecord(fr.done, s), "frame event"))) return st;
   fr.f = f;
   return GSR_OK;
@@ -468,7 +438,7 @@ gsr_status gsr_frame_release(gsr_context* ctx, const void* workspace) {
   DeviceGuard guard(ctx->device);
   gsr_status st = GSR_OK;
   if (it->second.done) st = check_hip(ctx, hipEventSynchronize(it->second.done), "wait for the frame");
-  release_frame(ctx, it->second);
+  release_frame(it->second);
   ctx->frames.erase(it);
   return st;
 }
@@ -533,9 +503,12 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
   FrameRecord& fr = it->second;
   const Frame& f = fr.f;
   DeviceGuard guard(ctx->device);
-  gsr_status st = check_hip(ctx, hipEventSynchronize(fr.done), "wait for the frame header");
+  gsr_status st = check_hip(ctx, hipEventSynchronize(fr.done), "wait for the frame");
   if (st) return st;
-  const uint32_t* h = fr.hdr;
+  // the counters stay in the workspace's header until the next forward on it
+  uint32_t h[kHdrBytes / 4];
+  if ((st = check_hip(ctx, hipMemcpy(h, f.header, kHdrBytes, hipMemcpyDeviceToHost), "read the frame header")))
+    return st;
   const int64_t nvis = h[gsr::kHdrVisibleClusters];
   const int64_t M = h[gsr::kHdrInstances];
   if (info) {

@@ -51,11 +51,11 @@ __global__ void k_emit(const uint32_t* __restrict__ sorted_rec, const uint32_t* 
 __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ header,
                          uint32_t* __restrict__ ranges) {
   const int64_t M = header[kHdrInstancesKept];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  const uint32_t t = inst_tile[k];
-  if (k == 0 || inst_tile[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
-  if (k == M - 1 || inst_tile[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = inst_tile[k];
+    if (k == 0 || inst_tile[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
+    if (k == M - 1 || inst_tile[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+  }
 }
 
 // Longest-list-first schedule for the raster (tiles are independent, so the order
@@ -122,7 +122,9 @@ void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream
 
 void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s) {
   if (M_max <= 0) return;
-  k_ranges<<<(unsigned)((M_max + 255) / 256), 256, 0, s>>>(inst_tile, f.header, f.ranges);
+  // grid-stride over the count on the device; the grid covers typical frames in one sweep
+  const int64_t g = std::min<int64_t>((M_max + 255) / 256, 4096);
+  k_ranges<<<(unsigned)g, 256, 0, s>>>(inst_tile, f.header, f.ranges);
 }
 
 }  // namespace gsr

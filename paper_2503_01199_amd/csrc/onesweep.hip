@@ -30,6 +30,10 @@ __device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
 
 // Exclusive prefix of `agg` over all earlier tiles, for the status column `col`
 // (stride `stride` words between tiles). Publishes this tile's inclusive prefix.
+// The walk reads kWindow predecessors per round trip and consumes them in order
+// until an inclusive prefix (tiles below 0 count as an empty prefix).
+constexpr int kWindow = 4;
+
 __device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, int col, uint32_t agg,
                               uint32_t* err) {
   uint32_t* mine = status + tile * stride + col;
@@ -45,20 +49,30 @@ __device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, in
   uint32_t excl = 0;
   int64_t b = tile - 1;
   int spins = 0;
-  while (b >= 0) {
-    const uint32_t s = ld_status(status + b * stride + col);
-    const uint32_t flag = s & ~kValueMask;
-    if (flag == 0) {
+  bool found = false;
+  while (!found) {
+    uint32_t st[kWindow];
+#pragma unroll
+    for (int q = 0; q < kWindow; ++q) st[q] = b - q >= 0 ? ld_status(status + (b - q) * stride + col) : kFlagPrefix;
+    int used = 0;
+#pragma unroll
+    for (int q = 0; q < kWindow; ++q) {
+      if (found || used < q) continue;  // stop at a prefix or at the first status not yet published
+      const uint32_t flag = st[q] & ~kValueMask;
+      if (flag == 0) continue;
+      excl += st[q] & kValueMask;
+      used = q + 1;
+      if (flag == kFlagPrefix) found = true;
+    }
+    if (found) break;
+    b -= used;
+    if (used < kWindow) {
       if (++spins > kSpinLimit) {
         atomicOr(err, 1u);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    excl += s & kValueMask;
-    if (flag == kFlagPrefix) break;
-    --b;
   }
   if ((uint64_t)excl + agg > kValueMask) atomicOr(err, 2u);
   st_status(mine, kFlagPrefix | ((excl + agg) & kValueMask));
@@ -137,8 +151,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 items per tile
-constexpr int kHistBlocks = 256;
+constexpr int kHistBlocks = 512;
+constexpr int64_t kHistChunk = 8192;  // keys per histogram block at least
 constexpr int kMaxPasses = 8;
+constexpr int kScatterBlocks = 1024;  // 4 resident blocks (33 KiB LDS each) on each of 256 CUs
 
 // Lanes of the wave holding the same 8-bit digit d (restricted to `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -152,27 +168,41 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 }
 
 // Digit histograms of every pass in one read of the keys; the last block to finish
-// turns them into per-pass exclusive digit offsets (offs[p][d]).
+// turns them into per-pass exclusive digit offsets (offs[p][d]). Counting needs no
+// ranks, so each key adds 1 to its digit's LDS counter directly (the LDS unit
+// serialises equal addresses within an instruction, cheaper than the ballot match
+// the scatter needs). Blocks take at least kHistChunk keys each (their number is
+// chosen from the count on the device, so the same-address atomics of the final
+// merge stay few) and load 8 keys per thread before counting them. Blocks beyond
+// the needed number leave at once.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ keys, int64_t n_host,
                                                           const uint32_t* __restrict__ n_dev, int passes,
                                                           uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
                                                           uint32_t* __restrict__ done) {
   __shared__ uint32_t h[kMaxPasses][256];
+  __shared__ uint32_t wsum[kSortThreads / 64];
   __shared__ bool last;
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  int64_t nb = (n + kHistChunk - 1) / kHistChunk;
+  if (nb < 1) nb = 1;
+  if (nb > gridDim.x) nb = gridDim.x;
+  if (blockIdx.x >= nb) return;
   const int t = threadIdx.x;
   const int lane = t & 63;
   for (int p = 0; p < passes; ++p) h[p][t] = 0;
   __syncthreads();
-  for (int64_t i0 = (int64_t)blockIdx.x * kSortThreads; i0 < n; i0 += (int64_t)gridDim.x * kSortThreads) {
-    const int64_t i = i0 + t;
-    const bool valid = i < n;
-    const K key = valid ? keys[i] : (K)0;
-    for (int p = 0; p < passes; ++p) {
-      const uint32_t d = (uint32_t)(key >> (8 * p)) & 255u;
-      const uint64_t peers = match_digit(d, valid);
-      if (valid && (peers & ((1ull << lane) - 1ull)) == 0) atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
+  for (int64_t base = (int64_t)blockIdx.x * kSortTile; base < n; base += nb * kSortTile) {
+    K key[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      const int64_t i = base + r * kSortThreads + t;
+      key[r] = i < n ? keys[i] : (K)0;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (base + r * kSortThreads + t < n)
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(key[r] >> (8 * p)) & 255u], 1u);
     }
   }
   __syncthreads();
@@ -180,11 +210,10 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
     if (h[p][t]) atomicAdd(&hist[p * 256 + t], h[p][t]);
   __threadfence();
   __syncthreads();
-  if (t == 0) last = atomicAdd(done, 1u) == gridDim.x - 1;
+  if (t == 0) last = atomicAdd(done, 1u) == (uint32_t)(nb - 1);
   __syncthreads();
   if (!last) return;
   __threadfence();
-  __shared__ uint32_t wsum[kSortThreads / 64];
   for (int p = 0; p < passes; ++p) {
     const uint32_t x = __hip_atomic_load(&hist[p * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t incl = wave_incl_scan(x);
@@ -197,10 +226,12 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
   }
 }
 
-// One pass: each block takes the next tile of 2048 items (8 coalesced rounds of
-// 256), ranks them stably within the tile (ballot match per wave, counts per
-// (round, wave, digit) in LDS), learns the per-digit counts of all earlier tiles by
-// look-back and scatters.
+// One pass: each block repeatedly takes the next tile of 2048 items (8 coalesced
+// rounds of 256) until the tiles run out, ranks them stably within the tile (ballot
+// match per wave, counts per (round, wave, digit) in LDS), learns the per-digit
+// counts of all earlier tiles by look-back and scatters. The grid is capped, so a
+// launch sized for the largest possible count costs little when the count on the
+// device is small.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -214,49 +245,53 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
   const int t = threadIdx.x;
   const int w = t >> 6;
   const int lane = t & 63;
-  if (t == 0) s_tile = atomicAdd(ctl, 1u);
-  for (int r = 0; r < kSortRounds; ++r)
+  for (;;) {
+    if (t == 0) s_tile = atomicAdd(ctl, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t base = tile * kSortTile;
+    if (base >= n) return;  // uniform over the block
+    for (int r = 0; r < kSortRounds; ++r)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cnt[r][q][t] = 0;
-  __syncthreads();
-  const int64_t tile = s_tile;
-  const int64_t base = tile * kSortTile;
-  if (base >= n) return;
-  K key[kSortRounds];
-  uint32_t val[kSortRounds];
-  uint32_t dig[kSortRounds];
-  uint32_t rank[kSortRounds];
+      for (int q = 0; q < 4; ++q) cnt[r][q][t] = 0;
+    __syncthreads();
+    K key[kSortRounds];
+    uint32_t val[kSortRounds];
+    uint32_t dig[kSortRounds];
+    uint32_t rank[kSortRounds];
 #pragma unroll
-  for (int r = 0; r < kSortRounds; ++r) {
-    const int64_t i = base + r * kSortThreads + t;
-    const bool valid = i < n;
-    key[r] = valid ? kin[i] : (K)0;
-    val[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
-    dig[r] = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
-    const uint64_t peers = match_digit(dig[r] & 255u, valid);
-    rank[r] = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
-    if (valid && rank[r] == 0) cnt[r][w][dig[r]] = (uint32_t)__popcll(peers);
-  }
-  __syncthreads();
-  // thread d: exclusive running count of digit d over (round, wave), then the tile total
-  uint32_t run = 0;
-  for (int r = 0; r < kSortRounds; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t c = cnt[r][q][t];
-      cnt[r][q][t] = run;
-      run += c;
+    for (int r = 0; r < kSortRounds; ++r) {
+      const int64_t i = base + r * kSortThreads + t;
+      const bool valid = i < n;
+      key[r] = valid ? kin[i] : (K)0;
+      val[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
+      dig[r] = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
+      const uint64_t peers = match_digit(dig[r] & 255u, valid);
+      rank[r] = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+      if (valid && rank[r] == 0) cnt[r][w][dig[r]] = (uint32_t)__popcll(peers);
     }
-  const uint32_t prior = look_back(ctl + 1, tile, 256, t, run, err);
-  gofs[t] = offs[t] + prior;
-  __syncthreads();
+    __syncthreads();
+    // thread d: exclusive running count of digit d over (round, wave), then the tile total
+    uint32_t run = 0;
+    for (int r = 0; r < kSortRounds; ++r)
 #pragma unroll
-  for (int r = 0; r < kSortRounds; ++r) {
-    if (dig[r] < 256u) {
-      const uint32_t pos = gofs[dig[r]] + cnt[r][w][dig[r]] + rank[r];
-      kout[pos] = key[r];
-      vout[pos] = val[r];
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t c = cnt[r][q][t];
+        cnt[r][q][t] = run;
+        run += c;
+      }
+    const uint32_t prior = look_back(ctl + 1, tile, 256, t, run, err);
+    gofs[t] = offs[t] + prior;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      if (dig[r] < 256u) {
+        const uint32_t pos = gofs[dig[r]] + cnt[r][w][dig[r]] + rank[r];
+        kout[pos] = key[r];
+        vout[pos] = val[r];
+      }
     }
+    __syncthreads();  // gofs, cnt and s_tile are reused by the next tile
   }
 }
 
@@ -271,15 +306,16 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   uint32_t* pass_ctl = done + 64;             // per pass: counter + status[tiles][256]
   const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
   const int64_t pass_words = 64 + tiles * 256;
-  int64_t hb = (n_max + kSortThreads * 8 - 1) / (kSortThreads * 8);
+  int64_t hb = (n_max + kHistChunk - 1) / kHistChunk;
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
   k_os_hist<K><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
   const K* kcur = keys_in;
   const uint32_t* vcur = vals_in;
   int out = 0;
+  const int64_t grid = tiles < kScatterBlocks ? tiles : kScatterBlocks;
   for (int p = 0; p < passes; ++p) {
-    k_os_scatter<K><<<(unsigned)tiles, kSortThreads, 0, s>>>(kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p,
+    k_os_scatter<K><<<(unsigned)grid, kSortThreads, 0, s>>>(kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p,
                                                              offs + p * 256, pass_ctl + p * pass_words, err);
     kcur = kb[out];
     vcur = vb[out];

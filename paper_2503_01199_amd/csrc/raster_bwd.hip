@@ -69,6 +69,7 @@ __device__ __forceinline__ void wave_reduce12(float v[12], float w[3]) {
   for (int i = 0; i < 3; ++i) w[i] += dpp_row_shr<0x118>(w[i]);
 }
 
+template <int P>
 __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ views, int32_t V,
                                                    const uint32_t* __restrict__ tile_order,
                                                    const uint32_t* __restrict__ ranges,
@@ -77,8 +78,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    const float* __restrict__ pix_rgb,
                                                    const uint32_t* __restrict__ pix_last,
                                                    float* __restrict__ grad2d) {
-  __shared__ Record batch[64];
-  __shared__ uint32_t brec[64];
+  __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
+  __shared__ uint32_t recA[64], recB[64];
   const uint32_t gt = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
@@ -124,32 +125,35 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = min(ranges[2 * gt + 1], s + mymax);
 
-  // Record gathers are pipelined: ids two batches ahead, records one batch ahead.
-  uint32_t r_cur = (s + lane < e) ? inst_rec[s + lane] : 0u;
-  Record g_cur = {};
-  if (s + lane < e) g_cur = rec[r_cur];
+  // Pipeline: record ids two batches ahead, records one batch ahead (in LDS).
+  if (s < e) {
+    const uint32_t r0 = (s + lane < e) ? inst_rec[s + lane] : 0u;
+    batch_fetch(bufA, rec, r0);
+    recA[lane] = r0;
+  }
   uint32_t r_next = (s + 64 + lane < e) ? inst_rec[s + 64 + lane] : 0u;
-
-  for (uint32_t b0 = s; b0 < e; b0 += 64) {
+  auto run_batch = [&](const BatchLDS& cur, const uint32_t* cur_rec, BatchLDS& nxt, uint32_t* nxt_rec,
+                       uint32_t b0) __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
     __syncthreads();
-    batch[lane] = g_cur;
-    brec[lane] = r_cur;
-    __syncthreads();
-    r_cur = r_next;
-    if (b0 + 64 + lane < e) g_cur = rec[r_cur];
+    if (b0 + 64 < e) {
+      batch_fetch(nxt, rec, r_next);
+      nxt_rec[lane] = r_next;
+    }
     r_next = (b0 + 128 + lane < e) ? inst_rec[b0 + 128 + lane] : 0u;
     const int cnt = (int)min(64u, e - b0);
     for (int k = 0; k < cnt; ++k) {
-      const Record g = batch[k];
+      const Record g = batch_get(cur, k);
       float ev[4], dx, dy;
       strip_exponents(g, pxc, pyc, ev, dx, dy);
       const uint32_t pos = b0 - s + (uint32_t)k;
       const float o = g.r2.x;
       float S0 = 0.f, S1 = 0.f, S2 = 0.f, dcr = 0.f, dcg = 0.f, dcb = 0.f, dop = 0.f, ss = 0.f, nfrag = 0.f;
+      float av[4], Gv[4], arv[4];
+      strip_alpha<P>(o, ev, av, Gv, arv);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float G, araw;
-        const float a = alpha_of(o, ev[j], G, araw);
+        const float a = av[j], G = Gv[j], araw = arv[j];
         const bool blend = (pos < last[j]) && (a >= kAlphaMin);
         if (blend) {
           nfrag += 1.0f;
@@ -162,7 +166,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
           const float one_m_a = 1.0f - a;
           // dL/dalpha = T (g . c) - (g . colour behind) / (1 - alpha)
           const float dA = __builtin_fmaf(T[j], gc, -(gIf[j] - gC[j]) * __builtin_amdgcn_rcpf(one_m_a));
-          const float go = (araw <= kAlphaMax) ? dA * G : 0.0f;
+          const float go = (araw <= alpha_clamp<P>()) ? dA * G : 0.0f;
           const float dE = go * o;
           S0 += dE;
           if (j == 1) {
@@ -195,22 +199,29 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
       if ((lane & 15) == 15) {
         const int row = lane >> 4;
         const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-        float* dst = grad2d + (int64_t)brec[k] * kGrad2D + sub;
+        float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D + sub;
         unsafeAtomicAdd(dst, tot[0]);
         unsafeAtomicAdd(dst + 4, tot[1]);
         if (sub != 3) unsafeAtomicAdd(dst + 8, tot[2]);
       }
     }
+  };
+  for (uint32_t b0 = s; b0 < e; b0 += 128) {
+    run_batch(bufA, recA, bufB, recB, b0);
+    if (b0 + 64 < e) run_batch(bufB, recB, bufA, recA, b0 + 64);
   }
 }
 
 }  // namespace
 
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s) {
-  (void)precision;
   if (f.tiles <= 0) return;
-  k_raster_bwd<<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec, dL,
-                                                f.pix_rgb, f.pix_last, f.grad2d);
+  if (precision == GSR_FP16_BLEND)
+    k_raster_bwd<GSR_FP16_BLEND><<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec,
+                                                                  f.rec, dL, f.pix_rgb, f.pix_last, f.grad2d);
+  else
+    k_raster_bwd<GSR_FP32><<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec,
+                                                            dL, f.pix_rgb, f.pix_last, f.grad2d);
 }
 
 }  // namespace gsr

@@ -41,6 +41,75 @@ __device__ __forceinline__ float alpha_of(float o, float e, float& G, float& ara
   return fminf(kAlphaMax, araw);
 }
 
+// FP16 blend (Sec. 3.1.2): the strip's exponents, computed in FP32, are rounded to
+// FP16 (toward zero, two per instruction); G = 2^e (v_exp_f16) and alpha =
+// min(0.99, o G) are evaluated on pixel pairs in packed FP16. Transmittance,
+// colour and all gradients stay FP32, taking these alphas as exact.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+extern "C" __device__ _Float16 __ocml_exp2_f16(_Float16);
+constexpr float kAlphaMaxH = 0.990234375f;  // 0.99 rounded to FP16: the clamp point of the FP16 blend
+
+__device__ __forceinline__ void strip_alpha_h(float o, const float e[4], float a[4], float G[4], float araw[4]) {
+  const _Float16 oh = (_Float16)o;
+  const half2_t o2 = {oh, oh};
+  const half2_t cap = {(_Float16)kAlphaMax, (_Float16)kAlphaMax};
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const half2_t eh = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(e[2 * p], e[2 * p + 1]));
+    const half2_t g = {__ocml_exp2_f16(eh.x), __ocml_exp2_f16(eh.y)};
+    const half2_t r = o2 * g;
+    const half2_t al = __builtin_elementwise_min(cap, r);
+    a[2 * p] = (float)al.x;
+    a[2 * p + 1] = (float)al.y;
+    G[2 * p] = (float)g.x;
+    G[2 * p + 1] = (float)g.y;
+    araw[2 * p] = (float)r.x;
+    araw[2 * p + 1] = (float)r.y;
+  }
+}
+
+// Alpha of the 4 strip pixels at precision P (GSR_FP32 or GSR_FP16_BLEND).
+template <int P>
+__device__ __forceinline__ void strip_alpha(float o, const float e[4], float a[4], float G[4], float araw[4]) {
+  if constexpr (P == GSR_FP16_BLEND) {
+    strip_alpha_h(o, e, a, G, araw);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] = alpha_of(o, e[j], G[j], araw[j]);
+  }
+}
+
+// The value of o G above which alpha is clamped (and its derivative is 0).
+template <int P>
+constexpr float alpha_clamp() {
+  return P == GSR_FP16_BLEND ? kAlphaMaxH : kAlphaMax;
+}
+
+// A batch of 64 records in LDS, stored as three planes of float4 (r0, r1, r2) and
+// filled by direct global-to-LDS loads (global_load_lds_dwordx4): lane l's record
+// part lands at plane + 16 l without passing through registers, so the next batch
+// is in flight while the wave works on the current one. Lanes past the end of the
+// list load record 0 (always valid; those slots are never read).
+struct BatchLDS {
+  float4 part[3][64];
+};
+
+__device__ __forceinline__ void batch_fetch(BatchLDS& dst, const Record* __restrict__ rec, uint32_t r) {
+  const float4* src = reinterpret_cast<const float4*>(rec + r);
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+    __builtin_amdgcn_global_load_lds((const void*)(src + p),
+                                     (__attribute__((address_space(3))) void*)(&dst.part[p][0]), 16, 0, 0);
+}
+
+__device__ __forceinline__ Record batch_get(const BatchLDS& b, int k) {
+  Record g;
+  g.r0 = b.part[0][k];
+  g.r1 = b.part[1][k];
+  g.r2 = b.part[2][k];
+  return g;
+}
+
 // Locate the view of global tile gt (views are few; the loop is wave-uniform).
 __device__ __forceinline__ int view_of_tile(const ViewDev* views, int32_t V, uint32_t gt) {
   int v = 0;

@@ -3,19 +3,22 @@
 //
 // Each lane walks its 4-pixel strip with the scanline exponent (App. A.2). The
 // tile's Gaussian records are staged through LDS in batches of 64 (one gather per
-// lane, coalesced on the instance list), then read by the whole wave as a
-// broadcast. A pixel skips alpha < 1/255, clamps alpha at 0.99 and stops at the
+// lane, coalesced on the instance list, loaded straight into LDS and double
+// buffered so the next batch arrives during the current one), then read by the
+// whole wave as a broadcast. A pixel skips alpha < 1/255, clamps alpha at 0.99 and stops at the
 // entry whose blend would take T below 1e-4 (that entry is not blended); the wave
 // leaves the list once all its pixels have stopped.
 //
 // Outputs: the image (planar RGB, background composited behind), and per pixel
 // the final colour, T and the list position + 1 of the last blended entry, which
-// the backward uses to bound its walk.
+// the backward uses to bound its walk. P selects the precision of alpha (FP32, or
+// the packed-FP16 blend of Sec. 3.1.2).
 #include "raster_common.h"
 
 namespace gsr {
 namespace {
 
+template <int P>
 __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ views, int32_t V,
                                                    const uint32_t* __restrict__ tile_order,
                                                    const uint32_t* __restrict__ ranges,
@@ -23,7 +26,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
                                                    const Record* __restrict__ rec, ImagePtrs images,
                                                    float* __restrict__ pix_rgb, float* __restrict__ pix_T,
                                                    uint32_t* __restrict__ pix_last) {
-  __shared__ Record batch[64];
+  __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
   const uint32_t gt = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
@@ -50,26 +53,25 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = ranges[2 * gt + 1];
   bool live = __any(fminf(fminf(amin[0], amin[1]), fminf(amin[2], amin[3])) < 1.0f);
-  // Record gathers are pipelined: ids two batches ahead, records one batch ahead.
+  // Pipeline: record ids two batches ahead, records one batch ahead (in LDS).
+  if (s < e) batch_fetch(bufA, rec, (s + lane < e) ? inst_rec[s + lane] : 0u);
   uint32_t r_next = (s + 64 + lane < e) ? inst_rec[s + 64 + lane] : 0u;
-  Record g_cur = {};
-  if (s + lane < e) g_cur = rec[inst_rec[s + lane]];
-  for (uint32_t b0 = s; b0 < e && live; b0 += 64) {
+  auto run_batch = [&](const BatchLDS& cur, BatchLDS& nxt, uint32_t b0) __attribute__((always_inline)) {
+    __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
     __syncthreads();
-    batch[lane] = g_cur;
-    __syncthreads();
-    if (b0 + 64 + lane < e) g_cur = rec[r_next];
+    if (b0 + 64 < e) batch_fetch(nxt, rec, r_next);
     r_next = (b0 + 128 + lane < e) ? inst_rec[b0 + 128 + lane] : 0u;
     const int cnt = (int)min(64u, e - b0);
     for (int k = 0; k < cnt; ++k) {
-      const Record g = batch[k];
+      const Record g = batch_get(cur, k);
       float ev[4], dx, dy;
       strip_exponents(g, pxc, pyc, ev, dx, dy);
       const uint32_t pos1 = b0 - s + (uint32_t)k + 1u;
+      float av[4], Gv[4], arv[4];
+      strip_alpha<P>(g.r2.x, ev, av, Gv, arv);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float G, araw;
-        const float a = alpha_of(g.r2.x, ev[j], G, araw);
+        const float a = av[j];
         const bool ok = a >= amin[j];
         const float Tn = T[j] * (1.0f - a);
         const bool stop = ok && (Tn < kTMin);
@@ -87,6 +89,10 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
         break;
       }
     }
+  };
+  for (uint32_t b0 = s; b0 < e && live; b0 += 128) {
+    run_batch(bufA, bufB, b0);
+    if (b0 + 64 < e && live) run_batch(bufB, bufA, b0 + 64);
   }
   if (px >= W) return;
   float* img = images.p[v];
@@ -114,10 +120,13 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
 }  // namespace
 
 void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s) {
-  (void)precision;
   if (f.tiles <= 0) return;
-  k_raster_fwd<<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec, images,
-                                                f.pix_rgb, f.pix_T, f.pix_last);
+  if (precision == GSR_FP16_BLEND)
+    k_raster_fwd<GSR_FP16_BLEND><<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec,
+                                                                  f.rec, images, f.pix_rgb, f.pix_T, f.pix_last);
+  else
+    k_raster_fwd<GSR_FP32><<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec,
+                                                            images, f.pix_rgb, f.pix_T, f.pix_last);
 }
 
 }  // namespace gsr
