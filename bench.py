@@ -65,6 +65,10 @@ def build_workload(name, n_override=None):
         sc = scenes.spheres_planes_scene(n_override or 200_000)
         cams = [scenes.spheres_planes_camera()]
         desc = "spheres-%dk-SH3-800x800" % (sc.n // 1000)
+    elif name == "unbounded":
+        sc = scenes.unbounded_scene(n_override or 3_000_000)
+        cams = scenes.orbit_cameras(8)
+        desc = "unbounded-%dk-SH3-8x1920x1080" % (sc.n // 1000)
     elif name == "tiny":
         sc = scenes.tiny_scene(n_override or 1024)
         cams = [scenes.tiny_camera()]
@@ -110,11 +114,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="room", choices=["room", "spheres", "tiny"])
+    ap.add_argument("--workload", default="room", choices=["room", "spheres", "unbounded", "tiny"])
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
     ap.add_argument("--no-cull", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=160)
+    ap.add_argument("--no-serving", action="store_true", help="skip the render-serving stream")
+    ap.add_argument("--serve-requests", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -147,12 +153,13 @@ def main():
     st = SceneTensors(*arrays, st.sh_degree)
     scene_sorted = scene.permuted(perm.cpu().numpy())
 
-    w_np, gt_np = scenes.l1_weights((3, cam.height, cam.width), config=2)
-    w = torch.as_tensor(w_np, device=dev)
-    gt = torch.as_tensor(gt_np, device=dev)
+    wgt = []
+    for v, c in enumerate(cams):
+        w_np, gt_np = scenes.l1_weights((3, c.height, c.width), config=2, salt=v)
+        wgt.append((torch.as_tensor(w_np, device=dev), torch.as_tensor(gt_np, device=dev)))
     ws = Workspace(dev)
     stats = new_stats(st.n, dev)
-    dl = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=dev)
+    dls = [torch.empty((3, c.height, c.width), dtype=torch.float32, device=dev) for c in cams]
     grads = {k: torch.empty_like(t) for k, t in zip(("means", "log_scales", "quats", "opacity_logits", "sh"),
                                                      st.tensors())}
     cull = not args.no_cull
@@ -161,8 +168,9 @@ def main():
 
     def step(check=False, precision=L.GSR_FP32):
         fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision)
-        rz.l1_grad(fr.images[0], w, gt, out=dl)
-        rz.backward(fr, [dl], grads=grads, stats=stats)
+        for img, (w, gt), dl in zip(fr.images, wgt, dls):
+            rz.l1_grad(img, w, gt, out=dl)
+        rz.backward(fr, dls, grads=grads, stats=stats)
         return fr
 
     log("warmup %d steps" % args.warmup)
@@ -175,7 +183,7 @@ def main():
     ins = rz.inspect(fr)
     E = int(ins["pixel_last"].to(torch.int64).sum().item())
     stats1 = new_stats(st.n, dev)
-    rz.backward(fr, [dl], grads=grads, stats=stats1)
+    rz.backward(fr, dls, grads=grads, stats=stats1)
     torch.cuda.synchronize()
     F = int(stats1["C"].to(torch.int64).sum().item())
     info = dict(ins["info"])
@@ -260,8 +268,13 @@ def main():
     roof["launch_ms"] = stages[dom]
     roof["work_per_launch"] = work
 
+    serving = None
+    if not args.no_serving:
+        from paper_2503_01199_amd.serve import serve_benchmark
+        serving = serve_benchmark(rz, n_warmup=200, n_measured=args.serve_requests, rate=200.0, log=log)
+
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and len(cams) == 1:
         threads = min(16, os.cpu_count() or 1)
         log("timing the FP64 oracle on %d rows with %d threads" % (args.cpu_rows, threads))
         cpu = cpu_baseline(scene_sorted, cam, args.cpu_rows, threads)
@@ -279,7 +292,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "gaussians": st.n, "sh_degree": st.sh_degree, "views": 1,
+        "config": {"workload": desc, "gaussians": st.n, "sh_degree": st.sh_degree, "views": len(cams),
                    "width": cam.width, "height": cam.height, "precision": "fp32", "cluster_cull": cull,
                    "morton_ordered": True},
         "p50_ms": round(percentile(times, 50), 4),
@@ -289,6 +302,7 @@ def main():
         "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

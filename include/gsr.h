@@ -53,7 +53,8 @@ typedef enum {
 
 #define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile */
 #define GSR_CLUSTER 128      /* primitives per cluster (Sec. 3.2.2) */
-#define GSR_MAX_VIEWS 64     /* views per gsr_forward / gsr_backward call */
+#define GSR_MAX_VIEWS 64     /* views per gsr_forward / gsr_backward call, and per gsr_raster_batch */
+#define GSR_MAX_BATCH 16     /* prepared frames per gsr_raster_batch call */
 
 typedef struct gsr_context gsr_context;
 
@@ -140,7 +141,8 @@ typedef struct {
  *   compact2full u32[slots]: full Gaussian index of each compact slot (0xffffffff: none)
  *   inst_tile   u32[M], inst_record u32[M]: instances sorted by (tile, depth, record)
  *   ranges      u32[tiles][2]: [start, end) of each tile's instances
- *   pixel_rgb   f32[pixels][3], pixel_T f32[pixels], pixel_last u32[pixels]
+ *   pixel_rgb   f64[pixels][3] (the composite, background included, accumulated in FP64),
+ *   pixel_T f32[pixels], pixel_last u32[pixels]
  *                 (list position + 1 of the last blended instance)
  *   grad2d      f32[R][12] (after gsr_backward): d/du, d/dv, d/da, d/db, d/dc, d/do,
  *                 d/dred, d/dgreen, d/dblue, S, C, 0 of each record
@@ -155,7 +157,7 @@ typedef struct {
   const uint32_t *inst_tile;
   const uint32_t *inst_record;
   const uint32_t *ranges;
-  const float *pixel_rgb;
+  const double *pixel_rgb;
   const float *pixel_T;
   const uint32_t *pixel_last;
   const float *grad2d;
@@ -193,10 +195,38 @@ gsr_status gsr_forward(gsr_context *ctx, const gsr_scene *scene, const gsr_camer
                        const gsr_options *opts, void *workspace, size_t ws_bytes, float *const *images,
                        void *stream);
 
+/* Every stage of gsr_forward before the raster (cluster cull and compaction of
+ * Sec. 3.2, projection, depth sort, binning, tile sort, tile ranges and the raster
+ * schedule), enqueued on `stream` with no host wait. Same arguments, validation
+ * and errors as gsr_forward, without images. The frame is then rendered by
+ * gsr_raster_batch, alone or together with other prepared frames. */
+gsr_status gsr_prepare(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
+                       const gsr_options *opts, void *workspace, size_t ws_bytes, void *stream);
+
+/* Bytes of the batch workspace that gsr_raster_batch needs for these prepared
+ * frames (4 per tile, rounded up to 256). */
+gsr_status gsr_raster_batch_workspace_size(gsr_context *ctx, int32_t n, const void *const *workspaces,
+                                           size_t *bytes);
+
+/* One forward-raster launch (Sec. 3, Eq. (1)) over all tiles of n prepared frames
+ * (1 <= n <= GSR_MAX_BATCH, distinct workspaces; any scenes and image sizes; at
+ * most GSR_MAX_VIEWS views in total), scheduled longest tile list first across the frames. images[i][v] is
+ * frame i's view v: a device pointer to f32 [3, H, W], overwritten. The frames'
+ * gsr_prepare work must be complete or enqueued earlier on `stream` (make `stream`
+ * wait for the streams that prepared them). A frame's images are bitwise equal to
+ * rendering it alone: tiles are independent and the forward has no atomics.
+ * batch_ws: device memory, 256-byte aligned, at least
+ * gsr_raster_batch_workspace_size bytes, overwritten (GSR_ERR_WORKSPACE_TOO_SMALL
+ * otherwise). Each frame can then be inspected, and differentiated by
+ * gsr_backward with the same precision. */
+gsr_status gsr_raster_batch(gsr_context *ctx, int32_t n, const void *const *workspaces, float *const *const *images,
+                            int32_t precision, void *batch_ws, size_t batch_ws_bytes, void *stream);
+
 /* Backward of the last gsr_forward on `workspace` with the same scene, cameras and
  * options (Sec. 3, Eq. (3); App. A.1-A.2). dL_dimages[v] is a device pointer to
  * f32 [3, height_v, width_v]. grads are overwritten; stats (nullable; used when
- * opts->stats = 1) are accumulated. Fully asynchronous. */
+ * opts->stats = 1) are accumulated. opts->precision must be the forward's. Fully
+ * asynchronous. */
 gsr_status gsr_backward(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
                         const gsr_options *opts, void *workspace, size_t ws_bytes,
                         const float *const *dL_dimages, const gsr_grads *grads, const gsr_stats *stats,

@@ -29,6 +29,7 @@ struct FrameRecord {
   int64_t pixel_base[GSR_MAX_VIEWS];
   hipEvent_t done = nullptr;           // recorded after the frame's last kernel
   int backwards = 0;                   // backward passes run on this frame
+  int precision = -1;                  // precision of the forward raster (-1: prepared, not rastered)
 };
 
 }  // namespace
@@ -184,7 +185,7 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.offsets = P.take<uint32_t>(nr + 1);
   f.ranges = P.take<uint32_t>(2 * (size_t)f.tiles);
   f.tile_order = P.take<uint32_t>((size_t)f.tiles);
-  f.pix_rgb = P.take<float>(3 * (size_t)f.pixels);
+  f.pix_rgb = P.take<double>(3 * (size_t)f.pixels);
   f.pix_T = P.take<float>((size_t)f.pixels);
   f.pix_last = P.take<uint32_t>((size_t)f.pixels);
   f.grad2d = P.take<float>(gsr::kGrad2D * std::max<size_t>(nr, 1));
@@ -325,19 +326,19 @@ gsr_status gsr_workspace_size(gsr_context* ctx, const gsr_scene* scene, const gs
   return GSR_OK;
 }
 
-gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
-                       const gsr_options* opts, void* workspace, size_t ws_bytes, float* const* images,
-                       void* stream) {
-  if (!ctx) return GSR_ERR_INVALID_ARG;
+namespace {
+
+// Every stage of a frame up to the raster schedule (Cluster-Cull-Compact,
+// preprocess, depth sort, offsets, emission, tile sort, ranges, tile order),
+// enqueued on `s` without any host wait.
+gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                         const gsr_options* opts, void* workspace, size_t ws_bytes, hipStream_t s, FrameRecord** out) {
   gsr_status st;
   if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
       (st = validate_records(ctx, scene, V)))
     return st;
   if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  if (!images) return fail(ctx, GSR_ERR_INVALID_ARG, "images is NULL");
-  for (int v = 0; v < V; ++v)
-    if (!images[v]) return fail(ctx, GSR_ERR_INVALID_ARG, "images[%d] is NULL", v);
   int64_t cap = instances_for_bytes(scene, cams, V, ws_bytes);
   if (cap < 0) {
     ctx->required = bytes_for_instances(scene, cams, V, 16 * (int64_t)scene->n + 1024);
@@ -349,14 +350,13 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
   const size_t total = plan_frame(scene, cams, V, cap, workspace, f);
   if (total > ws_bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: workspace plan exceeds its size");
 
-  DeviceGuard guard(ctx->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
   FrameRecord& fr = ctx->frames[workspace];
   if (!fr.done && (st = check_hip(ctx, hipEventCreateWithFlags(&fr.done, hipEventDisableTiming), "frame event")))
     return st;
   fr.scene = *scene;
   std::memcpy(fr.cams, cams, sizeof(gsr_camera) * V);
   fr.backwards = 0;
+  fr.precision = -1;
 
   ViewDev hv[GSR_MAX_VIEWS];
   fill_views(cams, V, hv);
@@ -418,16 +418,124 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
     gsr::launch_tile_ranges(f, f.inst_tile, cap, s);
     gsr::launch_tile_order(f, s);
   }
+  if ((st = check_hip(ctx, hipGetLastError(), "frame launches"))) return st;
+  if ((st = check_hip(ctx, hipEventRecord(fr.done, s), "frame event"))) return st;
+  fr.f = f;
+  *out = &fr;
+  return GSR_OK;
+}
+
+}  // namespace
+
+gsr_status gsr_prepare(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                       const gsr_options* opts, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  DeviceGuard guard(ctx->device);
+  FrameRecord* fr = nullptr;
+  return prepare_frame(ctx, scene, cams, V, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream), &fr);
+}
+
+gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                       const gsr_options* opts, void* workspace, size_t ws_bytes, float* const* images,
+                       void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (!images) return fail(ctx, GSR_ERR_INVALID_ARG, "images is NULL");
+  for (int v = 0; v < V && v < GSR_MAX_VIEWS; ++v)
+    if (!images[v]) return fail(ctx, GSR_ERR_INVALID_ARG, "images[%d] is NULL", v);
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FrameRecord* fr = nullptr;
+  gsr_status st = prepare_frame(ctx, scene, cams, V, opts, workspace, ws_bytes, s, &fr);
+  if (st) return st;
   gsr::ImagePtrs ip;
   std::memset(&ip, 0, sizeof(ip));
   for (int v = 0; v < V; ++v) ip.p[v] = images[v];
   {
     StageScope sc_(ctx, GSR_STAGE_RASTER_FWD, s);
-    gsr::launch_raster_fwd(f, ip, opts->precision, s);
+    gsr::launch_raster_fwd(fr->f, ip, opts->precision, s);
   }
-  if ((st = check_hip(ctx, hipGetLastError(), "forward launches"))) return st;
-  if ((st = check_hip(ctx, hipEventRecord(fr.done, s), "frame event"))) return st;
-  fr.f = f;
+  if ((st = check_hip(ctx, hipGetLastError(), "forward raster"))) return st;
+  if ((st = check_hip(ctx, hipEventRecord(fr->done, s), "frame event"))) return st;
+  fr->precision = opts->precision;
+  return GSR_OK;
+}
+
+gsr_status gsr_raster_batch_workspace_size(gsr_context* ctx, int32_t n, const void* const* workspaces,
+                                           size_t* bytes) {
+  if (!ctx || !bytes || !workspaces || n < 1 || n > gsr::kMaxBatch)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_raster_batch_workspace_size");
+  uint64_t tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    auto it = ctx->frames.find(workspaces[i]);
+    if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "frame %d was not prepared", i);
+    tiles += (uint64_t)it->second.f.tiles;
+  }
+  *bytes = (size_t)((tiles * 4 + kAlign - 1) & ~(uint64_t)(kAlign - 1));
+  return GSR_OK;
+}
+
+gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* workspaces, float* const* const* images,
+                            int32_t precision, void* batch_ws, size_t batch_ws_bytes, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (n < 1 || n > gsr::kMaxBatch || !workspaces || !images)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "n = %d not in [1, %d] or NULL arrays", n, gsr::kMaxBatch);
+  if (precision != GSR_FP32 && precision != GSR_FP16_BLEND)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "unknown precision %d", precision);
+  gsr::FrameTable tab;
+  std::memset(&tab, 0, sizeof(tab));
+  gsr::ImagePtrs ip;
+  std::memset(&ip, 0, sizeof(ip));
+  FrameRecord* frs[gsr::kMaxBatch];
+  uint64_t tiles = 0;
+  int views = 0;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < i; ++j)
+      if (workspaces[j] == workspaces[i]) return fail(ctx, GSR_ERR_INVALID_ARG, "frame %d appears twice", i);
+    auto it = ctx->frames.find(workspaces[i]);
+    if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "frame %d was not prepared", i);
+    FrameRecord& fr = it->second;
+    const Frame& f = fr.f;
+    if (views + f.V > GSR_MAX_VIEWS) return fail(ctx, GSR_ERR_INVALID_ARG, "more than %d views in a batch", GSR_MAX_VIEWS);
+    if (!images[i]) return fail(ctx, GSR_ERR_INVALID_ARG, "images[%d] is NULL", i);
+    for (int v = 0; v < f.V; ++v) {
+      if (!images[i][v]) return fail(ctx, GSR_ERR_INVALID_ARG, "images[%d][%d] is NULL", i, v);
+      ip.p[views + v] = images[i][v];
+    }
+    gsr::FrameRef& r = tab.f[i];
+    r.views = f.views;
+    r.ranges = f.ranges;
+    r.inst_rec = f.inst_rec;
+    r.rec = f.rec;
+    r.pix_rgb = f.pix_rgb;
+    r.pix_T = f.pix_T;
+    r.pix_last = f.pix_last;
+    r.V = f.V;
+    r.img_base = views;
+    tab.first[i] = (uint32_t)tiles;
+    tiles += (uint64_t)f.tiles;
+    views += f.V;
+    frs[i] = &fr;
+  }
+  if (tiles >= ((uint64_t)1 << 31)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles in a batch");
+  tab.first[n] = (uint32_t)tiles;
+  tab.n = n;
+  const size_t need = (size_t)((tiles * 4 + kAlign - 1) & ~(uint64_t)(kAlign - 1));
+  if (!batch_ws || batch_ws_bytes < need) {
+    ctx->required = need;
+    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "batch workspace of %zu bytes < %zu", batch_ws_bytes, need);
+  }
+  if (((uintptr_t)batch_ws & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "batch workspace not aligned");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* order = static_cast<uint32_t*>(batch_ws);
+  gsr::launch_batch_tile_order(tab, (uint32_t)tiles, order, s);
+  gsr::launch_raster_fwd_batch(tab, order, (uint32_t)tiles, ip, precision, s);
+  gsr_status st = check_hip(ctx, hipGetLastError(), "batched raster");
+  if (st) return st;
+  for (int i = 0; i < n; ++i) {
+    if ((st = check_hip(ctx, hipEventRecord(frs[i]->done, s), "frame event"))) return st;
+    frs[i]->precision = precision;
+  }
   return GSR_OK;
 }
 
@@ -456,6 +564,9 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
   if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "no forward was run on this workspace");
   FrameRecord& fr = it->second;
   const Frame& f = fr.f;
+  if (fr.precision < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "the frame was prepared but never rastered");
+  if (fr.precision != opts->precision)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "precision %d differs from the forward's %d", opts->precision, fr.precision);
   if (f.n != scene->n || f.V != V || fr.scene.sh_degree != scene->sh_degree)
     return fail(ctx, GSR_ERR_INVALID_ARG, "scene or views differ from the forward");
   {

@@ -64,17 +64,31 @@ __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t*
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4096;
 
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __restrict__ ranges, int64_t T,
-                                                              uint32_t* __restrict__ order) {
+// List length of concatenated tile i: one frame, or a batch of frames (a short
+// uniform search over the frames' first tiles).
+struct OneFrame {
+  const uint32_t* ranges;
+  __device__ uint32_t len(int64_t i) const { return ranges[2 * i + 1] - ranges[2 * i]; }
+};
+struct ManyFrames {
+  FrameTable tab;
+  __device__ uint32_t len(int64_t i) const {
+    int f = 0;
+    while (f + 1 < tab.n && tab.first[f + 1] <= (uint32_t)i) ++f;
+    const int64_t t = i - tab.first[f];
+    return tab.f[f].ranges[2 * t + 1] - tab.f[f].ranges[2 * t];
+  }
+};
+
+template <class Len>
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, uint32_t* __restrict__ order) {
   __shared__ uint32_t h[kOrderBuckets];
   __shared__ uint32_t wsum[kOrderThreads / 64];
   const int t = threadIdx.x;
   for (int b = t; b < kOrderBuckets; b += kOrderThreads) h[b] = 0;
   __syncthreads();
-  for (int64_t i = t; i < T; i += kOrderThreads) {
-    const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
-    atomicAdd(&h[kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1))], 1u);
-  }
+  for (int64_t i = t; i < T; i += kOrderThreads)
+    atomicAdd(&h[kOrderBuckets - 1 - min(L.len(i), (uint32_t)(kOrderBuckets - 1))], 1u);
   __syncthreads();
   // exclusive scan of the buckets, 4 per thread
   uint32_t v[4], sum = 0;
@@ -99,8 +113,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
   }
   __syncthreads();
   for (int64_t i = t; i < T; i += kOrderThreads) {
-    const uint32_t len = ranges[2 * i + 1] - ranges[2 * i];
-    const uint32_t pos = atomicAdd(&h[kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1))], 1u);
+    const uint32_t pos = atomicAdd(&h[kOrderBuckets - 1 - min(L.len(i), (uint32_t)(kOrderBuckets - 1))], 1u);
     order[pos] = (uint32_t)i;
   }
 }
@@ -109,7 +122,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const uint32_t* __
 
 void launch_tile_order(const Frame& f, hipStream_t s) {
   if (f.tiles <= 0) return;
-  k_tile_order<<<1, kOrderThreads, 0, s>>>(f.ranges, f.tiles, f.tile_order);
+  k_tile_order<OneFrame><<<1, kOrderThreads, 0, s>>>(OneFrame{f.ranges}, f.tiles, f.tile_order);
+}
+
+void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, hipStream_t s) {
+  if (total_tiles == 0) return;
+  k_tile_order<ManyFrames><<<1, kOrderThreads, 0, s>>>(ManyFrames{tab}, total_tiles, order);
 }
 
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {

@@ -84,7 +84,7 @@ struct Frame {
   uint32_t* inst_rec;
   uint32_t* ranges;         // [tiles][2]
   uint32_t* tile_order;     // [tiles] raster schedule: tiles by descending list length
-  float* pix_rgb;           // [pixels][3]
+  double* pix_rgb;          // [pixels][3] final colour accumulated in FP64
   float* pix_T;             // [pixels]
   uint32_t* pix_last;       // [pixels]
   float* grad2d;            // [nrec][12]
@@ -148,6 +148,30 @@ struct ConstImagePtrs {
   const float* p[GSR_MAX_VIEWS];
 };
 void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s);
+
+// Batched forward raster over several prepared frames (kernel-argument table).
+constexpr int kMaxBatch = GSR_MAX_BATCH;
+struct FrameRef {
+  const ViewDev* views;
+  const uint32_t* ranges;
+  const uint32_t* inst_rec;
+  const Record* rec;
+  double* pix_rgb;
+  float* pix_T;
+  uint32_t* pix_last;
+  int32_t V;
+  int32_t img_base;  // first image pointer of the frame in the batch's ImagePtrs
+};
+struct FrameTable {
+  FrameRef f[kMaxBatch];
+  uint32_t first[kMaxBatch + 1];  // concatenated tile index of each frame's first tile
+  int32_t n;
+};
+static_assert(sizeof(FrameTable) + sizeof(ImagePtrs) <= 3584, "the batch table travels in the kernel arguments");
+void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, uint32_t total_tiles,
+                             const ImagePtrs& images, int precision, hipStream_t s);
+// Longest-list-first order of the concatenated tiles of a batch of frames.
+void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, hipStream_t s);
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s);
 
 // morton.hip

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
                                                    const Record* __restrict__ rec, ConstImagePtrs dL,
-                                                   const float* __restrict__ pix_rgb,
+                                                   const double* __restrict__ pix_rgb,
                                                    const uint32_t* __restrict__ pix_last,
                                                    float* __restrict__ grad2d) {
   __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
@@ -96,15 +96,18 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
 
   // Per pixel: upstream gradient g, g . I_final, g . (colour composited so far), T
   // and the list position after its last blend. The colour behind entry k is
-  // I_final - C_{<=k}, so g . (colour behind) = gIf - gC.
-  float gI[4][3], gIf[4], gC[4], T[4];
+  // I_final - C_{<=k}, so g . (colour behind) = gIf - gC; both run in FP64, as the
+  // forward's colour sum does, so the difference keeps its relative precision
+  // behind entries near the front of deep lists.
+  float gI[4][3], T[4];
+  double gIf[4], gC[4];
   uint32_t last[4];
   uint32_t mymax = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     T[j] = 1.0f;
-    gC[j] = 0.0f;
-    gIf[j] = 0.0f;
+    gC[j] = 0.0;
+    gIf[j] = 0.0;
     last[j] = 0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) gI[j][ch] = 0.0f;
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
         gI[j][ch] = g_img[ch * plane + o];
-        gIf[j] = __builtin_fmaf(gI[j][ch], pix_rgb[3 * pp + ch], gIf[j]);
+        gIf[j] = __builtin_fma((double)gI[j][ch], pix_rgb[3 * pp + ch], gIf[j]);
       }
       mymax = max(mymax, last[j]);
     }
@@ -162,10 +165,11 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
           dcr = __builtin_fmaf(wt, gI[j][0], dcr);
           dcg = __builtin_fmaf(wt, gI[j][1], dcg);
           dcb = __builtin_fmaf(wt, gI[j][2], dcb);
-          gC[j] = __builtin_fmaf(wt, gc, gC[j]);
+          gC[j] = __builtin_fma((double)wt, (double)gc, gC[j]);
           const float one_m_a = 1.0f - a;
+          const float behind = (float)(gIf[j] - gC[j]);  // g . (colour behind this entry)
           // dL/dalpha = T (g . c) - (g . colour behind) / (1 - alpha)
-          const float dA = __builtin_fmaf(T[j], gc, -(gIf[j] - gC[j]) * __builtin_amdgcn_rcpf(one_m_a));
+          const float dA = __builtin_fmaf(T[j], gc, -behind * __builtin_amdgcn_rcpf(one_m_a));
           const float go = (araw <= alpha_clamp<P>()) ? dA * G : 0.0f;
           const float dE = go * o;
           S0 += dE;

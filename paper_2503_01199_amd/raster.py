@@ -210,6 +210,50 @@ class Rasterizer:
         self._check(st, "gsr_forward")
         raise L.GsrError(L.GSR_ERR_WORKSPACE_TOO_SMALL, "gsr_forward: workspace did not converge")
 
+    def prepare(self, scene: SceneTensors, cameras, cluster_cull=True, stats=True,
+                workspace: Workspace | None = None, stream=None) -> Frame:
+        """Enqueues every stage before the raster (gsr_prepare) on `stream` (a
+        torch.cuda.Stream; default the current stream); render with raster_batch."""
+        V = len(cameras)
+        cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
+        opts = self.options(L.GSR_FP32, cluster_cull, stats)
+        sc = scene.struct()
+        ws = workspace if workspace is not None else Workspace(self.device)
+        if ws.buf is None:
+            nbytes = ctypes.c_size_t()
+            self._check(self.lib.gsr_workspace_size(self.ctx, ctypes.byref(sc), cams, V, ctypes.byref(opts),
+                                                    8 * scene.n + 4096, ctypes.byref(nbytes)), "gsr_workspace_size")
+            ws.ensure(nbytes.value)
+        s = self._stream() if stream is None else stream.cuda_stream
+        self._check(self.lib.gsr_prepare(self.ctx, ctypes.byref(sc), cams, V, ctypes.byref(opts), ws.ptr, ws.nbytes,
+                                         s), "gsr_prepare")
+        ws.owner = (self.lib, self.ctx)
+        return Frame(scene, list(cameras), cams, opts, ws, None, {})
+
+    def raster_batch(self, frames, precision=L.GSR_FP32, batch_workspace: Workspace | None = None, stream=None,
+                     images=None):
+        """One gsr_raster_batch launch over prepared frames on `stream`; returns (and
+        stores in each frame) the list of its [3, H, W] images."""
+        n = len(frames)
+        wsp = (ctypes.c_void_p * n)(*[f.workspace.ptr for f in frames])
+        if images is None:
+            images = [[torch.empty((3, c.height, c.width), dtype=torch.float32, device=self.device) for c in f.cameras]
+                      for f in frames]
+        rows = [(ctypes.c_void_p * len(im))(*[t.data_ptr() for t in im]) for im in images]
+        table = (ctypes.POINTER(ctypes.c_void_p) * n)(*[ctypes.cast(r, ctypes.POINTER(ctypes.c_void_p)) for r in rows])
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.gsr_raster_batch_workspace_size(self.ctx, n, wsp, ctypes.byref(nbytes)),
+                    "gsr_raster_batch_workspace_size")
+        bws = batch_workspace if batch_workspace is not None else Workspace(self.device)
+        bws.ensure(max(nbytes.value, _ALIGN))
+        s = self._stream() if stream is None else stream.cuda_stream
+        self._check(self.lib.gsr_raster_batch(self.ctx, n, wsp, table, int(precision), bws.ptr, bws.nbytes, s),
+                    "gsr_raster_batch")
+        for f, im in zip(frames, images):
+            f.images = im
+            f.opts.precision = int(precision)
+        return images
+
     def _inspect(self, ws: Workspace, bufs):
         info = L.GsrFrameInfo()
         st = self.lib.gsr_frame_inspect(self.ctx, ws.ptr, ctypes.byref(info), None if bufs is None else ctypes.byref(bufs))
@@ -281,7 +325,7 @@ class Rasterizer:
             inst_tile=ws.view(b.inst_tile, M, u32) if M > 0 else torch.zeros(0, dtype=u32, device=self.device),
             inst_record=ws.view(b.inst_record, M, u32) if M > 0 else torch.zeros(0, dtype=u32, device=self.device),
             ranges=ws.view(b.ranges, 2 * info.tiles, u32).view(-1, 2),
-            pixel_rgb=ws.view(b.pixel_rgb, 3 * P, f32).view(P, 3),
+            pixel_rgb=ws.view(b.pixel_rgb, 3 * P, torch.float64).view(P, 3),
             pixel_T=ws.view(b.pixel_T, P, f32),
             pixel_last=ws.view(b.pixel_last, P, u32),
             grad2d=ws.view(b.grad2d, 12 * R, f32).view(R, 12),

@@ -1,0 +1,238 @@
+"""The 3M-Gaussian unbounded scene seen by 8 orbit views at 1920x1080, rendered as
+one frame (one raster launch over the 8 x 8,160 tiles, longest lists first):
+gradients through the torch.autograd.Function checked by finite differences on a
+random 5,000-Gaussian subset, and against the FP64 oracle on a 128x128 crop.
+
+Finite differences run on the GPU FP32 forward with the loss summed in FP64, with
+a per-element step h: 1e-3 of the Gaussian's largest scale for the means, 1e-3
+for log-scales and logits, 1e-3 of the quaternion's norm and 1e-3 of the subset's
+rms SH coefficient (a fixed fraction of each group's rms would move the means of
+this radius-100 scene by up to ~15 px). Any positive per-element scaling gives a
+valid directional derivative: (L(+) - L(-)) / 2 = sum g h d.
+
+The loss is only piecewise smooth: it jumps wherever a pixel-Gaussian pair
+crosses alpha = 1/255 (by about 1e-3) and wherever two overlapping Gaussians swap
+depth order (by up to their full contribution). Moving the geometry or opacity of
+5,000 Gaussians of this dense scene at once crosses or swaps many pairs, mostly
+in the middle of lists where no pixel's last blended position changes (measured:
+a 4 % spread for opacity alone, 6 % for all parameters at 1e-3 steps, worse at
+larger steps), so no screening makes such a difference usable. The check is:
+- 32 Rademacher directions over the SH coefficients of all 5,000 subset Gaussians
+  (the loss is linear in SH up to the colour clamp): each within 1e-2.
+- 200 single-scalar probes over all 59 parameters (one subset Gaussian, one
+  parameter, the step above). A probe whose stencil changes the tile lists, any
+  pixel's last blended position or any Gaussian's blended-fragment count (which
+  catches the cutoff crossings and order swaps that touch a blend) is replaced by
+  another; about one in five survives. Moving all 59 parameters of even one
+  visible Gaussian at once changes that state every time (0 of 384 tried), and a
+  step small enough to avoid it leaves the difference below FP32 noise, so the
+  geometry is differenced one scalar at a time. Tolerance 5e-2 against
+  max(|g|, 1e-2 max |g| of the group), which also absorbs FP32 forward noise.
+The gradient is pinned exactly by the oracle on the crop (second test).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from helpers import GRAD_TOL, ensure_built, grad_errors
+from paper_2503_01199_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+@pytest.fixture(scope="module")
+def rz():
+    ensure_built()
+    from paper_2503_01199_amd.raster import Rasterizer
+    return Rasterizer(0)
+
+
+@pytest.fixture(scope="module")
+def c4(rz):
+    from paper_2503_01199_amd.raster import SceneTensors
+    print("generating the 3M unbounded scene", flush=True)
+    sc = scenes.unbounded_scene()
+    cams = scenes.orbit_cameras(8)
+    st = SceneTensors.from_scene(sc, rz.device)
+    perm, _ = rz.morton_order(st.means)
+    arrs = rz.apply_permutation(perm, list(st.tensors()))
+    sc = sc.permuted(perm.cpu().numpy())
+    torch.cuda.synchronize()
+    return sc, cams, [a.contiguous() for a in arrs]
+
+
+def _weights(cams):
+    out = []
+    for v, c in enumerate(cams):
+        w, gt = scenes.l1_weights((3, c.height, c.width), config=4, salt=v)
+        out.append((w, gt))
+    return out
+
+
+def test_c4_frame_and_fd_gradcheck(rz, c4):
+    from paper_2503_01199_amd.autograd import rasterize
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace, new_stats
+    sc, cams, arrs = c4
+    dev = rz.device
+    wg = [(torch.as_tensor(w, device=dev, dtype=torch.float64), torch.as_tensor(g, device=dev, dtype=torch.float64))
+          for w, g in _weights(cams)]
+
+    def loss64(images):
+        return sum(float((w * (img.double() - g).abs()).sum().item()) for img, (w, g) in zip(images, wg))
+
+    params = [a.clone().requires_grad_(True) for a in arrs]
+    print("C4 forward + backward through autograd", flush=True)
+    imgs = rasterize(*params, cams, sc.sh_degree, rasterizer=rz)
+    loss = sum((w * (img.double() - g).abs()).sum() for img, (w, g) in zip(imgs, wg))
+    loss.backward()
+    grads = [p.grad.detach() for p in params]
+
+    ws = Workspace(dev)
+    fr = rz.forward(SceneTensors(*arrs, sc.sh_degree), cams, workspace=ws)
+    info = fr.info
+    print("C4 frame: %s" % info, flush=True)
+    assert info["views"] == 8 and info["tiles"] == 8 * 120 * 68
+    for a, b in zip(imgs, fr.images):
+        assert torch.equal(a.detach(), b)  # the forward is deterministic
+    ins = rz.inspect(fr)
+    T = ins["pixel_T"]
+    assert bool((T >= 1e-4).all()) and bool((T <= 1).all())
+
+    rng = np.random.default_rng(44)
+    sub = torch.as_tensor(np.sort(rng.choice(sc.n, 5000, replace=False)), device=dev)
+    smax = torch.exp(arrs[1][sub].max(dim=1).values)  # largest scale of each subset Gaussian
+    sh_rms = float(arrs[4][sub].pow(2).mean().sqrt().item())
+    qn = arrs[2][sub].norm(dim=1)
+    steps = [1e-3 * smax[:, None].expand(-1, 3), torch.full((5000, 3), 1e-3, device=dev),
+             1e-3 * qn[:, None].expand(-1, 4), torch.full((5000,), 1e-3, device=dev),
+             torch.full(tuple(arrs[4][sub].shape), 1e-3 * sh_rms, device=dev)]
+
+    zero_dl = [torch.zeros((3, c.height, c.width), device=dev) for c in cams]
+
+    def render_loss(arrays, counts=False):
+        f = rz.forward(SceneTensors(*arrays, sc.sh_degree), cams, workspace=ws)
+        i = rz.inspect(f)
+        lists = torch.cat([i["inst_tile"], i["inst_record"]])
+        C = None
+        if counts:
+            stats = new_stats(sc.n, dev)
+            rz.backward(f, zero_dl, stats=stats)
+            C = stats["C"]
+        return loss64(f.images), i["pixel_last"].clone(), lists, C
+
+    def perturbed(sign_dirs):
+        out = []
+        for a, d in zip(arrs, sign_dirs):
+            b = a.clone()
+            if d is not None:
+                b[sub] = (a[sub].double() + d.double()).float()
+            out.append(b)
+        return out
+
+    def same_state(a, b):
+        return (torch.equal(a[1], b[1]) and a[2].shape == b[2].shape and torch.equal(a[2], b[2])
+                and torch.equal(a[3], b[3]))
+
+    for k in range(32):
+        d = [torch.zeros_like(h) for h in steps[:4]]
+        d.append(torch.as_tensor(rng.choice([-1.0, 1.0], size=tuple(steps[4].shape)), device=dev,
+                                 dtype=torch.float32) * steps[4])
+        # the step actually taken after FP32 rounding of theta +/- h d
+        ap, am = perturbed(d), perturbed([-x for x in d])
+        lp = render_loss(ap)[0]
+        lm = render_loss(am)[0]
+        fd = (lp - lm) / 2.0
+        an = sum(float((g[sub].double() * (p[sub].double() - m[sub].double()) / 2.0).sum().item())
+                 for g, p, m in zip(grads, ap, am))
+        rel = abs(fd - an) / max(abs(an), 1e-30)
+        print("SH direction %2d over 5000 Gaussians: fd %+.6e analytic %+.6e rel %.2e" % (k, fd, an, rel), flush=True)
+        assert rel < 1e-2
+
+    gnp = [g[sub].cpu().numpy().reshape(5000, -1) for g in grads]
+    hs = [h.cpu().numpy().reshape(5000, -1) for h in steps]
+    checked, tried = 0, 0
+    while checked < 200 and tried < 1200:
+        tried += 1
+        gi = int(rng.integers(0, 5))
+        gmax = np.abs(gnp[gi]).max()
+        cand = np.argwhere(np.abs(gnp[gi]) > 1e-2 * gmax)
+        if len(cand) == 0:
+            continue
+        row, col = cand[int(rng.integers(0, len(cand)))]
+        h = float(hs[gi][row, col])
+        ap = [a.clone() for a in arrs]
+        am = [a.clone() for a in arrs]
+        idx = int(sub[row].item())
+        xv = ap[gi].view(sc.n, -1)[idx, col].item()
+        ap[gi].view(sc.n, -1)[idx, col] = xv + h
+        am[gi].view(sc.n, -1)[idx, col] = xv - h
+        step = ap[gi].view(sc.n, -1)[idx, col].item() - am[gi].view(sc.n, -1)[idx, col].item()
+        rp = render_loss(ap, counts=True)
+        rm = render_loss(am, counts=True)
+        if not same_state(rp, rm):
+            continue
+        lp, lm = rp[0], rm[0]
+        fd = (lp - lm) / step
+        an = float(gnp[gi][row, col])
+        rel = abs(fd - an) / max(abs(an), 1e-2 * gmax)
+        assert rel < 5e-2, (GROUPS[gi], idx, col, fd, an)
+        checked += 1
+    print("single-scalar probes: %d checked of %d tried" % (checked, tried))
+    assert checked == 200
+
+
+def test_c4_crop_gradient_matches_oracle(rz, c4):
+    """Analytic GPU gradient against the FP64 oracle, loss restricted to the 128x128
+    crop at the centre of view 0 (all other pixels and views get zero upstream)."""
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    sc, cams, arrs = c4
+    cam = cams[0]
+    x0, y0 = cam.width // 2 - 64, cam.height // 2 - 64
+    win = (x0, x0 + 128, y0, y0 + 128)
+    ref = orc.render(sc, cam, mode=2, window=win, threads=8)
+    w, gt = _weights(cams)[0]
+    g = orc.l1_grad(ref["image"], w, gt).astype(np.float32)
+    mask = np.zeros((cam.height, cam.width), bool)
+    mask[win[2]:win[3], win[0]:win[1]] = True
+    g[:, ~mask] = 0.0
+    g[:, ref["fragile"]] = 0.0
+    ob = orc.backward(sc, cam, g.astype(np.float64), mode=2, window=win, threads=8)
+    dev = rz.device
+    fr = rz.forward(SceneTensors(*arrs, sc.sh_degree), cams, workspace=Workspace(dev))
+    crop = (slice(None), slice(win[2], win[3]), slice(win[0], win[1]))
+    img = fr.images[0].cpu().numpy()[crop].astype(np.float64)
+    keep = ~ref["fragile"][win[2]:win[3], win[0]:win[1]]
+    err = np.abs(img - ref["image"][crop]) / np.maximum(1.0, np.abs(ref["image"][crop]))
+    print("C4 crop image max rel %.3g (fragile pixels %d)" % (err[:, keep].max(), int((~keep).sum())))
+    assert err[:, keep].max() < 1e-5
+    # zero upstream outside the crop and in views 1..7 contributes exactly zero to
+    # every gradient (the fragment count C would still count those views' blends,
+    # so it is compared by the single-view backward tests instead)
+    zero = [torch.zeros((3, c.height, c.width), device=dev) for c in cams]
+    zero[0] = torch.as_tensor(g, device=dev)
+    grads = rz.backward(fr, zero)
+    torch.cuda.synchronize()
+    skip = ob["fragile"]
+    C = ob["C"]
+    errs = {}
+    for k in GROUPS:
+        gk = grads[k].cpu().numpy().astype(np.float64).reshape(sc.n, -1)
+        rk = ob[k].reshape(sc.n, -1)
+        e = grad_errors(gk, rk, skip)
+        print("C4 crop gradient %-15s max rel %.3g" % (k, e))
+        floor = 1e-3 * np.abs(rk[~skip]).max()
+        rel = np.abs(gk - rk) / np.maximum(np.abs(rk), floor)
+        rel[skip] = 0
+        for flat in np.argsort(rel.ravel())[::-1][:4]:
+            i, c = divmod(int(flat), rk.shape[1])
+            z = float((np.asarray(cam.R, np.float64).reshape(3, 3) @ sc.means[i].astype(np.float64)
+                       + np.asarray(cam.t, np.float64))[2])
+            print("   worst: gaussian %d comp %d gpu %+.6e oracle %+.6e rel %.3g fragments %d |row| %.3e "
+                  "depth %.2f log-scales %s g2d %s"
+                  % (i, c, gk[i, c], rk[i, c], rel[i, c], C[i], np.abs(rk[i]).max(), z,
+                     np.round(sc.log_scales[i], 2), np.array2string(ob["g2d"][i], precision=3)))
+        errs[k] = e
+    assert max(errs.values()) < GRAD_TOL
