@@ -12,8 +12,8 @@ beforehand, as a trainer does every few epochs; that reorder is timed separately
 
 prints one JSON line: ms per step (mean over K timed steps, p50/p99), per-stage
 times, the roofline of the dominant kernel measured with HIP events on the
-stream it runs on, and the FP64 CPU reference timed on a band of rows of the
-same view, scaled to the full image.
+stream it runs on, the FP64 CPU reference timed on the same view, the FP16-blend
+variant and the render-serving stream (p50/p99 latency, views/s).
 """
 from __future__ import annotations
 
@@ -38,10 +38,39 @@ FP32_PEAK_TFLOPS = 157.3
 # FMAs, 3 behind-colour FMAs, two 3-term dot products, 1 - alpha, reciprocal,
 # dL/dalpha, g_o, dL/dE, the three scanline moments, the opacity sum, its square
 # sum, the count and the transmittance update).
+# HBM traffic per launch of the dominant kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs of this bench (profiles/room-1M-1600x1064_raster_bwd_pmc.md), scaled
+# by the same counters read on a plain 1 GiB device copy (FETCH_SIZE reads half of the
+# bytes copied, WRITE_SIZE all of them). Valid only for the kernel sources the counters
+# were taken on: any change to them makes the bench report traffic = null.
+TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
+                            "sources": ["paper_2503_01199_amd/csrc/raster_bwd.hip",
+                                        "paper_2503_01199_amd/csrc/raster_common.h",
+                                        "paper_2503_01199_amd/csrc/gsr_internal.h"],
+                            "sha1": "a72753822586e3c62b4da88422909f03512d1d5c",
+                            "fetch_kib": 80849.0, "write_kib": 97954.0}}
+FETCH_SCALE = 1048576.0 / 524300.0
+WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
 FWD_FLOP_FRAG = 9
 BWD_FLOP_EVAL = 7
 BWD_FLOP_FRAG = 41
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the recorded counters, or
+    None when they were taken on another workload or its sources have changed since."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None or t["workload"] != workload:
+        return None
+    h = hashlib.sha1()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha1"]:
+        return None
+    return int(round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024))
 
 
 def log(msg):
@@ -78,35 +107,26 @@ def build_workload(name, n_override=None):
     return sc, cams, desc
 
 
-def cpu_baseline(scene, cam, rows, threads):
-    """The FP64 oracle's forward + backward on full-width row bands, extrapolated
-    linearly in the number of rows to the whole image: t(H) = t(1) + (H - 1) slope,
-    slope = (t(R) - t(1)) / (R - 1)."""
+def cpu_baseline(scene, cam, repeats, threads):
+    """The FP64 oracle's forward + backward of the whole view (the same scene, camera
+    and loss as the GPU step), timed `repeats` times; the median is reported."""
     import numpy as np
     import oracle
     from paper_2503_01199_amd import scenes
     oracle.load()
     H, W = cam.height, cam.width
     w, gt = scenes.l1_weights((3, H, W), config=2)
-    y0 = max(0, H // 2 - rows // 2)
-
-    def run(nrows):
-        win = (0, W, y0, y0 + nrows)
+    times = []
+    for _ in range(repeats):
         t = time.perf_counter()
-        r = oracle.render(scene, cam, mode=1, window=win, threads=threads)
+        r = oracle.render(scene, cam, mode=1, threads=threads)
         g = oracle.l1_grad(r["image"], w, gt)
-        g[:, :y0] = 0.0
-        g[:, y0 + nrows:] = 0.0
-        oracle.backward(scene, cam, g, mode=1, window=win, threads=threads)
-        return time.perf_counter() - t
-
-    t1 = run(1)
-    tr = run(rows)
-    slope = max(tr - t1, 0.0) / max(rows - 1, 1)
-    full_s = t1 + (H - 1) * slope
-    return {"value": round(full_s * 1e3, 1), "unit": "ms/iter", "cores": threads, "kind": "oracle",
-            "sample": "FP64 oracle fwd+bwd on %d full-width rows (and on 1 row) of the same 1600x1064 view, "
-                      "%.1f s + %.1f s measured, extrapolated linearly in rows to %d rows" % (rows, tr, t1, H)}
+        oracle.backward(scene, cam, g, mode=1, threads=threads)
+        times.append(time.perf_counter() - t)
+    med = sorted(times)[len(times) // 2]
+    return {"value": round(med * 1e3, 1), "unit": "ms/iter", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle forward + backward of the whole %dx%d view, median of %d runs (%s s)"
+                      % (W, H, repeats, ", ".join("%.2f" % x for x in times))}
 
 
 def main():
@@ -118,8 +138,10 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
     ap.add_argument("--no-cull", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=160)
+    ap.add_argument("--cpu-repeats", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the render-serving stream")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device 3 times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-requests", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -134,6 +156,14 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a HIP device")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "copies": 3}), flush=True)
+        return
     log("generating workload %s" % args.workload)
     scene, cams, desc = build_workload(args.workload, args.n)
     cam = cams[0]
@@ -243,6 +273,8 @@ def main():
 
     # roofline of the dominant kernel (each stage below is one kernel launch)
     dom = max(("raster_bwd", "raster_fwd", "preprocess_bwd", "preprocess"), key=lambda k: stages.get(k, 0.0))
+    roof_kernel = {"raster_bwd": "k_raster_bwd", "raster_fwd": "k_raster_fwd", "preprocess_bwd": "k_sh_bwd",
+                   "preprocess": "k_preprocess_fwd"}[dom]
     dur_s = stages[dom] * 1e-3
     if dom == "raster_bwd":
         work = BWD_FLOP_EVAL * E + BWD_FLOP_FRAG * F
@@ -262,9 +294,8 @@ def main():
             work = nvis * (pbytes + 48 + 4 + 4 + 8 + 4)
         roof = {"bound": "hbm", "achieved": round(work / dur_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = None
-    roof["kernel"] = {"raster_bwd": "k_raster_bwd", "raster_fwd": "k_raster_fwd",
-                      "preprocess_bwd": "k_preprocess_bwd", "preprocess": "k_preprocess_fwd"}[dom]
+    roof["traffic"] = measured_traffic(roof_kernel, desc)
+    roof["kernel"] = roof_kernel
     roof["launch_ms"] = stages[dom]
     roof["work_per_launch"] = work
 
@@ -276,8 +307,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline and len(cams) == 1:
         threads = min(16, os.cpu_count() or 1)
-        log("timing the FP64 oracle on %d rows with %d threads" % (args.cpu_rows, threads))
-        cpu = cpu_baseline(scene_sorted, cam, args.cpu_rows, threads)
+        log("timing the FP64 oracle on the whole view, %d runs on %d threads" % (args.cpu_repeats, threads))
+        cpu = cpu_baseline(scene_sorted, cam, args.cpu_repeats, threads)
 
     out = {
         "metric": METRIC,

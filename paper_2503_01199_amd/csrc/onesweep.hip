@@ -2,10 +2,13 @@
 // look-back, both driven by counts that live in device memory (so a frame is
 // enqueued without waiting on the host).
 //
-// Look-back protocol: every block takes its tile index from an atomic counter (so
-// all lower tiles belong to blocks that are already running or done), publishes
-// its tile aggregate, then walks back over its predecessors' status words until it
-// meets an inclusive prefix, and publishes its own inclusive prefix. A status word
+// Look-back protocol: block b owns tile b and waits only on lower tiles, whose blocks
+// the dispatcher has placed before it (workgroups are dispatched in id order; an
+// atomic ticket per block would cost a serialised device-scope atomic per block on
+// one address, ~20 us per pass here). A block publishes its tile aggregate, then
+// walks back over its predecessors' status words until it meets an inclusive
+// prefix, and publishes its own inclusive prefix. Grids hold one block per tile of
+// the largest possible count; blocks past the count on the device leave at once. A status word
 // is (flag << 30 | value): flag 0 = not ready, 1 = aggregate, 2 = inclusive
 // prefix. Values must stay below 2^30: a larger prefix sets bit 1 of the error word
 // (the result is then wrong but every access stays in bounds). The walk waits only
@@ -32,7 +35,7 @@ __device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
 // (stride `stride` words between tiles). Publishes this tile's inclusive prefix.
 // The walk reads kWindow predecessors per round trip and consumes them in order
 // until an inclusive prefix (tiles below 0 count as an empty prefix).
-constexpr int kWindow = 4;
+constexpr int kWindow = 16;
 
 __device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, int col, uint32_t agg,
                               uint32_t* err) {
@@ -102,14 +105,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
                                                        int64_t n_host, const uint32_t* __restrict__ n_dev,
                                                        uint32_t* __restrict__ total, uint32_t* __restrict__ list,
                                                        uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
-  __shared__ uint32_t s_tile;
   __shared__ uint32_t wsum[kScanThreads / 64];
   __shared__ uint32_t s_excl;
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
-  if (t == 0) s_tile = atomicAdd(ctl, 1u);
-  __syncthreads();
-  const int64_t tile = s_tile;
+  const int64_t tile = blockIdx.x;
   const int64_t base = tile * kScanTile;
   if (base >= n && !(tile == 0 && n == 0)) return;
   uint32_t v[kScanItems];
@@ -154,7 +154,6 @@ constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 items per tile
 constexpr int kHistBlocks = 512;
 constexpr int64_t kHistChunk = 8192;  // keys per histogram block at least
 constexpr int kMaxPasses = 8;
-constexpr int kScatterBlocks = 1024;  // 4 resident blocks (33 KiB LDS each) on each of 256 CUs
 
 // Lanes of the wave holding the same 8-bit digit d (restricted to `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -226,12 +225,10 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
   }
 }
 
-// One pass: each block repeatedly takes the next tile of 2048 items (8 coalesced
-// rounds of 256) until the tiles run out, ranks them stably within the tile (ballot
-// match per wave, counts per (round, wave, digit) in LDS), learns the per-digit
-// counts of all earlier tiles by look-back and scatters. The grid is capped, so a
-// launch sized for the largest possible count costs little when the count on the
-// device is small.
+// One pass: block b takes tile b of 2048 items (8 coalesced rounds of 256), ranks
+// them stably within the tile (ballot match per wave, counts per (round, wave,
+// digit) in LDS), learns the per-digit counts of all earlier tiles by look-back and
+// scatters.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -240,15 +237,12 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
                                                              uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
   __shared__ uint32_t cnt[kSortRounds][4][256];
   __shared__ uint32_t gofs[256];
-  __shared__ uint32_t s_tile;
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
   const int w = t >> 6;
   const int lane = t & 63;
-  for (;;) {
-    if (t == 0) s_tile = atomicAdd(ctl, 1u);
-    __syncthreads();
-    const int64_t tile = s_tile;
+  {
+    const int64_t tile = blockIdx.x;
     const int64_t base = tile * kSortTile;
     if (base >= n) return;  // uniform over the block
     for (int r = 0; r < kSortRounds; ++r)
@@ -291,7 +285,6 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
         vout[pos] = val[r];
       }
     }
-    __syncthreads();  // gofs, cnt and s_tile are reused by the next tile
   }
 }
 
@@ -303,7 +296,7 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   uint32_t* hist = ctl;                       // [passes][256]
   uint32_t* offs = ctl + kMaxPasses * 256;    // [passes][256]
   uint32_t* done = offs + kMaxPasses * 256;   // 1 word (padded to 64)
-  uint32_t* pass_ctl = done + 64;             // per pass: counter + status[tiles][256]
+  uint32_t* pass_ctl = done + 64;             // per pass: 64 reserved words + status[tiles][256]
   const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
   const int64_t pass_words = 64 + tiles * 256;
   int64_t hb = (n_max + kHistChunk - 1) / kHistChunk;
@@ -313,9 +306,8 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   const K* kcur = keys_in;
   const uint32_t* vcur = vals_in;
   int out = 0;
-  const int64_t grid = tiles < kScatterBlocks ? tiles : kScatterBlocks;
   for (int p = 0; p < passes; ++p) {
-    k_os_scatter<K><<<(unsigned)grid, kSortThreads, 0, s>>>(kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p,
+    k_os_scatter<K><<<(unsigned)tiles, kSortThreads, 0, s>>>(kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p,
                                                              offs + p * 256, pass_ctl + p * pass_words, err);
     kcur = kb[out];
     vcur = vb[out];

@@ -10,8 +10,8 @@
 //   dL/dalpha  = T (g . c) - (g . R) / (1 - alpha)
 //   g_o        = dL/dalpha * G  (zero where alpha is clamped)  -> statistic S, M, C
 //   dL/dE      = g_o * o
-// Per lane, the exponent gradients of its strip are summed against j^0, j^1, j^2
-// (App. A.2, Eq. (10)-(11)) and turned into gradients of the screen mean and
+// Per lane, the exponent gradients of its strip are summed against s^0, s^1, s^2,
+// s the row offset from the strip's anchor (App. A.2, Eq. (10)-(11)) and turned into gradients of the screen mean and
 // conic at the strip's first pixel. The f_pixel and f_tile stages of App. A.1
 // thus end in ONE wave reduction (DPP row shifts and row broadcasts) per
 // (tile, Gaussian), and f_global is ONE atomic add per gradient per tile, issued
@@ -88,9 +88,9 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
   const int tx = lt % w.tiles_x, ty = lt / w.tiles_x;
   const int lane = threadIdx.x;
   const int px = tx * GSR_TILE + (lane & 15);
-  const int py0 = ty * GSR_TILE + (lane >> 4) * 4;
+  const int py0 = ty * GSR_TILE + (lane >> 4);  // rows py0 + 4 j
   const float pxc = (float)px + 0.5f;
-  const float pyc = (float)py0 + 0.5f;
+  const float pyc = (float)py0 + kStripAnchor + 0.5f;
   const int64_t plane = (int64_t)W * H;
   const float* g_img = dL.p[v];
 
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
     last[j] = 0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) gI[j][ch] = 0.0f;
-    if (px < W && py0 + j < H) {
-      const int64_t o = (int64_t)(py0 + j) * W + px;
+    if (px < W && py0 + kStripStep * j < H) {
+      const int64_t o = (int64_t)(py0 + kStripStep * j) * W + px;
       const int64_t pp = w.pixel_base + o;
       last[j] = pix_last[pp];
 #pragma unroll
@@ -173,21 +173,17 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
           const float go = (araw <= alpha_clamp<P>()) ? dA * G : 0.0f;
           const float dE = go * o;
           S0 += dE;
-          if (j == 1) {
-            S1 += dE;
-            S2 += dE;
-          } else if (j > 1) {
-            S1 = __builtin_fmaf((float)j, dE, S1);
-            S2 = __builtin_fmaf((float)(j * j), dE, S2);
-          }
+          S1 = __builtin_fmaf(kStripOffset[j], dE, S1);
+          S2 = __builtin_fmaf(kStripOffset[j] * kStripOffset[j], dE, S2);
           dop += go;
           ss = __builtin_fmaf(go, go, ss);
           T[j] *= one_m_a;
         }
       }
       if (!__any(nfrag > 0.0f)) continue;  // nobody blended this entry
-      // exponent -> conic (a, b, c) and mean (u, v) gradients at the strip start:
-      //   E_j = -1/2 (a dx^2 + 2 b dx (dy - j) + c (dy - j)^2), d = mean - pixel
+      // exponent -> conic (a, b, c) and mean (u, v) gradients at the strip anchor
+      // (pixel j is s_j rows below it):
+      //   E_j = -1/2 (a dx^2 + 2 b dx (dy - s_j) + c (dy - s_j)^2), d = mean - anchor
       const float ca = -2.0f * (float)kLn2 * g.r1.x;
       const float cb = ca * g.r1.y;
       const float cc = -2.0f * (float)kLn2 * g.r1.w;

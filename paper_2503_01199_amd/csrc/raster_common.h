@@ -1,8 +1,10 @@
 // Per-wave arithmetic shared by the forward and backward raster kernels.
 //
 // Tile/thread mapping: one wave64 per 16x16 tile; lane l owns pixel column l % 16
-// and the 4-pixel vertical strip of rows 4*(l/16) .. 4*(l/16)+3 (the scanline of
-// App. A.2 runs along y). Both kernels evaluate the exponent and alpha through
+// and the 4-pixel vertical strip of rows l/16 + 4 j, j = 0..3 (the scanline of
+// App. A.2 runs along y, with a row step of kStripStep). Step j of every lane thus
+// covers the compact 16x4 band of rows 4j .. 4j+3, so an entry that blends no pixel
+// of a band skips that band wave-wide. Both kernels evaluate the exponent and alpha through
 // the functions below with an explicit operation sequence (the library is built
 // without FP contraction), so the backward re-derives exactly the forward's
 // blend decisions and transmittances.
@@ -12,10 +14,17 @@
 
 namespace gsr {
 
+constexpr int kStripStep = 4;
+// Row offsets s_j of the strip's pixels from its anchor, the centre row of the strip
+// (anchoring at the centre halves the largest offset, and so the extrapolation of the
+// scanline form, against anchoring at the first pixel).
+constexpr float kStripOffset[4] = {-6.0f, -2.0f, 2.0f, 6.0f};
+constexpr float kStripAnchor = 6.0f;  // anchor row minus first row
+
 // Exponent of the 2-D Gaussian (Eq. (2)) in log2 units at the 4 pixels of a strip
-// whose first pixel centre is (pxc, pyc). Following the scanline split of
-// App. A.2 (Eq. (8)-(9)), it is Basic + Linear j + Quad j^2 with Basic and Linear
-// computed once per strip from the factored form
+// whose anchor pixel centre is (pxc, pyc). Following the scanline split of App. A.2
+// (Eq. (8)-(9)), it is Basic + Linear s + Quad s^2 at row offset s, with Basic and
+// Linear computed once per strip from the factored form
 //   E2 = k1 (dx + r dy)^2 + k2 dy^2,   d = screen mean - pixel centre,
 // whose two terms never cancel; the per-pixel cost is two FMAs.
 __device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, float e[4], float& dx,
@@ -28,10 +37,9 @@ __device__ __forceinline__ void strip_exponents(const Record& g, float pxc, floa
   const float basic = __builtin_fmaf(t1, D, t2 * dy);
   const float lin = -2.0f * __builtin_fmaf(t1, g.r1.y, t2);
   const float quad = g.r1.w;
-  e[0] = basic;
-  e[1] = __builtin_fmaf(1.0f, __builtin_fmaf(1.0f, quad, lin), basic);
-  e[2] = __builtin_fmaf(2.0f, __builtin_fmaf(2.0f, quad, lin), basic);
-  e[3] = __builtin_fmaf(3.0f, __builtin_fmaf(3.0f, quad, lin), basic);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    e[j] = __builtin_fmaf(kStripOffset[j], __builtin_fmaf(kStripOffset[j], quad, lin), basic);
 }
 
 // G = 2^e (v_exp_f32) and alpha = min(0.99, o G); araw = o G before the clamp.

@@ -36,9 +36,9 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
   const int tx = lt % w.tiles_x, ty = lt / w.tiles_x;
   const int lane = threadIdx.x;
   const int px = tx * GSR_TILE + (lane & 15);
-  const int py0 = ty * GSR_TILE + (lane >> 4) * 4;
+  const int py0 = ty * GSR_TILE + (lane >> 4);  // rows py0 + 4 j
   const float pxc = (float)px + 0.5f;
-  const float pyc = (float)py0 + 0.5f;
+  const float pyc = (float)py0 + kStripAnchor + 0.5f;
 
   // A pixel blends an entry when alpha >= amin; amin is 1/255 while the pixel is
   // live and 2 (unreachable) once it has stopped or lies outside the image.
@@ -47,7 +47,7 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
   uint32_t last[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    amin[j] = ((px < W) && (py0 + j < H)) ? kAlphaMin : 2.0f;
+    amin[j] = ((px < W) && (py0 + kStripStep * j < H)) ? kAlphaMin : 2.0f;
     T[j] = 1.0f;
     cr[j] = cg[j] = cb[j] = 0.0f;
     last[j] = 0;
@@ -76,6 +76,7 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
       for (int j = 0; j < 4; ++j) {
         const float a = av[j];
         const bool ok = a >= amin[j];
+        if (!__any(ok)) continue;  // nobody in this band blends the entry
         const float Tn = T[j] * (1.0f - a);
         const bool stop = ok && (Tn < kTMin);
         const bool blend = ok && !stop;
@@ -102,7 +103,7 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int py = py0 + j;
+    const int py = py0 + kStripStep * j;
     if (py >= H) break;
     const int64_t o = (int64_t)py * W + px;
     const double r = __builtin_fma((double)T[j], (double)w.bg[0], cr[j]);

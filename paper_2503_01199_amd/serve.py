@@ -203,11 +203,12 @@ class GpuExecutor:
         self.density = {}  # instances per pixel of each scene, from one probe view
 
     def calibrate(self, name, camera):
-        """Instances per pixel of a probe view of the scene: the planner's bound for
-        a request is margin x density x pixels instances."""
+        """Instances per pixel of a probe view of the scene (the largest over the
+        probes given): the planner's bound for a request is margin x density x pixels
+        instances. A frame that outgrows its bound raises its scene's density."""
         fr = self.rz.forward(self.scenes[name], [camera], precision=self.precision)
-        self.density[name] = fr.info["instances"] / float(camera.width * camera.height)
-        self.rz.check_frame(fr)
+        d = fr.info["instances"] / float(camera.width * camera.height)
+        self.density[name] = max(self.density.get(name, 0.0), d)
         fr.workspace._release()
 
     def bytes_needed(self, req) -> int:
@@ -258,6 +259,9 @@ class GpuExecutor:
         ok = st == self.L.GSR_OK
         if st == self.L.GSR_ERR_WORKSPACE_TOO_SMALL:
             need = int(self.rz.lib.gsr_required_workspace(self.rz.ctx)) + 512
+            cam = h.req.camera
+            seen = 1.1 * info["instances"] / float(cam.width * cam.height) / self.margin
+            self.density[h.req.scene] = max(self.density.get(h.req.scene, 0.0), seen)
         elif st != self.L.GSR_OK:
             self.rz._check(st, "gsr_frame_inspect")
         h.ws._release()
@@ -317,7 +321,8 @@ def serve_benchmark(rasterizer, n_warmup=200, n_measured=3000, rate=200.0, budge
     res, radii = resident_scenes(rasterizer, sizes)
     ex = GpuExecutor(rasterizer, res, slots=slots)
     for name in res:
-        ex.calibrate(name, S.orbit_camera(30.0, 10.0, radius=radii[name], width=512, height=512, fov_x=60.0))
+        for az in (0.0, 90.0, 180.0, 270.0):
+            ex.calibrate(name, S.orbit_camera(az, 10.0, radius=radii[name], width=512, height=512, fov_x=60.0))
     reqs = request_stream(radii, n_warmup + n_measured, rate)
     if log:
         log("serving %d requests at %.0f/s over %d scenes (budget %.1f GiB, %d slots)"

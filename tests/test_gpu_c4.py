@@ -18,7 +18,9 @@ in the middle of lists where no pixel's last blended position changes (measured:
 a 4 % spread for opacity alone, 6 % for all parameters at 1e-3 steps, worse at
 larger steps), so no screening makes such a difference usable. The check is:
 - 32 Rademacher directions over the SH coefficients of all 5,000 subset Gaussians
-  (the loss is linear in SH up to the colour clamp): each within 1e-2.
+  (the loss is linear in SH up to the colour clamp): each within 1e-2 of
+  max(|analytic|, 0.1 rms of the 32 analytic values) (a random direction's
+  derivative can be near zero while the differencing noise is absolute).
 - 200 single-scalar probes over all 59 parameters (one subset Gaussian, one
   parameter, the step above). A probe whose stencil changes the tile lists, any
   pixel's last blended position or any Gaussian's blended-fragment count (which
@@ -136,6 +138,7 @@ def test_c4_frame_and_fd_gradcheck(rz, c4):
         return (torch.equal(a[1], b[1]) and a[2].shape == b[2].shape and torch.equal(a[2], b[2])
                 and torch.equal(a[3], b[3]))
 
+    fds, ans = [], []
     for k in range(32):
         d = [torch.zeros_like(h) for h in steps[:4]]
         d.append(torch.as_tensor(rng.choice([-1.0, 1.0], size=tuple(steps[4].shape)), device=dev,
@@ -144,12 +147,17 @@ def test_c4_frame_and_fd_gradcheck(rz, c4):
         ap, am = perturbed(d), perturbed([-x for x in d])
         lp = render_loss(ap)[0]
         lm = render_loss(am)[0]
-        fd = (lp - lm) / 2.0
-        an = sum(float((g[sub].double() * (p[sub].double() - m[sub].double()) / 2.0).sum().item())
-                 for g, p, m in zip(grads, ap, am))
-        rel = abs(fd - an) / max(abs(an), 1e-30)
-        print("SH direction %2d over 5000 Gaussians: fd %+.6e analytic %+.6e rel %.2e" % (k, fd, an, rel), flush=True)
-        assert rel < 1e-2
+        fds.append((lp - lm) / 2.0)
+        ans.append(sum(float((g[sub].double() * (p[sub].double() - m[sub].double()) / 2.0).sum().item())
+                       for g, p, m in zip(grads, ap, am)))
+    # a random direction's derivative can be arbitrarily small while the differencing
+    # noise is absolute: relative error against max(|an|, 0.1 rms of the 32 values)
+    fds, ans = np.array(fds), np.array(ans)
+    floor = 0.1 * float(np.sqrt(np.mean(ans ** 2)))
+    rel = np.abs(fds - ans) / np.maximum(np.abs(ans), floor)
+    for k in range(32):
+        print("SH direction %2d over 5000 Gaussians: fd %+.6e analytic %+.6e rel %.2e" % (k, fds[k], ans[k], rel[k]))
+    assert rel.max() < 1e-2
 
     gnp = [g[sub].cpu().numpy().reshape(5000, -1) for g in grads]
     hs = [h.cpu().numpy().reshape(5000, -1) for h in steps]
