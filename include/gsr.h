@@ -51,7 +51,8 @@ typedef enum {
                           An approximation: its error against FP32 is measured, not bounded. */
 } gsr_precision;
 
-#define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile */
+#define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile, or per
+                                16x4 band of a tile with a long list; at most 2^28 tiles per call */
 #define GSR_CLUSTER 128      /* primitives per cluster (Sec. 3.2.2) */
 #define GSR_MAX_VIEWS 64     /* views per gsr_forward / gsr_backward call, and per gsr_raster_batch */
 #define GSR_MAX_BATCH 16     /* prepared frames per gsr_raster_batch call */
@@ -127,6 +128,8 @@ typedef struct {
   int32_t views;
   int32_t clusters;
   int32_t visible_clusters;
+  int32_t split_tiles;     /* tiles the forward rasters as four 16x4 band items (the longest lists) */
+  int32_t split_tiles_bwd; /* tiles the backward walks as two items of two bands each */
   int32_t reserved;
 } gsr_frame_info;
 
@@ -141,8 +144,7 @@ typedef struct {
  *   compact2full u32[slots]: full Gaussian index of each compact slot (0xffffffff: none)
  *   inst_tile   u32[M], inst_record u32[M]: instances sorted by (tile, depth, record)
  *   ranges      u32[tiles][2]: [start, end) of each tile's instances
- *   pixel_rgb   f64[pixels][3] (the composite, background included, accumulated in FP64),
- *   pixel_T f32[pixels], pixel_last u32[pixels]
+ *   pixel_T     f32[pixels] (final transmittance), pixel_last u32[pixels]
  *                 (list position + 1 of the last blended instance)
  *   grad2d      f32[R][12] (after gsr_backward): d/du, d/dv, d/da, d/db, d/dc, d/do,
  *                 d/dred, d/dgreen, d/dblue, S, C, 0 of each record
@@ -157,7 +159,6 @@ typedef struct {
   const uint32_t *inst_tile;
   const uint32_t *inst_record;
   const uint32_t *ranges;
-  const double *pixel_rgb;
   const float *pixel_T;
   const uint32_t *pixel_last;
   const float *grad2d;
@@ -204,13 +205,16 @@ gsr_status gsr_prepare(gsr_context *ctx, const gsr_scene *scene, const gsr_camer
                        const gsr_options *opts, void *workspace, size_t ws_bytes, void *stream);
 
 /* Bytes of the batch workspace that gsr_raster_batch needs for these prepared
- * frames (4 per tile, rounded up to 256). */
+ * frames: the raster work items (4 bytes each; a tile is one item, or four when
+ * its list is split into bands, at most one tile in four), rounded up to 256,
+ * plus 256 bytes for their count. */
 gsr_status gsr_raster_batch_workspace_size(gsr_context *ctx, int32_t n, const void *const *workspaces,
                                            size_t *bytes);
 
 /* One forward-raster launch (Sec. 3, Eq. (1)) over all tiles of n prepared frames
  * (1 <= n <= GSR_MAX_BATCH, distinct workspaces; any scenes and image sizes; at
- * most GSR_MAX_VIEWS views in total), scheduled longest tile list first across the frames. images[i][v] is
+ * most GSR_MAX_VIEWS views in total, at most 2^28 tiles), scheduled longest tile list first across the
+ * frames. images[i][v] is
  * frame i's view v: a device pointer to f32 [3, H, W], overwritten. The frames'
  * gsr_prepare work must be complete or enqueued earlier on `stream` (make `stream`
  * wait for the streams that prepared them). A frame's images are bitwise equal to

@@ -56,13 +56,13 @@ class GsrStats(ctypes.Structure):
 class GsrFrameInfo(ctypes.Structure):
     _fields_ = [("n", c_int64), ("n_visible_slots", c_int64), ("instances", c_int64), ("tiles", c_int64),
                 ("pixels", c_int64), ("views", c_int32), ("clusters", c_int32), ("visible_clusters", c_int32),
-                ("reserved", c_int32)]
+                ("split_tiles", c_int32), ("split_tiles_bwd", c_int32), ("reserved", c_int32)]
 
 
 class GsrFrameBuffers(ctypes.Structure):
     _fields_ = [("record", c_void_p), ("depth_key", c_void_p), ("tiles", c_void_p), ("rect", c_void_p),
                 ("compact2full", c_void_p), ("inst_tile", c_void_p), ("inst_record", c_void_p),
-                ("ranges", c_void_p), ("pixel_rgb", c_void_p), ("pixel_T", c_void_p), ("pixel_last", c_void_p),
+                ("ranges", c_void_p), ("pixel_T", c_void_p), ("pixel_last", c_void_p),
                 ("grad2d", c_void_p), ("cluster_bounds", c_void_p), ("cluster_visible", c_void_p),
                 ("pixel_base", c_int64 * GSR_MAX_VIEWS), ("tile_base", c_int64 * GSR_MAX_VIEWS)]
 

@@ -124,7 +124,8 @@ gsr_status validate_views(gsr_context* ctx, const gsr_camera* cams, int32_t V) {
         return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: t or bg not finite", v);
     tiles += (int64_t)((c.width + GSR_TILE - 1) / GSR_TILE) * ((c.height + GSR_TILE - 1) / GSR_TILE);
   }
-  if (tiles >= ((int64_t)1 << 31)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles");
+  // raster work items carry the tile index in their upper 29 bits
+  if (tiles >= ((int64_t)1 << 28)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles (limit 2^28)");
   return GSR_OK;
 }
 
@@ -184,8 +185,8 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.sval[1] = P.take<uint32_t>(nr + 1);
   f.offsets = P.take<uint32_t>(nr + 1);
   f.ranges = P.take<uint32_t>(2 * (size_t)f.tiles);
-  f.tile_order = P.take<uint32_t>((size_t)f.tiles);
-  f.pix_rgb = P.take<double>(3 * (size_t)f.pixels);
+  f.tile_order = P.take<uint32_t>((size_t)gsr::raster_max_items(f.tiles));
+  f.bwd_items = P.take<uint32_t>((size_t)gsr::raster_max_items(f.tiles));
   f.pix_T = P.take<float>((size_t)f.pixels);
   f.pix_last = P.take<uint32_t>((size_t)f.pixels);
   f.grad2d = P.take<float>(gsr::kGrad2D * std::max<size_t>(nr, 1));
@@ -460,6 +461,13 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
   return GSR_OK;
 }
 
+// Batch workspace: the raster work items of the concatenated tiles, then their count.
+static size_t batch_items_words(uint64_t tiles) {
+  const uint64_t bytes = (uint64_t)gsr::raster_max_items((int64_t)tiles) * 4;
+  return (size_t)(((bytes + kAlign - 1) & ~(uint64_t)(kAlign - 1)) / 4);
+}
+static size_t batch_workspace_bytes(uint64_t tiles) { return batch_items_words(tiles) * 4 + kAlign; }
+
 gsr_status gsr_raster_batch_workspace_size(gsr_context* ctx, int32_t n, const void* const* workspaces,
                                            size_t* bytes) {
   if (!ctx || !bytes || !workspaces || n < 1 || n > gsr::kMaxBatch)
@@ -470,7 +478,7 @@ gsr_status gsr_raster_batch_workspace_size(gsr_context* ctx, int32_t n, const vo
     if (it == ctx->frames.end()) return fail(ctx, GSR_ERR_INVALID_ARG, "frame %d was not prepared", i);
     tiles += (uint64_t)it->second.f.tiles;
   }
-  *bytes = (size_t)((tiles * 4 + kAlign - 1) & ~(uint64_t)(kAlign - 1));
+  *bytes = batch_workspace_bytes(tiles);
   return GSR_OK;
 }
 
@@ -506,7 +514,6 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
     r.ranges = f.ranges;
     r.inst_rec = f.inst_rec;
     r.rec = f.rec;
-    r.pix_rgb = f.pix_rgb;
     r.pix_T = f.pix_T;
     r.pix_last = f.pix_last;
     r.V = f.V;
@@ -516,10 +523,10 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
     views += f.V;
     frs[i] = &fr;
   }
-  if (tiles >= ((uint64_t)1 << 31)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles in a batch");
+  if (tiles >= ((uint64_t)1 << 28)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles in a batch (limit 2^28)");
   tab.first[n] = (uint32_t)tiles;
   tab.n = n;
-  const size_t need = (size_t)((tiles * 4 + kAlign - 1) & ~(uint64_t)(kAlign - 1));
+  const size_t need = batch_workspace_bytes(tiles);
   if (!batch_ws || batch_ws_bytes < need) {
     ctx->required = need;
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "batch workspace of %zu bytes < %zu", batch_ws_bytes, need);
@@ -528,8 +535,9 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   uint32_t* order = static_cast<uint32_t*>(batch_ws);
-  gsr::launch_batch_tile_order(tab, (uint32_t)tiles, order, s);
-  gsr::launch_raster_fwd_batch(tab, order, (uint32_t)tiles, ip, precision, s);
+  uint32_t* n_items = order + batch_items_words(tiles);
+  gsr::launch_batch_tile_order(tab, (uint32_t)tiles, order, n_items, s);
+  gsr::launch_raster_fwd_batch(tab, order, n_items, (uint32_t)tiles, ip, precision, s);
   gsr_status st = check_hip(ctx, hipGetLastError(), "batched raster");
   if (st) return st;
   for (int i = 0; i < n; ++i) {
@@ -632,6 +640,8 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
     info->views = f.V;
     info->clusters = f.nclusters;
     info->visible_clusters = (int32_t)nvis;
+    info->split_tiles = (int32_t)((h[gsr::kHdrItems] - (uint32_t)f.tiles) / 3);
+    info->split_tiles_bwd = (int32_t)(h[gsr::kHdrItemsBwd] - (uint32_t)f.tiles);
   }
   if (bufs) {
     std::memset(bufs, 0, sizeof(*bufs));
@@ -643,7 +653,6 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
     bufs->inst_tile = f.inst_tile;
     bufs->inst_record = f.inst_rec;
     bufs->ranges = f.ranges;
-    bufs->pixel_rgb = f.pix_rgb;
     bufs->pixel_T = f.pix_T;
     bufs->pixel_last = f.pix_last;
     bufs->grad2d = f.grad2d;

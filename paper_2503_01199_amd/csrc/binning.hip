@@ -8,7 +8,7 @@
 // moves 4-byte keys and sorts the instances on the tile bits only.
 #include <algorithm>
 
-#include "gsr_internal.h"
+#include "raster_common.h"
 
 namespace gsr {
 namespace {
@@ -58,9 +58,13 @@ __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t*
   }
 }
 
-// Longest-list-first schedule for the raster (tiles are independent, so the order
-// changes no result): one block buckets the list lengths (clamped to 4095) in LDS in
-// descending order, scans the buckets and scatters the tile ids.
+// Raster schedules (tiles are independent and a pixel's arithmetic does not
+// depend on how its tile is split, so the schedule changes no result): one block
+// buckets the list lengths (clamped to 4095) in LDS in descending order and scans
+// the buckets, giving each tile its rank. For each list, the ns longest tiles with
+// more than its split length (ns at most a quarter of the tiles) become 4 (forward)
+// or 2 (backward) band items each, placed first; every other tile is one whole item, after them;
+// both groups in descending length. The item counts go to *n_items (and *n_bwd).
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4096;
 
@@ -80,16 +84,43 @@ struct ManyFrames {
   }
 };
 
+// Item codes of band group b of a tile split `ways` ways.
+__device__ __forceinline__ uint32_t split_code(uint32_t ways, uint32_t b) { return ways == 4 ? b : kItemHalf + b; }
+
+// Places tile i, of rank pos, in an item list that splits its ns first tiles.
+__device__ __forceinline__ void place_items(uint32_t* items, uint32_t i, uint32_t pos, uint32_t ns, uint32_t ways) {
+  if (pos < ns) {
+    for (uint32_t b = 0; b < ways; ++b) items[ways * pos + b] = (i << 3) | split_code(ways, b);
+  } else {
+    items[(ways - 1) * ns + pos] = (i << 3) | kItemWhole;
+  }
+}
+
 template <class Len>
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, uint32_t* __restrict__ order) {
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, uint32_t* __restrict__ items,
+                                                              uint32_t* __restrict__ n_items,
+                                                              uint32_t* __restrict__ bwd,
+                                                              uint32_t* __restrict__ n_bwd) {
   __shared__ uint32_t h[kOrderBuckets];
   __shared__ uint32_t wsum[kOrderThreads / 64];
+  __shared__ uint32_t nlong[2];
   const int t = threadIdx.x;
   for (int b = t; b < kOrderBuckets; b += kOrderThreads) h[b] = 0;
+  if (t < 2) nlong[t] = 0;
   __syncthreads();
-  for (int64_t i = t; i < T; i += kOrderThreads)
-    atomicAdd(&h[kOrderBuckets - 1 - min(L.len(i), (uint32_t)(kOrderBuckets - 1))], 1u);
+  uint32_t my_long = 0, my_long_b = 0;
+  for (int64_t i = t; i < T; i += kOrderThreads) {
+    const uint32_t len = L.len(i);
+    atomicAdd(&h[kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1))], 1u);
+    my_long += len > kSplitLen ? 1u : 0u;
+    my_long_b += len > kSplitLenBwd ? 1u : 0u;
+  }
+  atomicAdd(&nlong[0], my_long);
+  if (bwd) atomicAdd(&nlong[1], my_long_b);
   __syncthreads();
+  const uint32_t cap = (uint32_t)((T + kSplitShare - 1) / kSplitShare);
+  const uint32_t ns = min(nlong[0], cap);
+  const uint32_t ns_b = min(nlong[1], cap);
   // exclusive scan of the buckets, 4 per thread
   uint32_t v[4], sum = 0;
   for (int q = 0; q < 4; ++q) {
@@ -114,7 +145,12 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   __syncthreads();
   for (int64_t i = t; i < T; i += kOrderThreads) {
     const uint32_t pos = atomicAdd(&h[kOrderBuckets - 1 - min(L.len(i), (uint32_t)(kOrderBuckets - 1))], 1u);
-    order[pos] = (uint32_t)i;
+    place_items(items, (uint32_t)i, pos, ns, 4);
+    if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+  }
+  if (t == 0) {
+    *n_items = (uint32_t)T + 3 * ns;
+    if (bwd) *n_bwd = (uint32_t)T + ns_b;
   }
 }
 
@@ -122,13 +158,18 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
 
 void launch_tile_order(const Frame& f, hipStream_t s) {
   if (f.tiles <= 0) return;
-  k_tile_order<OneFrame><<<1, kOrderThreads, 0, s>>>(OneFrame{f.ranges}, f.tiles, f.tile_order);
+  k_tile_order<OneFrame><<<1, kOrderThreads, 0, s>>>(OneFrame{f.ranges}, f.tiles, f.tile_order,
+                                                     f.header + kHdrItems, f.bwd_items, f.header + kHdrItemsBwd);
 }
 
-void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, hipStream_t s) {
+void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, uint32_t* n_items,
+                             hipStream_t s) {
   if (total_tiles == 0) return;
-  k_tile_order<ManyFrames><<<1, kOrderThreads, 0, s>>>(ManyFrames{tab}, total_tiles, order);
+  k_tile_order<ManyFrames><<<1, kOrderThreads, 0, s>>>(ManyFrames{tab}, total_tiles, order, n_items, nullptr,
+                                                       nullptr);
 }
+
+int64_t raster_max_items(int64_t tiles) { return max_items(tiles); }
 
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
   int64_t n = std::max<int64_t>(f.nrec, 2 * f.tiles);

@@ -57,6 +57,8 @@ enum HeaderWord {
   kHdrRecords = 3,          // active records = 128 * visible clusters * views
   kHdrOverflow = 4,         // 1 when M exceeded the workspace capacity
   kHdrError = 5,            // bit 0: a look-back wait gave up; bit 1: a scanned count reached 2^30
+  kHdrItems = 6,            // forward raster work items (whole tiles plus the bands of split tiles)
+  kHdrItemsBwd = 7,         // backward raster work items
 };
 
 struct Frame {
@@ -83,8 +85,8 @@ struct Frame {
   uint32_t* inst_tile;      // sorted instances (points into ikey/ival)
   uint32_t* inst_rec;
   uint32_t* ranges;         // [tiles][2]
-  uint32_t* tile_order;     // [tiles] raster schedule: tiles by descending list length
-  double* pix_rgb;          // [pixels][3] final colour accumulated in FP64
+  uint32_t* tile_order;     // [max_items(tiles)] forward raster work items, longest lists first
+  uint32_t* bwd_items;      // [max_items(tiles)] backward raster work items
   float* pix_T;             // [pixels]
   uint32_t* pix_last;       // [pixels]
   float* grad2d;            // [nrec][12]
@@ -156,7 +158,6 @@ struct FrameRef {
   const uint32_t* ranges;
   const uint32_t* inst_rec;
   const Record* rec;
-  double* pix_rgb;
   float* pix_T;
   uint32_t* pix_last;
   int32_t V;
@@ -168,10 +169,13 @@ struct FrameTable {
   int32_t n;
 };
 static_assert(sizeof(FrameTable) + sizeof(ImagePtrs) <= 3584, "the batch table travels in the kernel arguments");
-void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, uint32_t total_tiles,
-                             const ImagePtrs& images, int precision, hipStream_t s);
-// Longest-list-first order of the concatenated tiles of a batch of frames.
-void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, hipStream_t s);
+void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
+                             uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s);
+// Raster work items of the concatenated tiles of a batch of frames (n_items <- count).
+void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, uint32_t* n_items,
+                             hipStream_t s);
+// Largest number of raster work items for `tiles` tiles (every split tile adds 3).
+int64_t raster_max_items(int64_t tiles);
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s);
 
 // morton.hip

@@ -4,7 +4,13 @@
 // and the 4-pixel vertical strip of rows l/16 + 4 j, j = 0..3 (the scanline of
 // App. A.2 runs along y, with a row step of kStripStep). Step j of every lane thus
 // covers the compact 16x4 band of rows 4j .. 4j+3, so an entry that blends no pixel
-// of a band skips that band wave-wide. Both kernels evaluate the exponent and alpha through
+// of a band skips that band wave-wide. A tile whose list is long is instead split
+// into its 4 bands, one wave each with one pixel per lane (NB = 1), so that the
+// longest lists do not set the kernel's duration. A band item evaluates its pixel
+// with the same strip anchor and row offset as the whole-tile walk, so every
+// pixel's arithmetic is the same whichever way its tile is scheduled (a batch of
+// frames may split other tiles than each frame alone, and the backward may walk
+// another schedule than the forward). Both kernels evaluate the exponent and alpha through
 // the functions below with an explicit operation sequence (the library is built
 // without FP contraction), so the backward re-derives exactly the forward's
 // blend decisions and transmittances.
@@ -15,20 +21,44 @@
 namespace gsr {
 
 constexpr int kStripStep = 4;
+
+// Raster work items: (tile << 3) | code. kItemWhole (4) is the whole tile, 4
+// pixels per lane; codes 0..3 are band `code` of a tile split four ways, 1 pixel per
+// lane; kItemHalf + h (5, 6) are bands 2h and 2h + 1 of a tile split two ways, 2
+// pixels per lane. The forward splits tiles with more than kSplitLen entries four
+// ways; the backward, whose per-entry wave reduction and atomics are repeated by
+// every item of a tile, splits those with more than kSplitLenBwd entries two
+// ways. Either takes the longest first, at most one tile in kSplitShare.
+constexpr uint32_t kItemWhole = 4;
+constexpr uint32_t kItemHalf = 5;
+constexpr uint32_t kSplitLen = 256;
+constexpr uint32_t kSplitLenBwd = 512;
+constexpr int64_t kSplitShare = 4;
+__host__ __device__ inline int64_t max_items(int64_t tiles) { return tiles + 3 * ((tiles + kSplitShare - 1) / kSplitShare); }
 // Row offsets s_j of the strip's pixels from its anchor, the centre row of the strip
 // (anchoring at the centre halves the largest offset, and so the extrapolation of the
 // scanline form, against anchoring at the first pixel).
 constexpr float kStripOffset[4] = {-6.0f, -2.0f, 2.0f, 6.0f};
 constexpr float kStripAnchor = 6.0f;  // anchor row minus first row
 
-// Exponent of the 2-D Gaussian (Eq. (2)) in log2 units at the 4 pixels of a strip
-// whose anchor pixel centre is (pxc, pyc). Following the scanline split of App. A.2
-// (Eq. (8)-(9)), it is Basic + Linear s + Quad s^2 at row offset s, with Basic and
-// Linear computed once per strip from the factored form
-//   E2 = k1 (dx + r dy)^2 + k2 dy^2,   d = screen mean - pixel centre,
+// Row offsets from the strip anchor of the NB pixels a lane evaluates, in bands
+// band .. band + NB - 1: s = 4 b - 6 for band b (the whole strip when NB = 4).
+template <int NB>
+__device__ __forceinline__ void strip_offsets(int band, float s[NB]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    s[j] = NB == 4 ? kStripOffset[j] : (float)(kStripStep * (band + j)) - kStripAnchor;
+}
+
+// Exponent of the 2-D Gaussian (Eq. (2)) in log2 units at row offsets s[j] from a
+// strip anchor whose pixel centre is (pxc, pyc). Following the scanline split of
+// App. A.2 (Eq. (8)-(9)), it is Basic + Linear s + Quad s^2, with Basic and Linear
+// computed once per strip from the factored form
+//   E2 = k1 (dx + r dy)^2 + k2 dy^2,   d = screen mean - anchor centre,
 // whose two terms never cancel; the per-pixel cost is two FMAs.
-__device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, float e[4], float& dx,
-                                                float& dy) {
+template <int NB>
+__device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, const float s[NB],
+                                                float e[NB], float& dx, float& dy) {
   dx = (g.r0.x - pxc) + g.r0.z;
   dy = (g.r0.y - pyc) + g.r0.w;
   const float D = __builtin_fmaf(g.r1.y, dy, dx);
@@ -38,8 +68,7 @@ __device__ __forceinline__ void strip_exponents(const Record& g, float pxc, floa
   const float lin = -2.0f * __builtin_fmaf(t1, g.r1.y, t2);
   const float quad = g.r1.w;
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
-    e[j] = __builtin_fmaf(kStripOffset[j], __builtin_fmaf(kStripOffset[j], quad, lin), basic);
+  for (int j = 0; j < NB; ++j) e[j] = __builtin_fmaf(s[j], __builtin_fmaf(s[j], quad, lin), basic);
 }
 
 // G = 2^e (v_exp_f32) and alpha = min(0.99, o G); araw = o G before the clamp.
@@ -57,33 +86,37 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 extern "C" __device__ _Float16 __ocml_exp2_f16(_Float16);
 constexpr float kAlphaMaxH = 0.990234375f;  // 0.99 rounded to FP16: the clamp point of the FP16 blend
 
-__device__ __forceinline__ void strip_alpha_h(float o, const float e[4], float a[4], float G[4], float araw[4]) {
+template <int NB>
+__device__ __forceinline__ void strip_alpha_h(float o, const float e[NB], float a[NB], float G[NB], float araw[NB]) {
   const _Float16 oh = (_Float16)o;
   const half2_t o2 = {oh, oh};
   const half2_t cap = {(_Float16)kAlphaMax, (_Float16)kAlphaMax};
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const half2_t eh = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(e[2 * p], e[2 * p + 1]));
+  for (int p = 0; p < (NB + 1) / 2; ++p) {
+    const float e1 = (2 * p + 1 < NB) ? e[2 * p + 1] : e[2 * p];
+    const half2_t eh = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(e[2 * p], e1));
     const half2_t g = {__ocml_exp2_f16(eh.x), __ocml_exp2_f16(eh.y)};
     const half2_t r = o2 * g;
     const half2_t al = __builtin_elementwise_min(cap, r);
     a[2 * p] = (float)al.x;
-    a[2 * p + 1] = (float)al.y;
     G[2 * p] = (float)g.x;
-    G[2 * p + 1] = (float)g.y;
     araw[2 * p] = (float)r.x;
-    araw[2 * p + 1] = (float)r.y;
+    if (2 * p + 1 < NB) {
+      a[2 * p + 1] = (float)al.y;
+      G[2 * p + 1] = (float)g.y;
+      araw[2 * p + 1] = (float)r.y;
+    }
   }
 }
 
-// Alpha of the 4 strip pixels at precision P (GSR_FP32 or GSR_FP16_BLEND).
-template <int P>
-__device__ __forceinline__ void strip_alpha(float o, const float e[4], float a[4], float G[4], float araw[4]) {
+// Alpha of the NB strip pixels at precision P (GSR_FP32 or GSR_FP16_BLEND).
+template <int P, int NB>
+__device__ __forceinline__ void strip_alpha(float o, const float e[NB], float a[NB], float G[NB], float araw[NB]) {
   if constexpr (P == GSR_FP16_BLEND) {
-    strip_alpha_h(o, e, a, G, araw);
+    strip_alpha_h<NB>(o, e, a, G, araw);
   } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) a[j] = alpha_of(o, e[j], G[j], araw[j]);
+    for (int j = 0; j < NB; ++j) a[j] = alpha_of(o, e[j], G[j], araw[j]);
   }
 }
 

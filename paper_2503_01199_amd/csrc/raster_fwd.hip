@@ -1,5 +1,7 @@
 // Forward raster: front-to-back alpha compositing (Sec. 3, Eq. (1)) of each
-// tile's depth-ordered list, one wave64 per 16x16 tile.
+// tile's depth-ordered list, one wave64 per work item: a 16x16 tile, or one 16x4
+// band of a tile whose list is long (the longest lists would otherwise set the
+// launch's duration; a band item walks the same list for a quarter of the pixels).
 //
 // Each lane walks its 4-pixel strip with the scanline exponent (App. A.2). The
 // tile's Gaussian records are staged through LDS in batches of 64 (one gather per
@@ -10,25 +12,23 @@
 // leaves the list once all its pixels have stopped.
 //
 // Outputs: the image (planar RGB, background composited behind), and per pixel
-// the final colour, T and the list position + 1 of the last blended entry, which
-// the backward uses to bound its walk. The colour sum runs in FP64 (gfx950 issues
-// an FP64 FMA at the rate of an unpacked FP32 one): the backward takes the colour
-// behind an entry as this final colour minus the colour composited up to the
-// entry, a difference that in FP32 would lose ~n ulps of the whole colour. P selects the precision of alpha (FP32, or
+// the final T and the list position + 1 of the last blended entry, from which the
+// backward starts its back-to-front walk. P selects the precision of alpha (FP32, or
 // the packed-FP16 blend of Sec. 3.1.2).
 #include "raster_common.h"
 
 namespace gsr {
 namespace {
 
-// One tile gt of a frame (views, ranges, lists and records of that frame); its
-// image planes are images.p[img_base + view].
-template <int P>
-__device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* __restrict__ views,
-                                                int32_t V, uint32_t gt, const uint32_t* __restrict__ ranges,
+// One work item of a frame (views, ranges, lists and records of that frame): tile
+// gt whole (NB = 4 pixels per lane) or its band `band` (NB = 1); its image planes
+// are images.p[img_base + view].
+template <int P, int NB>
+__device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* __restrict__ views,
+                                                int32_t V, uint32_t gt, int band, const uint32_t* __restrict__ ranges,
                                                 const uint32_t* __restrict__ inst_rec, const Record* __restrict__ rec,
-                                                const ImagePtrs& images, int img_base, double* __restrict__ pix_rgb,
-                                                float* __restrict__ pix_T, uint32_t* __restrict__ pix_last) {
+                                                const ImagePtrs& images, int img_base, float* __restrict__ pix_T,
+                                                uint32_t* __restrict__ pix_last) {
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
   const int W = w.width, H = w.height;
@@ -36,25 +36,33 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
   const int tx = lt % w.tiles_x, ty = lt / w.tiles_x;
   const int lane = threadIdx.x;
   const int px = tx * GSR_TILE + (lane & 15);
-  const int py0 = ty * GSR_TILE + (lane >> 4);  // rows py0 + 4 j
+  const int ys = ty * GSR_TILE + (lane >> 4);  // first row of the lane's whole-tile strip
+  const int py0 = ys + kStripStep * band;      // rows py0 + 4 j
   const float pxc = (float)px + 0.5f;
-  const float pyc = (float)py0 + kStripAnchor + 0.5f;
+  const float pyc = (float)ys + kStripAnchor + 0.5f;
+  float soff[NB];
+  strip_offsets<NB>(band, soff);
 
   // A pixel blends an entry when alpha >= amin; amin is 1/255 while the pixel is
   // live and 2 (unreachable) once it has stopped or lies outside the image.
-  float amin[4], T[4];
-  double cr[4], cg[4], cb[4];
-  uint32_t last[4];
+  float amin[NB], T[NB], cr[NB], cg[NB], cb[NB];
+  uint32_t last[NB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NB; ++j) {
     amin[j] = ((px < W) && (py0 + kStripStep * j < H)) ? kAlphaMin : 2.0f;
     T[j] = 1.0f;
     cr[j] = cg[j] = cb[j] = 0.0f;
     last[j] = 0;
   }
+  auto any_live = [&]() __attribute__((always_inline)) {
+    float m = amin[0];
+#pragma unroll
+    for (int j = 1; j < NB; ++j) m = fminf(m, amin[j]);
+    return __any(m < 1.0f);
+  };
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = ranges[2 * gt + 1];
-  bool live = __any(fminf(fminf(amin[0], amin[1]), fminf(amin[2], amin[3])) < 1.0f);
+  bool live = any_live();
   // Pipeline: record ids two batches ahead, records one batch ahead (in LDS).
   if (s < e) batch_fetch(bufA, rec, (s + lane < e) ? inst_rec[s + lane] : 0u);
   uint32_t r_next = (s + 64 + lane < e) ? inst_rec[s + 64 + lane] : 0u;
@@ -66,14 +74,13 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
     const int cnt = (int)min(64u, e - b0);
     for (int k = 0; k < cnt; ++k) {
       const Record g = batch_get(cur, k);
-      float ev[4], dx, dy;
-      strip_exponents(g, pxc, pyc, ev, dx, dy);
+      float ev[NB], dx, dy;
+      strip_exponents<NB>(g, pxc, pyc, soff, ev, dx, dy);
       const uint32_t pos1 = b0 - s + (uint32_t)k + 1u;
-      float av[4], Gv[4], arv[4];
-      strip_alpha<P>(g.r2.x, ev, av, Gv, arv);
-      const double cR = g.r2.y, cG = g.r2.z, cB = g.r2.w;
+      float av[NB], Gv[NB], arv[NB];
+      strip_alpha<P, NB>(g.r2.x, ev, av, Gv, arv);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < NB; ++j) {
         const float a = av[j];
         const bool ok = a >= amin[j];
         if (!__any(ok)) continue;  // nobody in this band blends the entry
@@ -81,14 +88,14 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
         const bool stop = ok && (Tn < kTMin);
         const bool blend = ok && !stop;
         const float wt = blend ? a * T[j] : 0.0f;
-        cr[j] = __builtin_fma((double)wt, cR, cr[j]);
-        cg[j] = __builtin_fma((double)wt, cG, cg[j]);
-        cb[j] = __builtin_fma((double)wt, cB, cb[j]);
+        cr[j] = __builtin_fmaf(wt, g.r2.y, cr[j]);
+        cg[j] = __builtin_fmaf(wt, g.r2.z, cg[j]);
+        cb[j] = __builtin_fmaf(wt, g.r2.w, cb[j]);
         T[j] = blend ? Tn : T[j];
         last[j] = blend ? pos1 : last[j];
         amin[j] = stop ? 2.0f : amin[j];
       }
-      if (!__any(fminf(fminf(amin[0], amin[1]), fminf(amin[2], amin[3])) < 1.0f)) {
+      if (!any_live()) {
         live = false;
         break;
       }
@@ -102,71 +109,87 @@ __device__ __forceinline__ void raster_fwd_tile(BatchLDS& bufA, BatchLDS& bufB, 
   float* img = images.p[img_base + v];
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const int py = py0 + kStripStep * j;
     if (py >= H) break;
     const int64_t o = (int64_t)py * W + px;
-    const double r = __builtin_fma((double)T[j], (double)w.bg[0], cr[j]);
-    const double gg = __builtin_fma((double)T[j], (double)w.bg[1], cg[j]);
-    const double b = __builtin_fma((double)T[j], (double)w.bg[2], cb[j]);
-    img[o] = (float)r;
-    img[plane + o] = (float)gg;
-    img[2 * plane + o] = (float)b;
+    img[o] = __builtin_fmaf(T[j], w.bg[0], cr[j]);
+    img[plane + o] = __builtin_fmaf(T[j], w.bg[1], cg[j]);
+    img[2 * plane + o] = __builtin_fmaf(T[j], w.bg[2], cb[j]);
     const int64_t pp = w.pixel_base + o;
-    pix_rgb[3 * pp + 0] = r;
-    pix_rgb[3 * pp + 1] = gg;
-    pix_rgb[3 * pp + 2] = b;
     pix_T[pp] = T[j];
     pix_last[pp] = last[j];
   }
 }
 
+// Work item `item` of a frame: a whole tile or one band of a split tile.
+template <int P>
+__device__ __forceinline__ void raster_fwd_work(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* views, int32_t V,
+                                                uint32_t item, uint32_t tile_offset, const uint32_t* ranges,
+                                                const uint32_t* inst_rec, const Record* rec, const ImagePtrs& images,
+                                                int img_base, float* pix_T, uint32_t* pix_last) {
+  const uint32_t gt = (item >> 3) - tile_offset;
+  const uint32_t code = item & 7u;
+  if (code == kItemWhole)
+    raster_fwd_item<P, 4>(bufA, bufB, views, V, gt, 0, ranges, inst_rec, rec, images, img_base, pix_T, pix_last);
+  else
+    raster_fwd_item<P, 1>(bufA, bufB, views, V, gt, (int)code, ranges, inst_rec, rec, images, img_base, pix_T,
+                          pix_last);
+}
+
+// One frame: block b renders work item items[b] (blocks past the count leave).
 template <int P>
 __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ views, int32_t V,
-                                                   const uint32_t* __restrict__ tile_order,
+                                                   const uint32_t* __restrict__ items,
+                                                   const uint32_t* __restrict__ n_items,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
                                                    const Record* __restrict__ rec, ImagePtrs images,
-                                                   double* __restrict__ pix_rgb, float* __restrict__ pix_T,
-                                                   uint32_t* __restrict__ pix_last) {
+                                                   float* __restrict__ pix_T, uint32_t* __restrict__ pix_last) {
   __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
-  const uint32_t gt = tile_order ? tile_order[blockIdx.x] : blockIdx.x;
-  raster_fwd_tile<P>(bufA, bufB, views, V, gt, ranges, inst_rec, rec, images, 0, pix_rgb, pix_T, pix_last);
+  if (blockIdx.x >= *n_items) return;
+  raster_fwd_work<P>(bufA, bufB, views, V, items[blockIdx.x], 0, ranges, inst_rec, rec, images, 0, pix_T,
+                     pix_last);
 }
 
-// Several prepared frames in one launch: block b renders work item order[b], an
-// index into the frames' concatenated tiles (frame f owns [first[f], first[f+1])).
+// Several prepared frames in one launch: block b renders work item order[b], whose
+// tile indexes the frames' concatenated tiles (frame f owns [first[f], first[f+1])).
 template <int P>
 __global__ __launch_bounds__(64) void k_raster_fwd_batch(FrameTable tab, const uint32_t* __restrict__ order,
-                                                         ImagePtrs images) {
+                                                         const uint32_t* __restrict__ n_items, ImagePtrs images) {
   __shared__ BatchLDS bufA, bufB;
-  const uint32_t g = order[blockIdx.x];
+  if (blockIdx.x >= *n_items) return;
+  const uint32_t item = order[blockIdx.x];
+  const uint32_t g = item >> 3;
   int f = 0;
   while (f + 1 < tab.n && tab.first[f + 1] <= g) ++f;
   const FrameRef& fr = tab.f[f];
-  raster_fwd_tile<P>(bufA, bufB, fr.views, fr.V, g - tab.first[f], fr.ranges, fr.inst_rec, fr.rec, images,
-                     fr.img_base, fr.pix_rgb, fr.pix_T, fr.pix_last);
+  raster_fwd_work<P>(bufA, bufB, fr.views, fr.V, item, tab.first[f], fr.ranges, fr.inst_rec, fr.rec, images,
+                     fr.img_base, fr.pix_T, fr.pix_last);
 }
 
 }  // namespace
 
-void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, uint32_t total_tiles,
-                             const ImagePtrs& images, int precision, hipStream_t s) {
+void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
+                             uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s) {
   if (total_tiles == 0) return;
+  const unsigned grid = (unsigned)max_items(total_tiles);
   if (precision == GSR_FP16_BLEND)
-    k_raster_fwd_batch<GSR_FP16_BLEND><<<total_tiles, 64, 0, s>>>(tab, order, images);
+    k_raster_fwd_batch<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(tab, order, n_items, images);
   else
-    k_raster_fwd_batch<GSR_FP32><<<total_tiles, 64, 0, s>>>(tab, order, images);
+    k_raster_fwd_batch<GSR_FP32><<<grid, 64, 0, s>>>(tab, order, n_items, images);
 }
 
 void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s) {
   if (f.tiles <= 0) return;
+  const unsigned grid = (unsigned)max_items(f.tiles);
+  const uint32_t* n_items = f.header + kHdrItems;
   if (precision == GSR_FP16_BLEND)
-    k_raster_fwd<GSR_FP16_BLEND><<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec,
-                                                                  f.rec, images, f.pix_rgb, f.pix_T, f.pix_last);
+    k_raster_fwd<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec,
+                                                     f.rec, images, f.pix_T, f.pix_last);
   else
-    k_raster_fwd<GSR_FP32><<<(unsigned)f.tiles, 64, 0, s>>>(f.views, f.V, f.tile_order, f.ranges, f.inst_rec, f.rec,
-                                                            images, f.pix_rgb, f.pix_T, f.pix_last);
+    k_raster_fwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec, f.rec,
+                                               images, f.pix_T, f.pix_last);
 }
 
 }  // namespace gsr

@@ -325,7 +325,6 @@ class Rasterizer:
             inst_tile=ws.view(b.inst_tile, M, u32) if M > 0 else torch.zeros(0, dtype=u32, device=self.device),
             inst_record=ws.view(b.inst_record, M, u32) if M > 0 else torch.zeros(0, dtype=u32, device=self.device),
             ranges=ws.view(b.ranges, 2 * info.tiles, u32).view(-1, 2),
-            pixel_rgb=ws.view(b.pixel_rgb, 3 * P, torch.float64).view(P, 3),
             pixel_T=ws.view(b.pixel_T, P, f32),
             pixel_last=ws.view(b.pixel_last, P, u32),
             grad2d=ws.view(b.grad2d, 12 * R, f32).view(R, 12),

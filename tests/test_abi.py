@@ -40,8 +40,8 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(L.GsrScene) == 8 + 8 + 5 * 8
     assert ctypes.sizeof(L.GsrCamera) == 4 * (2 + 4 + 9 + 3 + 1 + 3)
     assert ctypes.sizeof(L.GsrOptions) == 16
-    assert ctypes.sizeof(L.GsrFrameInfo) == 5 * 8 + 4 * 4
-    assert ctypes.sizeof(L.GsrFrameBuffers) == 14 * 8 + 2 * 64 * 8
+    assert ctypes.sizeof(L.GsrFrameInfo) == 5 * 8 + 6 * 4
+    assert ctypes.sizeof(L.GsrFrameBuffers) == 13 * 8 + 2 * 64 * 8
 
 
 def _scene(n=10, deg=0):

@@ -64,7 +64,7 @@ def oracle_sum(scene, cams, gI):
     return out
 
 
-def compare(grads, stats, ref, what):
+def compare(grads, stats, ref, what, max_fragile=0.1):
     none = np.zeros(ref["C"].shape, bool)
     for k in GROUPS:
         e = grad_errors(grads[k], ref[k], none)
@@ -74,7 +74,7 @@ def compare(grads, stats, ref, what):
     assert grad_errors(stats["S"], ref["S"], none) <= GRAD_TOL
     skip = ref["fragile"]
     print("%s: fragment counts compared on %d of %d Gaussians" % (what, (~skip).sum(), skip.size))
-    assert skip.mean() < 0.1
+    assert skip.mean() < max_fragile
     keep = ~skip
     assert np.array_equal(stats["C"].astype(np.int64)[keep], ref["C"][keep])
     # M is dL/do summed over fragments, so M o (1 - o) = dL/dlogit
@@ -90,6 +90,24 @@ def test_tiny_scene_gradients(rz, cull):
     ref = oracle_sum(sc, [cam], gI)
     ref["_logits"] = sc.opacity_logits
     compare(grads, stats, ref, "tiny cull=%s" % cull)
+
+
+@pytest.mark.parametrize("size", [(128, 128), (100, 75)])
+def test_split_tiles_gradients(rz, size):
+    """Gradients and statistic when the longest tile lists are walked as pairs of
+    16x4 bands (6,000 Gaussians on a small image). Pixels here blend many Gaussians, so a
+    fragile pixel takes more Gaussians out of the exact fragment-count check: up to
+    a fifth of them may be skipped."""
+    sc = scenes.tiny_scene(6000, seed_salt=9)
+    cam = scenes.tiny_camera(*size)
+    gI = upstream(sc, [cam])
+    fr, grads, stats = run_gpu(rz, sc, [cam], gI)
+    info = rz.inspect(fr)["info"]
+    print("split tiles: forward %d, backward %d" % (info["split_tiles"], info["split_tiles_bwd"]))
+    assert info["split_tiles"] > 0 and info["split_tiles_bwd"] > 0
+    ref = oracle_sum(sc, [cam], gI)
+    ref["_logits"] = sc.opacity_logits
+    compare(grads, stats, ref, "split tiles %dx%d" % size, max_fragile=0.2)
 
 
 def test_screen_space_gradients_match(rz):

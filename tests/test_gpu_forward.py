@@ -135,6 +135,32 @@ def test_pixel_state_matches_tiled_oracle(rz):
     assert (ref["T"] < 1e-3).sum() > 50
 
 
+@pytest.mark.parametrize("size", [(128, 128), (100, 75)])
+def test_split_tiles_match_oracle(rz, size):
+    """6,000 Gaussians on a small image: most tile lists exceed 256 entries, so the
+    longest (at most a quarter of the tiles) are rastered as four 16x4 band items.
+    The image and the per-pixel state (T, last blended position) match the oracle
+    as for whole tiles; at 100x75 the split tiles include the ragged bottom row,
+    whose last band lies wholly below the image."""
+    sc = scenes.tiny_scene(6000, seed_salt=9)
+    cam = scenes.tiny_camera(*size)
+    fr = gpu_forward(rz, sc, [cam])
+    ref = check_image(fr, sc, cam, what="split tiles %dx%d" % size)
+    ins = rz.inspect(fr)
+    _, _, ranges = _oracle_bins(sc, [cam])
+    lens = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+    cap = -(-len(lens) // 4)
+    expect, expect_bwd = min(int((lens > 256).sum()), cap), min(int((lens > 512).sum()), cap)
+    print("split tiles %d of %d (longest list %d)" % (ins["info"]["split_tiles"], len(lens), lens.max()))
+    assert ins["info"]["split_tiles"] == expect and expect > 0
+    assert ins["info"]["split_tiles_bwd"] == expect_bwd
+    keep = ~ref["fragile"].ravel()
+    last = ins["pixel_last"].cpu().numpy().view(np.uint32)
+    assert np.array_equal(last[keep], ref["n_contrib"].ravel()[keep])
+    T = ins["pixel_T"].cpu().numpy()
+    assert np.abs(T - ref["T"].ravel())[keep].max() < 1e-5
+
+
 def test_ragged_and_batched_views_equal_single(rz):
     sc = scenes.tiny_scene(700, seed_salt=6)
     cams = [scenes.tiny_camera(100, 75), scenes.tiny_camera(37, 53), scenes.tiny_camera(128, 128)]
