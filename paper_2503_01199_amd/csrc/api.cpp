@@ -413,6 +413,7 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
                                            f.tile_bits, f.ctl_tile_sort, err, s);
     f.inst_tile = ri >= 0 ? ik[ri] : f.ikey[0];
     f.inst_rec = ri >= 0 ? iv[ri] : f.ival[0];
+    f.inst_mask = f.inst_rec == f.ival[0] ? f.ival[1] : f.ival[0];  // free once the sort is done
   }
   {
     StageScope sc_(ctx, GSR_STAGE_RANGES, s);
@@ -513,6 +514,7 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
     r.views = f.views;
     r.ranges = f.ranges;
     r.inst_rec = f.inst_rec;
+    r.inst_mask = f.inst_mask;
     r.rec = f.rec;
     r.pix_T = f.pix_T;
     r.pix_last = f.pix_last;

@@ -84,6 +84,8 @@ struct Frame {
   uint32_t *ikey[2], *ival[2];   // instance buffers [inst_cap]
   uint32_t* inst_tile;      // sorted instances (points into ikey/ival)
   uint32_t* inst_rec;
+  uint32_t* inst_mask;      // per instance: byte b nonzero where the forward found a live pixel of band b
+                            // with alpha >= 1/255 (the tile sort's spare value buffer)
   uint32_t* ranges;         // [tiles][2]
   uint32_t* tile_order;     // [max_items(tiles)] forward raster work items, longest lists first
   uint32_t* bwd_items;      // [max_items(tiles)] backward raster work items
@@ -157,6 +159,7 @@ struct FrameRef {
   const ViewDev* views;
   const uint32_t* ranges;
   const uint32_t* inst_rec;
+  uint32_t* inst_mask;
   const Record* rec;
   float* pix_T;
   uint32_t* pix_last;

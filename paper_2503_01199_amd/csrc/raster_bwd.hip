@@ -14,12 +14,14 @@
 //   dL/dalpha  = T (g . c) - (g . R) / (1 - alpha)
 //   g_o        = dL/dalpha * G  (zero where alpha is clamped)  -> statistic S, M, C
 //   dL/dE      = g_o * o
-// Per lane, the exponent gradients of its strip are summed against s^0, s^1, s^2,
-// s the row offset from the strip's anchor (App. A.2, Eq. (10)-(11)) and turned into gradients of the screen mean and
-// conic at the strip's anchor. The f_pixel and f_tile stages of App. A.1
-// thus end in ONE wave reduction (DPP row shifts and row broadcasts) per
-// (tile, Gaussian), and f_global is ONE atomic add per gradient per tile, issued
-// as a single 11-lane atomic instruction on the record's contiguous 48-byte row.
+// Per lane, the opacity gradients of its strip are summed against s^0, s^1, s^2,
+// s the row offset from the strip's anchor (App. A.2, Eq. (10)-(11)); times o they
+// are the exponent-gradient sums, turned into gradients of the screen mean and
+// conic at the anchor. The f_pixel and f_tile stages of App. A.1 thus end in ONE
+// transposed wave reduction (permlane swaps, then DPP row shifts) per (tile,
+// Gaussian); the fragment count is a popcount of the blend masks on the scalar
+// unit. f_global is ONE atomic add per gradient per tile, issued as three 4-lane
+// atomic instructions on the record's contiguous 48-byte row.
 #include "raster_common.h"
 
 namespace gsr {
@@ -44,22 +46,22 @@ __device__ __forceinline__ void swap16(float& a, float& b) {
   b = __uint_as_float(r[1]);
 }
 
-// Transposed wave reduction of 12 per-lane values v[0..11]. Two swap-and-add
-// stages halve the registers while halving the lanes each value spans (so each
-// add reduces two values at once), then a 4-step DPP row reduction finishes the
-// 16-lane rows. On return w[i] holds, in lanes 15, 31, 47 and 63, the wave totals
-// of values 4i, 4i+2, 4i+1 and 4i+3.
-__device__ __forceinline__ void wave_reduce12(float v[12], float w[3]) {
-  float u[6];
+// Transposed wave reduction of 10 per-lane values v[0..9] (slots 10 and 11 are
+// zero). Two swap-and-add stages halve the registers while halving the lanes each
+// value spans (so each add reduces two values at once), then a 4-step DPP row
+// reduction finishes the 16-lane rows. On return w[i] holds, in lanes 15, 31, 47
+// and 63, the wave totals of slots 4i, 4i+2, 4i+1 and 4i+3.
+__device__ __forceinline__ void wave_reduce10(const float v[10], float w[3]) {
+  float u[5];
 #pragma unroll
-  for (int i = 0; i < 6; ++i) {
+  for (int i = 0; i < 5; ++i) {
     float a = v[2 * i], b = v[2 * i + 1];
     swap32(a, b);
     u[i] = a + b;  // lanes 0-31: value 2i, lanes 32-63: value 2i+1
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    float a = u[2 * i], b = u[2 * i + 1];
+    float a = u[2 * i], b = (i < 2) ? u[2 * i + 1] : 0.0f;
     swap16(a, b);
     w[i] = a + b;  // rows 0, 1, 2, 3: values 4i, 4i+2, 4i+1, 4i+3
   }
@@ -80,6 +82,7 @@ __device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, 
                                                 const ViewDev* __restrict__ views, int32_t V, uint32_t gt, int band,
                                                 const uint32_t* __restrict__ ranges,
                                                 const uint32_t* __restrict__ inst_rec,
+                                                const uint32_t* __restrict__ inst_mask,
                                                 const Record* __restrict__ rec, const ConstImagePtrs& dL,
                                                 const float* __restrict__ pix_T,
                                                 const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d) {
@@ -131,41 +134,54 @@ __device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, 
 
   // Batches from the back: the first one processed starts at the last multiple of 64
   // below e. Pipeline as in the forward, in reverse: record ids two batches ahead,
-  // records one batch ahead (in LDS).
+  // records (in LDS) and the forward's band masks (lane k: entry k) one batch ahead.
   const uint32_t first = s + ((e - s - 1) / 64) * 64;
+  uint32_t maskA, maskB = 0;
   {
     const uint32_t r0 = (first + lane < e) ? inst_rec[first + lane] : 0u;
     batch_fetch(bufA, rec, r0);
     recA[lane] = r0;
+    maskA = (first + lane < e) ? inst_mask[first + lane] : 0u;
   }
+  // the item's bands in the mask bytes: all four, or two from `band` on
+  const uint32_t mask_shift = 8u * (uint32_t)band;
+  const uint32_t mask_keep = NB == 4 ? 0xFFFFFFFFu : 0xFFFFu;
   uint32_t r_next = (first >= s + 64) ? inst_rec[first - 64 + lane] : 0u;
   // per-entry accumulators; zero at the start and again after each reduction that
-  // consumes them (an entry that blends nowhere leaves them at zero)
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f, dcr = 0.f, dcg = 0.f, dcb = 0.f, dop = 0.f, ss = 0.f, nfrag = 0.f;
-  auto run_batch = [&](const BatchLDS& cur, const uint32_t* cur_rec, BatchLDS& nxt, uint32_t* nxt_rec,
-                       uint32_t b0) __attribute__((always_inline)) {
+  // consumes them (an entry that blends nowhere leaves them at zero). The opacity
+  // gradients g_o are summed against s^0 (dop), s^1 and s^2; times o they are the
+  // exponent-gradient sums S0, S1, S2.
+  float P1 = 0.f, P2 = 0.f, dcr = 0.f, dcg = 0.f, dcb = 0.f, dop = 0.f, ss = 0.f;
+  auto run_batch = [&](const BatchLDS& cur, const uint32_t* cur_rec, uint32_t cur_mask, BatchLDS& nxt,
+                       uint32_t* nxt_rec, uint32_t& nxt_mask, uint32_t b0) __attribute__((always_inline)) {
     __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
     __syncthreads();
     if (b0 >= s + 64) {
       batch_fetch(nxt, rec, r_next);
       nxt_rec[lane] = r_next;
+      nxt_mask = inst_mask[b0 - 64 + lane];
     }
     r_next = (b0 >= s + 128) ? inst_rec[b0 - 128 + lane] : 0u;
     const int cnt = (int)min(64u, e - b0);
     for (int k = cnt - 1; k >= 0; --k) {
+      const uint32_t m = ((uint32_t)__builtin_amdgcn_readlane((int)cur_mask, k) >> mask_shift) & mask_keep;
+      if (m == 0) continue;  // no pixel of the item blends this entry
       const Record g = batch_get(cur, k);
-      float ev[NB], dx, dy;
-      strip_exponents<NB>(g, pxc, pyc, soff, ev, dx, dy);
+      float dx, dy;
+      const StripTerms et = strip_terms(g, pxc, pyc, dx, dy);
       const uint32_t pos = b0 - s + (uint32_t)k;
       const float o = g.r2.x;
-      float av[NB], Gv[NB], arv[NB];
-      strip_alpha<P, NB>(o, ev, av, Gv, arv);
+      uint32_t nfrag = 0;  // blended pixels of this entry over the wave (scalar)
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        const float a = av[j], G = Gv[j], araw = arv[j];
-        const bool blend = (pos < last[j]) && (a >= kAlphaMin);
+        if (((m >> (8 * j)) & 0xFFu) == 0) continue;  // no pixel of band j blends it
+        float G, araw;
+        const float a = pixel_alpha<P>(o, et.at(soff[j]), G, araw);
+        const bool before = pos < last[j], visible = a >= kAlphaMin;
+        const bool blend = before && visible;
+        nfrag += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(before) &
+                                                __builtin_amdgcn_ballot_w64(visible));
         if (blend) {
-          nfrag += 1.0f;
           const float inv = __builtin_amdgcn_rcpf(1.0f - a);
           const float Tb = T[j] * inv;  // T before this entry
           const float wt = a * Tb;
@@ -176,17 +192,16 @@ __device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, 
           // dL/dalpha = T (g . c) - (g . colour behind) / (1 - alpha)
           const float dA = __builtin_fmaf(Tb, gc, -gR[j] * inv);
           const float go = (araw <= alpha_clamp<P>()) ? dA * G : 0.0f;
-          const float dE = go * o;
-          S0 += dE;
-          S1 = __builtin_fmaf(soff[j], dE, S1);
-          S2 = __builtin_fmaf(soff[j] * soff[j], dE, S2);
           dop += go;
+          P1 = __builtin_fmaf(soff[j], go, P1);
+          P2 = __builtin_fmaf(soff[j] * soff[j], go, P2);
           ss = __builtin_fmaf(go, go, ss);
           gR[j] = __builtin_fmaf(wt, gc, gR[j]);  // now the colour behind the previous entry
           T[j] = Tb;
         }
       }
-      if (!__any(nfrag > 0.0f)) continue;  // nobody blended this entry
+      if (nfrag == 0) continue;  // nobody blended this entry
+      const float S0 = o * dop, S1 = o * P1, S2 = o * P2;  // dL/dE sums
       // exponent -> conic (a, b, c) and mean (u, v) gradients at the strip anchor
       // (pixel j is s_j rows below it):
       //   E_j = -1/2 (a dx^2 + 2 b dx (dy - s_j) + c (dy - s_j)^2), d = mean - anchor
@@ -198,24 +213,25 @@ __device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, 
       const float ga = -0.5f * dx * dx * S0;
       const float gb = __builtin_fmaf(dx, S1, -dx * dy * S0);
       const float gcn = __builtin_fmaf(dy, S1, __builtin_fmaf(-0.5f * dy * dy, S0, -0.5f * S2));
-      float vals[12] = {gu, gv, ga, gb, gcn, dop, dcr, dcg, dcb, ss, nfrag, 0.0f};
+      const float vals[10] = {gu, gv, ga, gb, gcn, dop, dcr, dcg, dcb, ss};
       float tot[3];
-      wave_reduce12(vals, tot);
-      S0 = S1 = S2 = dcr = dcg = dcb = dop = ss = nfrag = 0.f;
-      // lanes 15, 31, 47, 63 of tot[i] hold slots 4i, 4i+2, 4i+1, 4i+3 (slot 11 is padding)
+      wave_reduce10(vals, tot);
+      P1 = P2 = dcr = dcg = dcb = dop = ss = 0.f;
+      // lanes 15, 31, 47, 63 of tot[i] hold slots 4i, 4i+2, 4i+1, 4i+3; slot 10 (the
+      // fragment count, lane 31 of tot[2]) comes from the scalar count, 11 is padding
       if ((lane & 15) == 15) {
         const int row = lane >> 4;
         const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
         float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D + sub;
         unsafeAtomicAdd(dst, tot[0]);
         unsafeAtomicAdd(dst + 4, tot[1]);
-        if (sub != 3) unsafeAtomicAdd(dst + 8, tot[2]);
+        if (sub != 3) unsafeAtomicAdd(dst + 8, sub == 2 ? (float)nfrag : tot[2]);
       }
     }
   };
   for (int64_t b0 = first; b0 >= (int64_t)s; b0 -= 128) {
-    run_batch(bufA, recA, bufB, recB, (uint32_t)b0);
-    if (b0 >= (int64_t)s + 64) run_batch(bufB, recB, bufA, recA, (uint32_t)(b0 - 64));
+    run_batch(bufA, recA, maskA, bufB, recB, maskB, (uint32_t)b0);
+    if (b0 >= (int64_t)s + 64) run_batch(bufB, recB, maskB, bufA, recA, maskA, (uint32_t)(b0 - 64));
   }
 }
 
@@ -225,6 +241,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    const uint32_t* __restrict__ n_items,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
+                                                   const uint32_t* __restrict__ inst_mask,
                                                    const Record* __restrict__ rec, ConstImagePtrs dL,
                                                    const float* __restrict__ pix_T,
                                                    const uint32_t* __restrict__ pix_last,
@@ -236,11 +253,11 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
   const uint32_t gt = item >> 3;
   const uint32_t code = item & 7u;
   if (code == kItemWhole)
-    raster_bwd_item<P, 4>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, rec, dL, pix_T, pix_last,
-                          grad2d);
+    raster_bwd_item<P, 4>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL, pix_T,
+                          pix_last, grad2d);
   else  // half of a split tile
-    raster_bwd_item<P, 2>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges, inst_rec, rec,
-                          dL, pix_T, pix_last, grad2d);
+    raster_bwd_item<P, 2>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges, inst_rec,
+                          inst_mask, rec, dL, pix_T, pix_last, grad2d);
 }
 
 }  // namespace
@@ -251,10 +268,10 @@ void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, 
   const uint32_t* n_items = f.header + kHdrItemsBwd;
   if (precision == GSR_FP16_BLEND)
     k_raster_bwd<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, n_items, f.ranges, f.inst_rec,
-                                                     f.rec, dL, f.pix_T, f.pix_last, f.grad2d);
+                                                     f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d);
   else
-    k_raster_bwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, n_items, f.ranges, f.inst_rec, f.rec, dL,
-                                               f.pix_T, f.pix_last, f.grad2d);
+    k_raster_bwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, n_items, f.ranges, f.inst_rec,
+                                               f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d);
 }
 
 }  // namespace gsr

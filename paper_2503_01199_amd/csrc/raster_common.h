@@ -56,19 +56,31 @@ __device__ __forceinline__ void strip_offsets(int band, float s[NB]) {
 // computed once per strip from the factored form
 //   E2 = k1 (dx + r dy)^2 + k2 dy^2,   d = screen mean - anchor centre,
 // whose two terms never cancel; the per-pixel cost is two FMAs.
-template <int NB>
-__device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, const float s[NB],
-                                                float e[NB], float& dx, float& dy) {
+struct StripTerms {
+  float basic, lin, quad;
+  // exponent at row offset s from the anchor
+  __device__ __forceinline__ float at(float s) const { return __builtin_fmaf(s, __builtin_fmaf(s, quad, lin), basic); }
+};
+
+__device__ __forceinline__ StripTerms strip_terms(const Record& g, float pxc, float pyc, float& dx, float& dy) {
   dx = (g.r0.x - pxc) + g.r0.z;
   dy = (g.r0.y - pyc) + g.r0.w;
   const float D = __builtin_fmaf(g.r1.y, dy, dx);
   const float t1 = g.r1.x * D;
   const float t2 = g.r1.z * dy;
-  const float basic = __builtin_fmaf(t1, D, t2 * dy);
-  const float lin = -2.0f * __builtin_fmaf(t1, g.r1.y, t2);
-  const float quad = g.r1.w;
+  StripTerms t;
+  t.basic = __builtin_fmaf(t1, D, t2 * dy);
+  t.lin = -2.0f * __builtin_fmaf(t1, g.r1.y, t2);
+  t.quad = g.r1.w;
+  return t;
+}
+
+template <int NB>
+__device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, const float s[NB],
+                                                float e[NB], float& dx, float& dy) {
+  const StripTerms t = strip_terms(g, pxc, pyc, dx, dy);
 #pragma unroll
-  for (int j = 0; j < NB; ++j) e[j] = __builtin_fmaf(s[j], __builtin_fmaf(s[j], quad, lin), basic);
+  for (int j = 0; j < NB; ++j) e[j] = t.at(s[j]);
 }
 
 // G = 2^e (v_exp_f32) and alpha = min(0.99, o G); araw = o G before the clamp.
@@ -117,6 +129,23 @@ __device__ __forceinline__ void strip_alpha(float o, const float e[NB], float a[
   } else {
 #pragma unroll
     for (int j = 0; j < NB; ++j) a[j] = alpha_of(o, e[j], G[j], araw[j]);
+  }
+}
+
+// Alpha of one pixel at precision P: the same value, operation for operation, as
+// strip_alpha gives that pixel (the FP16 pair operations act elementwise).
+template <int P>
+__device__ __forceinline__ float pixel_alpha(float o, float e, float& G, float& araw) {
+  if constexpr (P == GSR_FP16_BLEND) {
+    const half2_t eh = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(e, e));
+    const _Float16 g = __ocml_exp2_f16(eh.x);
+    const _Float16 r = (_Float16)o * g;
+    const _Float16 al = __builtin_elementwise_min((_Float16)kAlphaMax, r);
+    G = (float)g;
+    araw = (float)r;
+    return (float)al;
+  } else {
+    return alpha_of(o, e, G, araw);
   }
 }
 

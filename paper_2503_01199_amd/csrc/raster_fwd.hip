@@ -11,9 +11,11 @@
 // entry whose blend would take T below 1e-4 (that entry is not blended); the wave
 // leaves the list once all its pixels have stopped.
 //
-// Outputs: the image (planar RGB, background composited behind), and per pixel
-// the final T and the list position + 1 of the last blended entry, from which the
-// backward starts its back-to-front walk. P selects the precision of alpha (FP32, or
+// Outputs: the image (planar RGB, background composited behind), per pixel the
+// final T and the list position + 1 of the last blended entry, from which the
+// backward starts its back-to-front walk, and per instance a band mask (byte b
+// nonzero where a live pixel of band b had alpha >= 1/255) that lets the backward
+// skip bands and entries that blend nowhere. P selects the precision of alpha (FP32, or
 // the packed-FP16 blend of Sec. 3.1.2).
 #include "raster_common.h"
 
@@ -26,7 +28,8 @@ namespace {
 template <int P, int NB>
 __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* __restrict__ views,
                                                 int32_t V, uint32_t gt, int band, const uint32_t* __restrict__ ranges,
-                                                const uint32_t* __restrict__ inst_rec, const Record* __restrict__ rec,
+                                                const uint32_t* __restrict__ inst_rec,
+                                                uint32_t* __restrict__ inst_mask, const Record* __restrict__ rec,
                                                 const ImagePtrs& images, int img_base, float* __restrict__ pix_T,
                                                 uint32_t* __restrict__ pix_last) {
   const int v = view_of_tile(views, V, gt);
@@ -72,6 +75,9 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
     if (b0 + 64 < e) batch_fetch(nxt, rec, r_next);
     r_next = (b0 + 128 + lane < e) ? inst_rec[b0 + 128 + lane] : 0u;
     const int cnt = (int)min(64u, e - b0);
+    uint64_t bm[NB];  // bit k of bm[j]: band j has a live pixel with alpha >= 1/255 at entry b0 + k
+#pragma unroll
+    for (int j = 0; j < NB; ++j) bm[j] = 0;
     for (int k = 0; k < cnt; ++k) {
       const Record g = batch_get(cur, k);
       float ev[NB], dx, dy;
@@ -84,6 +90,7 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
         const float a = av[j];
         const bool ok = a >= amin[j];
         if (!__any(ok)) continue;  // nobody in this band blends the entry
+        bm[j] |= 1ull << k;
         const float Tn = T[j] * (1.0f - a);
         const bool stop = ok && (Tn < kTMin);
         const bool blend = ok && !stop;
@@ -99,6 +106,17 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
         live = false;
         break;
       }
+    }
+    // lane k stores entry k's mask, byte j for band j (entries past a break stay 0:
+    // every pixel of the item has stopped before them)
+    if (lane < cnt) {
+      uint32_t mk = 0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) mk |= (uint32_t)((bm[j] >> lane) & 1ull) << (8 * j);
+      if constexpr (NB == 4)
+        inst_mask[b0 + lane] = mk;
+      else
+        reinterpret_cast<uint8_t*>(inst_mask)[4 * (size_t)(b0 + lane) + band] = (uint8_t)mk;
     }
   };
   for (uint32_t b0 = s; b0 < e && live; b0 += 128) {
@@ -126,15 +144,17 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
 template <int P>
 __device__ __forceinline__ void raster_fwd_work(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* views, int32_t V,
                                                 uint32_t item, uint32_t tile_offset, const uint32_t* ranges,
-                                                const uint32_t* inst_rec, const Record* rec, const ImagePtrs& images,
-                                                int img_base, float* pix_T, uint32_t* pix_last) {
+                                                const uint32_t* inst_rec, uint32_t* inst_mask, const Record* rec,
+                                                const ImagePtrs& images, int img_base, float* pix_T,
+                                                uint32_t* pix_last) {
   const uint32_t gt = (item >> 3) - tile_offset;
   const uint32_t code = item & 7u;
   if (code == kItemWhole)
-    raster_fwd_item<P, 4>(bufA, bufB, views, V, gt, 0, ranges, inst_rec, rec, images, img_base, pix_T, pix_last);
-  else
-    raster_fwd_item<P, 1>(bufA, bufB, views, V, gt, (int)code, ranges, inst_rec, rec, images, img_base, pix_T,
+    raster_fwd_item<P, 4>(bufA, bufB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, images, img_base, pix_T,
                           pix_last);
+  else
+    raster_fwd_item<P, 1>(bufA, bufB, views, V, gt, (int)code, ranges, inst_rec, inst_mask, rec, images, img_base,
+                          pix_T, pix_last);
 }
 
 // One frame: block b renders work item items[b] (blocks past the count leave).
@@ -144,12 +164,13 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
                                                    const uint32_t* __restrict__ n_items,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
+                                                   uint32_t* __restrict__ inst_mask,
                                                    const Record* __restrict__ rec, ImagePtrs images,
                                                    float* __restrict__ pix_T, uint32_t* __restrict__ pix_last) {
   __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
   if (blockIdx.x >= *n_items) return;
-  raster_fwd_work<P>(bufA, bufB, views, V, items[blockIdx.x], 0, ranges, inst_rec, rec, images, 0, pix_T,
-                     pix_last);
+  raster_fwd_work<P>(bufA, bufB, views, V, items[blockIdx.x], 0, ranges, inst_rec, inst_mask, rec, images, 0,
+                     pix_T, pix_last);
 }
 
 // Several prepared frames in one launch: block b renders work item order[b], whose
@@ -164,8 +185,8 @@ __global__ __launch_bounds__(64) void k_raster_fwd_batch(FrameTable tab, const u
   int f = 0;
   while (f + 1 < tab.n && tab.first[f + 1] <= g) ++f;
   const FrameRef& fr = tab.f[f];
-  raster_fwd_work<P>(bufA, bufB, fr.views, fr.V, item, tab.first[f], fr.ranges, fr.inst_rec, fr.rec, images,
-                     fr.img_base, fr.pix_T, fr.pix_last);
+  raster_fwd_work<P>(bufA, bufB, fr.views, fr.V, item, tab.first[f], fr.ranges, fr.inst_rec, fr.inst_mask, fr.rec,
+                     images, fr.img_base, fr.pix_T, fr.pix_last);
 }
 
 }  // namespace
@@ -186,10 +207,10 @@ void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, h
   const uint32_t* n_items = f.header + kHdrItems;
   if (precision == GSR_FP16_BLEND)
     k_raster_fwd<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec,
-                                                     f.rec, images, f.pix_T, f.pix_last);
+                                                     f.inst_mask, f.rec, images, f.pix_T, f.pix_last);
   else
-    k_raster_fwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec, f.rec,
-                                               images, f.pix_T, f.pix_last);
+    k_raster_fwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec,
+                                               f.inst_mask, f.rec, images, f.pix_T, f.pix_last);
 }
 
 }  // namespace gsr
