@@ -331,10 +331,13 @@ namespace {
 
 // Every stage of a frame up to the raster schedule (Cluster-Cull-Compact,
 // preprocess, depth sort, offsets, emission, tile sort, ranges, tile order),
-// enqueued on `s` without any host wait.
+// enqueued on `s` without any host wait. With record_done the frame's event
+// completes with its last kernel (gsr_forward leaves it to the raster).
 gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
-                         const gsr_options* opts, void* workspace, size_t ws_bytes, hipStream_t s, FrameRecord** out) {
+                         const gsr_options* opts, void* workspace, size_t ws_bytes, hipStream_t s, bool record_done,
+                         FrameRecord** out) {
   gsr_status st;
+  bool attached = false;
   if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
       (st = validate_records(ctx, scene, V)))
     return st;
@@ -418,10 +421,10 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   {
     StageScope sc_(ctx, GSR_STAGE_RANGES, s);
     gsr::launch_tile_ranges(f, f.inst_tile, cap, s);
-    gsr::launch_tile_order(f, s);
+    attached = gsr::launch_tile_order(f, s, record_done ? fr.done : nullptr);
   }
   if ((st = check_hip(ctx, hipGetLastError(), "frame launches"))) return st;
-  if ((st = check_hip(ctx, hipEventRecord(fr.done, s), "frame event"))) return st;
+  if (record_done && !attached && (st = check_hip(ctx, hipEventRecord(fr.done, s), "frame event"))) return st;
   fr.f = f;
   *out = &fr;
   return GSR_OK;
@@ -434,7 +437,7 @@ gsr_status gsr_prepare(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
   if (!ctx) return GSR_ERR_INVALID_ARG;
   DeviceGuard guard(ctx->device);
   FrameRecord* fr = nullptr;
-  return prepare_frame(ctx, scene, cams, V, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream), &fr);
+  return prepare_frame(ctx, scene, cams, V, opts, workspace, ws_bytes, static_cast<hipStream_t>(stream), true, &fr);
 }
 
 gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
@@ -447,17 +450,18 @@ gsr_status gsr_forward(gsr_context* ctx, const gsr_scene* scene, const gsr_camer
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   FrameRecord* fr = nullptr;
-  gsr_status st = prepare_frame(ctx, scene, cams, V, opts, workspace, ws_bytes, s, &fr);
+  gsr_status st = prepare_frame(ctx, scene, cams, V, opts, workspace, ws_bytes, s, false, &fr);
   if (st) return st;
+  bool attached = false;
   gsr::ImagePtrs ip;
   std::memset(&ip, 0, sizeof(ip));
   for (int v = 0; v < V; ++v) ip.p[v] = images[v];
   {
     StageScope sc_(ctx, GSR_STAGE_RASTER_FWD, s);
-    gsr::launch_raster_fwd(fr->f, ip, opts->precision, s);
+    attached = gsr::launch_raster_fwd(fr->f, ip, opts->precision, s, fr->done);
   }
   if ((st = check_hip(ctx, hipGetLastError(), "forward raster"))) return st;
-  if ((st = check_hip(ctx, hipEventRecord(fr->done, s), "frame event"))) return st;
+  if (!attached && (st = check_hip(ctx, hipEventRecord(fr->done, s), "frame event"))) return st;
   fr->precision = opts->precision;
   return GSR_OK;
 }
@@ -539,11 +543,12 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
   uint32_t* order = static_cast<uint32_t*>(batch_ws);
   uint32_t* n_items = order + batch_items_words(tiles);
   gsr::launch_batch_tile_order(tab, (uint32_t)tiles, order, n_items, s);
-  gsr::launch_raster_fwd_batch(tab, order, n_items, (uint32_t)tiles, ip, precision, s);
+  const bool attached = gsr::launch_raster_fwd_batch(tab, order, n_items, (uint32_t)tiles, ip, precision, s,
+                                                     frs[0]->done);
   gsr_status st = check_hip(ctx, hipGetLastError(), "batched raster");
   if (st) return st;
   for (int i = 0; i < n; ++i) {
-    if ((st = check_hip(ctx, hipEventRecord(frs[i]->done, s), "frame event"))) return st;
+    if ((i > 0 || !attached) && (st = check_hip(ctx, hipEventRecord(frs[i]->done, s), "frame event"))) return st;
     frs[i]->precision = precision;
   }
   return GSR_OK;

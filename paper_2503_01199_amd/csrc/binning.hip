@@ -67,6 +67,12 @@ __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t*
 // both groups in descending length. The item counts go to *n_items (and *n_bwd).
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4096;
+constexpr int kOrderUnroll = 8;  // list lengths loaded per thread before they are counted
+
+// Bucket of a list length: descending length, lengths clamped to kOrderBuckets - 1.
+__device__ __forceinline__ uint32_t order_bucket(uint32_t len) {
+  return kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1));
+}
 
 // List length of concatenated tile i: one frame, or a batch of frames (a short
 // uniform search over the frames' first tiles).
@@ -109,11 +115,21 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   if (t < 2) nlong[t] = 0;
   __syncthreads();
   uint32_t my_long = 0, my_long_b = 0;
-  for (int64_t i = t; i < T; i += kOrderThreads) {
-    const uint32_t len = L.len(i);
-    atomicAdd(&h[kOrderBuckets - 1 - min(len, (uint32_t)(kOrderBuckets - 1))], 1u);
-    my_long += len > kSplitLen ? 1u : 0u;
-    my_long_b += len > kSplitLenBwd ? 1u : 0u;
+  for (int64_t i0 = t; i0 < T; i0 += (int64_t)kOrderThreads * kOrderUnroll) {
+    uint32_t len[kOrderUnroll];
+#pragma unroll
+    for (int q = 0; q < kOrderUnroll; ++q) {  // unconditional loads (index clamped), so all are in flight at once
+      const int64_t i = i0 + (int64_t)q * kOrderThreads;
+      const uint32_t l = L.len(i < T ? i : T - 1);
+      len[q] = i < T ? l : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kOrderUnroll; ++q) {
+      if (i0 + (int64_t)q * kOrderThreads >= T) continue;
+      atomicAdd(&h[order_bucket(len[q])], 1u);
+      my_long += len[q] > kSplitLen ? 1u : 0u;
+      my_long_b += len[q] > kSplitLenBwd ? 1u : 0u;
+    }
   }
   atomicAdd(&nlong[0], my_long);
   if (bwd) atomicAdd(&nlong[1], my_long_b);
@@ -143,10 +159,22 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
     off += v[q];
   }
   __syncthreads();
-  for (int64_t i = t; i < T; i += kOrderThreads) {
-    const uint32_t pos = atomicAdd(&h[kOrderBuckets - 1 - min(L.len(i), (uint32_t)(kOrderBuckets - 1))], 1u);
-    place_items(items, (uint32_t)i, pos, ns, 4);
-    if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+  for (int64_t i0 = t; i0 < T; i0 += (int64_t)kOrderThreads * kOrderUnroll) {
+    uint32_t len[kOrderUnroll];
+#pragma unroll
+    for (int q = 0; q < kOrderUnroll; ++q) {  // unconditional loads (index clamped), so all are in flight at once
+      const int64_t i = i0 + (int64_t)q * kOrderThreads;
+      const uint32_t l = L.len(i < T ? i : T - 1);
+      len[q] = i < T ? l : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kOrderUnroll; ++q) {
+      const int64_t i = i0 + (int64_t)q * kOrderThreads;
+      if (i >= T) continue;
+      const uint32_t pos = atomicAdd(&h[order_bucket(len[q])], 1u);
+      place_items(items, (uint32_t)i, pos, ns, 4);
+      if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+    }
   }
   if (t == 0) {
     *n_items = (uint32_t)T + 3 * ns;
@@ -156,10 +184,11 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
 
 }  // namespace
 
-void launch_tile_order(const Frame& f, hipStream_t s) {
-  if (f.tiles <= 0) return;
-  k_tile_order<OneFrame><<<1, kOrderThreads, 0, s>>>(OneFrame{f.ranges}, f.tiles, f.tile_order,
-                                                     f.header + kHdrItems, f.bwd_items, f.header + kHdrItemsBwd);
+bool launch_tile_order(const Frame& f, hipStream_t s, hipEvent_t done) {
+  if (f.tiles <= 0) return false;
+  launch_tracked(k_tile_order<OneFrame>, 1, kOrderThreads, s, done, OneFrame{f.ranges}, (int64_t)f.tiles,
+                 f.tile_order, f.header + kHdrItems, f.bwd_items, f.header + kHdrItemsBwd);
+  return true;
 }
 
 void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, uint32_t* n_items,

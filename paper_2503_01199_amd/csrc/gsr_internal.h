@@ -1,12 +1,26 @@
 // Internal declarations shared by the HIP sources of libgsr (not part of the ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "gsr.h"
 
 namespace gsr {
+
+// Launches `kernel` on stream s. A non-null `done` event completes with the kernel
+// itself (its completion signal), instead of through a marker enqueued after it:
+// a marker makes the next launch in the stream wait for an extra round trip.
+// The launchers that take an event return whether a kernel carried it (false
+// when there was nothing to launch; the caller then records the event itself).
+template <typename K, typename... Args>
+inline void launch_tracked(K kernel, unsigned grid, unsigned block, hipStream_t s, hipEvent_t done, Args... args) {
+  if (done)
+    hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, nullptr, done, 0, args...);
+  else
+    kernel<<<grid, block, 0, s>>>(args...);
+}
 
 // Thresholds of the compositing rule (Sec. 3, Eq. (1) with the alpha skip, clamp
 // and transmittance stop that the rasterizer applies).
@@ -142,7 +156,7 @@ void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const 
 // binning.hip (counts read from the frame header)
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
 void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s);
-void launch_tile_order(const Frame& f, hipStream_t s);
+bool launch_tile_order(const Frame& f, hipStream_t s, hipEvent_t done);
 
 // raster_fwd.hip / raster_bwd.hip
 struct ImagePtrs {
@@ -151,7 +165,7 @@ struct ImagePtrs {
 struct ConstImagePtrs {
   const float* p[GSR_MAX_VIEWS];
 };
-void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s);
+bool launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s, hipEvent_t done);
 
 // Batched forward raster over several prepared frames (kernel-argument table).
 constexpr int kMaxBatch = GSR_MAX_BATCH;
@@ -172,8 +186,9 @@ struct FrameTable {
   int32_t n;
 };
 static_assert(sizeof(FrameTable) + sizeof(ImagePtrs) <= 3584, "the batch table travels in the kernel arguments");
-void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
-                             uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s);
+bool launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
+                             uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s,
+                             hipEvent_t done);
 // Raster work items of the concatenated tiles of a batch of frames (n_items <- count).
 void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, uint32_t* n_items,
                              hipStream_t s);

@@ -115,13 +115,25 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
   uint32_t v[kScanItems];
   uint32_t sum = 0;
   const int64_t first = base + (int64_t)t * kScanItems;
+  if (n > 0) {
+    // all loads first (indices clamped into range, so none sits behind a branch),
+    // then the gathers, then the masking: the memory round trips overlap
+    uint32_t j[kScanItems];
 #pragma unroll
-  for (int q = 0; q < kScanItems; ++q) {
-    const int64_t i = first + q;
-    uint32_t x = 0;
-    if (i < n) x = src[idx ? idx[i] : i];
-    v[q] = x;
-    sum += x;
+    for (int q = 0; q < kScanItems; ++q) {
+      const int64_t i = first + q < n ? first + q : n - 1;
+      j[q] = idx ? idx[i] : (uint32_t)i;
+    }
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) v[q] = src[j[q]];
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      v[q] = first + q < n ? v[q] : 0u;
+      sum += v[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) v[q] = 0u;
   }
   const uint32_t incl = wave_incl_scan(sum);
   if ((t & 63) == 63) wsum[t >> 6] = incl;
@@ -253,12 +265,27 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
     uint32_t val[kSortRounds];
     uint32_t dig[kSortRounds];
     uint32_t rank[kSortRounds];
+    // every round's loads first (indices clamped into range, so none sits behind a
+    // branch and their round trips overlap), then the ranking
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      const int64_t i = base + r * kSortThreads + t;
+      key[r] = kin[i < n ? i : n - 1];
+    }
+    if (vin) {
+#pragma unroll
+      for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kSortThreads + t;
+        val[r] = vin[i < n ? i : n - 1];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < kSortRounds; ++r) val[r] = (uint32_t)(base + r * kSortThreads + t);
+    }
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
       const int64_t i = base + r * kSortThreads + t;
       const bool valid = i < n;
-      key[r] = valid ? kin[i] : (K)0;
-      val[r] = valid ? (vin ? vin[i] : (uint32_t)i) : 0u;
       dig[r] = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
       const uint64_t peers = match_digit(dig[r] & 255u, valid);
       rank[r] = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));

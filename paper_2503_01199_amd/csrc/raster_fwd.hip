@@ -191,26 +191,31 @@ __global__ __launch_bounds__(64) void k_raster_fwd_batch(FrameTable tab, const u
 
 }  // namespace
 
-void launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
-                             uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s) {
-  if (total_tiles == 0) return;
+bool launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
+                             uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s,
+                             hipEvent_t done) {
+  if (total_tiles == 0) return false;
   const unsigned grid = (unsigned)max_items(total_tiles);
   if (precision == GSR_FP16_BLEND)
-    k_raster_fwd_batch<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(tab, order, n_items, images);
+    launch_tracked(k_raster_fwd_batch<GSR_FP16_BLEND>, grid, 64, s, done, tab, order, n_items, images);
   else
-    k_raster_fwd_batch<GSR_FP32><<<grid, 64, 0, s>>>(tab, order, n_items, images);
+    launch_tracked(k_raster_fwd_batch<GSR_FP32>, grid, 64, s, done, tab, order, n_items, images);
+  return true;
 }
 
-void launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s) {
-  if (f.tiles <= 0) return;
+bool launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s, hipEvent_t done) {
+  if (f.tiles <= 0) return false;
   const unsigned grid = (unsigned)max_items(f.tiles);
   const uint32_t* n_items = f.header + kHdrItems;
   if (precision == GSR_FP16_BLEND)
-    k_raster_fwd<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec,
-                                                     f.inst_mask, f.rec, images, f.pix_T, f.pix_last);
+    launch_tracked(k_raster_fwd<GSR_FP16_BLEND>, grid, 64, s, done, (const ViewDev*)f.views, f.V,
+                   (const uint32_t*)f.tile_order, n_items, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
+                   f.inst_mask, (const Record*)f.rec, images, f.pix_T, f.pix_last);
   else
-    k_raster_fwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.tile_order, n_items, f.ranges, f.inst_rec,
-                                               f.inst_mask, f.rec, images, f.pix_T, f.pix_last);
+    launch_tracked(k_raster_fwd<GSR_FP32>, grid, 64, s, done, (const ViewDev*)f.views, f.V,
+                   (const uint32_t*)f.tile_order, n_items, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
+                   f.inst_mask, (const Record*)f.rec, images, f.pix_T, f.pix_last);
+  return true;
 }
 
 }  // namespace gsr
