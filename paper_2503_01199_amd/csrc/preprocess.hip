@@ -24,6 +24,70 @@ namespace gsr {
 namespace {
 
 constexpr int kThreads = 128;
+static_assert(kThreads == GSR_CLUSTER, "the SH kernels take one cluster (a run of consecutive Gaussians) per block");
+
+// SH rows (R floats per Gaussian) of a block's consecutive Gaussians move between
+// global memory and LDS with coalesced float4 accesses (a wave moves 1 KB per
+// instruction), instead of one strided 4- or 16-byte access per thread and row. In
+// LDS a row has stride R + 1 floats (odd for R = 12, 48), so the threads' walks
+// along their own rows hit distinct banks.
+template <int R>
+__device__ __forceinline__ void rows_to_lds(float* lds, const float* __restrict__ src, int nrows) {
+  constexpr int S = R + 1;
+  const int t = threadIdx.x;
+  if constexpr (R % 4 == 0) {
+    if (nrows == kThreads) {
+      const float4* s4 = reinterpret_cast<const float4*>(src);
+      float4 v[R / 4];
+#pragma unroll
+      for (int m = 0; m < R / 4; ++m) v[m] = s4[m * kThreads + t];
+#pragma unroll
+      for (int m = 0; m < R / 4; ++m) {
+        const int e = 4 * (m * kThreads + t);  // 4 floats of one row (R % 4 == 0)
+        float* d = lds + (e / R) * S + e % R;
+        d[0] = v[m].x;
+        d[1] = v[m].y;
+        d[2] = v[m].z;
+        d[3] = v[m].w;
+      }
+      return;
+    }
+  }
+  for (int e = t; e < nrows * R; e += kThreads) lds[(e / R) * S + e % R] = src[e];
+}
+
+template <int R>
+__device__ __forceinline__ void rows_from_lds(float* __restrict__ dst, const float* lds, int nrows) {
+  constexpr int S = R + 1;
+  const int t = threadIdx.x;
+  if constexpr (R % 4 == 0) {
+    if (nrows == kThreads) {
+      float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+      for (int m = 0; m < R / 4; ++m) {
+        const int e = 4 * (m * kThreads + t);
+        const float* s = lds + (e / R) * S + e % R;
+        d4[m * kThreads + t] = make_float4(s[0], s[1], s[2], s[3]);
+      }
+      return;
+    }
+  }
+  for (int e = t; e < nrows * R; e += kThreads) dst[e] = lds[(e / R) * S + e % R];
+}
+
+template <int R>
+__device__ __forceinline__ void zero_rows(float* __restrict__ dst, int nrows) {
+  const int t = threadIdx.x;
+  if constexpr (R % 4 == 0) {
+    if (nrows == kThreads) {
+      float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+      for (int m = 0; m < R / 4; ++m) d4[m * kThreads + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
+    }
+  }
+  for (int e = t; e < nrows * R; e += kThreads) dst[e] = 0.0f;
+}
 
 struct GaussParams {
   double m[3];
@@ -242,14 +306,19 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
                                                              uint32_t* __restrict__ tiles,
                                                              ushort4* __restrict__ rect,
                                                              float* __restrict__ grad2d) {
-  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (j >= ncap) return;
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  __shared__ float lsh[kThreads * (3 * K + 1)];  // the cluster's SH rows
+  const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // block = compact slot p (grid covers ncap)
   const uint32_t nvis = header[kHdrVisibleClusters];
   if (j == 0) header[kHdrRecords] = nvis * GSR_CLUSTER * (uint32_t)V;
-  const int64_t p = j / GSR_CLUSTER;
+  const int64_t p = blockIdx.x;
+  (void)ncap;
   int64_t i = -1;
-  if (p < (int64_t)nvis) {
-    i = (int64_t)cluster_list[p] * GSR_CLUSTER + (j % GSR_CLUSTER);
+  if (p < (int64_t)nvis) {  // uniform over the block
+    const int64_t i0 = (int64_t)cluster_list[p] * GSR_CLUSTER;
+    rows_to_lds<3 * K>(lsh, sc.sh + i0 * (3 * K), (int)min<int64_t>(kThreads, sc.n - i0));
+    __syncthreads();
+    i = i0 + threadIdx.x;
     if (i >= sc.n) i = -1;
   }
   compact2full[j] = i < 0 ? 0xffffffffu : (uint32_t)i;
@@ -264,8 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
   }
   GaussParams g;
   load_gaussian(sc, i, g);
-  constexpr int K = (DEG + 1) * (DEG + 1);
-  const float* shp = sc.sh + (int64_t)i * K * 3;
+  const float* shp = lsh + threadIdx.x * (3 * K + 1);  // this Gaussian's SH coefficients
   for (int v = 0; v < V; ++v) {
     const int64_t r = j * V + v;
     const ViewDev& w = views[v];
@@ -474,30 +542,29 @@ __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev
                                                      const uint32_t* __restrict__ tiles,
                                                      const float* __restrict__ grad2d, gsr_grads gr) {
   constexpr int K = (DEG + 1) * (DEG + 1);
-  constexpr bool kVec = (3 * K) % 4 == 0;
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= sc.n) return;
-  const int64_t c = i / GSR_CLUSTER;
-  const bool vis = visible[c] != 0;
-  const int64_t j = (int64_t)cluster_offset[c] * GSR_CLUSTER + (i % GSR_CLUSTER);
-  float f[3 * K];
-  const float* shp = sc.sh + i * (3 * K);
-  if constexpr (kVec) {
-    const float4* s4 = reinterpret_cast<const float4*>(shp);
-#pragma unroll
-    for (int q = 0; q < 3 * K / 4; ++q) {
-      const float4 t = s4[q];
-      f[4 * q] = t.x, f[4 * q + 1] = t.y, f[4 * q + 2] = t.z, f[4 * q + 3] = t.w;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 3 * K; ++q) f[q] = shp[q];
+  constexpr int R = 3 * K, S = R + 1;
+  __shared__ float lsh[kThreads * S];  // the cluster's SH rows, then their gradients
+  const int t = threadIdx.x;
+  const int64_t c = blockIdx.x;  // one cluster per block
+  const int64_t i0 = c * GSR_CLUSTER;
+  const int nrows = (int)min<int64_t>(kThreads, sc.n - i0);
+  float* osh = gr.sh + i0 * R;
+  if (visible[c] == 0) {  // a culled cluster: its SH gradient rows are zero (written, not accumulated)
+    zero_rows<R>(osh, nrows);
+    return;
   }
-  float* osh = gr.sh + i * (3 * K);
+  rows_to_lds<R>(lsh, sc.sh + i0 * R, nrows);
+  __syncthreads();
+  const int64_t i = i0 + t;
+  const float* f = lsh + t * S;  // this Gaussian's SH coefficients
+  float gsh[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) gsh[q] = 0.0f;
   float dmu[3] = {0.f, 0.f, 0.f};
   bool written = false;
-  const double m0 = sc.means[3 * i], m1 = sc.means[3 * i + 1], m2 = sc.means[3 * i + 2];
-  if (vis) {
+  if (t < nrows) {
+    const int64_t j = (int64_t)cluster_offset[c] * GSR_CLUSTER + t;
+    const double m0 = sc.means[3 * i], m1 = sc.means[3 * i + 1], m2 = sc.means[3 * i + 2];
     for (int v = 0; v < V; ++v) {
       const int64_t r = j * V + v;
       if (tiles[r] == 0) continue;
@@ -523,26 +590,9 @@ __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev
       const float xf = (float)x, yf = (float)y, zf = (float)z;
       float Yf[16];
       sh_basis<DEG, float>(xf, yf, zf, Yf, nullptr);
-      // d colour / d f_k = Y_k, written per view (the row belongs to this thread)
-      if constexpr (kVec) {
-        float4* o4 = reinterpret_cast<float4*>(osh);
+      // d colour / d f_k = Y_k, summed over the views
 #pragma unroll
-        for (int q = 0; q < 3 * K / 4; ++q) {
-          float4 t;
-          t.x = gc[(4 * q) % 3] * Yf[(4 * q) / 3];
-          t.y = gc[(4 * q + 1) % 3] * Yf[(4 * q + 1) / 3];
-          t.z = gc[(4 * q + 2) % 3] * Yf[(4 * q + 2) / 3];
-          t.w = gc[(4 * q + 3) % 3] * Yf[(4 * q + 3) / 3];
-          if (written) {
-            const float4 o = o4[q];
-            t.x += o.x, t.y += o.y, t.z += o.z, t.w += o.w;
-          }
-          o4[q] = t;
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 3 * K; ++q) osh[q] = gc[q % 3] * Yf[q / 3] + (written ? osh[q] : 0.0f);
-      }
+      for (int q = 0; q < R; ++q) gsh[q] += gc[q % 3] * Yf[q / 3];
       written = true;
       if constexpr (DEG > 0) {
         // d colour / d dir = grad of sum_k (sum_ch gc_ch f_k,ch) Y_k
@@ -559,18 +609,13 @@ __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev
       }
     }
   }
-  if (!written) {
-    if constexpr (kVec) {
-      float4* o4 = reinterpret_cast<float4*>(osh);
+  __syncthreads();  // every thread has read its coefficients: the rows now take the gradients
+  float* orow = lsh + t * S;
 #pragma unroll
-      for (int q = 0; q < 3 * K / 4; ++q) o4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-    } else {
-#pragma unroll
-      for (int q = 0; q < 3 * K; ++q) osh[q] = 0.0f;
-    }
-    return;
-  }
-  if (DEG > 0) {
+  for (int q = 0; q < R; ++q) orow[q] = gsh[q];
+  __syncthreads();
+  rows_from_lds<R>(osh, lsh, nrows);
+  if (DEG > 0 && written) {
     float* om = gr.means + 3 * i;
     om[0] += dmu[0];
     om[1] += dmu[1];
