@@ -27,6 +27,9 @@
 namespace gsr {
 namespace {
 
+constexpr int kBatch = 64;  // records per LDS batch
+using BwdBatch = BatchLDS<kBatch>;
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_row_shr(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
@@ -78,7 +81,7 @@ __device__ __forceinline__ void wave_reduce10(const float v[10], float w[3]) {
 // One work item: tile gt whole (NB = 4 pixels per lane), or its two bands from
 // `band` on (NB = 2, at their row offsets from the whole strip's anchor).
 template <int P, int NB>
-__device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, uint32_t* recA, uint32_t* recB,
+__device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, uint32_t* recA, uint32_t* recB,
                                                 const ViewDev* __restrict__ views, int32_t V, uint32_t gt, int band,
                                                 const uint32_t* __restrict__ ranges,
                                                 const uint32_t* __restrict__ inst_rec,
@@ -132,37 +135,39 @@ __device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, 
   const uint32_t e = min(ranges[2 * gt + 1], s + mymax);
   if (e <= s) return;
 
-  // Batches from the back: the first one processed starts at the last multiple of 64
-  // below e. Pipeline as in the forward, in reverse: record ids two batches ahead,
-  // records (in LDS) and the forward's band masks (lane k: entry k) one batch ahead.
-  const uint32_t first = s + ((e - s - 1) / 64) * 64;
+  // Batches from the back: the first one processed starts at the last multiple of
+  // kBatch below e. Pipeline as in the forward, in reverse: record ids two batches
+  // ahead, records (in LDS) and the forward's band masks (lane k: entry k) one
+  // batch ahead.
+  const bool batch_lane = lane < kBatch;
+  const uint32_t first = s + ((e - s - 1) / kBatch) * kBatch;
   uint32_t maskA, maskB = 0;
   {
-    const uint32_t r0 = (first + lane < e) ? inst_rec[first + lane] : 0u;
+    const uint32_t r0 = (batch_lane && first + lane < e) ? inst_rec[first + lane] : 0u;
     batch_fetch(bufA, rec, r0);
-    recA[lane] = r0;
-    maskA = (first + lane < e) ? inst_mask[first + lane] : 0u;
+    if (batch_lane) recA[lane] = r0;
+    maskA = (batch_lane && first + lane < e) ? inst_mask[first + lane] : 0u;
   }
   // the item's bands in the mask bytes: all four, or two from `band` on
   const uint32_t mask_shift = 8u * (uint32_t)band;
   const uint32_t mask_keep = NB == 4 ? 0xFFFFFFFFu : 0xFFFFu;
-  uint32_t r_next = (first >= s + 64) ? inst_rec[first - 64 + lane] : 0u;
+  uint32_t r_next = (batch_lane && first >= s + kBatch) ? inst_rec[first - kBatch + lane] : 0u;
   // per-entry accumulators; zero at the start and again after each reduction that
   // consumes them (an entry that blends nowhere leaves them at zero). The opacity
   // gradients g_o are summed against s^0 (dop), s^1 and s^2; times o they are the
   // exponent-gradient sums S0, S1, S2.
   float P1 = 0.f, P2 = 0.f, dcr = 0.f, dcg = 0.f, dcb = 0.f, dop = 0.f, ss = 0.f;
-  auto run_batch = [&](const BatchLDS& cur, const uint32_t* cur_rec, uint32_t cur_mask, BatchLDS& nxt,
+  auto run_batch = [&](const BwdBatch& cur, const uint32_t* cur_rec, uint32_t cur_mask, BwdBatch& nxt,
                        uint32_t* nxt_rec, uint32_t& nxt_mask, uint32_t b0) __attribute__((always_inline)) {
     __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
     __syncthreads();
-    if (b0 >= s + 64) {
+    if (b0 >= s + kBatch) {
       batch_fetch(nxt, rec, r_next);
-      nxt_rec[lane] = r_next;
-      nxt_mask = inst_mask[b0 - 64 + lane];
+      if (batch_lane) nxt_rec[lane] = r_next;
+      nxt_mask = batch_lane ? inst_mask[b0 - kBatch + lane] : 0u;
     }
-    r_next = (b0 >= s + 128) ? inst_rec[b0 - 128 + lane] : 0u;
-    const int cnt = (int)min(64u, e - b0);
+    r_next = (batch_lane && b0 >= s + 2 * kBatch) ? inst_rec[b0 - 2 * kBatch + lane] : 0u;
+    const int cnt = (int)min((uint32_t)kBatch, e - b0);
     for (int k = cnt - 1; k >= 0; --k) {
       const uint32_t m = ((uint32_t)__builtin_amdgcn_readlane((int)cur_mask, k) >> mask_shift) & mask_keep;
       if (m == 0) continue;  // no pixel of the item blends this entry
@@ -229,9 +234,9 @@ __device__ __forceinline__ void raster_bwd_item(BatchLDS& bufA, BatchLDS& bufB, 
       }
     }
   };
-  for (int64_t b0 = first; b0 >= (int64_t)s; b0 -= 128) {
+  for (int64_t b0 = first; b0 >= (int64_t)s; b0 -= 2 * kBatch) {
     run_batch(bufA, recA, maskA, bufB, recB, maskB, (uint32_t)b0);
-    if (b0 >= (int64_t)s + 64) run_batch(bufB, recB, maskB, bufA, recA, maskA, (uint32_t)(b0 - 64));
+    if (b0 >= (int64_t)s + kBatch) run_batch(bufB, recB, maskB, bufA, recA, maskA, (uint32_t)(b0 - kBatch));
   }
 }
 
@@ -246,8 +251,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    const float* __restrict__ pix_T,
                                                    const uint32_t* __restrict__ pix_last,
                                                    float* __restrict__ grad2d) {
-  __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
-  __shared__ uint32_t recA[64], recB[64];
+  __shared__ BwdBatch bufA, bufB;  // two objects, so reads of one never wait on loads into the other
+  __shared__ uint32_t recA[kBatch], recB[kBatch];
   if (blockIdx.x >= *n_items) return;
   const uint32_t item = items[blockIdx.x];
   const uint32_t gt = item >> 3;

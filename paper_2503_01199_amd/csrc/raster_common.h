@@ -155,16 +155,22 @@ constexpr float alpha_clamp() {
   return P == GSR_FP16_BLEND ? kAlphaMaxH : kAlphaMax;
 }
 
-// A batch of 64 records in LDS, stored as three planes of float4 (r0, r1, r2) and
-// filled by direct global-to-LDS loads (global_load_lds_dwordx4): lane l's record
-// part lands at plane + 16 l without passing through registers, so the next batch
-// is in flight while the wave works on the current one. Lanes past the end of the
-// list load record 0 (always valid; those slots are never read).
+// A batch of B records (B a power of two, at most 64) in LDS, stored as three
+// planes of float4 (r0, r1, r2) and filled by direct global-to-LDS loads
+// (global_load_lds_dwordx4): lane l < B has its record part land at plane + 16 l
+// without passing through registers, so the next batch is in flight while the
+// wave works on the current one. Lanes past the end of the list load record 0
+// (always valid; those slots are never read). The batch size trades the batch
+// overhead (a barrier and a fetch per batch) against LDS per wave, which bounds
+// how many waves a CU holds.
+template <int B>
 struct BatchLDS {
-  float4 part[3][64];
+  float4 part[3][B];
 };
 
-__device__ __forceinline__ void batch_fetch(BatchLDS& dst, const Record* __restrict__ rec, uint32_t r) {
+template <int B>
+__device__ __forceinline__ void batch_fetch(BatchLDS<B>& dst, const Record* __restrict__ rec, uint32_t r) {
+  if (B < 64 && (int)threadIdx.x >= B) return;
   const float4* src = reinterpret_cast<const float4*>(rec + r);
 #pragma unroll
   for (int p = 0; p < 3; ++p)
@@ -172,7 +178,8 @@ __device__ __forceinline__ void batch_fetch(BatchLDS& dst, const Record* __restr
                                      (__attribute__((address_space(3))) void*)(&dst.part[p][0]), 16, 0, 0);
 }
 
-__device__ __forceinline__ Record batch_get(const BatchLDS& b, int k) {
+template <int B>
+__device__ __forceinline__ Record batch_get(const BatchLDS<B>& b, int k) {
   Record g;
   g.r0 = b.part[0][k];
   g.r1 = b.part[1][k];

@@ -22,11 +22,16 @@
 namespace gsr {
 namespace {
 
+// 32 records per batch: 3 KB of LDS per wave for the two buffers, so LDS no longer
+// caps the waves a CU holds below what the registers allow.
+constexpr int kBatch = 32;
+using FwdBatch = BatchLDS<kBatch>;
+
 // One work item of a frame (views, ranges, lists and records of that frame): tile
 // gt whole (NB = 4 pixels per lane) or its band `band` (NB = 1); its image planes
 // are images.p[img_base + view].
 template <int P, int NB>
-__device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* __restrict__ views,
+__device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, const ViewDev* __restrict__ views,
                                                 int32_t V, uint32_t gt, int band, const uint32_t* __restrict__ ranges,
                                                 const uint32_t* __restrict__ inst_rec,
                                                 uint32_t* __restrict__ inst_mask, const Record* __restrict__ rec,
@@ -67,14 +72,14 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
   const uint32_t e = ranges[2 * gt + 1];
   bool live = any_live();
   // Pipeline: record ids two batches ahead, records one batch ahead (in LDS).
-  if (s < e) batch_fetch(bufA, rec, (s + lane < e) ? inst_rec[s + lane] : 0u);
-  uint32_t r_next = (s + 64 + lane < e) ? inst_rec[s + 64 + lane] : 0u;
-  auto run_batch = [&](const BatchLDS& cur, BatchLDS& nxt, uint32_t b0) __attribute__((always_inline)) {
+  if (s < e) batch_fetch(bufA, rec, (lane < kBatch && s + lane < e) ? inst_rec[s + lane] : 0u);
+  uint32_t r_next = (lane < kBatch && s + kBatch + lane < e) ? inst_rec[s + kBatch + lane] : 0u;
+  auto run_batch = [&](const FwdBatch& cur, FwdBatch& nxt, uint32_t b0) __attribute__((always_inline)) {
     __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
     __syncthreads();
-    if (b0 + 64 < e) batch_fetch(nxt, rec, r_next);
-    r_next = (b0 + 128 + lane < e) ? inst_rec[b0 + 128 + lane] : 0u;
-    const int cnt = (int)min(64u, e - b0);
+    if (b0 + kBatch < e) batch_fetch(nxt, rec, r_next);
+    r_next = (lane < kBatch && b0 + 2 * kBatch + lane < e) ? inst_rec[b0 + 2 * kBatch + lane] : 0u;
+    const int cnt = (int)min((uint32_t)kBatch, e - b0);
     uint64_t bm[NB];  // bit k of bm[j]: band j has a live pixel with alpha >= 1/255 at entry b0 + k
 #pragma unroll
     for (int j = 0; j < NB; ++j) bm[j] = 0;
@@ -119,9 +124,9 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
         reinterpret_cast<uint8_t*>(inst_mask)[4 * (size_t)(b0 + lane) + band] = (uint8_t)mk;
     }
   };
-  for (uint32_t b0 = s; b0 < e && live; b0 += 128) {
+  for (uint32_t b0 = s; b0 < e && live; b0 += 2 * kBatch) {
     run_batch(bufA, bufB, b0);
-    if (b0 + 64 < e && live) run_batch(bufB, bufA, b0 + 64);
+    if (b0 + kBatch < e && live) run_batch(bufB, bufA, b0 + kBatch);
   }
   if (px >= W) return;
   float* img = images.p[img_base + v];
@@ -142,7 +147,7 @@ __device__ __forceinline__ void raster_fwd_item(BatchLDS& bufA, BatchLDS& bufB, 
 
 // Work item `item` of a frame: a whole tile or one band of a split tile.
 template <int P>
-__device__ __forceinline__ void raster_fwd_work(BatchLDS& bufA, BatchLDS& bufB, const ViewDev* views, int32_t V,
+__device__ __forceinline__ void raster_fwd_work(FwdBatch& bufA, FwdBatch& bufB, const ViewDev* views, int32_t V,
                                                 uint32_t item, uint32_t tile_offset, const uint32_t* ranges,
                                                 const uint32_t* inst_rec, uint32_t* inst_mask, const Record* rec,
                                                 const ImagePtrs& images, int img_base, float* pix_T,
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
                                                    uint32_t* __restrict__ inst_mask,
                                                    const Record* __restrict__ rec, ImagePtrs images,
                                                    float* __restrict__ pix_T, uint32_t* __restrict__ pix_last) {
-  __shared__ BatchLDS bufA, bufB;  // two objects, so reads of one never wait on loads into the other
+  __shared__ FwdBatch bufA, bufB;  // two objects, so reads of one never wait on loads into the other
   if (blockIdx.x >= *n_items) return;
   raster_fwd_work<P>(bufA, bufB, views, V, items[blockIdx.x], 0, ranges, inst_rec, inst_mask, rec, images, 0,
                      pix_T, pix_last);
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ v
 template <int P>
 __global__ __launch_bounds__(64) void k_raster_fwd_batch(FrameTable tab, const uint32_t* __restrict__ order,
                                                          const uint32_t* __restrict__ n_items, ImagePtrs images) {
-  __shared__ BatchLDS bufA, bufB;
+  __shared__ FwdBatch bufA, bufB;
   if (blockIdx.x >= *n_items) return;
   const uint32_t item = order[blockIdx.x];
   const uint32_t g = item >> 3;
