@@ -94,19 +94,28 @@ struct ManyFrames {
 __device__ __forceinline__ uint32_t split_code(uint32_t ways, uint32_t b) { return ways == 4 ? b : kItemHalf + b; }
 
 // Places tile i, of rank pos, in an item list that splits its ns first tiles.
-__device__ __forceinline__ void place_items(uint32_t* items, uint32_t i, uint32_t pos, uint32_t ns, uint32_t ways) {
+template <typename W>
+__device__ __forceinline__ void place_items(W* items, uint32_t i, uint32_t pos, uint32_t ns, uint32_t ways) {
   if (pos < ns) {
-    for (uint32_t b = 0; b < ways; ++b) items[ways * pos + b] = (i << 3) | split_code(ways, b);
+    for (uint32_t b = 0; b < ways; ++b) items[ways * pos + b] = (W)((i << 3) | split_code(ways, b));
   } else {
-    items[(ways - 1) * ns + pos] = (i << 3) | kItemWhole;
+    items[(ways - 1) * ns + pos] = (W)((i << 3) | kItemWhole);
   }
 }
+
+// Up to kStageTiles tiles an item fits in 16 bits and both lists are built in LDS,
+// then stored with coalesced writes (one CU issuing ~3 scattered 4-byte stores per
+// tile is otherwise the kernel's bottleneck); larger frames store items directly.
+constexpr int64_t kStageTiles = 8192;
+constexpr int kStageItems = (int)(kStageTiles + 3 * ((kStageTiles + kSplitShare - 1) / kSplitShare));
 
 template <class Len>
 __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, uint32_t* __restrict__ items,
                                                               uint32_t* __restrict__ n_items,
                                                               uint32_t* __restrict__ bwd,
                                                               uint32_t* __restrict__ n_bwd) {
+  __shared__ uint16_t s_items[2][kStageItems];
+  const bool staged = T <= kStageTiles;
   __shared__ uint32_t h[kOrderBuckets];
   __shared__ uint32_t wsum[kOrderThreads / 64];
   __shared__ uint32_t nlong[2];
@@ -172,13 +181,25 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
       const int64_t i = i0 + (int64_t)q * kOrderThreads;
       if (i >= T) continue;
       const uint32_t pos = atomicAdd(&h[order_bucket(len[q])], 1u);
-      place_items(items, (uint32_t)i, pos, ns, 4);
-      if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+      if (staged) {
+        place_items(s_items[0], (uint32_t)i, pos, ns, 4);
+        if (bwd) place_items(s_items[1], (uint32_t)i, pos, ns_b, 2);
+      } else {
+        place_items(items, (uint32_t)i, pos, ns, 4);
+        if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+      }
     }
   }
+  const uint32_t ni = (uint32_t)T + 3 * ns, nb = (uint32_t)T + ns_b;
+  if (staged) {
+    __syncthreads();
+    for (uint32_t k = t; k < ni; k += kOrderThreads) items[k] = s_items[0][k];
+    if (bwd)
+      for (uint32_t k = t; k < nb; k += kOrderThreads) bwd[k] = s_items[1][k];
+  }
   if (t == 0) {
-    *n_items = (uint32_t)T + 3 * ns;
-    if (bwd) *n_bwd = (uint32_t)T + ns_b;
+    *n_items = ni;
+    if (bwd) *n_bwd = nb;
   }
 }
 

@@ -26,7 +26,8 @@ def small_scenes(rz):
     b = SceneTensors.from_scene(scenes.spheres_planes_scene(30_000, seed_salt=5), rz.device)
     perm, _ = rz.morton_order(b.means)
     b = SceneTensors(*rz.apply_permutation(perm, list(b.tensors())), b.sh_degree)
-    return {"tiny": a, "spheres": b}
+    d = SceneTensors.from_scene(scenes.tiny_scene(6000, seed_salt=9), rz.device)  # lists long enough to split
+    return {"tiny": a, "spheres": b, "dense": d}
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
@@ -56,6 +57,25 @@ def test_batched_raster_equals_single_frames(rz, small_scenes, precision):
     for k in g_batch:  # equal up to the order of the float atomics
         scale = float(g_alone[k].abs().max().item()) + 1e-30
         assert float((g_batch[k] - g_alone[k]).abs().max().item()) <= 1e-5 * scale, k
+
+
+def test_batched_split_tiles_equal_single_frames(rz, small_scenes):
+    """A batch caps its split tiles over all its frames, so a dense frame's tiles can
+    be split differently in the batch and alone; its image must not change (a band
+    item evaluates its pixels exactly as the whole-tile walk does)."""
+    from paper_2503_01199_amd.raster import Workspace
+    jobs = [("dense", [scenes.tiny_camera()]), ("spheres", [scenes.orbit_camera(20.0, 5.0, radius=7.0, width=200,
+                                                                                  height=150)]),
+            ("dense", [scenes.tiny_camera(100, 75)])]
+    frames = [rz.prepare(small_scenes[n], cams, workspace=Workspace(rz.device)) for n, cams in jobs]
+    imgs = rz.raster_batch(frames)
+    torch.cuda.synchronize()
+    for (n, cams), im in zip(jobs, imgs):
+        alone = rz.forward(small_scenes[n], cams, workspace=Workspace(rz.device))
+        if n == "dense":
+            assert rz.inspect(alone)["info"]["split_tiles"] > 0
+        for a, b in zip(alone.images, im):
+            assert torch.equal(a, b)
 
 
 def test_served_images_equal_rendering_alone(rz, small_scenes):
