@@ -395,7 +395,7 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
     StageScope sc_(ctx, GSR_STAGE_DEPTH_SORT, s);
     uint32_t* kb[2] = {f.skey[0], f.skey[1]};
     uint32_t* vb[2] = {f.sval[0], f.sval[1]};
-    const int r = gsr::radix_sort_u32_dev(f.dkey, nullptr, kb, vb, f.nrec, n_rec, 32, f.ctl_depth_sort, err, s);
+    const int r = gsr::radix_sort_u32_dev(f.dkey, nullptr, kb, vb, f.nrec, n_rec, 32, f.ctl_depth_sort, err, true, s);
     sorted_rec = r >= 0 ? vb[r] : vb[0];  // no pass only when there are no records
   }
   {
@@ -413,7 +413,7 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
     uint32_t* ik[2] = {f.ikey[1], f.ikey[0]};
     uint32_t* iv[2] = {f.ival[1], f.ival[0]};
     const int ri = gsr::radix_sort_u32_dev(f.ikey[0], f.ival[0], ik, iv, cap, f.header + gsr::kHdrInstancesKept,
-                                           f.tile_bits, f.ctl_tile_sort, err, s);
+                                           f.tile_bits, f.ctl_tile_sort, err, false, s);
     f.inst_tile = ri >= 0 ? ik[ri] : f.ikey[0];
     f.inst_rec = ri >= 0 ? iv[ri] : f.ival[0];
     f.inst_mask = f.inst_rec == f.ival[0] ? f.ival[1] : f.ival[0];  // free once the sort is done

@@ -126,12 +126,16 @@ void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits), 8 bits per pass.
 // The input is read-only; passes alternate between (kb[0], vb[0]) and (kb[1], vb[1]).
 // Returns the index of the pair holding the result, or -1 when no pass was needed
-// (then the input is the result). vals_in == nullptr stands for 0..n-1.
+// (then the input is the result). vals_in == nullptr stands for 0..n-1. spatial:
+// neighbouring keys tend to share their high bytes (the digit counting then adds
+// runs of equal digits at once).
 size_t sort_ctl_words(int64_t n_max, int bits);
 int radix_sort_u32_dev(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2],
-                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s);
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
+                       hipStream_t s);
 int radix_sort_u64_dev(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2],
-                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s);
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
+                       hipStream_t s);
 
 // cluster.hip
 constexpr int kViewChunk = 16;

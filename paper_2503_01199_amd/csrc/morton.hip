@@ -143,7 +143,7 @@ bool morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, 
   k_bounds_partial<<<G, 256, 0, s>>>(means, n, part);
   k_bounds_final<<<1, 384, 0, s>>>(part, G, bounds);
   k_morton_encode<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(means, n, bounds, cin, codes);
-  const int r = radix_sort_u64_dev(cin, nullptr, ck, vb, n, nullptr, 63, ctl, err, s);
+  const int r = radix_sort_u64_dev(cin, nullptr, ck, vb, n, nullptr, 63, ctl, err, false, s);
   k_perm_out<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(vb[r], n, perm);
   return true;
 }

@@ -180,13 +180,14 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 
 // Digit histograms of every pass in one read of the keys; the last block to finish
 // turns them into per-pass exclusive digit offsets (offs[p][d]). Counting needs no
-// ranks, so each key adds 1 to its digit's LDS counter directly (the LDS unit
-// serialises equal addresses within an instruction, cheaper than the ballot match
-// the scatter needs). Blocks take at least kHistChunk keys each (their number is
-// chosen from the count on the device, so the same-address atomics of the final
-// merge stay few) and load 8 keys per thread before counting them. Blocks beyond
-// the needed number leave at once.
-template <typename K>
+// ranks. With kRuns (keys in spatial order, whose high bytes repeat), each thread
+// takes 8 consecutive keys and adds each run of equal digits to its LDS counter
+// with one atomic, since per-key atomics on one address would serialise within an
+// instruction; otherwise each key adds 1 directly.
+// Blocks take at least kHistChunk keys each (their number is chosen from the count
+// on the device, so the same-address atomics of the final merge stay few). Blocks
+// beyond the needed number leave at once.
+template <typename K, bool kRuns>
 __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ keys, int64_t n_host,
                                                           const uint32_t* __restrict__ n_dev, int passes,
                                                           uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
@@ -204,16 +205,40 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
   for (int p = 0; p < passes; ++p) h[p][t] = 0;
   __syncthreads();
   for (int64_t base = (int64_t)blockIdx.x * kSortTile; base < n; base += nb * kSortTile) {
+    if constexpr (!kRuns) {
+      K key[kSortRounds];
+#pragma unroll
+      for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = base + r * kSortThreads + t;
+        key[r] = keys[i < n ? i : n - 1];
+      }
+#pragma unroll
+      for (int r = 0; r < kSortRounds; ++r) {
+        if (base + r * kSortThreads + t < n)
+          for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(key[r] >> (8 * p)) & 255u], 1u);
+      }
+      continue;
+    }
+    const int64_t first = base + (int64_t)t * kSortRounds;  // this thread's consecutive keys
     K key[kSortRounds];
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-      const int64_t i = base + r * kSortThreads + t;
-      key[r] = i < n ? keys[i] : (K)0;
-    }
+    for (int r = 0; r < kSortRounds; ++r) key[r] = keys[first + r < n ? first + r : n - 1];
+    const int nv = (int)max<int64_t>(0, min<int64_t>(kSortRounds, n - first));  // valid keys of the thread
+    for (int p = 0; p < passes; ++p) {
+      uint32_t prev = (uint32_t)(key[0] >> (8 * p)) & 255u, run = nv > 0 ? 1u : 0u;
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-      if (base + r * kSortThreads + t < n)
-        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(key[r] >> (8 * p)) & 255u], 1u);
+      for (int r = 1; r < kSortRounds; ++r) {
+        if (r >= nv) break;
+        const uint32_t d = (uint32_t)(key[r] >> (8 * p)) & 255u;
+        if (d == prev) {
+          ++run;
+        } else {
+          atomicAdd(&h[p][prev], run);
+          prev = d;
+          run = 1;
+        }
+      }
+      if (run) atomicAdd(&h[p][prev], run);
     }
   }
   __syncthreads();
@@ -317,7 +342,7 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
 
 template <typename K>
 int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t* vb[2], int64_t n_max,
-                  const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s) {
+                  const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool runs, hipStream_t s) {
   const int passes = (bits + 7) / 8;
   if (n_max <= 0 || passes == 0) return -1;
   uint32_t* hist = ctl;                       // [passes][256]
@@ -329,7 +354,10 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   int64_t hb = (n_max + kHistChunk - 1) / kHistChunk;
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
-  k_os_hist<K><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
+  if (runs)
+    k_os_hist<K, true><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
+  else
+    k_os_hist<K, false><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
   const K* kcur = keys_in;
   const uint32_t* vcur = vals_in;
   int out = 0;
@@ -360,13 +388,15 @@ void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n
 }
 
 int radix_sort_u32_dev(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2],
-                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s) {
-  return radix_sort_os<uint32_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, s);
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
+                       hipStream_t s) {
+  return radix_sort_os<uint32_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, spatial, s);
 }
 
 int radix_sort_u64_dev(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2],
-                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, hipStream_t s) {
-  return radix_sort_os<uint64_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, s);
+                       int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
+                       hipStream_t s) {
+  return radix_sort_os<uint64_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, spatial, s);
 }
 
 }  // namespace gsr
