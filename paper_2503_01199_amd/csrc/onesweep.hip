@@ -31,26 +31,14 @@ __device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of `agg` over all earlier tiles, for the status column `col`
-// (stride `stride` words between tiles). Publishes this tile's inclusive prefix.
-// The walk reads kWindow predecessors per round trip and consumes them in order
-// until an inclusive prefix (tiles below 0 count as an empty prefix).
+// Sum, in status column `col` (stride `stride` words between entries), of the
+// values from entry b down to the nearest inclusive prefix, that prefix included
+// (entries below 0 count as an empty prefix). The walk reads kWindow entries per
+// round trip and consumes them in order, waiting on entries not yet published.
 constexpr int kWindow = 16;
 
-__device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, int col, uint32_t agg,
-                              uint32_t* err) {
-  uint32_t* mine = status + tile * stride + col;
-  if (agg > kValueMask) {
-    atomicOr(err, 2u);
-    agg &= kValueMask;
-  }
-  if (tile == 0) {
-    st_status(mine, kFlagPrefix | agg);
-    return 0;
-  }
-  st_status(mine, kFlagAgg | agg);
+__device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride, int col, uint32_t* err) {
   uint32_t excl = 0;
-  int64_t b = tile - 1;
   int spins = 0;
   bool found = false;
   while (!found) {
@@ -77,9 +65,81 @@ __device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, in
       __builtin_amdgcn_s_sleep(1);
     }
   }
+  return excl;
+}
+
+// Exclusive prefix of `agg` over all earlier tiles, for the status column `col`
+// (stride `stride` words between tiles). Publishes this tile's inclusive prefix.
+__device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, int col, uint32_t agg,
+                              uint32_t* err) {
+  uint32_t* mine = status + tile * stride + col;
+  if (agg > kValueMask) {
+    atomicOr(err, 2u);
+    agg &= kValueMask;
+  }
+  if (tile == 0) {
+    st_status(mine, kFlagPrefix | agg);
+    return 0;
+  }
+  st_status(mine, kFlagAgg | agg);
+  const uint32_t excl = walk_back(status, tile - 1, stride, col, err);
   if ((uint64_t)excl + agg > kValueMask) atomicOr(err, 2u);
   st_status(mine, kFlagPrefix | ((excl + agg) & kValueMask));
   return excl;
+}
+
+// Two-level look-back for many tiles. Tiles form groups of kGroup; a tile adds
+// the aggregates of the earlier tiles of its group (published right after they
+// rank, so one round trip) and walks back over whole groups, whose last tile
+// publishes the group's aggregate and then its inclusive prefix. An inclusive
+// prefix thus reaches kWindow * kGroup tiles further per round trip, instead of
+// kWindow. Every wait is on a lower tile, so in-order dispatch guarantees
+// progress. tstat: [tiles][stride] per-tile aggregates; gstat: [groups][stride].
+constexpr int kGroup = 16;
+
+__device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t tile, int64_t stride, int col,
+                                      uint32_t agg, uint32_t* err) {
+  if (agg > kValueMask) {
+    atomicOr(err, 2u);
+    agg &= kValueMask;
+  }
+  const int64_t g = tile / kGroup, g0 = g * kGroup;
+  const bool last = tile % kGroup == kGroup - 1;
+  st_status(tstat + tile * stride + col, kFlagAgg | agg);
+  // exclusive sum over the group's earlier tiles g0 .. tile - 1
+  uint32_t E = 0;
+  int spins = 0;
+  for (;;) {
+    uint32_t v[kGroup - 1];
+#pragma unroll
+    for (int q = 0; q < kGroup - 1; ++q) {  // clamped index: all loads in flight at once
+      const int64_t j = tile - 1 - q;
+      const uint32_t x = ld_status(tstat + (j >= g0 ? j : g0) * stride + col);
+      v[q] = j >= g0 ? x : kFlagAgg;
+    }
+    bool ready = true;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kGroup - 1; ++q) {
+      ready = ready && (v[q] & ~kValueMask) != 0;
+      sum += v[q] & kValueMask;
+    }
+    if (ready) {
+      E = sum;
+      break;
+    }
+    if (++spins > kSpinLimit) {
+      atomicOr(err, 1u);
+      E = sum;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (last) st_status(gstat + g * stride + col, kFlagAgg | ((E + agg) & kValueMask));
+  const uint32_t X = g > 0 ? walk_back(gstat, g - 1, stride, col, err) : 0u;
+  if ((uint64_t)X + E + agg > kValueMask) atomicOr(err, 2u);
+  if (last) st_status(gstat + g * stride + col, kFlagPrefix | ((X + E + agg) & kValueMask));
+  return X + E;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -326,7 +386,8 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
         cnt[r][q][t] = run;
         run += c;
       }
-    const uint32_t prior = look_back(ctl + 1, tile, 256, t, run, err);
+    const int64_t tiles = (n_host + kSortTile - 1) / kSortTile;
+    const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err);
     gofs[t] = offs[t] + prior;
     __syncthreads();
 #pragma unroll
@@ -348,9 +409,9 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   uint32_t* hist = ctl;                       // [passes][256]
   uint32_t* offs = ctl + kMaxPasses * 256;    // [passes][256]
   uint32_t* done = offs + kMaxPasses * 256;   // 1 word (padded to 64)
-  uint32_t* pass_ctl = done + 64;             // per pass: 64 reserved words + status[tiles][256]
+  uint32_t* pass_ctl = done + 64;             // per pass: 64 reserved words, tile then group status [.][256]
   const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
-  const int64_t pass_words = 64 + tiles * 256;
+  const int64_t pass_words = 64 + (tiles + (tiles + kGroup - 1) / kGroup) * 256;
   int64_t hb = (n_max + kHistChunk - 1) / kHistChunk;
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
@@ -378,7 +439,7 @@ size_t scan_ctl_words(int64_t n_max) { return 64 + (size_t)((n_max + kScanTile -
 size_t sort_ctl_words(int64_t n_max, int bits) {
   const int passes = (bits + 7) / 8;
   const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
-  return 2 * kMaxPasses * 256 + 64 + (size_t)passes * (64 + tiles * 256);
+  return 2 * kMaxPasses * 256 + 64 + (size_t)passes * (64 + (tiles + (tiles + kGroup - 1) / kGroup) * 256);
 }
 
 void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
