@@ -5,15 +5,19 @@
 // Look-back protocol: block b owns tile b and waits only on lower tiles, whose blocks
 // the dispatcher has placed before it (workgroups are dispatched in id order; an
 // atomic ticket per block would cost a serialised device-scope atomic per block on
-// one address, ~20 us per pass here). A block publishes its tile aggregate, then
-// walks back over its predecessors' status words until it meets an inclusive
-// prefix, and publishes its own inclusive prefix. Grids hold one block per tile of
-// the largest possible count; blocks past the count on the device leave at once. A status word
+// one address, ~20 us per pass here). A block publishes its tile aggregate, adds
+// the aggregates of the earlier tiles of its group of 16, and walks back over the
+// groups' status words until it meets an inclusive prefix; a group's last tile
+// publishes the group's aggregate and then its inclusive prefix (look_back_grouped).
+// Grids hold one block per tile of the largest possible count; blocks past the
+// count on the device leave at once. A status word
 // is (flag << 30 | value): flag 0 = not ready, 1 = aggregate, 2 = inclusive
 // prefix. Values must stay below 2^30: a larger prefix sets bit 1 of the error word
 // (the result is then wrong but every access stays in bounds). The walk waits only
 // on blocks that have started, so it terminates; a bounded spin additionally sets
 // bit 0 of the error word instead of hanging.
+#include <algorithm>
+
 #include "gsr_internal.h"
 
 namespace gsr {
@@ -65,26 +69,6 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  return excl;
-}
-
-// Exclusive prefix of `agg` over all earlier tiles, for the status column `col`
-// (stride `stride` words between tiles). Publishes this tile's inclusive prefix.
-__device__ uint32_t look_back(uint32_t* status, int64_t tile, int64_t stride, int col, uint32_t agg,
-                              uint32_t* err) {
-  uint32_t* mine = status + tile * stride + col;
-  if (agg > kValueMask) {
-    atomicOr(err, 2u);
-    agg &= kValueMask;
-  }
-  if (tile == 0) {
-    st_status(mine, kFlagPrefix | agg);
-    return 0;
-  }
-  st_status(mine, kFlagAgg | agg);
-  const uint32_t excl = walk_back(status, tile - 1, stride, col, err);
-  if ((uint64_t)excl + agg > kValueMask) atomicOr(err, 2u);
-  st_status(mine, kFlagPrefix | ((excl + agg) & kValueMask));
   return excl;
 }
 
@@ -204,7 +188,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     off += (w < (t >> 6)) ? wsum[w] : 0u;
     agg += wsum[w];
   }
-  if (t == 0) s_excl = look_back(ctl + 1, tile, 1, 0, agg, err);
+  if (t == 0) {
+    const int64_t tiles = max<int64_t>(1, (n_host + kScanTile - 1) / kScanTile);
+    s_excl = look_back_grouped(ctl + 1, ctl + 1 + tiles, tile, 1, 0, agg, err);
+  }
   __syncthreads();
   uint32_t run = s_excl + off + incl - sum;
 #pragma unroll
@@ -434,7 +421,10 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
 
 }  // namespace
 
-size_t scan_ctl_words(int64_t n_max) { return 64 + (size_t)((n_max + kScanTile - 1) / kScanTile) + 64; }
+size_t scan_ctl_words(int64_t n_max) {
+  const int64_t tiles = std::max<int64_t>(1, (n_max + kScanTile - 1) / kScanTile);
+  return 64 + (size_t)(tiles + (tiles + kGroup - 1) / kGroup) + 64;
+}
 
 size_t sort_ctl_words(int64_t n_max, int bits) {
   const int passes = (bits + 7) / 8;
