@@ -312,15 +312,19 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
 // One pass: block b takes tile b of 2048 items (8 coalesced rounds of 256), ranks
 // them stably within the tile (ballot match per wave, counts per (round, wave,
 // digit) in LDS), learns the per-digit counts of all earlier tiles by look-back and
-// scatters.
+// scatters. The tile is first reordered by digit in LDS (reusing the counters'
+// space), so that consecutive threads store consecutive positions of each digit's
+// run: a direct per-item scatter writes 256 short runs from scattered lanes.
 template <typename K>
 __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n_host, const uint32_t* __restrict__ n_dev,
                                                              int shift, const uint32_t* __restrict__ offs,
                                                              uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
-  __shared__ uint32_t cnt[kSortRounds][4][256];
-  __shared__ uint32_t gofs[256];
+  __shared__ __align__(16) uint32_t cnt[kSortRounds][4][256];
+  __shared__ uint32_t gofs[256], ldig[256], wtot[4];
+  static_assert(sizeof(K) * kSortTile + 4 * kSortTile <= sizeof(uint32_t) * kSortRounds * 4 * 256,
+                "the staged tile fits in the counters' space");
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
   const int w = t >> 6;
@@ -376,14 +380,36 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
     const int64_t tiles = (n_host + kSortTile - 1) / kSortTile;
     const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err);
     gofs[t] = offs[t] + prior;
+    // tile-local digit offsets: exclusive scan over the digits of the tile's totals
+    const uint32_t incl = wave_incl_scan(run);
+    if (lane == 63) wtot[w] = incl;
     __syncthreads();
+    uint32_t woff = 0;
+    for (int q = 0; q < w; ++q) woff += wtot[q];
+    ldig[t] = woff + incl - run;
+    __syncthreads();
+    uint32_t lpos[kSortRounds];  // position in the tile sorted by digit (stable)
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+      lpos[r] = dig[r] < 256u ? ldig[dig[r]] + cnt[r][w][dig[r]] + rank[r] : 0xffffffffu;
+    __syncthreads();  // the counters are consumed: their space takes the staged tile
+    K* s_key = reinterpret_cast<K*>(&cnt[0][0][0]);
+    uint32_t* s_val = reinterpret_cast<uint32_t*>(s_key + kSortTile);
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
-      if (dig[r] < 256u) {
-        const uint32_t pos = gofs[dig[r]] + cnt[r][w][dig[r]] + rank[r];
-        kout[pos] = key[r];
-        vout[pos] = val[r];
+      if (lpos[r] < (uint32_t)kSortTile) {
+        s_key[lpos[r]] = key[r];
+        s_val[lpos[r]] = val[r];
       }
+    }
+    __syncthreads();
+    const int nv = (int)min<int64_t>(kSortTile, n - base);
+    for (int q = t; q < nv; q += kSortThreads) {
+      const K k = s_key[q];
+      const uint32_t d = (uint32_t)(k >> shift) & 255u;
+      const uint32_t pos = gofs[d] + ((uint32_t)q - ldig[d]);
+      kout[pos] = k;
+      vout[pos] = s_val[q];
     }
   }
 }
