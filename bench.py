@@ -10,10 +10,13 @@ beforehand, as a trainer does every few epochs; that reorder is timed separately
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-prints one JSON line: ms per step (mean over K timed steps, p50/p99), per-stage
+prints one JSON line: ms per step (mean over K steps enqueued back to back), the
+p50/p99 of single steps (200 after 20 warm-up, each alone on the device), per-stage
 times, the roofline of the dominant kernel measured with HIP events on the
 stream it runs on, the FP64 CPU reference timed on the same view, the FP16-blend
-variant and the render-serving stream (p50/p99 latency, views/s).
+variant, a 16-view cycle over the room (one view per step, so that the scene does
+not stay resident in the 256 MB Infinity Cache as it does for one repeated view)
+and the render-serving stream (p50/p99 latency, views/s).
 """
 from __future__ import annotations
 
@@ -134,6 +137,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--latency-iters", type=int, default=200,
+                    help="steps timed one at a time (after 20 warm-up steps) for p50/p99")
+    ap.add_argument("--cycle-views", type=int, default=16,
+                    help="views of the room cycled through, one per step (0 skips; room workload only)")
     ap.add_argument("--workload", default="room", choices=["room", "spheres", "unbounded", "tiny"])
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (testing only)")
     ap.add_argument("--no-cull", action="store_true")
@@ -229,12 +236,13 @@ def main():
     rz.check_frame(fr)  # the frame's instances fitted the workspace
     ms_per_step = wall * 1e3 / args.steps
 
-    # per-step latency and per-stage times (HIP events on the launch stream), in a
-    # separate pass because the per-stage events and waits cost time of their own
-    log("profiling %d steps" % args.steps)
-    rz.set_profiling(True)
-    times, stage_acc = [], {}
-    for _ in range(args.steps):
+    # per-step latency: each step alone on the device, timed by events around it
+    log("latency over %d single steps" % args.latency_iters)
+    for _ in range(20):
+        step()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.latency_iters):
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
@@ -242,6 +250,14 @@ def main():
         b.record()
         b.synchronize()
         times.append(a.elapsed_time(b))
+
+    # per-stage times (HIP events on the launch stream), in a separate pass because
+    # the per-stage events and waits cost time of their own
+    log("profiling %d steps" % args.steps)
+    rz.set_profiling(True)
+    stage_acc = {}
+    for _ in range(args.steps):
+        step()
         for k, v in rz.stage_times().items():
             if v >= 0:
                 stage_acc.setdefault(k, []).append(v)
@@ -270,6 +286,34 @@ def main():
     st16 = {k: round(sum(v) / len(v), 4) for k, v in acc16.items()}
     fp16 = {"ms_per_step": round(fp16_ms, 4), "raster_fwd_ms": st16.get("raster_fwd"),
             "raster_bwd_ms": st16.get("raster_bwd")}
+
+    # a cycle over views of the room, one per step, so that no view's working set
+    # stays resident in the caches as it does when one view repeats
+    cycle = None
+    if args.workload == "room" and args.cycle_views > 0:
+        ccams = scenes.room_cycle_cameras(args.cycle_views)
+        log("timing a %d-view cycle" % len(ccams))
+
+        def cstep(c, check=False):
+            f = rz.forward(st, [c], cluster_cull=cull, workspace=ws, check=check)
+            rz.l1_grad(f.images[0], *wgt[0], out=dls[0])
+            rz.backward(f, [dls[0]], grads=grads, stats=stats)
+            return f
+
+        inst = []
+        for c in ccams:  # sizes the workspace for every view of the cycle
+            inst.append(rz.inspect(cstep(c, check=True))["info"]["instances"])
+        torch.cuda.synchronize()
+        nsteps = 2 * len(ccams)
+        wall0 = time.perf_counter()
+        for i in range(nsteps):
+            frc = cstep(ccams[i % len(ccams)])
+        torch.cuda.synchronize()
+        cyc_ms = (time.perf_counter() - wall0) * 1e3 / nsteps
+        rz.check_frame(frc)
+        cycle = {"views": len(ccams), "steps": nsteps, "ms_per_step": round(cyc_ms, 4),
+                 "instances_min": int(min(inst)), "instances_max": int(max(inst)),
+                 "instances_mean": int(sum(inst) / len(inst))}
 
     # roofline of the dominant kernel (each stage below is one kernel launch)
     dom = max(("raster_bwd", "raster_fwd", "preprocess_bwd", "preprocess"), key=lambda k: stages.get(k, 0.0))
@@ -333,6 +377,7 @@ def main():
         "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
+        "view_cycle": cycle,
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,

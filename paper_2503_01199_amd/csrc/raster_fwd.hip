@@ -87,7 +87,8 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
       const Record g = batch_get(cur, k);
       float ev[NB], dx, dy;
       strip_exponents<NB>(g, pxc, pyc, soff, ev, dx, dy);
-      const uint32_t pos1 = b0 - s + (uint32_t)k + 1u;
+      uint32_t pos1 = b0 - s + (uint32_t)k + 1u;
+      asm volatile("" : "+v"(pos1));  // one register copy per entry, not one per band select
       float av[NB], Gv[NB], arv[NB];
       strip_alpha<P, NB>(g.r2.x, ev, av, Gv, arv);
 #pragma unroll
@@ -97,8 +98,9 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
         if (!__any(ok)) continue;  // nobody in this band blends the entry
         bm[j] |= 1ull << k;
         const float Tn = T[j] * (1.0f - a);
-        const bool stop = ok && (Tn < kTMin);
-        const bool blend = ok && !stop;
+        const bool below = Tn < kTMin;  // one compare serves both outcomes
+        const bool stop = ok && below;
+        const bool blend = ok && !below;
         const float wt = blend ? a * T[j] : 0.0f;
         cr[j] = __builtin_fmaf(wt, g.r2.y, cr[j]);
         cg[j] = __builtin_fmaf(wt, g.r2.z, cg[j]);

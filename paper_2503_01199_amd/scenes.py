@@ -286,6 +286,18 @@ def room_camera(width=1600, height=1064):
     return pinhole(width, height, 70.0, R, t)
 
 
+def room_cycle_cameras(k=16, width=1600, height=1064):
+    """k views of the room from an ellipse at mid-height (semi-axes 3.5 m along x,
+    2.5 m along z), evenly spaced in angle, each looking at the room's centre: a
+    cycle over which no view's working set stays cache-resident."""
+    cams = []
+    for i in range(k):
+        a = 2.0 * math.pi * i / k
+        R, t = look_at((3.5 * math.sin(a), 0.0, 2.5 * math.cos(a)), (0.0, 0.0, 0.0))
+        cams.append(pinhole(width, height, 70.0, R, t))
+    return cams
+
+
 # --------------------------------------------------------------------------- C4
 def unbounded_scene(n=3_000_000, degree=3, seed_salt=0):
     """60% of the Gaussians volume-uniform in a ball of radius 10 (log-scales
