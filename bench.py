@@ -50,8 +50,8 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                             "sources": ["paper_2503_01199_amd/csrc/raster_bwd.hip",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
-                            "sha1": "edba9bf96de76a05c4f2190021ce2eab763e5d81",
-                            "fetch_kib": 70544.0, "write_kib": 99531.0}}
+                            "sha1": "f7d932a9cbb13fc67235a33cee0db7f2702a75ba",
+                            "fetch_kib": 70605.0, "write_kib": 99531.0}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
