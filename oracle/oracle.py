@@ -20,7 +20,7 @@ _lib = None
 
 __all__ = ["build", "load", "camera_array", "sh_basis", "preprocess", "render", "backward", "chain",
            "morton", "cluster_bounds", "bin_instances", "count_instances", "variance", "l1_grad",
-           "l1_loss"]
+           "l1_loss", "ADAM_GROUPS", "sparse_adam"]
 
 
 def build(force: bool = True) -> str:
@@ -228,3 +228,52 @@ def l1_loss(image, w, gt) -> float:
 def l1_grad(image, w, gt):
     """dL/dI of l1_loss: w * sign(I - gt)."""
     return np.asarray(w, np.float64) * np.sign(np.asarray(image, np.float64) - np.asarray(gt, np.float64))
+
+
+ADAM_GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def sparse_adam(params, grads, m, v, visible, lr, beta1, beta2, eps, step, csize: int = 128):
+    """One Adam step (Kingma and Ba, Algorithm 1) applied at cluster granularity,
+    as Sec. 3.2.3 applies the sparse update of the per-view visible primitives to
+    whole clusters of ``csize`` consecutive Gaussians. The paper gives neither the
+    rates nor the handling of skipped Gaussians; the reading is that of the sparse
+    Adam it builds on: the moments and parameters of a cluster that is not visible
+    stay as they are, and the bias corrections use the global step count
+    ``step`` >= 1.
+
+    params, grads, m, v: dicts over ADAM_GROUPS of arrays with n rows (any trailing
+    shape). visible: flags per cluster (nonzero = visible), or None for all.
+    lr: dict with a rate per group, the SH group split into 'sh_dc' (the first 3
+    floats of each row: the degree-0 coefficient of the 3 colours) and 'sh_rest'.
+    Returns new (params, m, v) dicts in FP64; the inputs are not modified.
+    """
+    n = params["means"].shape[0]
+    nc = (n + csize - 1) // csize
+    rows = np.ones(n, dtype=bool)
+    if visible is not None:
+        vis = np.asarray(visible).reshape(-1)[:nc] != 0
+        rows = np.repeat(vis, csize)[:n]
+    bc1 = 1.0 - beta1 ** step
+    bc2 = 1.0 - beta2 ** step
+    out_p, out_m, out_v = {}, {}, {}
+    for k in ADAM_GROUPS:
+        p0 = np.asarray(params[k], np.float64).reshape(n, -1)
+        g = np.asarray(grads[k], np.float64).reshape(n, -1)
+        m0 = np.asarray(m[k], np.float64).reshape(n, -1)
+        v0 = np.asarray(v[k], np.float64).reshape(n, -1)
+        if k == "sh":
+            rate = np.full(p0.shape[1], lr["sh_rest"], np.float64)
+            rate[:3] = lr["sh_dc"]
+        else:
+            rate = np.full(p0.shape[1], lr[k], np.float64)
+        m1 = beta1 * m0 + (1.0 - beta1) * g            # biased first moment
+        v1 = beta2 * v0 + (1.0 - beta2) * g * g        # biased second raw moment
+        m_hat = m1 / bc1
+        v_hat = v1 / bc2
+        p1 = p0 - rate[None, :] * m_hat / (np.sqrt(v_hat) + eps)
+        shape = np.shape(params[k])
+        out_p[k] = np.where(rows[:, None], p1, p0).reshape(shape)
+        out_m[k] = np.where(rows[:, None], m1, m0).reshape(shape)
+        out_v[k] = np.where(rows[:, None], v1, v0).reshape(shape)
+    return out_p, out_m, out_v

@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs: Gaussian scenes, cameras and loss weights.
+"""Seeded synthetic inputs: Gaussian scenes, cameras, loss weights and optimiser state.
 
 This module only draws inputs. It holds none of the rasterizer's arithmetic, and it
 is the one module that both the GPU path and the test oracle receive data from.
@@ -346,6 +346,47 @@ def l1_weights(shape, config=0, salt=0):
     w = rng.uniform(0, 1, size=shape).astype(np.float32)
     gt = rng.uniform(0, 1, size=shape).astype(np.float32)
     return w, gt
+
+
+# ------------------------------------------------------------------ optimiser step
+ADAM_GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def adam_inputs(n, degree=3, salt=0, zero_rows=0.1):
+    """Parameters, gradients and the two Adam moments of n Gaussians: four dicts
+    over ADAM_GROUPS of f32 arrays with the scene shapes. Values span several
+    decades, as a trained scene's do: p ~ N(0, 1); g, m ~ N(0, 1) 10^U(-6, -1);
+    v = (N(0, 1) 10^U(-6, -1))^2 >= 0; a fraction `zero_rows` of the Gaussians have
+    an exact zero gradient (Gaussians that no view blends)."""
+    rng = rng_for(300, salt)
+    K = (degree + 1) ** 2
+    shapes = {"means": (n, 3), "log_scales": (n, 3), "quats": (n, 4), "opacity_logits": (n,), "sh": (n, K, 3)}
+    zero = rng.uniform(0, 1, size=n) < zero_rows
+
+    def spread(shape):
+        return rng.standard_normal(shape) * 10.0 ** rng.uniform(-6, -1, size=shape)
+
+    P, G, M, V = {}, {}, {}, {}
+    for k, sh in shapes.items():
+        P[k] = _f32(rng.standard_normal(sh))
+        g = spread(sh)
+        g[zero] = 0.0
+        G[k] = _f32(g)
+        M[k] = _f32(spread(sh))
+        V[k] = _f32(spread(sh) ** 2)
+    return P, G, M, V
+
+
+def cluster_flags(nc, pattern="random", salt=0):
+    """Visibility flags u32[nc] of clusters: 'all', 'none', 'random' (each visible
+    with probability 1/2) or 'alternate' (even clusters)."""
+    if pattern == "all":
+        return np.ones(nc, np.uint32)
+    if pattern == "none":
+        return np.zeros(nc, np.uint32)
+    if pattern == "alternate":
+        return (np.arange(nc) % 2 == 0).astype(np.uint32)
+    return (rng_for(301, salt).uniform(0, 1, size=nc) < 0.5).astype(np.uint32)
 
 
 def scene_by_name(name: str, n: int | None = None):

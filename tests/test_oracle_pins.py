@@ -530,3 +530,123 @@ def test_gradients_through_jacobian_clamp(orc):
             assert abs(fd - an) <= 2e-5 * scale + 1e-10, (field, idx, fd, an)
             checked += 1
     assert checked >= 25
+
+
+# ------------------------------------------------------------------ sparse Adam (Sec. 3.2.3)
+ADAM_LR = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 2.5e-2, "sh_dc": 2.5e-3,
+           "sh_rest": 1.25e-4}
+
+
+def _adam_f64(n, degree, salt):
+    P, G, M, V = scenes.adam_inputs(n, degree, salt=salt)
+    f = lambda d: {k: v.astype(np.float64) for k, v in d.items()}
+    return f(P), f(G), f(M), f(V)
+
+
+def test_adam_all_visible_equals_torch_adam(orc):
+    """Every cluster visible: the library's Adam (torch.optim.Adam, FP64 on the CPU,
+    one parameter group per rate) over four steps with fresh gradients."""
+    import torch
+    n, degree = 300, 3
+    P, _, _, _ = _adam_f64(n, degree, 0)
+    tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.items() if k != "sh"}
+    tp["sh_dc"] = torch.tensor(P["sh"][:, :1, :], requires_grad=True)
+    tp["sh_rest"] = torch.tensor(P["sh"][:, 1:, :], requires_grad=True)
+    opt = torch.optim.Adam([{"params": [t], "lr": ADAM_LR[k]} for k, t in tp.items()], betas=(0.9, 0.999),
+                           eps=1e-15)
+    m = {k: np.zeros_like(v) for k, v in P.items()}
+    v = {k: np.zeros_like(x) for k, x in P.items()}
+    p = P
+    for t in range(1, 5):
+        _, G, _, _ = _adam_f64(n, degree, 10 + t)
+        for k, x in tp.items():
+            g = G["sh"][:, :1, :] if k == "sh_dc" else G["sh"][:, 1:, :] if k == "sh_rest" else G[k]
+            x.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = orc.sparse_adam(p, G, m, v, None, ADAM_LR, 0.9, 0.999, 1e-15, t)
+    ref = {k: tp[k].detach().numpy() for k in tp if not k.startswith("sh")}
+    ref["sh"] = np.concatenate([tp["sh_dc"].detach().numpy(), tp["sh_rest"].detach().numpy()], axis=1)
+    for k in ref:
+        assert np.allclose(p[k], ref[k], rtol=1e-12, atol=1e-15), k
+
+
+def test_adam_constant_gradient_closed_form(orc):
+    """With a constant gradient from zero moments the bias corrections are exact:
+    m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so every step moves a parameter by
+    lr g / (|g| + eps) and t steps by t times that."""
+    n = 200
+    P, G, _, _ = _adam_f64(n, 1, 1)
+    m = {k: np.zeros_like(x) for k, x in P.items()}
+    v = {k: np.zeros_like(x) for k, x in P.items()}
+    p = P
+    b1, b2, eps, T = 0.8, 0.95, 1e-8, 7
+    for t in range(1, T + 1):
+        p, m, v = orc.sparse_adam(p, G, m, v, None, ADAM_LR, b1, b2, eps, t)
+    for k in P:
+        g = G[k]
+        if k == "sh":
+            lr = np.full(g.shape, ADAM_LR["sh_rest"])
+            lr[:, 0, :] = ADAM_LR["sh_dc"]
+        else:
+            lr = ADAM_LR[k]
+        assert np.allclose(p[k], P[k] - T * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-14), k
+        assert np.allclose(m[k], (1 - b1 ** T) * g, rtol=1e-12, atol=0), k
+        assert np.allclose(v[k], (1 - b2 ** T) * g * g, rtol=1e-12, atol=0), k
+
+
+def test_adam_moments_equal_their_sums(orc):
+    """The recursions unrolled (Kingma and Ba, Sec. 3): from zero moments,
+    m_t = (1 - b1) sum_k b1^(t-k) g_k and v_t = (1 - b2) sum_k b2^(t-k) g_k^2; and
+    the step of the last update is lr (m_t / (1 - b1^t)) / (sqrt(v_t / (1 - b2^t)) + eps)."""
+    n, b1, b2, eps = 150, 0.7, 0.9, 1e-6
+    P, _, _, _ = _adam_f64(n, 0, 2)
+    gs = [_adam_f64(n, 0, 20 + t)[1] for t in range(1, 4)]
+    m = {k: np.zeros_like(x) for k, x in P.items()}
+    v = {k: np.zeros_like(x) for k, x in P.items()}
+    p = P
+    for t, G in enumerate(gs, start=1):
+        prev = p
+        p, m, v = orc.sparse_adam(p, G, m, v, None, ADAM_LR, b1, b2, eps, t)
+    T = len(gs)
+    for k in P:
+        ms = (1 - b1) * sum(b1 ** (T - j) * gs[j - 1][k] for j in range(1, T + 1))
+        vs = (1 - b2) * sum(b2 ** (T - j) * gs[j - 1][k] ** 2 for j in range(1, T + 1))
+        assert np.allclose(m[k], ms, rtol=1e-12, atol=1e-18), k
+        assert np.allclose(v[k], vs, rtol=1e-12, atol=1e-30), k
+        lr = ADAM_LR["sh_dc"] if k == "sh" else ADAM_LR[k]  # degree 0: the SH rows are DC only
+        step = lr * (ms / (1 - b1 ** T)) / (np.sqrt(vs / (1 - b2 ** T)) + eps)
+        assert np.allclose(prev[k] - p[k], step, rtol=1e-9, atol=1e-15), k
+
+
+def test_adam_sparse_clusters(orc):
+    """Cluster granularity: a cluster that is not visible keeps its parameters and
+    moments bit for bit; a cluster skipped at step 2 of a constant gradient g from
+    zero moments decays its moments once, so after step 3 (global t = 3)
+    m = (1 - b1^2) g and the step is lr m / (1 - b1^3) / (sqrt(v / (1 - b2^3)) + eps)
+    with v = (1 - b2^2) g^2. The last cluster is partial (n = 5 * 128 + 37)."""
+    n, b1, b2, eps = 5 * 128 + 37, 0.9, 0.99, 1e-12
+    P, G, M0, V0 = _adam_f64(n, 2, 3)
+    flags = np.array([1, 0, 1, 0, 1, 1], np.uint32)
+    p, m, v = orc.sparse_adam(P, G, M0, V0, flags, ADAM_LR, b1, b2, eps, 5)
+    rows = np.repeat(flags != 0, 128)[:n]
+    for k in P:
+        assert np.array_equal(p[k][~rows], P[k][~rows]) and np.array_equal(m[k][~rows], M0[k][~rows])
+        assert np.array_equal(v[k][~rows], V0[k][~rows])
+        assert not np.any(p[k][rows] == P[k][rows])  # zero-gradient rows still move by momentum
+    # skip pattern over three steps: cluster 0 always, cluster 1 at steps 1 and 3
+    z = {k: np.zeros_like(x) for k, x in P.items()}
+    p, m, v = P, z, dict(z)
+    for t, fl in ((1, [1, 1]), (2, [1, 0]), (3, [1, 1])):
+        p, m, v = orc.sparse_adam(p, G, m, v, np.array(fl + [0] * 4, np.uint32), ADAM_LR, b1, b2, eps, t)
+    sel = slice(128, 256)
+    g = G["means"][sel]
+    mt, vt = (1 - b1 ** 2) * g, (1 - b2 ** 2) * g * g
+    assert np.allclose(m["means"][sel], mt, rtol=1e-12, atol=0)
+    assert np.allclose(v["means"][sel], vt, rtol=1e-12, atol=0)
+    s1 = ADAM_LR["means"] * g / (np.abs(g) + eps)  # the step at t = 1 (closed form above)
+    s3 = ADAM_LR["means"] * (mt / (1 - b1 ** 3)) / (np.sqrt(vt / (1 - b2 ** 3)) + eps)
+    assert np.allclose(P["means"][sel] - p["means"][sel], s1 + s3, rtol=1e-10, atol=1e-15)
+    g0 = G["means"][:128]
+    assert np.allclose(P["means"][:128] - p["means"][:128], 3 * ADAM_LR["means"] * g0 / (np.abs(g0) + eps),
+                       rtol=1e-10, atol=1e-15)
+    assert np.array_equal(p["means"][256:], P["means"][256:])
