@@ -15,8 +15,10 @@ p50/p99 of single steps (200 after 20 warm-up, each alone on the device), per-st
 times, the roofline of the dominant kernel measured with HIP events on the
 stream it runs on, the FP64 CPU reference timed on the same view, the FP16-blend
 variant, a 16-view cycle over the room (one view per step, so that the scene does
-not stay resident in the 256 MB Infinity Cache as it does for one repeated view)
-and the render-serving stream (p50/p99 latency, views/s).
+not stay resident in the 256 MB Infinity Cache as it does for one repeated view),
+the cluster-granular Adam step that follows the backward (over the kept clusters
+and, for comparison, over all) and the render-serving stream (p50/p99 latency,
+views/s).
 """
 from __future__ import annotations
 
@@ -110,6 +112,53 @@ def build_workload(name, n_override=None):
     return sc, cams, desc
 
 
+ADAM_LR = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 2.5e-2, "sh_dc": 2.5e-3,
+           "sh_rest": 1.25e-4}
+
+
+def adam_leg(rz, st, grads, visible, steps):
+    """Cluster-granular Adam (Sec. 3.2.3) over the frame's kept clusters, and the
+    dense update over every cluster for comparison: per-launch times from HIP events
+    on the launch stream and the algorithmic HBM bytes (parameter, gradient and both
+    moments read, parameter and moments written: 28 B per float of a row)."""
+    import torch
+    keys = ("means", "log_scales", "quats", "opacity_logits", "sh")
+    params = {k: t.clone() for k, t in zip(keys, st.tensors())}
+    m = {k: torch.zeros_like(t) for k, t in params.items()}
+    v = {k: torch.zeros_like(t) for k, t in params.items()}
+    row_floats = sum(t[0].numel() for t in params.values())
+    kept = int(visible.to(torch.int64).sum().item())
+    nc = visible.numel()
+    full_rows = min(st.n, kept * 128) if kept < nc else st.n  # the last cluster may be partial
+    out = {}
+    for name, vis, rows in (("sparse", visible, full_rows), ("dense", None, st.n)):
+        t = [0]
+
+        def launch():
+            t[0] += 1
+            rz.sparse_adam(params, grads, m, v, vis, ADAM_LR, t[0])
+        for _ in range(3):
+            launch()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            launch()
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        nbytes = 28 * row_floats * rows
+        out[name] = {"ms": round(ms, 4), "gaussians": rows, "bytes_per_launch": nbytes,
+                     "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["kept_clusters"] = kept
+    out["clusters"] = nc
+    out["bound"] = "hbm"
+    out["peak_GBs"] = HBM_PEAK_GBS
+    return out
+
+
 def cpu_baseline(scene, cam, repeats, threads):
     """The FP64 oracle's forward + backward of the whole view (the same scene, camera
     and loss as the GPU step), timed `repeats` times; the median is reported."""
@@ -147,6 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the render-serving stream")
+    ap.add_argument("--no-adam", action="store_true", help="skip the cluster-granular Adam leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 3 times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-requests", type=int, default=3000)
@@ -315,6 +365,14 @@ def main():
                  "instances_min": int(min(inst)), "instances_max": int(max(inst)),
                  "instances_mean": int(sum(inst) / len(inst))}
 
+    # the optimiser step that follows the backward (not part of the metric's step)
+    adam = None
+    if not args.no_adam:
+        log("timing the cluster-granular Adam step")
+        fr = step()  # the room view's frame again (the legs above reused the workspace)
+        ins = rz.inspect(fr)
+        adam = adam_leg(rz, st, grads, ins["cluster_visible"][: ins["info"]["clusters"]].clone(), args.steps)
+
     # roofline of the dominant kernel (each stage below is one kernel launch)
     dom = max(("raster_bwd", "raster_fwd", "preprocess_bwd", "preprocess"), key=lambda k: stages.get(k, 0.0))
     roof_kernel = {"raster_bwd": "k_raster_bwd", "raster_fwd": "k_raster_fwd", "preprocess_bwd": "k_sh_bwd",
@@ -378,6 +436,7 @@ def main():
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
         "view_cycle": cycle,
+        "sparse_adam": adam,
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -278,6 +278,51 @@ gsr_status gsr_apply_permutation(gsr_context *ctx, const int64_t *perm, int64_t 
 gsr_status gsr_l1_grad(gsr_context *ctx, const float *image, const float *w, const float *gt, int64_t count,
                        float *out, void *stream);
 
+/* Rates and constants of one Adam step (Kingma and Ba, Algorithm 1). The paper
+ * does not give the rates; 3DGS trains with rates of the order of 1.6e-4 (means),
+ * 5e-3 (log-scales), 1e-3 (quaternions), 2.5e-2 (opacity), 2.5e-3 (SH degree 0)
+ * and 1.25e-4 (higher SH), betas 0.9 / 0.999 and eps 1e-15. */
+typedef struct {
+  float lr_means;
+  float lr_log_scales;
+  float lr_quats;
+  float lr_opacity;
+  float lr_sh_dc;    /* the first 3 floats of each SH row: the degree-0 coefficient of each colour */
+  float lr_sh_rest;  /* the other floats of each SH row */
+  float beta1;       /* in [0, 1) */
+  float beta2;       /* in [0, 1) */
+  float eps;         /* >= 0, added to sqrt(v / (1 - beta2^t)) */
+  int32_t reserved;  /* must be 0 */
+  int64_t step;      /* t >= 1: this update's number, counted over all updates; both bias
+                        corrections use it, for a cluster skipped before as for any other */
+} gsr_adam_options;
+
+/* One Adam step at cluster granularity (Sec. 3.2.3): the sparse update of the
+ * visible primitives is applied to whole clusters of GSR_CLUSTER consecutive
+ * Gaussians, which keeps every read and write of the update on contiguous
+ * memory. For every Gaussian i of a cluster c with cluster_visible[c] != 0 and
+ * every float x of its parameters, with g its gradient and m, v its moments:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   x = x - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)
+ * (FP32; the bias corrections are formed in FP64 once per call). Parameters and
+ * both moments of every other cluster are left untouched: they keep their values
+ * bit for bit and do not decay.
+ *   n, sh_degree: as in gsr_scene; params, exp_avg, exp_avg_sq: the parameters and
+ *     the first and second moments, device arrays with gsr_scene's shapes, updated
+ *     in place (gsr_grads serves as the holder of five such arrays); grads: the
+ *     gradients in the same shapes, read only (gsr_backward's output).
+ *   cluster_visible: device u32[ceil(n / GSR_CLUSTER)], nonzero = update the
+ *     cluster, e.g. gsr_frame_buffers.cluster_visible of the frame that produced
+ *     grads (the clusters its cull kept in any of its views); NULL updates all
+ *     (dense Adam).
+ * Every array must be 16-byte aligned and no two of the twenty may overlap
+ * (GSR_ERR_INVALID_ARG otherwise, as for a null array with n > 0, a degree
+ * outside 0..3, step < 1, a beta outside [0, 1) or eps < 0). Asynchronous on
+ * `stream`; n = 0 enqueues nothing. */
+gsr_status gsr_sparse_adam(gsr_context *ctx, int64_t n, int32_t sh_degree, const uint32_t *cluster_visible,
+                           const gsr_grads *params, const gsr_grads *grads, const gsr_grads *exp_avg,
+                           const gsr_grads *exp_avg_sq, const gsr_adam_options *opts, void *stream);
+
 /* Stages of gsr_forward and gsr_backward, in launch order. */
 typedef enum {
   GSR_STAGE_CLUSTER = 0,     /* cluster bounds, frustum cull, compaction list */

@@ -49,6 +49,12 @@ class GsrGrads(ctypes.Structure):
                 ("sh", c_void_p)]
 
 
+class GsrAdamOptions(ctypes.Structure):
+    _fields_ = [("lr_means", c_float), ("lr_log_scales", c_float), ("lr_quats", c_float), ("lr_opacity", c_float),
+                ("lr_sh_dc", c_float), ("lr_sh_rest", c_float), ("beta1", c_float), ("beta2", c_float),
+                ("eps", c_float), ("reserved", c_int32), ("step", c_int64)]
+
+
 class GsrStats(ctypes.Structure):
     _fields_ = [("S", c_void_p), ("M", c_void_p), ("C", c_void_p)]
 
@@ -94,6 +100,9 @@ EXPORTS = {
     "gsr_apply_permutation": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(c_void_p),
                                         ctypes.POINTER(c_void_p), ctypes.POINTER(c_int32), c_void_p]),
     "gsr_l1_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "gsr_sparse_adam": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, ctypes.POINTER(GsrGrads),
+                                  ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads),
+                                  ctypes.POINTER(GsrAdamOptions), c_void_p]),
     "gsr_set_profiling": (c_int32, [c_void_p, c_int32]),
     "gsr_stage_times": (c_int32, [c_void_p, ctypes.POINTER(c_float)]),
 }

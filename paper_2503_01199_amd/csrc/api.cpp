@@ -699,6 +699,73 @@ gsr_status gsr_l1_grad(gsr_context* ctx, const float* image, const float* w, con
   return check_hip(ctx, hipGetLastError(), "l1 grad");
 }
 
+gsr_status gsr_sparse_adam(gsr_context* ctx, int64_t n, int32_t sh_degree, const uint32_t* cluster_visible,
+                           const gsr_grads* params, const gsr_grads* grads, const gsr_grads* exp_avg,
+                           const gsr_grads* exp_avg_sq, const gsr_adam_options* opts, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (n < 0 || n > (int64_t(1) << 40) || sh_degree < 0 || sh_degree > 3 || !params || !grads || !exp_avg ||
+      !exp_avg_sq || !opts)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_sparse_adam");
+  const gsr_adam_options& o = *opts;
+  if (o.reserved != 0 || o.step < 1 || !(o.beta1 >= 0.0f && o.beta1 < 1.0f) || !(o.beta2 >= 0.0f && o.beta2 < 1.0f) ||
+      !(o.eps >= 0.0f))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sparse_adam: need step >= 1, betas in [0, 1), eps >= 0");
+  if (n == 0) return GSR_OK;
+  const int32_t K = (sh_degree + 1) * (sh_degree + 1);
+  const int32_t rows[gsr::kAdamGroups] = {3, 3, 4, 1, 3 * K};
+  // the five arrays of each set, in the order of the kernel's groups
+  float* arr[4][gsr::kAdamGroups];
+  const gsr_grads* sets[4] = {params, grads, exp_avg, exp_avg_sq};
+  struct Extent {
+    uintptr_t lo, hi;
+  };
+  std::vector<Extent> ext;
+  for (int j = 0; j < 4; ++j) {
+    const gsr_grads& g = *sets[j];
+    float* ptrs[gsr::kAdamGroups] = {g.means, g.log_scales, g.quats, g.opacity_logits, g.sh};
+    for (int k = 0; k < gsr::kAdamGroups; ++k) {
+      const uintptr_t a = reinterpret_cast<uintptr_t>(ptrs[k]);
+      if (!a || (a & 15u))
+        return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sparse_adam: every array must be non-null and 16-byte aligned");
+      ext.push_back({a, a + uintptr_t(n) * rows[k] * sizeof(float)});
+      arr[j][k] = ptrs[k];
+    }
+  }
+  std::sort(ext.begin(), ext.end(), [](const Extent& x, const Extent& y) { return x.lo < y.lo; });
+  for (size_t i = 1; i < ext.size(); ++i)
+    if (ext[i].lo < ext[i - 1].hi) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sparse_adam: arrays overlap");
+
+  gsr::AdamDev a{};
+  const double t = double(o.step);
+  const double bc1 = 1.0 - std::pow(double(o.beta1), t);
+  const double bc2 = 1.0 - std::pow(double(o.beta2), t);
+  const float lr[gsr::kAdamGroups] = {o.lr_means, o.lr_log_scales, o.lr_quats, o.lr_opacity, o.lr_sh_dc};
+  int32_t row_sum = 0;
+  for (int k = 0; k < gsr::kAdamGroups; ++k) {
+    gsr::AdamGroupDev& q = a.grp[k];
+    q.p = arr[0][k];
+    q.g = arr[1][k];
+    q.m = arr[2][k];
+    q.v = arr[3][k];
+    q.row = rows[k];
+    q.head = k == 4 ? 3 : rows[k];  // SH: the degree-0 floats take lr_sh_dc, the rest lr_sh_rest
+    q.step_head = float(double(lr[k]) / bc1);
+    q.step_rest = float(double(k == 4 ? o.lr_sh_rest : lr[k]) / bc1);
+    row_sum += rows[k];
+  }
+  a.n = n;
+  a.units = (GSR_CLUSTER / 4) * row_sum;
+  a.beta1 = o.beta1;
+  a.beta2 = o.beta2;
+  a.c1 = float(1.0 - double(o.beta1));
+  a.c2 = float(1.0 - double(o.beta2));
+  a.eps = o.eps;
+  a.inv_sqrt_bc2 = float(1.0 / std::sqrt(bc2));
+  DeviceGuard guard(ctx->device);
+  gsr::launch_sparse_adam(a, cluster_visible, static_cast<hipStream_t>(stream));
+  return check_hip(ctx, hipGetLastError(), "sparse adam");
+}
+
 gsr_status gsr_set_profiling(gsr_context* ctx, int enable) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   DeviceGuard guard(ctx->device);

@@ -210,4 +210,26 @@ void launch_gather_rows(const int64_t* perm, int64_t n, const float* src, float*
 void launch_variance(const float* S, const float* M, const uint32_t* C, int64_t n, float* out, hipStream_t s);
 void launch_l1_grad(const float* image, const float* w, const float* gt, int64_t n, float* out, hipStream_t s);
 
+// adam.hip: one Adam step over the Gaussians of visible clusters (Sec. 3.2.3).
+constexpr int kAdamGroups = 5;  // means, log-scales, quaternions, opacity logits, SH
+struct AdamGroupDev {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int32_t row;      // floats per Gaussian
+  int32_t head;     // leading floats of a row that take step_head (row: all of them)
+  float step_head;  // lr / (1 - beta1^t)
+  float step_rest;
+};
+struct AdamDev {
+  AdamGroupDev grp[kAdamGroups];
+  int64_t n;
+  int32_t units;  // float4 units of a full cluster over all groups: GSR_CLUSTER / 4 x sum of rows
+  float beta1, beta2, c1, c2, eps;
+  float inv_sqrt_bc2;  // 1 / sqrt(1 - beta2^t)
+};
+// Every pointer 16-byte aligned; visible u32[ceil(n / GSR_CLUSTER)] or null (all).
+void launch_sparse_adam(const AdamDev& a, const uint32_t* visible, hipStream_t s);
+
 }  // namespace gsr

@@ -8,11 +8,14 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import math
 
 import numpy as np
 import torch
 
 from . import _lib as L
+
+GRAD_KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 _ALIGN = 256
 
@@ -386,6 +389,37 @@ class Rasterizer:
         s.S, s.M, s.C = S.data_ptr(), M.data_ptr(), C.data_ptr()
         self._check(self.lib.gsr_variance(self.ctx, ctypes.byref(s), n, out.data_ptr(), self._stream()), "gsr_variance")
         return out
+
+
+    def sparse_adam(self, params: dict, grads: dict, exp_avg: dict, exp_avg_sq: dict, visible, lr: dict,
+                    step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, sh_degree=None):
+        """One Adam step in place over the Gaussians of visible clusters (gsr_sparse_adam).
+        params / grads / exp_avg / exp_avg_sq: dicts of float32 tensors with the scene
+        shapes; visible: u32 (int32) flags per cluster, e.g. inspect(frame)['cluster_visible'],
+        or None for every cluster; lr: rates keyed means, log_scales, quats,
+        opacity_logits, sh_dc, sh_rest."""
+        n = int(params["means"].shape[0])
+        if sh_degree is None:
+            K = params["sh"].shape[1] if params["sh"].dim() == 3 else params["sh"].shape[1] // 3
+            sh_degree = int(round(math.sqrt(K))) - 1
+        sets = []
+        for d in (params, grads, exp_avg, exp_avg_sq):
+            g = L.GsrGrads()
+            for k in GRAD_KEYS:
+                t = d[k]
+                if t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device or t.shape[0] != n:
+                    raise ValueError("sparse_adam: %s must be a contiguous float32 tensor on %s with %d rows"
+                                     % (k, self.device, n))
+                setattr(g, k, t.data_ptr())
+            sets.append(g)
+        nc = (n + 127) // 128
+        if visible is not None:
+            if visible.dtype not in (torch.int32, torch.uint32) or visible.numel() < nc or visible.device != self.device:
+                raise ValueError("sparse_adam: visible must hold %d u32 flags on %s" % (nc, self.device))
+        o = L.GsrAdamOptions(lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"],
+                             lr["sh_rest"], beta1, beta2, eps, 0, int(step))
+        self._check(self.lib.gsr_sparse_adam(self.ctx, n, int(sh_degree), _ptr(visible), *[ctypes.byref(g) for g in sets],
+                                             ctypes.byref(o), self._stream()), "gsr_sparse_adam")
 
 
 def new_stats(n: int, device) -> dict:

@@ -42,6 +42,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(L.GsrOptions) == 16
     assert ctypes.sizeof(L.GsrFrameInfo) == 5 * 8 + 6 * 4
     assert ctypes.sizeof(L.GsrFrameBuffers) == 13 * 8 + 2 * 64 * 8
+    assert ctypes.sizeof(L.GsrAdamOptions) == 9 * 4 + 4 + 8
 
 
 def _scene(n=10, deg=0):
@@ -117,6 +118,7 @@ def test_null_context_is_rejected(lib):
     assert lib.gsr_forward(None, ctypes.byref(_scene()), _cams(), 1, ctypes.byref(o), 0x1000, 1 << 20, imgs,
                            None) == L.GSR_ERR_INVALID_ARG
     assert lib.gsr_variance(None, None, 0, None, None) == L.GSR_ERR_INVALID_ARG
+    assert lib.gsr_sparse_adam(None, 0, 0, None, None, None, None, None, None, None) == L.GSR_ERR_INVALID_ARG
     assert isinstance(lib.gsr_last_error(None), bytes)
     out = ctypes.c_size_t()
     assert lib.gsr_morton_workspace_size(None, 1000, ctypes.byref(out)) == L.GSR_OK and out.value > 8000
