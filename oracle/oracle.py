@@ -20,7 +20,7 @@ _lib = None
 
 __all__ = ["build", "load", "camera_array", "sh_basis", "preprocess", "render", "backward", "chain",
            "morton", "cluster_bounds", "bin_instances", "count_instances", "variance", "l1_grad",
-           "l1_loss", "ADAM_GROUPS", "sparse_adam"]
+           "l1_loss", "ADAM_GROUPS", "sparse_adam", "quat_to_rotation", "densify", "opacity_decay"]
 
 
 def build(force: bool = True) -> str:
@@ -277,3 +277,84 @@ def sparse_adam(params, grads, m, v, visible, lr, beta1, beta2, eps, step, csize
         out_m[k] = np.where(rows[:, None], m1, m0).reshape(shape)
         out_v[k] = np.where(rows[:, None], v1, v0).reshape(shape)
     return out_p, out_m, out_v
+
+
+def quat_to_rotation(q):
+    """Rotation matrices [n,3,3] of quaternions (w, x, y, z) [n,4], normalised first."""
+    q = np.asarray(q, np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def densify(params, metric, noise, threshold, max_candidates, split_log_scale, split_factor, prune_logit,
+            state=None):
+    """Densification driven by the opacity-gradient variance metric (Sec. 3.3): the
+    Gaussians whose metric C Var (gsr_variance's output) is largest are the ones a
+    single primitive no longer represents, and get split or cloned.
+
+    The paper fixes the metric only; the rest follows the densification of 3DGS that
+    it modifies, with every threshold an argument:
+      * candidates: metric >= threshold (threshold > 0), the max_candidates largest,
+        ties to the lower index; the decision compares the FP32 values given;
+      * a candidate whose largest log-scale exceeds split_log_scale is split into two
+        children at mean + R (exp(s) * z_c), z_c = noise[i, c] (standard normal draws
+        passed in), with log-scales s - ln(split_factor) and the parent's other
+        parameters; the parent is removed. Any other candidate is cloned (an exact
+        copy is appended; the original stays);
+      * an original (not a candidate's child or clone) with opacity logit below
+        prune_logit is removed.
+    Output rows: the kept originals in index order, then per candidate in rank order
+    its clone, or its two children. ``state``: dict of per-Gaussian arrays (optimiser
+    moments) whose kept rows move with their Gaussians and whose new rows are zero.
+
+    Returns (out_params, out_state, src, kind): src[j] the input row of output row j,
+    kind[j] 0 kept original, 1 clone, 2 / 3 first / second child of a split.
+    """
+    n = params["means"].shape[0]
+    m = np.asarray(metric, np.float32)
+    thr = np.float32(threshold)
+    qual = np.nonzero(m >= thr)[0]
+    order = qual[np.argsort(-m[qual], kind="stable")]     # descending metric, ties by index
+    cand = order[:max_candidates]
+    ls = np.asarray(params["log_scales"], np.float32)
+    split = ls[cand].max(axis=1) > np.float32(split_log_scale)
+    removed = np.zeros(n, bool)
+    removed[cand[split]] = True
+    removed |= np.asarray(params["opacity_logits"], np.float32) < np.float32(prune_logit)
+    kept = np.nonzero(~removed)[0]
+    src, kind = [kept], [np.zeros(len(kept), np.int64)]
+    for i, sp in zip(cand, split):
+        src.append(np.array([i, i] if sp else [i]))
+        kind.append(np.array([2, 3] if sp else [1]))
+    src = np.concatenate(src).astype(np.int64)
+    kind = np.concatenate(kind).astype(np.int64)
+    out = {k: np.asarray(v)[src].copy() for k, v in params.items()}
+    child = kind >= 2
+    if child.any():
+        i = src[child]
+        c = kind[child] - 2
+        R = quat_to_rotation(np.asarray(params["quats"])[i])
+        z = np.asarray(noise, np.float64).reshape(n, 2, 3)[i, c]
+        off = np.einsum("nij,nj->ni", R, np.exp(ls[i].astype(np.float64)) * z)
+        out["means"][child] = (np.asarray(params["means"], np.float64)[i] + off).astype(np.float32)
+        out["log_scales"][child] = (ls[i].astype(np.float64) - np.log(np.float64(np.float32(split_factor)))
+                                    ).astype(np.float32)
+    out_state = {}
+    for k, v in (state or {}).items():
+        a = np.asarray(v)[src].copy()
+        a[kind != 0] = 0
+        out_state[k] = a
+    return out, out_state, src, kind
+
+
+def opacity_decay(logits, factor):
+    """Opacity decay (Sec. 3.3), the gentler replacement of the opacity reset: the
+    activated opacity o = sigmoid(l) is multiplied by factor (the paper halves it)
+    and turned back into a logit, FP64."""
+    l = np.asarray(logits, np.float64)
+    o = factor / (1.0 + np.exp(-l))
+    return (np.log(o) - np.log1p(-o)).astype(np.float32)

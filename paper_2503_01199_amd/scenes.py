@@ -389,6 +389,16 @@ def cluster_flags(nc, pattern="random", salt=0):
     return (rng_for(301, salt).uniform(0, 1, size=nc) < 0.5).astype(np.uint32)
 
 
+def densify_inputs(n, salt=0, zero_frac=0.2):
+    """Densification metric f32[n] (C Var values log-uniform over 10^[-8, -2], a
+    fraction zero_frac exactly 0: Gaussians no pixel blended) and the standard
+    normal draws f32[n, 2, 3] that place the two children of a split."""
+    rng = rng_for(302, salt)
+    metric = 10.0 ** rng.uniform(-8, -2, size=n)
+    metric[rng.uniform(0, 1, size=n) < zero_frac] = 0.0
+    return _f32(metric), _f32(rng.standard_normal((n, 2, 3)))
+
+
 def scene_by_name(name: str, n: int | None = None):
     if name == "tiny":
         return tiny_scene(n or 1024), [tiny_camera()]

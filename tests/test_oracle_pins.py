@@ -650,3 +650,94 @@ def test_adam_sparse_clusters(orc):
     assert np.allclose(P["means"][:128] - p["means"][:128], 3 * ADAM_LR["means"] * g0 / (np.abs(g0) + eps),
                        rtol=1e-10, atol=1e-15)
     assert np.array_equal(p["means"][256:], P["means"][256:])
+
+
+# ------------------------------------------------------------------ densification (Sec. 3.3)
+def _dens_params(n, degree=1, salt=0):
+    P, _, _, _ = scenes.adam_inputs(n, degree, salt=salt)
+    return P
+
+
+def test_densify_hand_example(orc):
+    """Six Gaussians worked by hand: candidates are the metrics >= 0.4, largest first,
+    ties to the lower index; max log-scale above -2 splits, else clones; logit below
+    -5 prunes an original."""
+    P = _dens_params(6)
+    P["log_scales"][:] = -4.0
+    P["log_scales"][5, 1] = -1.0   # split
+    P["log_scales"][2, 0] = -3.0   # clone
+    P["log_scales"][4, 2] = -1.5   # split
+    P["opacity_logits"][:] = 0.0
+    P["opacity_logits"][1] = -6.0  # pruned
+    metric = np.array([0.5, 0.0, 2.0, 0.5, 1.0, 3.0], np.float32)
+    noise = np.zeros((6, 2, 3), np.float32)
+    out, _, src, kind = orc.densify(P, metric, noise, 0.4, 3, -2.0, 1.6, -5.0)
+    assert list(src) == [0, 2, 3, 5, 5, 2, 4, 4]
+    assert list(kind) == [0, 0, 0, 2, 3, 1, 2, 3]
+    _, _, src4, kind4 = orc.densify(P, metric, noise, 0.4, 4, -2.0, 1.6, -5.0)
+    assert list(src4) == [0, 2, 3, 5, 5, 2, 4, 4, 0] and list(kind4) == [0, 0, 0, 2, 3, 1, 2, 3, 1]  # 0 before 3
+    _, _, src0, kind0 = orc.densify(P, metric, noise, 5.0, 3, -2.0, 1.6, -5.0)  # nothing qualifies
+    assert list(src0) == [0, 2, 3, 4, 5] and not kind0.any()
+    # zero noise: children sit on the parent's mean with the scales divided by 1.6
+    assert np.array_equal(out["means"][3], P["means"][5]) and np.array_equal(out["means"][4], P["means"][5])
+    assert np.allclose(np.exp(out["log_scales"][3].astype(np.float64)), np.exp(P["log_scales"][5]) / 1.6,
+                       rtol=1e-6)
+    for k in P:  # the clone is an exact copy
+        assert np.array_equal(out[k][5], P[k][2])
+
+
+def test_densify_children_follow_the_parent_covariance(orc):
+    """A split child sits at mean + R(q) diag(exp(s)) z: its Mahalanobis distance under
+    the parent's covariance Sigma = R diag(exp(2s)) R^T is |z| (R from scipy's
+    rotation of the same quaternion), and children drawn with z and -z are symmetric
+    about the parent's mean."""
+    from scipy.spatial.transform import Rotation
+    n = 400
+    P = _dens_params(n, salt=3)
+    P["log_scales"] = np.float32(np.random.default_rng(0).uniform(-3, 0, size=(n, 3)))
+    metric = np.full(n, 1.0, np.float32)
+    z = np.random.default_rng(1).standard_normal((n, 3)).astype(np.float32)
+    noise = np.stack([z, -z], 1)
+    out, _, src, kind = orc.densify(P, metric, noise, 0.5, n, -10.0, 1.6, -100.0)
+    assert len(src) == 2 * n and np.array_equal(kind, np.tile([2, 3], n))
+    c0 = out["means"][0::2].astype(np.float64)
+    c1 = out["means"][1::2].astype(np.float64)
+    mu = P["means"].astype(np.float64)
+    q = P["quats"].astype(np.float64)
+    R = Rotation.from_quat(np.concatenate([q[:, 1:], q[:, :1]], 1)).as_matrix()  # scipy takes (x, y, z, w)
+    S = np.exp(2 * P["log_scales"].astype(np.float64))
+    Sigma = np.einsum("nij,nj,nkj->nik", R, S, R)
+    d = c0 - mu
+    maha = np.einsum("ni,ni->n", d, np.linalg.solve(Sigma, d[..., None])[..., 0])
+    zz = np.einsum("ni,ni->n", z.astype(np.float64), z.astype(np.float64))
+    scale = np.abs(mu).max(axis=1) / np.sqrt(S.min(axis=1))  # FP32 rounding of the means, in sigma units
+    assert np.all(np.abs(np.sqrt(maha) - np.sqrt(zz)) <= 1e-6 * (1 + scale)), np.abs(np.sqrt(maha) - np.sqrt(zz)).max()
+    assert np.allclose((c0 + c1) / 2, mu, rtol=0, atol=1e-6 * (1 + np.abs(mu).max()))
+
+
+def test_densify_moves_state_and_zeroes_new_rows(orc):
+    n = 300
+    P = _dens_params(n, salt=4)
+    metric, noise = scenes.densify_inputs(n, salt=4)
+    st = {"m": np.arange(n * 2, dtype=np.float32).reshape(n, 2) + 1}
+    out, ost, src, kind = orc.densify(P, metric, noise, 1e-4, 40, -1.5, 1.6, -1.0, state=st)
+    assert np.array_equal(ost["m"][kind == 0], st["m"][src[kind == 0]])
+    assert not ost["m"][kind != 0].any()
+    kept = src[kind == 0]
+    assert np.all(np.diff(kept) > 0)  # kept originals in index order
+    removed = np.setdiff1d(np.arange(n), kept)
+    low = P["opacity_logits"] < np.float32(-1.0)
+    split_parents = np.unique(src[kind >= 2])
+    assert np.array_equal(removed, np.union1d(np.nonzero(low)[0], split_parents))
+    assert len(src) == n - len(removed) + np.sum(kind == 1) + np.sum(kind >= 2)
+    for k in P:
+        assert np.array_equal(out[k][kind == 1], P[k][src[kind == 1]])
+
+
+def test_opacity_decay_halves_the_activated_opacity(orc):
+    import scipy.special as spx
+    l = np.float32(np.random.default_rng(2).uniform(-12, 12, size=1000))
+    l2 = orc.opacity_decay(l, 0.5)
+    assert np.allclose(spx.expit(l2.astype(np.float64)), spx.expit(l.astype(np.float64)) / 2, rtol=1e-6)
+    low = l < -10  # sigmoid(l) ~ e^l there: halving subtracts ln 2 from the logit
+    assert np.allclose(l2[low], l[low] - np.log(2.0), atol=1e-4)
