@@ -17,8 +17,9 @@ stream it runs on, the FP64 CPU reference timed on the same view, the FP16-blend
 variant, a 16-view cycle over the room (one view per step, so that the scene does
 not stay resident in the 256 MB Infinity Cache as it does for one repeated view),
 the cluster-granular Adam step that follows the backward (over the kept clusters
-and, for comparison, over all) and the render-serving stream (p50/p99 latency,
-views/s).
+and, for comparison, over all), a densification round (variance metric, split and
+clone, opacity decay, Morton re-sort) and the render-serving stream (p50/p99
+latency, views/s).
 """
 from __future__ import annotations
 
@@ -159,6 +160,48 @@ def adam_leg(rz, st, grads, visible, steps):
     return out
 
 
+def densify_leg(rz, st, stats, steps):
+    """Densification round of Sec. 3.3 on the room: the variance metric of the
+    statistic the timed steps accumulated, densification of the 5 % largest (half of
+    them split: the split bound is the median largest log-scale), the Adam moments
+    moved along, the opacity decay and the Morton re-sort of the grown scene. Per-call
+    times from HIP events on the launch stream."""
+    import torch
+    n = st.n
+    K = n // 20
+    metric = rz.variance(stats["S"], stats["M"], stats["C"])
+    split_ls = float(st.log_scales.max(dim=1).values.median().item())
+    noise = torch.randn((n, 2, 3), device=rz.device, generator=torch.Generator(device=rz.device).manual_seed(3))
+    state = {"exp_avg": torch.zeros_like(st.sh).view(n, -1), "exp_avg_sq": torch.zeros_like(st.sh).view(n, -1)}
+    times = {"densify": [], "opacity_decay": [], "morton_resort": []}
+    n_out = None
+    for it in range(steps + 2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record()
+        grown, _, n_dev = rz.densify(st, metric, noise, 1e-12, K, split_ls, state=state, sync=False)
+        ev[1].record()
+        if n_out is None:  # the same every round: read once
+            n_out = int(n_dev.item())
+        cut = [t[:n_out] for t in grown.tensors()]
+        ev[2].record()
+        rz.opacity_decay(cut[3], 0.5)
+        ev[3].record()
+        e4 = torch.cuda.Event(enable_timing=True)
+        e5 = torch.cuda.Event(enable_timing=True)
+        e4.record()
+        perm, _ = rz.morton_order(cut[0])
+        rz.apply_permutation(perm, cut)
+        e5.record()
+        e5.synchronize()
+        if it >= 2:
+            times["densify"].append(ev[0].elapsed_time(ev[1]))
+            times["opacity_decay"].append(ev[2].elapsed_time(ev[3]))
+            times["morton_resort"].append(e4.elapsed_time(e5))
+    out = {k: round(sorted(v)[len(v) // 2], 4) for k, v in times.items()}
+    out.update({"n": n, "candidates": K, "n_out": n_out, "state_arrays": 2, "reps": steps})
+    return out
+
+
 def cpu_baseline(scene, cam, repeats, threads):
     """The FP64 oracle's forward + backward of the whole view (the same scene, camera
     and loss as the GPU step), timed `repeats` times; the median is reported."""
@@ -197,6 +240,7 @@ def main():
     ap.add_argument("--cpu-repeats", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the render-serving stream")
     ap.add_argument("--no-adam", action="store_true", help="skip the cluster-granular Adam leg")
+    ap.add_argument("--no-densify", action="store_true", help="skip the densification round")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 3 times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-requests", type=int, default=3000)
@@ -373,6 +417,11 @@ def main():
         ins = rz.inspect(fr)
         adam = adam_leg(rz, st, grads, ins["cluster_visible"][: ins["info"]["clusters"]].clone(), args.steps)
 
+    dens = None
+    if not args.no_densify:
+        log("timing a densification round")
+        dens = densify_leg(rz, st, stats, min(args.steps, 10))
+
     # roofline of the dominant kernel (each stage below is one kernel launch)
     dom = max(("raster_bwd", "raster_fwd", "preprocess_bwd", "preprocess"), key=lambda k: stages.get(k, 0.0))
     roof_kernel = {"raster_bwd": "k_raster_bwd", "raster_fwd": "k_raster_fwd", "preprocess_bwd": "k_sh_bwd",
@@ -437,6 +486,7 @@ def main():
         "fp16_blend": fp16,
         "view_cycle": cycle,
         "sparse_adam": adam,
+        "densify": dens,
         "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,

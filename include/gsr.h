@@ -323,6 +323,57 @@ gsr_status gsr_sparse_adam(gsr_context *ctx, int64_t n, int32_t sh_degree, const
                            const gsr_grads *params, const gsr_grads *grads, const gsr_grads *exp_avg,
                            const gsr_grads *exp_avg_sq, const gsr_adam_options *opts, void *stream);
 
+/* Densification of Sec. 3.3: the Gaussians whose opacity-gradient variance metric
+ * (gsr_variance's C Var) is largest are split or cloned. The paper fixes the
+ * metric only; the thresholds and the split geometry follow the densification of
+ * 3DGS that it modifies and are arguments:
+ *   candidates: metric >= threshold, the max_candidates largest (ties: lower index
+ *     first), compared as the FP32 values given;
+ *   a candidate whose largest log-scale exceeds split_log_scale is split into two
+ *     children at mean + R(q) (exp(s) * z_c), c = 0, 1, with z_c = noise[i][c][0..2]
+ *     (standard normal draws the caller supplies), log-scales s - ln(split_factor)
+ *     and the parent's quaternion, opacity and SH; the parent leaves. Any other
+ *     candidate is cloned: an exact copy is appended and the original stays;
+ *   an original whose opacity logit is below prune_logit leaves (-INFINITY: none).
+ * Output rows: the kept originals in index order, then per candidate, largest metric
+ * first, its clone or its two children (child 0 first). Means and log-scales of
+ * children are computed in FP64 and rounded once. */
+typedef struct {
+  float threshold;         /* > 0 */
+  float split_log_scale;
+  float split_factor;      /* > 0 (3DGS divides the scales by 1.6) */
+  float prune_logit;
+  int64_t max_candidates;  /* >= 0; values above n mean n */
+} gsr_densify_options;
+
+/* Workspace bytes for gsr_densify on n Gaussians (ctx may be NULL). */
+gsr_status gsr_densify_workspace_size(gsr_context *ctx, int64_t n, int64_t max_candidates, size_t *bytes);
+
+/* One densification (see gsr_densify_options), out of place and asynchronous.
+ *   scene: the n input Gaussians (device arrays, read only); metric: f32[n] device;
+ *   noise: f32[n][2][3] device (rows of Gaussians that are not split are not read).
+ *   out: device arrays of `capacity` rows with gsr_scene's shapes; capacity >= n +
+ *     min(max_candidates, n), the largest possible output.
+ *   State arrays (e.g. optimiser moments): n_state arrays of row_floats[a] floats per
+ *     Gaussian; a kept original's row moves with it, new rows are zero.
+ *   workspace: device, 256-byte aligned, gsr_densify_workspace_size bytes.
+ *   n_out: device int64 (nullable): receives the output row count, or -1 if a
+ *     device-wide wait gave up (the output is then not valid).
+ * Inputs and outputs must not overlap (GSR_ERR_INVALID_ARG, as for bad sizes, null
+ * arrays, n >= 2^30, more than 16 state arrays or bad options). Re-sorting the
+ * output by Morton code afterwards (Sec. 3.2.1 re-sorts after every densification)
+ * is gsr_morton_order + gsr_apply_permutation on the n_out rows. */
+gsr_status gsr_densify(gsr_context *ctx, const gsr_scene *scene, const float *metric, const float *noise,
+                       const gsr_densify_options *opts, const gsr_grads *out, int64_t capacity, int32_t n_state,
+                       const float *const *state_in, float *const *state_out, const int32_t *state_row_floats,
+                       void *workspace, size_t ws_bytes, int64_t *n_out, void *stream);
+
+/* Opacity decay of Sec. 3.3, the gentler replacement of the opacity reset: each
+ * activated opacity o = sigmoid(l) becomes factor * o (the paper halves it), stored
+ * back as a logit, in FP64: l = ln(o') - ln(1 - o'). 0 < factor < 1. In place on
+ * opacity_logits[n] (device), asynchronous. */
+gsr_status gsr_opacity_decay(gsr_context *ctx, float *opacity_logits, int64_t n, float factor, void *stream);
+
 /* Stages of gsr_forward and gsr_backward, in launch order. */
 typedef enum {
   GSR_STAGE_CLUSTER = 0,     /* cluster bounds, frustum cull, compaction list */

@@ -55,6 +55,11 @@ class GsrAdamOptions(ctypes.Structure):
                 ("eps", c_float), ("reserved", c_int32), ("step", c_int64)]
 
 
+class GsrDensifyOptions(ctypes.Structure):
+    _fields_ = [("threshold", c_float), ("split_log_scale", c_float), ("split_factor", c_float),
+                ("prune_logit", c_float), ("max_candidates", c_int64)]
+
+
 class GsrStats(ctypes.Structure):
     _fields_ = [("S", c_void_p), ("M", c_void_p), ("C", c_void_p)]
 
@@ -103,6 +108,12 @@ EXPORTS = {
     "gsr_sparse_adam": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, ctypes.POINTER(GsrGrads),
                                   ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads),
                                   ctypes.POINTER(GsrAdamOptions), c_void_p]),
+    "gsr_densify_workspace_size": (c_int32, [c_void_p, c_int64, c_int64, ctypes.POINTER(c_size_t)]),
+    "gsr_densify": (c_int32, [c_void_p, ctypes.POINTER(GsrScene), c_void_p, c_void_p,
+                              ctypes.POINTER(GsrDensifyOptions), ctypes.POINTER(GsrGrads), c_int64, c_int32,
+                              ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_int32), c_void_p,
+                              c_size_t, c_void_p, c_void_p]),
+    "gsr_opacity_decay": (c_int32, [c_void_p, c_void_p, c_int64, c_float, c_void_p]),
     "gsr_set_profiling": (c_int32, [c_void_p, c_int32]),
     "gsr_stage_times": (c_int32, [c_void_p, ctypes.POINTER(c_float)]),
 }

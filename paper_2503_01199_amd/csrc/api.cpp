@@ -766,6 +766,123 @@ gsr_status gsr_sparse_adam(gsr_context* ctx, int64_t n, int32_t sh_degree, const
   return check_hip(ctx, hipGetLastError(), "sparse adam");
 }
 
+gsr_status gsr_densify_workspace_size(gsr_context* ctx, int64_t n, int64_t max_candidates, size_t* bytes) {
+  if (n < 0 || n >= ((int64_t)1 << 30) || max_candidates < 0 || !bytes)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_densify_workspace_size");
+  *bytes = n == 0 ? kAlign : gsr::densify_words(n, std::min(max_candidates, n)) * 4 + kAlign;
+  return GSR_OK;
+}
+
+gsr_status gsr_densify(gsr_context* ctx, const gsr_scene* scene, const float* metric, const float* noise,
+                       const gsr_densify_options* opts, const gsr_grads* out, int64_t capacity, int32_t n_state,
+                       const float* const* state_in, float* const* state_out, const int32_t* state_row_floats,
+                       void* workspace, size_t ws_bytes, int64_t* n_out, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (!scene || !opts || !out || n_state < 0 || n_state > gsr::kMaxDensCopy - 3 ||
+      (n_state > 0 && (!state_in || !state_out || !state_row_floats)))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_densify");
+  const int64_t n = scene->n;
+  const gsr_densify_options& o = *opts;
+  if (n < 0 || n >= ((int64_t)1 << 30) || scene->sh_degree < 0 || scene->sh_degree > 3)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: bad scene size or degree");
+  if (!(o.threshold > 0.0f) || !(o.split_factor > 0.0f) || std::isnan(o.split_log_scale) ||
+      std::isnan(o.prune_logit) || o.max_candidates < 0)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: need threshold > 0, split_factor > 0, max_candidates >= 0");
+  const int64_t K = std::min(o.max_candidates, n);
+  if (capacity < n + K) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: capacity %lld < n + candidates %lld",
+                                    (long long)capacity, (long long)(n + K));
+  size_t need = 0;
+  gsr_densify_workspace_size(ctx, n, K, &need);
+  if (ws_bytes < need) {
+    ctx->required = need;
+    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "densify workspace %zu < %zu", ws_bytes, need);
+  }
+  if (!workspace || ((uintptr_t)workspace & (kAlign - 1)) != 0)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: workspace must be 256-byte aligned");
+  const int32_t K3 = 3 * (scene->sh_degree + 1) * (scene->sh_degree + 1);
+  const float* in_p[5] = {scene->means, scene->log_scales, scene->quats, scene->opacity_logits, scene->sh};
+  float* out_p[5] = {out->means, out->log_scales, out->quats, out->opacity_logits, out->sh};
+  const int32_t rf[5] = {3, 3, 4, 1, K3};
+  struct Extent {
+    uintptr_t lo, hi;
+  };
+  std::vector<Extent> ins, outs;
+  auto ext = [](const void* p, int64_t rows, int64_t floats) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    return Extent{a, a + uintptr_t(rows) * uintptr_t(floats) * 4};
+  };
+  for (int k = 0; k < 5; ++k) {
+    if (n > 0 && (!in_p[k] || !out_p[k])) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: null scene array");
+    ins.push_back(ext(in_p[k], n, rf[k]));
+    outs.push_back(ext(out_p[k], capacity, rf[k]));
+  }
+  if (n > 0 && (!metric || !noise)) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: null metric or noise");
+  ins.push_back(ext(metric, n, 1));
+  ins.push_back(ext(noise, n, 6));
+  for (int a = 0; a < n_state; ++a) {
+    if (state_row_floats[a] <= 0 || (n > 0 && (!state_in[a] || !state_out[a])))
+      return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: state array %d: bad pointer or row size", a);
+    ins.push_back(ext(state_in[a], n, state_row_floats[a]));
+    outs.push_back(ext(state_out[a], capacity, state_row_floats[a]));
+  }
+  outs.push_back(Extent{reinterpret_cast<uintptr_t>(workspace), reinterpret_cast<uintptr_t>(workspace) + need});
+  if (n_out) outs.push_back(ext(n_out, 1, 2));
+  auto meet = [](const Extent& x, const Extent& y) { return x.lo < y.hi && y.lo < x.hi; };
+  for (size_t i = 0; i < outs.size(); ++i) {
+    for (size_t j = i + 1; j < outs.size(); ++j)
+      if (meet(outs[i], outs[j])) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: outputs overlap");
+    for (const Extent& e : ins)
+      if (meet(outs[i], e)) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_densify: an output overlaps an input");
+  }
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n == 0) {
+    if (n_out) gsr::fill_u32(reinterpret_cast<uint32_t*>(n_out), 2, 0u, s);
+    return check_hip(ctx, hipGetLastError(), "densify");
+  }
+  gsr::DensifyArgs a{};
+  a.n = n;
+  a.max_candidates = K;
+  a.metric = metric;
+  a.noise = noise;
+  a.means = scene->means;
+  a.log_scales = scene->log_scales;
+  a.quats = scene->quats;
+  a.opacity_logits = scene->opacity_logits;
+  a.threshold = o.threshold;
+  a.split_log_scale = o.split_log_scale;
+  a.prune_logit = o.prune_logit;
+  a.ln_split_factor = std::log(double(o.split_factor));
+  a.out_means = out->means;
+  a.out_log_scales = out->log_scales;
+  for (int k = 2; k < 5; ++k) {
+    a.copy_in[a.n_copy] = in_p[k];
+    a.copy_out[a.n_copy] = out_p[k];
+    a.copy_rf[a.n_copy] = rf[k];
+    a.copy_zero_new[a.n_copy] = 0;
+    ++a.n_copy;
+  }
+  for (int q = 0; q < n_state; ++q) {
+    a.copy_in[a.n_copy] = state_in[q];
+    a.copy_out[a.n_copy] = state_out[q];
+    a.copy_rf[a.n_copy] = state_row_floats[q];
+    a.copy_zero_new[a.n_copy] = 1;
+    ++a.n_copy;
+  }
+  a.n_out = n_out;
+  gsr::densify(a, static_cast<uint32_t*>(workspace), s);
+  return check_hip(ctx, hipGetLastError(), "densify");
+}
+
+gsr_status gsr_opacity_decay(gsr_context* ctx, float* opacity_logits, int64_t n, float factor, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (n < 0 || (n > 0 && !opacity_logits) || !(factor > 0.0f && factor < 1.0f))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_opacity_decay (need 0 < factor < 1)");
+  DeviceGuard guard(ctx->device);
+  gsr::launch_opacity_decay(opacity_logits, n, double(factor), static_cast<hipStream_t>(stream));
+  return check_hip(ctx, hipGetLastError(), "opacity decay");
+}
+
 gsr_status gsr_set_profiling(gsr_context* ctx, int enable) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   DeviceGuard guard(ctx->device);

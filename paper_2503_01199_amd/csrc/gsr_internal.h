@@ -232,4 +232,24 @@ struct AdamDev {
 // Every pointer 16-byte aligned; visible u32[ceil(n / GSR_CLUSTER)] or null (all).
 void launch_sparse_adam(const AdamDev& a, const uint32_t* visible, hipStream_t s);
 
+// densify.hip: densification by the variance metric and opacity decay (Sec. 3.3).
+constexpr int kMaxDensCopy = 3 + 16;  // quaternions, opacity logits, SH and up to 16 state arrays
+struct DensifyArgs {
+  int64_t n, max_candidates;  // max_candidates <= n
+  const float *metric, *noise, *means, *log_scales, *quats, *opacity_logits;
+  float threshold, split_log_scale, prune_logit;
+  double ln_split_factor;
+  float *out_means, *out_log_scales;
+  int32_t n_copy;  // arrays written through the row map besides the means and log-scales
+  const float* copy_in[kMaxDensCopy];
+  float* copy_out[kMaxDensCopy];
+  int32_t copy_rf[kMaxDensCopy];
+  int32_t copy_zero_new[kMaxDensCopy];  // 1: state array (new rows are zero)
+  int64_t* n_out;                       // device, nullable: output rows, -1 if a device wait gave up
+};
+size_t densify_words(int64_t n, int64_t max_candidates);
+// n >= 1; ws: densify_words(n, max_candidates) words, 256-byte aligned.
+void densify(const DensifyArgs& a, uint32_t* ws, hipStream_t s);
+void launch_opacity_decay(float* logits, int64_t n, double factor, hipStream_t s);
+
 }  // namespace gsr

@@ -366,6 +366,60 @@ class Rasterizer:
                                                    self._stream()), "gsr_apply_permutation")
         return dsts
 
+    def densify(self, scene: SceneTensors, metric: torch.Tensor, noise: torch.Tensor, threshold: float,
+                max_candidates: int, split_log_scale: float, split_factor: float = 1.6,
+                prune_logit: float = float("-inf"), state: dict | None = None, capacity: int | None = None,
+                sync: bool = True):
+        """Densification by the variance metric (gsr_densify, Sec. 3.3). Returns
+        (scene, state, n_out): new tensors of `capacity` rows (default n + the
+        candidates) and the output row count; with sync the count is read back (one
+        host wait) and the tensors are cut to it, else n_out is a device int64 tensor."""
+        n = scene.n
+        K = min(int(max_candidates), n)
+        cap = n + K if capacity is None else int(capacity)
+        sc = scene.struct()
+        if metric.dtype != torch.float32 or metric.numel() != n or noise.dtype != torch.float32 or noise.numel() != 6 * n:
+            raise ValueError("metric must be float32 [n], noise float32 [n, 2, 3]")
+        out = [torch.empty((cap,) + tuple(t.shape[1:]), dtype=torch.float32, device=self.device)
+               for t in scene.tensors()]
+        g = L.GsrGrads()
+        g.means, g.log_scales, g.quats, g.opacity_logits, g.sh = (t.data_ptr() for t in out)
+        names = list(state) if state else []
+        s_in = [state[k].contiguous() for k in names]
+        s_out = [torch.empty((cap,) + tuple(t.shape[1:]), dtype=torch.float32, device=self.device) for t in s_in]
+        for t in s_in:
+            if t.dtype != torch.float32 or t.shape[0] != n:
+                raise ValueError("state arrays must be float32 with n rows")
+        rows = (ctypes.c_int32 * max(1, len(names)))(*[int(t[0].numel()) if n > 0 else 1 for t in s_in])
+        sp = (ctypes.c_void_p * max(1, len(names)))(*[t.data_ptr() for t in s_in])
+        dp = (ctypes.c_void_p * max(1, len(names)))(*[t.data_ptr() for t in s_out])
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.gsr_densify_workspace_size(self.ctx, n, K, ctypes.byref(nbytes)),
+                    "gsr_densify_workspace_size")
+        self.morton_workspace.ensure(nbytes.value)
+        n_out = torch.empty(1, dtype=torch.int64, device=self.device)
+        o = L.GsrDensifyOptions(threshold, split_log_scale, split_factor, prune_logit, K)
+        self._check(self.lib.gsr_densify(self.ctx, ctypes.byref(sc), metric.contiguous().data_ptr(),
+                                         noise.contiguous().data_ptr(), ctypes.byref(o), ctypes.byref(g), cap,
+                                         len(names), sp, dp, rows, self.morton_workspace.ptr,
+                                         self.morton_workspace.nbytes, n_out.data_ptr(), self._stream()),
+                    "gsr_densify")
+        if not sync:
+            return SceneTensors(*out, scene.sh_degree), dict(zip(names, s_out)), n_out
+        rows_out = int(n_out.item())
+        if rows_out < 0:
+            raise L.GsrError(L.GSR_ERR_DEVICE, "gsr_densify: a device-wide wait gave up")
+        cut = lambda t: t[:rows_out]  # noqa: E731
+        return (SceneTensors(*[cut(t) for t in out], scene.sh_degree), {k: cut(t) for k, t in zip(names, s_out)},
+                rows_out)
+
+    def opacity_decay(self, logits: torch.Tensor, factor: float = 0.5):
+        """In place: sigmoid(l) <- factor sigmoid(l) (gsr_opacity_decay, Sec. 3.3)."""
+        if logits.dtype != torch.float32 or not logits.is_contiguous():
+            raise ValueError("logits must be contiguous float32")
+        self._check(self.lib.gsr_opacity_decay(self.ctx, logits.data_ptr(), logits.numel(), factor, self._stream()),
+                    "gsr_opacity_decay")
+
     def l1_grad(self, image: torch.Tensor, w: torch.Tensor, gt: torch.Tensor, out: torch.Tensor | None = None):
         """dL/dI of L = sum w |I - gt| computed by the library's kernel."""
         out = torch.empty_like(image) if out is None else out

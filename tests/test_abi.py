@@ -43,6 +43,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(L.GsrFrameInfo) == 5 * 8 + 6 * 4
     assert ctypes.sizeof(L.GsrFrameBuffers) == 13 * 8 + 2 * 64 * 8
     assert ctypes.sizeof(L.GsrAdamOptions) == 9 * 4 + 4 + 8
+    assert ctypes.sizeof(L.GsrDensifyOptions) == 4 * 4 + 8
 
 
 def _scene(n=10, deg=0):
@@ -119,6 +120,10 @@ def test_null_context_is_rejected(lib):
                            None) == L.GSR_ERR_INVALID_ARG
     assert lib.gsr_variance(None, None, 0, None, None) == L.GSR_ERR_INVALID_ARG
     assert lib.gsr_sparse_adam(None, 0, 0, None, None, None, None, None, None, None) == L.GSR_ERR_INVALID_ARG
+    assert lib.gsr_opacity_decay(None, None, 0, 0.5, None) == L.GSR_ERR_INVALID_ARG
+    out = ctypes.c_size_t()
+    assert lib.gsr_densify_workspace_size(None, 1000, 100, ctypes.byref(out)) == L.GSR_OK and out.value > 4000
+    assert lib.gsr_densify_workspace_size(None, -1, 100, ctypes.byref(out)) == L.GSR_ERR_INVALID_ARG
     assert isinstance(lib.gsr_last_error(None), bytes)
     out = ctypes.c_size_t()
     assert lib.gsr_morton_workspace_size(None, 1000, ctypes.byref(out)) == L.GSR_OK and out.value > 8000
