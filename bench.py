@@ -14,8 +14,9 @@ prints one JSON line: ms per step (mean over K steps enqueued back to back), the
 p50/p99 of single steps (200 after 20 warm-up, each alone on the device), per-stage
 times, the roofline of the dominant kernel measured with HIP events on the
 stream it runs on, the FP64 CPU reference timed on the same view, the FP16-blend
-variant, a 16-view cycle over the room (one view per step, so that the scene does
-not stay resident in the 256 MB Infinity Cache as it does for one repeated view),
+variant, the deterministic (fixed-point) backward, a 16-view cycle over the room
+(one view per step, so that the scene does not stay resident in the 256 MB
+Infinity Cache as it does for one repeated view),
 the cluster-granular Adam step that follows the backward (over the kept clusters
 and, for comparison, over all), a densification round (variance metric, split and
 clone, opacity decay, Morton re-sort) and the render-serving stream (p50/p99
@@ -297,8 +298,9 @@ def main():
 
     from paper_2503_01199_amd import _lib as L
 
-    def step(check=False, precision=L.GSR_FP32):
-        fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision)
+    def step(check=False, precision=L.GSR_FP32, deterministic=False):
+        fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision,
+                        deterministic=deterministic)
         for img, (w, gt), dl in zip(fr.images, wgt, dls):
             rz.l1_grad(img, w, gt, out=dl)
         rz.backward(fr, dls, grads=grads, stats=stats)
@@ -380,6 +382,29 @@ def main():
     st16 = {k: round(sum(v) / len(v), 4) for k, v in acc16.items()}
     fp16 = {"ms_per_step": round(fp16_ms, 4), "raster_fwd_ms": st16.get("raster_fwd"),
             "raster_bwd_ms": st16.get("raster_bwd")}
+
+    # the deterministic backward (fixed-point per-tile sums) on the same protocol
+    log("timing %d deterministic steps" % args.steps)
+    step(check=True, deterministic=True)  # grows the workspace by the fixed-point rows
+    for _ in range(max(args.warmup, 1)):
+        step(deterministic=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(deterministic=True)
+    torch.cuda.synchronize()
+    det_ms = (time.perf_counter() - wall0) * 1e3 / args.steps
+    rz.set_profiling(True)
+    accd = {}
+    for _ in range(args.steps):
+        step(deterministic=True)
+        for k, v in rz.stage_times().items():
+            if v >= 0:
+                accd.setdefault(k, []).append(v)
+    rz.set_profiling(False)
+    std = {k: round(sum(v) / len(v), 4) for k, v in accd.items()}
+    det = {"ms_per_step": round(det_ms, 4), "raster_bwd_ms": std.get("raster_bwd"),
+           "zero_grad_ms": std.get("zero_grad")}
 
     # a cycle over views of the room, one per step, so that no view's working set
     # stays resident in the caches as it does when one view repeats
@@ -484,6 +509,7 @@ def main():
         "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
+        "deterministic": det,
         "view_cycle": cycle,
         "sparse_adam": adam,
         "densify": dens,

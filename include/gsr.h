@@ -95,7 +95,15 @@ typedef struct {
   int32_t cluster_cull; /* 1: cull clusters of GSR_CLUSTER consecutive Gaussians against the
                            frusta and compact the visible ones (Sec. 3.2.2); 0: keep all */
   int32_t stats;        /* 1: gsr_backward accumulates the statistic into gsr_stats */
-  int32_t reserved;     /* must be 0 */
+  int32_t deterministic; /* 1: the backward adds the per-tile gradient sums (App. A.1's
+                           f_global) as 64-bit fixed-point integers with 32 fraction bits
+                           instead of FP32 atomics (the integer reduction of Sec. 3.1.2,
+                           carried to the device-wide sum), so gradients and statistic
+                           are bitwise reproducible whatever the order in which tiles
+                           finish. Each per-tile sum is rounded to a multiple of 2^-32
+                           and saturates at 2^31 in magnitude. The workspace grows by
+                           48 B per record; forward and backward must agree. 0: FP32
+                           atomics. */
 } gsr_options;
 
 /* Parameter gradients, device memory, the shapes of gsr_scene's arrays. Overwritten

@@ -144,7 +144,8 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   if (o->cluster_cull != 0 && o->cluster_cull != 1)
     return fail(ctx, GSR_ERR_INVALID_ARG, "cluster_cull must be 0 or 1");
   if (o->stats != 0 && o->stats != 1) return fail(ctx, GSR_ERR_INVALID_ARG, "stats must be 0 or 1");
-  if (o->reserved != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "reserved option field must be 0");
+  if (o->deterministic != 0 && o->deterministic != 1)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "deterministic must be 0 or 1");
   return GSR_OK;
 }
 
@@ -152,7 +153,8 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
 // room for inst_cap instances. Returns the total bytes. Layout: per-scene and
 // per-pixel buffers, then the header and control words (cleared together at the
 // frame start; their size grows with inst_cap), then the instance buffers.
-size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t inst_cap, void* ws, Frame& f) {
+size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t inst_cap, bool fixed, void* ws,
+                  Frame& f) {
   std::memset(&f, 0, sizeof(f));
   f.n = sc->n;
   f.V = V;
@@ -190,6 +192,7 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.pix_T = P.take<float>((size_t)f.pixels);
   f.pix_last = P.take<uint32_t>((size_t)f.pixels);
   f.grad2d = P.take<float>(gsr::kGrad2D * std::max<size_t>(nr, 1));
+  f.grad2d_fx = fixed ? P.take<unsigned long long>(gsr::kGrad2D * std::max<size_t>(nr, 1)) : nullptr;
   auto up = [](size_t w) { return (w + 63) & ~(size_t)63; };
   const size_t w_cluster = up(gsr::scan_ctl_words(f.nclusters));
   const size_t w_depth = up(gsr::sort_ctl_words(f.nrec, 32));
@@ -211,18 +214,18 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   return (P.off + kAlign - 1) & ~(kAlign - 1);
 }
 
-size_t bytes_for_instances(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t m) {
+size_t bytes_for_instances(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t m, bool fixed) {
   Frame f;
-  return plan_frame(sc, cams, V, m, nullptr, f);
+  return plan_frame(sc, cams, V, m, fixed, nullptr, f);
 }
 
 // Largest instance capacity whose layout fits in ws_bytes (-1 if not even 0 fits).
-int64_t instances_for_bytes(const gsr_scene* sc, const gsr_camera* cams, int32_t V, size_t ws_bytes) {
-  if (bytes_for_instances(sc, cams, V, 0) > ws_bytes) return -1;
+int64_t instances_for_bytes(const gsr_scene* sc, const gsr_camera* cams, int32_t V, size_t ws_bytes, bool fixed) {
+  if (bytes_for_instances(sc, cams, V, 0, fixed) > ws_bytes) return -1;
   int64_t lo = 0, hi = (int64_t)(ws_bytes / 16) + 1;
   while (lo < hi) {
     const int64_t mid = lo + (hi - lo + 1) / 2;
-    if (bytes_for_instances(sc, cams, V, mid) <= ws_bytes) lo = mid;
+    if (bytes_for_instances(sc, cams, V, mid, fixed) <= ws_bytes) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -323,7 +326,7 @@ gsr_status gsr_workspace_size(gsr_context* ctx, const gsr_scene* scene, const gs
     return st;
   if (max_instances < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances < 0");
   if (max_instances >= ((int64_t)1 << 30)) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances >= 2^30");
-  *bytes = bytes_for_instances(scene, cams, V, max_instances);
+  *bytes = bytes_for_instances(scene, cams, V, max_instances, opts->deterministic != 0);
   return GSR_OK;
 }
 
@@ -343,15 +346,16 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
     return st;
   if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  int64_t cap = instances_for_bytes(scene, cams, V, ws_bytes);
+  const bool fixed = opts->deterministic != 0;
+  int64_t cap = instances_for_bytes(scene, cams, V, ws_bytes, fixed);
   if (cap < 0) {
-    ctx->required = bytes_for_instances(scene, cams, V, 16 * (int64_t)scene->n + 1024);
+    ctx->required = bytes_for_instances(scene, cams, V, 16 * (int64_t)scene->n + 1024, fixed);
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes < %zu needed before instances", ws_bytes,
-                bytes_for_instances(scene, cams, V, 0));
+                bytes_for_instances(scene, cams, V, 0, fixed));
   }
   cap = std::min<int64_t>(cap, ((int64_t)1 << 30) - 1);
   Frame f;
-  const size_t total = plan_frame(scene, cams, V, cap, workspace, f);
+  const size_t total = plan_frame(scene, cams, V, cap, fixed, workspace, f);
   if (total > ws_bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: workspace plan exceeds its size");
 
   FrameRecord& fr = ctx->frames[workspace];
@@ -582,11 +586,13 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
   if (fr.precision < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "the frame was prepared but never rastered");
   if (fr.precision != opts->precision)
     return fail(ctx, GSR_ERR_INVALID_ARG, "precision %d differs from the forward's %d", opts->precision, fr.precision);
+  if ((f.grad2d_fx != nullptr) != (opts->deterministic != 0))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "deterministic %d differs from the forward's", opts->deterministic);
   if (f.n != scene->n || f.V != V || fr.scene.sh_degree != scene->sh_degree)
     return fail(ctx, GSR_ERR_INVALID_ARG, "scene or views differ from the forward");
   {
     Frame chk;
-    const size_t total = plan_frame(scene, cams, V, f.inst_cap, workspace, chk);
+    const size_t total = plan_frame(scene, cams, V, f.inst_cap, f.grad2d_fx != nullptr, workspace, chk);
     if (chk.tiles != f.tiles || chk.pixels != f.pixels || chk.grad2d != f.grad2d || total > ws_bytes)
       return fail(ctx, GSR_ERR_INVALID_ARG, "cameras or workspace differ from the forward");
   }
@@ -605,7 +611,10 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
   if (fr.backwards > 0) {
     // the forward cleared the rows of its records; a repeated backward clears them again
     StageScope sc_(ctx, GSR_STAGE_ZERO_GRAD, s);
-    gsr::fill_f32(f.grad2d, gsr::kGrad2D * f.nrec, 0.0f, s);
+    if (f.grad2d_fx)
+      gsr::fill_u32(reinterpret_cast<uint32_t*>(f.grad2d_fx), 2 * gsr::kGrad2D * f.nrec, 0u, s);
+    else
+      gsr::fill_f32(f.grad2d, gsr::kGrad2D * f.nrec, 0.0f, s);
   }
   gsr::ConstImagePtrs dp;
   std::memset(&dp, 0, sizeof(dp));
@@ -673,7 +682,7 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
   if (h[gsr::kHdrError] & 2u) return fail(ctx, GSR_ERR_UNSUPPORTED, "the frame has 2^30 or more instances");
   if (h[gsr::kHdrError]) return fail(ctx, GSR_ERR_DEVICE, "a device-wide scan or sort wait gave up");
   if (h[gsr::kHdrOverflow]) {
-    ctx->required = bytes_for_instances(&fr.scene, fr.cams, f.V, M + M / 8 + 1024);
+    ctx->required = bytes_for_instances(&fr.scene, fr.cams, f.V, M + M / 8 + 1024, f.grad2d_fx != nullptr);
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
                 (long long)f.inst_cap);
   }

@@ -106,6 +106,7 @@ struct Frame {
   float* pix_T;             // [pixels]
   uint32_t* pix_last;       // [pixels]
   float* grad2d;            // [nrec][12]
+  unsigned long long* grad2d_fx;  // [nrec][12] fixed-point sums (deterministic backward), else null
   uint32_t* ctl;            // look-back / histogram control words, cleared with the header
   size_t ctl_words;
   uint32_t *ctl_cluster_scan, *ctl_depth_sort, *ctl_offsets_scan, *ctl_tile_sort;

@@ -305,7 +305,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
                                                              Record* __restrict__ rec, uint32_t* __restrict__ dkey,
                                                              uint32_t* __restrict__ tiles,
                                                              ushort4* __restrict__ rect,
-                                                             float* __restrict__ grad2d) {
+                                                             float* __restrict__ grad2d,
+                                                             unsigned long long* __restrict__ grad_fx) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float lsh[kThreads * (3 * K + 1)];  // the cluster's SH rows
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // block = compact slot p (grid covers ncap)
@@ -386,8 +387,14 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
                          (float)(-0.5 * c * kLog2e));
     out.r2 = make_float4((float)g.o, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0), (float)fmax(col[2], 0.0));
     rec[r] = out;
-    float4* g4 = reinterpret_cast<float4*>(grad2d + r * kGrad2D);  // cleared for the backward's atomics
-    g4[0] = g4[1] = g4[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (grad_fx) {  // cleared for the backward's atomics: fixed-point sums, or FP32 sums
+      ulonglong2* q = reinterpret_cast<ulonglong2*>(grad_fx + r * kGrad2D);
+#pragma unroll
+      for (int k = 0; k < kGrad2D / 2; ++k) q[k] = make_ulonglong2(0ull, 0ull);
+    } else {
+      float4* g4 = reinterpret_cast<float4*>(grad2d + r * kGrad2D);
+      g4[0] = g4[1] = g4[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     dkey[r] = __float_as_uint((float)pr.tz);
     tiles[r] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
     rect[r] = make_ushort4((unsigned short)x0, (unsigned short)x1, (unsigned short)y0, (unsigned short)y1);
@@ -402,8 +409,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
 __global__ __launch_bounds__(kThreads) void k_project_bwd(
     gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, const uint32_t* __restrict__ visible,
     const uint32_t* __restrict__ cluster_offset, const uint32_t* __restrict__ tiles,
-    const float* __restrict__ grad2d, gsr_grads gr, float* __restrict__ S, float* __restrict__ Mst,
-    uint32_t* __restrict__ Cst) {
+    float* __restrict__ grad2d, const unsigned long long* __restrict__ grad_fx, gsr_grads gr,
+    float* __restrict__ S, float* __restrict__ Mst, uint32_t* __restrict__ Cst) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= sc.n) return;
   const int64_t c = i / GSR_CLUSTER;
@@ -419,9 +426,34 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
   if (vis) {
     for (int v = 0; v < V; ++v) {
       const int64_t r = j * V + v;
-      if (tiles[r] == 0) continue;
-      const float4* gg4 = reinterpret_cast<const float4*>(grad2d + r * kGrad2D);
-      const float4 q0 = gg4[0], q1 = gg4[1], q2 = gg4[2];
+      float4* gg4 = reinterpret_cast<float4*>(grad2d + r * kGrad2D);
+      if (tiles[r] == 0) {
+        if (grad_fx) gg4[0] = gg4[1] = gg4[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        continue;
+      }
+      float4 q0, q1, q2;
+      if (grad_fx) {
+        // the fixed-point sums of the deterministic backward, as the FP32 row that the
+        // SH backward (and inspection) reads
+        float x[kGrad2D];
+        const ulonglong2* fq = reinterpret_cast<const ulonglong2*>(grad_fx + r * kGrad2D);
+#pragma unroll
+        for (int k = 0; k < kGrad2D / 2; ++k) {
+          const ulonglong2 w2 = fq[k];
+          x[2 * k] = (float)((double)(long long)w2.x * 0x1p-32);
+          x[2 * k + 1] = (float)((double)(long long)w2.y * 0x1p-32);
+        }
+        q0 = make_float4(x[0], x[1], x[2], x[3]);
+        q1 = make_float4(x[4], x[5], x[6], x[7]);
+        q2 = make_float4(x[8], x[9], x[10], x[11]);
+        gg4[0] = q0;
+        gg4[1] = q1;
+        gg4[2] = q2;
+      } else {
+        q0 = gg4[0];
+        q1 = gg4[1];
+        q2 = gg4[2];
+      }
       const double du = q0.x, dv = q0.y, da = q0.z, db = q0.w, dc = q1.x, dop = q1.y;
       sS += q2.y;
       sM += dop;
@@ -676,7 +708,7 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
   const unsigned grid = (unsigned)((f.ncap + kThreads - 1) / kThreads);
 #define GSR_PRE_FWD(D)                                                                                          \
   k_preprocess_fwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.ncap, f.header, f.cluster_list, f.compact2full, \
-                                                f.rec, f.dkey, f.tiles_touched, f.rect, f.grad2d)
+                                                f.rec, f.dkey, f.tiles_touched, f.rect, f.grad2d, f.grad2d_fx)
   switch (sc.sh_degree) {
     case 0: GSR_PRE_FWD(0); break;
     case 1: GSR_PRE_FWD(1); break;
@@ -692,8 +724,8 @@ void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const 
   if (sc.n <= 0) return;
   const unsigned grid = (unsigned)((sc.n + kThreads - 1) / kThreads);
   k_project_bwd<<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset, f.tiles_touched,
-                                          f.grad2d, g, stats ? stats->S : nullptr, stats ? stats->M : nullptr,
-                                          stats ? stats->C : nullptr);
+                                          f.grad2d, f.grad2d_fx, g, stats ? stats->S : nullptr,
+                                          stats ? stats->M : nullptr, stats ? stats->C : nullptr);
 #define GSR_SH_BWD(D)                                                                                      \
   k_sh_bwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset, f.tiles_touched, \
                                         f.grad2d, g)

@@ -21,13 +21,23 @@
 // transposed wave reduction (permlane swaps, then DPP row shifts) per (tile,
 // Gaussian); the fragment count is a popcount of the blend masks on the scalar
 // unit. f_global is ONE atomic add per gradient per tile, issued as three 4-lane
-// atomic instructions on the record's contiguous 48-byte row.
+// atomic instructions on the record's contiguous 48-byte row (FP32), or, for a
+// bitwise reproducible backward, on its 96-byte row of 64-bit fixed-point sums.
 #include "raster_common.h"
 
 namespace gsr {
 namespace {
 
 constexpr int kBatch = 64;  // records per LDS batch
+
+// Deterministic backward: per-tile sums become two's-complement fixed point with
+// kFixedBits fraction bits (round to nearest, saturating), so that the device-wide
+// integer sum does not depend on the order in which tiles add.
+constexpr int kFixedBits = 32;
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+  const float x = fminf(fmaxf(v * 0x1p32f, -0x1p63f), 0x1.fffffep62f);
+  return (unsigned long long)(long long)__builtin_rintf(x);
+}
 using BwdBatch = BatchLDS<kBatch>;
 
 template <int CTRL>
@@ -80,7 +90,7 @@ __device__ __forceinline__ void wave_reduce10(const float v[10], float w[3]) {
 
 // One work item: tile gt whole (NB = 4 pixels per lane), or its two bands from
 // `band` on (NB = 2, at their row offsets from the whole strip's anchor).
-template <int P, int NB>
+template <int P, int NB, bool kFixed>
 __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, uint32_t* recA, uint32_t* recB,
                                                 const ViewDev* __restrict__ views, int32_t V, uint32_t gt, int band,
                                                 const uint32_t* __restrict__ ranges,
@@ -88,7 +98,8 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
                                                 const uint32_t* __restrict__ inst_mask,
                                                 const Record* __restrict__ rec, const ConstImagePtrs& dL,
                                                 const float* __restrict__ pix_T,
-                                                const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d) {
+                                                const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d,
+                                                unsigned long long* __restrict__ grad_fx) {
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
   const int W = w.width, H = w.height;
@@ -227,10 +238,17 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
       if ((lane & 15) == 15) {
         const int row = lane >> 4;
         const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-        float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D + sub;
-        unsafeAtomicAdd(dst, tot[0]);
-        unsafeAtomicAdd(dst + 4, tot[1]);
-        if (sub != 3) unsafeAtomicAdd(dst + 8, sub == 2 ? (float)nfrag : tot[2]);
+        if constexpr (kFixed) {
+          unsigned long long* dst = grad_fx + (int64_t)cur_rec[k] * kGrad2D + sub;
+          atomicAdd(dst, to_fixed(tot[0]));
+          atomicAdd(dst + 4, to_fixed(tot[1]));
+          if (sub != 3) atomicAdd(dst + 8, sub == 2 ? (unsigned long long)nfrag << kFixedBits : to_fixed(tot[2]));
+        } else {
+          float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D + sub;
+          unsafeAtomicAdd(dst, tot[0]);
+          unsafeAtomicAdd(dst + 4, tot[1]);
+          if (sub != 3) unsafeAtomicAdd(dst + 8, sub == 2 ? (float)nfrag : tot[2]);
+        }
       }
     }
   };
@@ -240,7 +258,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
   }
 }
 
-template <int P>
+template <int P, bool kFixed>
 __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ views, int32_t V,
                                                    const uint32_t* __restrict__ items,
                                                    const uint32_t* __restrict__ n_items,
@@ -250,7 +268,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    const Record* __restrict__ rec, ConstImagePtrs dL,
                                                    const float* __restrict__ pix_T,
                                                    const uint32_t* __restrict__ pix_last,
-                                                   float* __restrict__ grad2d) {
+                                                   float* __restrict__ grad2d,
+                                                   unsigned long long* __restrict__ grad_fx) {
   __shared__ BwdBatch bufA, bufB;  // two objects, so reads of one never wait on loads into the other
   __shared__ uint32_t recA[kBatch], recB[kBatch];
   if (blockIdx.x >= *n_items) return;
@@ -258,25 +277,30 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
   const uint32_t gt = item >> 3;
   const uint32_t code = item & 7u;
   if (code == kItemWhole)
-    raster_bwd_item<P, 4>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL, pix_T,
-                          pix_last, grad2d);
+    raster_bwd_item<P, 4, kFixed>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL,
+                                  pix_T, pix_last, grad2d, grad_fx);
   else  // half of a split tile
-    raster_bwd_item<P, 2>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges, inst_rec,
-                          inst_mask, rec, dL, pix_T, pix_last, grad2d);
+    raster_bwd_item<P, 2, kFixed>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges,
+                                  inst_rec, inst_mask, rec, dL, pix_T, pix_last, grad2d, grad_fx);
+}
+
+template <int P, bool kFixed>
+void launch_bwd(const Frame& f, const ConstImagePtrs& dL, hipStream_t s) {
+  const unsigned grid = (unsigned)max_items(f.tiles);
+  k_raster_bwd<P, kFixed><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, f.header + kHdrItemsBwd, f.ranges,
+                                              f.inst_rec, f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d,
+                                              f.grad2d_fx);
 }
 
 }  // namespace
 
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s) {
   if (f.tiles <= 0) return;
-  const unsigned grid = (unsigned)max_items(f.tiles);
-  const uint32_t* n_items = f.header + kHdrItemsBwd;
+  const bool fixed = f.grad2d_fx != nullptr;
   if (precision == GSR_FP16_BLEND)
-    k_raster_bwd<GSR_FP16_BLEND><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, n_items, f.ranges, f.inst_rec,
-                                                     f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d);
+    fixed ? launch_bwd<GSR_FP16_BLEND, true>(f, dL, s) : launch_bwd<GSR_FP16_BLEND, false>(f, dL, s);
   else
-    k_raster_bwd<GSR_FP32><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, n_items, f.ranges, f.inst_rec,
-                                               f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d);
+    fixed ? launch_bwd<GSR_FP32, true>(f, dL, s) : launch_bwd<GSR_FP32, false>(f, dL, s);
 }
 
 }  // namespace gsr

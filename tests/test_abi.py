@@ -102,7 +102,7 @@ def test_workspace_size_and_validation_on_host(lib):
     c[0].t[1] = float("nan")
     assert _size(lib, _scene(), c, 1, o)[0] == L.GSR_ERR_INVALID_ARG
     o2 = L.GsrOptions()
-    o2.reserved = 1
+    o2.deterministic = 2
     assert _size(lib, _scene(), _cams(), 1, o2)[0] == L.GSR_ERR_INVALID_ARG
     o3 = L.GsrOptions()
     o3.precision = 7

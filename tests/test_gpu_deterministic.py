@@ -1,0 +1,114 @@
+"""The deterministic backward (gsr_options.deterministic): per-tile gradient sums
+added as 64-bit fixed-point integers (32 fraction bits).
+
+Integer addition is associative, so the result cannot depend on the order in
+which tiles finish: repeated backward passes and the same frame rendered in a batch
+of other frames must give bitwise identical gradients and statistic. Each per-tile
+sum is rounded to a multiple of 2^-32 before it is added, which moves a gradient
+by at most (tiles touched) x 2^-33 from the FP32 sum: far inside the 1e-3 parity
+bar, which the tests below also apply against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as orc
+from helpers import ensure_built
+from paper_2503_01199_amd import scenes
+from test_gpu_backward import GROUPS, compare, oracle_sum, upstream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rz():
+    ensure_built()
+    from paper_2503_01199_amd.raster import Rasterizer
+    return Rasterizer(0)
+
+
+def _backward(rz, fr, gI, stats=True):
+    from paper_2503_01199_amd.raster import new_stats
+    st = new_stats(fr.scene.n, rz.device) if stats else None
+    g = rz.backward(fr, [torch.as_tensor(x, device=rz.device) for x in gI], stats=st)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy().copy() for k, v in g.items()}
+    if st is not None:
+        out.update({"stat_" + k: v.cpu().numpy().copy() for k, v in st.items()})
+    return out
+
+
+@pytest.mark.parametrize("which", ["tiny", "split"])
+def test_deterministic_gradients_match_oracle(rz, which):
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    if which == "tiny":
+        sc, cam, max_fragile = scenes.tiny_scene(), scenes.tiny_camera(), 0.1
+    else:  # long lists: split tiles in both rasters
+        sc, cam, max_fragile = scenes.tiny_scene(6000, seed_salt=9), scenes.tiny_camera(), 0.2
+    gI = upstream(sc, [cam])
+    print("deterministic backward %s n=%d" % (which, sc.n), flush=True)
+    fr = rz.forward(SceneTensors.from_scene(sc, rz.device), [cam], workspace=Workspace(rz.device), deterministic=True)
+    out = _backward(rz, fr, gI)
+    ref = oracle_sum(sc, [cam], gI)
+    ref["_logits"] = sc.opacity_logits
+    grads = {k: out[k] for k in GROUPS}
+    stats = {k: out["stat_" + k] for k in ("S", "M", "C")}
+    compare(grads, stats, ref, "deterministic %s" % which, max_fragile=max_fragile)
+
+
+def test_repeated_backward_is_bitwise_identical(rz):
+    """30k Gaussians on spheres and planes, 320x240: many tiles add into the same
+    records. Three deterministic backward passes agree bit for bit; the FP32-atomic
+    passes are reported (they may differ in the last bits)."""
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    sc = scenes.spheres_planes_scene(30_000, seed_salt=5)
+    _, perm = orc.morton(sc.means)
+    sc = sc.permuted(perm)
+    cam = scenes.orbit_camera(30.0, 15.0, radius=5.0, width=320, height=240)
+    w, _ = scenes.l1_weights((3, cam.height, cam.width), config=0, salt=4)
+    gI = [w * np.sign(np.random.default_rng(4).standard_normal(w.shape)).astype(np.float32)]
+    st = SceneTensors.from_scene(sc, rz.device)
+    print("repeated deterministic backward n=%d" % sc.n, flush=True)
+    fr = rz.forward(st, [cam], workspace=Workspace(rz.device), deterministic=True)
+    runs = [_backward(rz, fr, gI) for _ in range(3)]
+    for r in runs[1:]:
+        for k in runs[0]:
+            assert np.array_equal(r[k], runs[0][k]), k
+    ff = rz.forward(st, [cam], workspace=Workspace(rz.device))
+    fl = [_backward(rz, ff, gI) for _ in range(3)]
+    differ = sum(int(not np.array_equal(r[k], fl[0][k])) for r in fl[1:] for k in fl[0])
+    print("FP32 atomics: %d of %d arrays differ between repeated passes" % (differ, 2 * len(fl[0])))
+    for k in GROUPS:  # the two reductions agree to FP32 rounding of the per-tile sums
+        scale = float(np.abs(fl[0][k]).max()) + 1e-30
+        assert float(np.abs(runs[0][k] - fl[0][k]).max()) <= 1e-5 * scale, k
+
+
+def test_batched_frame_backward_is_bitwise_identical(rz):
+    """A frame rastered inside a batch of other frames and the same frame alone:
+    identical gradients, bit for bit."""
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    a = SceneTensors.from_scene(scenes.tiny_scene(6000, seed_salt=9), rz.device)
+    b = SceneTensors.from_scene(scenes.spheres_planes_scene(20_000, seed_salt=2), rz.device)
+    cam_a = scenes.tiny_camera(100, 75)
+    cam_b = scenes.orbit_camera(10.0, 5.0, radius=7.0, width=200, height=150)
+    gI = [np.random.default_rng(8).uniform(-1, 1, (3, cam_a.height, cam_a.width)).astype(np.float32)]
+    print("batched deterministic backward", flush=True)
+    frames = [rz.prepare(b, [cam_b], workspace=Workspace(rz.device), deterministic=True),
+              rz.prepare(a, [cam_a], workspace=Workspace(rz.device), deterministic=True)]
+    rz.raster_batch(frames)
+    torch.cuda.synchronize()
+    rz.check_frame(frames[1])
+    g_batch = _backward(rz, frames[1], gI)
+    alone = rz.forward(a, [cam_a], workspace=Workspace(rz.device), deterministic=True)
+    g_alone = _backward(rz, alone, gI)
+    for k in g_alone:
+        assert np.array_equal(g_batch[k], g_alone[k]), k
+
+
+def test_backward_must_match_the_forward_mode(rz):
+    from paper_2503_01199_amd import _lib as L
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    fr = rz.forward(SceneTensors.from_scene(sc, rz.device), [cam], workspace=Workspace(rz.device))
+    fr.opts.deterministic = 1  # the frame was rendered without the fixed-point buffer
+    with pytest.raises(L.GsrError):
+        rz.backward(fr, [torch.zeros((3, cam.height, cam.width), device=rz.device)])
