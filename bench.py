@@ -242,6 +242,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the render-serving stream")
     ap.add_argument("--no-adam", action="store_true", help="skip the cluster-granular Adam leg")
     ap.add_argument("--no-densify", action="store_true", help="skip the densification round")
+    ap.add_argument("--schedule-sweep", action="store_true",
+                    help="also time the rasters over a sweep of the band-split thresholds")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 3 times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-requests", type=int, default=3000)
@@ -406,6 +408,34 @@ def main():
     det = {"ms_per_step": round(det_ms, 4), "raster_bwd_ms": std.get("raster_bwd"),
            "zero_grad_ms": std.get("zero_grad")}
 
+    # raster schedule sweep (F4): the list length above which a tile is rastered as
+    # band items, 1 pixel per lane in the forward's four 16x4 bands, 2 in the
+    # backward's halves, against whole 16x16 tiles with 4 pixels per lane
+    sweep = None
+    if args.schedule_sweep:
+        never = 0xffffffff
+        sweep = {"forward": {}, "backward": {}}
+        for key, settings in (("forward", [(never, 0), (1024, 0), (512, 0), (256, 0), (128, 0), (64, 0), (0, 0)]),
+                              ("backward", [(0, never), (0, 1024), (0, 512), (0, 256), (0, 128)])):
+            for fl, bl in settings:
+                rz.set_raster_split(fl, bl)
+                step(check=True)
+                rz.set_profiling(True)
+                acc = {}
+                for _ in range(min(args.steps, 20)):
+                    f_ = step()
+                    for k, v in rz.stage_times().items():
+                        if v >= 0:
+                            acc.setdefault(k, []).append(v)
+                rz.set_profiling(False)
+                inf = rz.inspect(f_)["info"]
+                stage = "raster_fwd" if key == "forward" else "raster_bwd"
+                thr = fl if key == "forward" else bl
+                name = "never" if thr == never else ("default" if thr == 0 else str(thr))
+                sweep[key][name] = {"ms": round(sorted(acc[stage])[len(acc[stage]) // 2], 4),
+                                    "split_tiles": inf["split_tiles" if key == "forward" else "split_tiles_bwd"]}
+        rz.set_raster_split(0, 0)
+
     # a cycle over views of the room, one per step, so that no view's working set
     # stays resident in the caches as it does when one view repeats
     cycle = None
@@ -510,6 +540,7 @@ def main():
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
         "deterministic": det,
+        "schedule_sweep": sweep,
         "view_cycle": cycle,
         "sparse_adam": adam,
         "densify": dens,

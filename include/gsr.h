@@ -100,7 +100,7 @@ typedef struct {
                            instead of FP32 atomics (the integer reduction of Sec. 3.1.2,
                            carried to the device-wide sum), so gradients and statistic
                            are bitwise reproducible whatever the order in which tiles
-                           finish. Each per-tile sum is rounded to a multiple of 2^-32
+                           finish (for one raster schedule, gsr_set_raster_split). Each per-tile sum is rounded to a multiple of 2^-32
                            and saturates at 2^31 in magnitude. The workspace grows by
                            48 B per record; forward and backward must agree. 0: FP32
                            atomics. */
@@ -381,6 +381,17 @@ gsr_status gsr_densify(gsr_context *ctx, const gsr_scene *scene, const float *me
  * back as a logit, in FP64: l = ln(o') - ln(1 - o'). 0 < factor < 1. In place on
  * opacity_logits[n] (device), asynchronous. */
 gsr_status gsr_opacity_decay(gsr_context *ctx, float *opacity_logits, int64_t n, float factor, void *stream);
+
+/* Raster schedule of the frames this context prepares from now on (Sec. 3.1 fixes one
+ * tile shape; this sets which tiles run in a second one). A work item is normally a
+ * whole 16x16 tile, 4 pixels per lane. The forward rasters a tile whose list is
+ * longer than split_len entries as four 16x4 band items (1 pixel per lane); the
+ * backward walks a tile longer than split_len_bwd as two halves (2 pixels per
+ * lane). Longest lists first, at most one tile in four. 0 restores a default (256,
+ * 512); UINT32_MAX never splits. Images do not depend on it (a band evaluates its
+ * pixels exactly as the whole tile does); gradients only through rounding (a tile
+ * walked as two halves adds two per-item sums instead of one). */
+gsr_status gsr_set_raster_split(gsr_context *ctx, uint32_t split_len, uint32_t split_len_bwd);
 
 /* Stages of gsr_forward and gsr_backward, in launch order. */
 typedef enum {

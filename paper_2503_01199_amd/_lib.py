@@ -114,6 +114,7 @@ EXPORTS = {
                               ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), ctypes.POINTER(c_int32), c_void_p,
                               c_size_t, c_void_p, c_void_p]),
     "gsr_opacity_decay": (c_int32, [c_void_p, c_void_p, c_int64, c_float, c_void_p]),
+    "gsr_set_raster_split": (c_int32, [c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
     "gsr_set_profiling": (c_int32, [c_void_p, c_int32]),
     "gsr_stage_times": (c_int32, [c_void_p, ctypes.POINTER(c_float)]),
 }

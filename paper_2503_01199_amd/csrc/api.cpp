@@ -43,6 +43,8 @@ struct gsr_context {
   bool events_ready = false;
   hipEvent_t ev[2 * GSR_STAGE_COUNT];
   bool recorded[GSR_STAGE_COUNT] = {};
+  uint32_t split_len = gsr::kSplitLen;          // raster schedules of the frames prepared from now on
+  uint32_t split_len_bwd = gsr::kSplitLenBwd;
 };
 
 namespace {
@@ -356,6 +358,8 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   cap = std::min<int64_t>(cap, ((int64_t)1 << 30) - 1);
   Frame f;
   const size_t total = plan_frame(scene, cams, V, cap, fixed, workspace, f);
+  f.split_len = ctx->split_len;
+  f.split_len_bwd = ctx->split_len_bwd;
   if (total > ws_bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: workspace plan exceeds its size");
 
   FrameRecord& fr = ctx->frames[workspace];
@@ -546,7 +550,7 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
   hipStream_t s = static_cast<hipStream_t>(stream);
   uint32_t* order = static_cast<uint32_t*>(batch_ws);
   uint32_t* n_items = order + batch_items_words(tiles);
-  gsr::launch_batch_tile_order(tab, (uint32_t)tiles, order, n_items, s);
+  gsr::launch_batch_tile_order(tab, (uint32_t)tiles, ctx->split_len, order, n_items, s);
   const bool attached = gsr::launch_raster_fwd_batch(tab, order, n_items, (uint32_t)tiles, ip, precision, s,
                                                      frs[0]->done);
   gsr_status st = check_hip(ctx, hipGetLastError(), "batched raster");
@@ -890,6 +894,13 @@ gsr_status gsr_opacity_decay(gsr_context* ctx, float* opacity_logits, int64_t n,
   DeviceGuard guard(ctx->device);
   gsr::launch_opacity_decay(opacity_logits, n, double(factor), static_cast<hipStream_t>(stream));
   return check_hip(ctx, hipGetLastError(), "opacity decay");
+}
+
+gsr_status gsr_set_raster_split(gsr_context* ctx, uint32_t split_len, uint32_t split_len_bwd) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  ctx->split_len = split_len == 0 ? gsr::kSplitLen : split_len;
+  ctx->split_len_bwd = split_len_bwd == 0 ? gsr::kSplitLenBwd : split_len_bwd;
+  return GSR_OK;
 }
 
 gsr_status gsr_set_profiling(gsr_context* ctx, int enable) {

@@ -110,7 +110,8 @@ constexpr int64_t kStageTiles = 8192;
 constexpr int kStageItems = (int)(kStageTiles + 3 * ((kStageTiles + kSplitShare - 1) / kSplitShare));
 
 template <class Len>
-__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, uint32_t* __restrict__ items,
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, uint32_t split_len,
+                                                              uint32_t split_len_bwd, uint32_t* __restrict__ items,
                                                               uint32_t* __restrict__ n_items,
                                                               uint32_t* __restrict__ bwd,
                                                               uint32_t* __restrict__ n_bwd) {
@@ -136,8 +137,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
     for (int q = 0; q < kOrderUnroll; ++q) {
       if (i0 + (int64_t)q * kOrderThreads >= T) continue;
       atomicAdd(&h[order_bucket(len[q])], 1u);
-      my_long += len[q] > kSplitLen ? 1u : 0u;
-      my_long_b += len[q] > kSplitLenBwd ? 1u : 0u;
+      my_long += len[q] > split_len ? 1u : 0u;
+      my_long_b += len[q] > split_len_bwd ? 1u : 0u;
     }
   }
   atomicAdd(&nlong[0], my_long);
@@ -208,15 +209,16 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
 bool launch_tile_order(const Frame& f, hipStream_t s, hipEvent_t done) {
   if (f.tiles <= 0) return false;
   launch_tracked(k_tile_order<OneFrame>, 1, kOrderThreads, s, done, OneFrame{f.ranges}, (int64_t)f.tiles,
-                 f.tile_order, f.header + kHdrItems, f.bwd_items, f.header + kHdrItemsBwd);
+                 f.split_len, f.split_len_bwd, f.tile_order, f.header + kHdrItems, f.bwd_items,
+                 f.header + kHdrItemsBwd);
   return true;
 }
 
-void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, uint32_t* n_items,
-                             hipStream_t s) {
+void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t split_len, uint32_t* order,
+                             uint32_t* n_items, hipStream_t s) {
   if (total_tiles == 0) return;
-  k_tile_order<ManyFrames><<<1, kOrderThreads, 0, s>>>(ManyFrames{tab}, total_tiles, order, n_items, nullptr,
-                                                       nullptr);
+  k_tile_order<ManyFrames><<<1, kOrderThreads, 0, s>>>(ManyFrames{tab}, total_tiles, split_len, 0u, order, n_items,
+                                                       nullptr, nullptr);
 }
 
 int64_t raster_max_items(int64_t tiles) { return max_items(tiles); }

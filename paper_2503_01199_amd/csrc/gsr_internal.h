@@ -75,6 +75,11 @@ enum HeaderWord {
   kHdrItemsBwd = 7,         // backward raster work items
 };
 
+// Default list lengths above which the raster splits a tile into band items
+// (forward: four 16x4 bands; backward: two halves).
+constexpr uint32_t kSplitLen = 256;
+constexpr uint32_t kSplitLenBwd = 512;
+
 struct Frame {
   // sizes (host)
   int64_t n, ncap, nrec;    // Gaussians, compact slots (128 * clusters), records = ncap * V
@@ -107,6 +112,8 @@ struct Frame {
   uint32_t* pix_last;       // [pixels]
   float* grad2d;            // [nrec][12]
   unsigned long long* grad2d_fx;  // [nrec][12] fixed-point sums (deterministic backward), else null
+  uint32_t split_len = kSplitLen;         // forward: tiles with longer lists are rastered as four bands
+  uint32_t split_len_bwd = kSplitLenBwd;  // backward: tiles with longer lists are walked as two halves
   uint32_t* ctl;            // look-back / histogram control words, cleared with the header
   size_t ctl_words;
   uint32_t *ctl_cluster_scan, *ctl_depth_sort, *ctl_offsets_scan, *ctl_tile_sort;
@@ -195,8 +202,8 @@ bool launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const
                              uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s,
                              hipEvent_t done);
 // Raster work items of the concatenated tiles of a batch of frames (n_items <- count).
-void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t* order, uint32_t* n_items,
-                             hipStream_t s);
+void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t split_len, uint32_t* order,
+                             uint32_t* n_items, hipStream_t s);
 // Largest number of raster work items for `tiles` tiles (every split tile adds 3).
 int64_t raster_max_items(int64_t tiles);
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s);

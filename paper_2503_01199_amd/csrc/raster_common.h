@@ -25,14 +25,13 @@ constexpr int kStripStep = 4;
 // Raster work items: (tile << 3) | code. kItemWhole (4) is the whole tile, 4
 // pixels per lane; codes 0..3 are band `code` of a tile split four ways, 1 pixel per
 // lane; kItemHalf + h (5, 6) are bands 2h and 2h + 1 of a tile split two ways, 2
-// pixels per lane. The forward splits tiles with more than kSplitLen entries four
-// ways; the backward, whose per-entry wave reduction and atomics are repeated by
-// every item of a tile, splits those with more than kSplitLenBwd entries two
-// ways. Either takes the longest first, at most one tile in kSplitShare.
+// pixels per lane. By default the forward splits tiles with more than kSplitLen
+// (gsr_internal.h) entries four ways; the backward, whose per-entry wave reduction and atomics are
+// repeated by every item of a tile, splits those with more than kSplitLenBwd
+// entries two ways (both thresholds can be set per context). Either takes the
+// longest first, at most one tile in kSplitShare.
 constexpr uint32_t kItemWhole = 4;
 constexpr uint32_t kItemHalf = 5;
-constexpr uint32_t kSplitLen = 256;
-constexpr uint32_t kSplitLenBwd = 512;
 constexpr int64_t kSplitShare = 4;
 __host__ __device__ inline int64_t max_items(int64_t tiles) { return tiles + 3 * ((tiles + kSplitShare - 1) / kSplitShare); }
 // Row offsets s_j of the strip's pixels from its anchor, the centre row of the strip

@@ -430,6 +430,13 @@ class Rasterizer:
                                          out.data_ptr(), self._stream()), "gsr_l1_grad")
         return out
 
+    def set_raster_split(self, split_len: int = 0, split_len_bwd: int = 0):
+        """Lists longer than split_len (forward) / split_len_bwd (backward) are rastered
+        as band items in frames prepared from now on; 0 restores the default,
+        0xffffffff never splits (gsr_set_raster_split)."""
+        self._check(self.lib.gsr_set_raster_split(self.ctx, int(split_len), int(split_len_bwd)),
+                    "gsr_set_raster_split")
+
     def set_profiling(self, enable: bool):
         self._check(self.lib.gsr_set_profiling(self.ctx, 1 if enable else 0), "gsr_set_profiling")
 

@@ -112,3 +112,40 @@ def test_backward_must_match_the_forward_mode(rz):
     fr.opts.deterministic = 1  # the frame was rendered without the fixed-point buffer
     with pytest.raises(L.GsrError):
         rz.backward(fr, [torch.zeros((3, cam.height, cam.width), device=rz.device)])
+
+
+@pytest.mark.parametrize("split", [(0xffffffff, 0xffffffff), (64, 128), (0, 0)])
+def test_raster_schedule_changes_nothing_but_time(rz, split):
+    """The split thresholds of the raster schedules (never, low, default) leave the
+    image bitwise unchanged and split the expected tiles: the longest min(#lists
+    above the threshold, T/4). The deterministic gradients are bitwise unchanged
+    while the backward's schedule is; a tile walked as two halves adds two
+    separately rounded sums, which moves a gradient by FP32 rounding only."""
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace
+    sc, cam = scenes.tiny_scene(6000, seed_salt=9), scenes.tiny_camera()
+    st = SceneTensors.from_scene(sc, rz.device)
+    gI = [np.random.default_rng(2).uniform(-1, 1, (3, cam.height, cam.width)).astype(np.float32)]
+    ref = rz.forward(st, [cam], workspace=Workspace(rz.device), deterministic=True)
+    g_ref = _backward(rz, ref, gI)
+    bwd_ref = rz.inspect(ref)["info"]["split_tiles_bwd"]
+    print("schedule split=%s" % (split,), flush=True)
+    rz.set_raster_split(*split)
+    try:
+        fr = rz.forward(st, [cam], workspace=Workspace(rz.device), deterministic=True)
+        g = _backward(rz, fr, gI)
+        ins = rz.inspect(fr)
+    finally:
+        rz.set_raster_split(0, 0)
+    assert torch.equal(fr.images[0], ref.images[0])
+    for k in g_ref:
+        if ins["info"]["split_tiles_bwd"] == bwd_ref:
+            assert np.array_equal(g[k], g_ref[k]), k
+        else:
+            scale = float(np.abs(g_ref[k]).max()) + 1e-30
+            assert float(np.abs(g[k].astype(np.float64) - g_ref[k]).max()) <= 1e-5 * scale, k
+    lens = np.diff(ins["ranges"].cpu().numpy().astype(np.int64), axis=1).ravel()
+    cap = (lens.size + 3) // 4
+    f_len = 256 if split[0] == 0 else split[0]
+    b_len = 512 if split[1] == 0 else split[1]
+    assert ins["info"]["split_tiles"] == min(int((lens > f_len).sum()), cap)
+    assert ins["info"]["split_tiles_bwd"] == min(int((lens > b_len).sum()), cap)
