@@ -59,12 +59,17 @@ __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t*
 }
 
 // Raster schedules (tiles are independent and a pixel's arithmetic does not
-// depend on how its tile is split, so the schedule changes no result): one block
+// depend on how its tile is split, so the schedule changes no image): one block
 // buckets the list lengths (clamped to 4095) in LDS in descending order and scans
 // the buckets, giving each tile its rank. For each list, the ns longest tiles with
 // more than its split length (ns at most a quarter of the tiles) become 4 (forward)
-// or 2 (backward) band items each, placed first; every other tile is one whole item, after them;
-// both groups in descending length. The item counts go to *n_items (and *n_bwd).
+// or 2 (backward) band items each, placed first; every other tile is one whole
+// item, after them; both groups in descending length. The item counts go to
+// *n_items (and *n_bwd). Within a bucket ranks come from LDS atomics, in no fixed
+// order, except in a bucket that holds both a list's last split tile and its first
+// whole one (the cap cuts through tiles of equal length): there ranks follow the
+// tile index, so which tiles are split never depends on the order of atomics (a
+// split changes how the backward rounds its per-item sums).
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 4096;
 constexpr int kOrderUnroll = 8;  // list lengths loaded per thread before they are counted
@@ -120,9 +125,14 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   __shared__ uint32_t h[kOrderBuckets];
   __shared__ uint32_t wsum[kOrderThreads / 64];
   __shared__ uint32_t nlong[2];
+  __shared__ uint32_t edge[2];  // bucket holding the forward's / backward's last split rank (none: kOrderBuckets)
+  __shared__ uint32_t wcnt[2][kOrderThreads / 64];
   const int t = threadIdx.x;
   for (int b = t; b < kOrderBuckets; b += kOrderThreads) h[b] = 0;
-  if (t < 2) nlong[t] = 0;
+  if (t < 2) {
+    nlong[t] = 0;
+    edge[t] = kOrderBuckets;
+  }
   __syncthreads();
   uint32_t my_long = 0, my_long_b = 0;
   for (int64_t i0 = t; i0 < T; i0 += (int64_t)kOrderThreads * kOrderUnroll) {
@@ -165,10 +175,58 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   for (int w = 0; w < (t >> 6); ++w) off += wsum[w];
   __syncthreads();
   for (int q = 0; q < 4; ++q) {
+    // a list's split edge: the bucket that holds both its last split rank, ns - 1,
+    // and the first whole one, ns (the quarter cap cuts through equal lengths)
+    if (ns > 0 && off < ns && ns < off + v[q]) edge[0] = 4 * t + q;
+    if (bwd && ns_b > 0 && off < ns_b && ns_b < off + v[q]) edge[1] = 4 * t + q;
     h[4 * t + q] = off;
     off += v[q];
   }
   __syncthreads();
+  // Edge buckets: ranks in tile-index order. Each thread takes a contiguous run of
+  // tiles, counts its edge tiles, and a block scan of the counts gives its first rank.
+  const uint32_t e0 = edge[0], e1 = edge[1];
+  if (e0 < kOrderBuckets || e1 < kOrderBuckets) {
+    const int64_t per = (T + kOrderThreads - 1) / kOrderThreads;
+    const int64_t lo = min<int64_t>(T, (int64_t)t * per), hi = min<int64_t>(T, lo + per);
+    uint32_t c0 = 0, c1 = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+      const uint32_t b = order_bucket(L.len(i));
+      c0 += b == e0 ? 1u : 0u;
+      c1 += (b == e1 && e1 != e0) ? 1u : 0u;
+    }
+    uint32_t x0 = c0, x1 = c1;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y0 = __shfl_up(x0, d, 64), y1 = __shfl_up(x1, d, 64);
+      if (lane >= d) {
+        x0 += y0;
+        x1 += y1;
+      }
+    }
+    if (lane == 63) {
+      wcnt[0][t >> 6] = x0;
+      wcnt[1][t >> 6] = x1;
+    }
+    __syncthreads();
+    uint32_t r0 = x0 - c0, r1 = x1 - c1;
+    for (int w = 0; w < (t >> 6); ++w) {
+      r0 += wcnt[0][w];
+      r1 += wcnt[1][w];
+    }
+    const uint32_t s0 = e0 < kOrderBuckets ? h[e0] : 0u, s1 = e1 < kOrderBuckets ? h[e1] : 0u;
+    for (int64_t i = lo; i < hi; ++i) {
+      const uint32_t b = order_bucket(L.len(i));
+      if (b != e0 && b != e1) continue;
+      const uint32_t pos = (b == e0) ? s0 + r0++ : s1 + r1++;
+      if (staged) {
+        place_items(s_items[0], (uint32_t)i, pos, ns, 4);
+        if (bwd) place_items(s_items[1], (uint32_t)i, pos, ns_b, 2);
+      } else {
+        place_items(items, (uint32_t)i, pos, ns, 4);
+        if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+      }
+    }
+  }
   for (int64_t i0 = t; i0 < T; i0 += (int64_t)kOrderThreads * kOrderUnroll) {
     uint32_t len[kOrderUnroll];
 #pragma unroll
@@ -181,7 +239,9 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
     for (int q = 0; q < kOrderUnroll; ++q) {
       const int64_t i = i0 + (int64_t)q * kOrderThreads;
       if (i >= T) continue;
-      const uint32_t pos = atomicAdd(&h[order_bucket(len[q])], 1u);
+      const uint32_t b = order_bucket(len[q]);
+      if (b == e0 || b == e1) continue;  // placed above
+      const uint32_t pos = atomicAdd(&h[b], 1u);
       if (staged) {
         place_items(s_items[0], (uint32_t)i, pos, ns, 4);
         if (bwd) place_items(s_items[1], (uint32_t)i, pos, ns_b, 2);
