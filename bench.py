@@ -18,7 +18,8 @@ variant, the deterministic (fixed-point) backward, a 16-view cycle over the room
 (one view per step, so that the scene does not stay resident in the 256 MB
 Infinity Cache as it does for one repeated view),
 the cluster-granular Adam step that follows the backward (over the kept clusters
-and, for comparison, over all), a densification round (variance metric, split and
+and, for comparison, over all), whole training iterations with that step (as a
+separate call and fused into the backward), a densification round (variance metric, split and
 clone, opacity decay, Morton re-sort) and the render-serving stream (p50/p99
 latency, views/s).
 """
@@ -472,6 +473,42 @@ def main():
         ins = rz.inspect(fr)
         adam = adam_leg(rz, st, grads, ins["cluster_visible"][: ins["info"]["clusters"]].clone(), args.steps)
 
+    # whole training iterations (forward, loss gradient, backward, Adam over the kept
+    # clusters), steps enqueued back to back: the backward and the Adam step as two
+    # calls, and fused (gsr_backward_adam: no gradient array is written or read)
+    train = None
+    if not args.no_adam:
+        log("timing training iterations with the Adam step")
+        keys = ("means", "log_scales", "quats", "opacity_logits", "sh")
+        tp = SceneTensors(*[t.clone() for t in st.tensors()], st.sh_degree)
+        mom = [{k: torch.zeros_like(t) for k, t in zip(keys, tp.tensors())} for _ in range(2)]
+        fr_t = rz.forward(tp, cams, cluster_cull=cull, workspace=ws, check=True)
+        vis_view = rz.inspect(fr_t)["cluster_visible"][: fr_t.info["clusters"]]  # the workspace's flags, live
+        counter = [0]
+
+        def train_iter(fused):
+            counter[0] += 1
+            f_ = rz.forward(tp, cams, cluster_cull=cull, workspace=ws, check=False)
+            for img, (w, gt), dl in zip(f_.images, wgt, dls):
+                rz.l1_grad(img, w, gt, out=dl)
+            if fused:
+                rz.backward_adam(f_, dls, mom[0], mom[1], ADAM_LR, counter[0], stats=stats)
+            else:
+                rz.backward(f_, dls, grads=grads, stats=stats)
+                rz.sparse_adam(dict(zip(keys, tp.tensors())), grads, mom[0], mom[1], vis_view, ADAM_LR, counter[0])
+            return f_
+        train = {}
+        for name, fused in (("two_calls", False), ("fused", True)):
+            for _ in range(3):
+                train_iter(fused)
+            torch.cuda.synchronize()
+            wall0 = time.perf_counter()
+            for _ in range(args.steps):
+                f_ = train_iter(fused)
+            torch.cuda.synchronize()
+            train[name + "_ms"] = round((time.perf_counter() - wall0) * 1e3 / args.steps, 4)
+            rz.check_frame(f_)
+
     dens = None
     if not args.no_densify:
         log("timing a densification round")
@@ -543,6 +580,7 @@ def main():
         "schedule_sweep": sweep,
         "view_cycle": cycle,
         "sparse_adam": adam,
+        "train_iteration": train,
         "densify": dens,
         "serving": serving,
         "roofline": roof,

@@ -331,6 +331,22 @@ gsr_status gsr_sparse_adam(gsr_context *ctx, int64_t n, int32_t sh_degree, const
                            const gsr_grads *params, const gsr_grads *grads, const gsr_grads *exp_avg,
                            const gsr_grads *exp_avg_sq, const gsr_adam_options *opts, void *stream);
 
+/* gsr_backward and gsr_sparse_adam over the frame's kept clusters in one pass (the
+ * fused update of Sec. 3.2.3): the projection backward applies the Adam step of
+ * gsr_sparse_adam to each Gaussian of a cluster the forward's cull kept, with the
+ * gradient it has just computed, and no gradient array is written or read; culled
+ * clusters are not touched at all. The scene's arrays are the parameters and are
+ * updated IN PLACE (they must be writable device memory; the forward that made the
+ * frame read them before the update); exp_avg / exp_avg_sq are the moments, in
+ * place. Same arguments and checks as gsr_backward (without grads) and
+ * gsr_sparse_adam (with cluster_visible = the frame's flags); stats are accumulated
+ * as by gsr_backward. The result equals gsr_backward followed by gsr_sparse_adam on
+ * the frame's cluster_visible, bit for bit. */
+gsr_status gsr_backward_adam(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
+                             const gsr_options *opts, void *workspace, size_t ws_bytes,
+                             const float *const *dL_dimages, const gsr_grads *exp_avg, const gsr_grads *exp_avg_sq,
+                             const gsr_adam_options *adam_opts, const gsr_stats *stats, void *stream);
+
 /* Densification of Sec. 3.3: the Gaussians whose opacity-gradient variance metric
  * (gsr_variance's C Var) is largest are split or cloned. The paper fixes the
  * metric only; the thresholds and the split geometry follow the densification of

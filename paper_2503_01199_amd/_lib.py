@@ -108,6 +108,10 @@ EXPORTS = {
     "gsr_sparse_adam": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, ctypes.POINTER(GsrGrads),
                                   ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads),
                                   ctypes.POINTER(GsrAdamOptions), c_void_p]),
+    "gsr_backward_adam": (c_int32, [c_void_p, ctypes.POINTER(GsrScene), ctypes.POINTER(GsrCamera), c_int32,
+                                    ctypes.POINTER(GsrOptions), c_void_p, c_size_t, ctypes.POINTER(c_void_p),
+                                    ctypes.POINTER(GsrGrads), ctypes.POINTER(GsrGrads),
+                                    ctypes.POINTER(GsrAdamOptions), ctypes.POINTER(GsrStats), c_void_p]),
     "gsr_densify_workspace_size": (c_int32, [c_void_p, c_int64, c_int64, ctypes.POINTER(c_size_t)]),
     "gsr_densify": (c_int32, [c_void_p, ctypes.POINTER(GsrScene), c_void_p, c_void_p,
                               ctypes.POINTER(GsrDensifyOptions), ctypes.POINTER(GsrGrads), c_int64, c_int32,

@@ -40,13 +40,6 @@ __device__ __forceinline__ void store_stream(float* p, const float (&x)[4]) {
   __builtin_nontemporal_store(y, reinterpret_cast<adam_v4*>(p));
 }
 
-__device__ __forceinline__ void adam_float(float& p, float g, float& m, float& v, float step, const AdamDev& a) {
-  m = fmaf(a.beta1, m, a.c1 * g);
-  v = fmaf(a.beta2, v, a.c2 * (g * g));
-  const float den = fmaf(sqrtf(v), a.inv_sqrt_bc2, a.eps);
-  p = p - step * (m / den);
-}
-
 // Rate of float `r` of a row (r < row): the group's head floats take step_head.
 __device__ __forceinline__ float adam_rate(const AdamGroupDev& q, uint32_t r) {
   return r < (uint32_t)q.head ? q.step_head : q.step_rest;

@@ -194,6 +194,7 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.pix_T = P.take<float>((size_t)f.pixels);
   f.pix_last = P.take<uint32_t>((size_t)f.pixels);
   f.grad2d = P.take<float>(gsr::kGrad2D * std::max<size_t>(nr, 1));
+  f.dmean = P.take<float>(3 * std::max<size_t>(f.ncap, 1));
   f.grad2d_fx = fixed ? P.take<unsigned long long>(gsr::kGrad2D * std::max<size_t>(nr, 1)) : nullptr;
   auto up = [](size_t w) { return (w + 63) & ~(size_t)63; };
   const size_t w_cluster = up(gsr::scan_ctl_words(f.nclusters));
@@ -574,9 +575,15 @@ gsr_status gsr_frame_release(gsr_context* ctx, const void* workspace) {
   return st;
 }
 
-gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
-                        const gsr_options* opts, void* workspace, size_t ws_bytes, const float* const* dL_dimages,
-                        const gsr_grads* grads, const gsr_stats* stats, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// gsr_backward, and with `adam` set the fused backward + Adam of gsr_backward_adam
+// (no gradient arrays then).
+gsr_status backward_impl(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                         const gsr_options* opts, void* workspace, size_t ws_bytes, const float* const* dL_dimages,
+                         const gsr_grads* grads, const gsr_stats* stats, const gsr::AdamDev* adam, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   gsr_status st;
   if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
@@ -603,8 +610,9 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
   if (!dL_dimages) return fail(ctx, GSR_ERR_INVALID_ARG, "dL_dimages is NULL");
   for (int v = 0; v < V; ++v)
     if (!dL_dimages[v]) return fail(ctx, GSR_ERR_INVALID_ARG, "dL_dimages[%d] is NULL", v);
-  if (!grads) return fail(ctx, GSR_ERR_INVALID_ARG, "grads is NULL");
-  if (scene->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
+  if (!adam && !grads) return fail(ctx, GSR_ERR_INVALID_ARG, "grads is NULL");
+  if (!adam && scene->n > 0 &&
+      (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits || !grads->sh))
     return fail(ctx, GSR_ERR_INVALID_ARG, "a gradient array pointer is NULL");
   const bool use_stats = opts->stats && stats;
   if (use_stats && scene->n > 0 && (!stats->S || !stats->M || !stats->C))
@@ -629,10 +637,21 @@ gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_came
   }
   {
     StageScope sc_(ctx, GSR_STAGE_PREPROCESS_BWD, s);
-    gsr::launch_preprocess_bwd(*scene, f, 1, *grads, use_stats ? stats : nullptr, s);
+    const gsr_grads none{};
+    gsr::launch_preprocess_bwd(*scene, f, 1, adam ? none : *grads, use_stats ? stats : nullptr, adam, s);
   }
   fr.backwards++;
   return check_hip(ctx, hipGetLastError(), "backward");
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_backward(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                        const gsr_options* opts, void* workspace, size_t ws_bytes, const float* const* dL_dimages,
+                        const gsr_grads* grads, const gsr_stats* stats, void* stream) {
+  return backward_impl(ctx, scene, cams, V, opts, workspace, ws_bytes, dL_dimages, grads, stats, nullptr, stream);
 }
 
 gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_info* info, gsr_frame_buffers* bufs) {
@@ -712,43 +731,49 @@ gsr_status gsr_l1_grad(gsr_context* ctx, const float* image, const float* w, con
   return check_hip(ctx, hipGetLastError(), "l1 grad");
 }
 
-gsr_status gsr_sparse_adam(gsr_context* ctx, int64_t n, int32_t sh_degree, const uint32_t* cluster_visible,
-                           const gsr_grads* params, const gsr_grads* grads, const gsr_grads* exp_avg,
-                           const gsr_grads* exp_avg_sq, const gsr_adam_options* opts, void* stream) {
-  if (!ctx) return GSR_ERR_INVALID_ARG;
-  if (n < 0 || n > (int64_t(1) << 40) || sh_degree < 0 || sh_degree > 3 || !params || !grads || !exp_avg ||
-      !exp_avg_sq || !opts)
-    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_sparse_adam");
+}  // extern "C"
+
+namespace {
+
+// Validates an Adam step over n Gaussians and fills the device constants. grads may
+// be null (the fused backward computes them on the fly); every other array must be
+// non-null, 16-byte aligned, and no two of the arrays may overlap.
+gsr_status build_adam(gsr_context* ctx, int64_t n, int32_t sh_degree, const gsr_grads* params, const gsr_grads* grads,
+                      const gsr_grads* exp_avg, const gsr_grads* exp_avg_sq, const gsr_adam_options* opts,
+                      gsr::AdamDev& a) {
+  if (n < 0 || n > (int64_t(1) << 40) || sh_degree < 0 || sh_degree > 3 || !params || !exp_avg || !exp_avg_sq ||
+      !opts)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to the Adam step");
   const gsr_adam_options& o = *opts;
   if (o.reserved != 0 || o.step < 1 || !(o.beta1 >= 0.0f && o.beta1 < 1.0f) || !(o.beta2 >= 0.0f && o.beta2 < 1.0f) ||
       !(o.eps >= 0.0f))
-    return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sparse_adam: need step >= 1, betas in [0, 1), eps >= 0");
-  if (n == 0) return GSR_OK;
+    return fail(ctx, GSR_ERR_INVALID_ARG, "Adam step: need step >= 1, betas in [0, 1), eps >= 0");
   const int32_t K = (sh_degree + 1) * (sh_degree + 1);
   const int32_t rows[gsr::kAdamGroups] = {3, 3, 4, 1, 3 * K};
   // the five arrays of each set, in the order of the kernel's groups
-  float* arr[4][gsr::kAdamGroups];
+  float* arr[4][gsr::kAdamGroups] = {};
   const gsr_grads* sets[4] = {params, grads, exp_avg, exp_avg_sq};
   struct Extent {
     uintptr_t lo, hi;
   };
   std::vector<Extent> ext;
   for (int j = 0; j < 4; ++j) {
+    if (!sets[j]) continue;
     const gsr_grads& g = *sets[j];
     float* ptrs[gsr::kAdamGroups] = {g.means, g.log_scales, g.quats, g.opacity_logits, g.sh};
     for (int k = 0; k < gsr::kAdamGroups; ++k) {
-      const uintptr_t a = reinterpret_cast<uintptr_t>(ptrs[k]);
-      if (!a || (a & 15u))
-        return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sparse_adam: every array must be non-null and 16-byte aligned");
-      ext.push_back({a, a + uintptr_t(n) * rows[k] * sizeof(float)});
+      const uintptr_t p = reinterpret_cast<uintptr_t>(ptrs[k]);
+      if (n > 0 && (!p || (p & 15u)))
+        return fail(ctx, GSR_ERR_INVALID_ARG, "Adam step: every array must be non-null and 16-byte aligned");
+      ext.push_back({p, p + uintptr_t(n) * rows[k] * sizeof(float)});
       arr[j][k] = ptrs[k];
     }
   }
   std::sort(ext.begin(), ext.end(), [](const Extent& x, const Extent& y) { return x.lo < y.lo; });
-  for (size_t i = 1; i < ext.size(); ++i)
-    if (ext[i].lo < ext[i - 1].hi) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sparse_adam: arrays overlap");
+  for (size_t i = 1; i < ext.size() && n > 0; ++i)
+    if (ext[i].lo < ext[i - 1].hi) return fail(ctx, GSR_ERR_INVALID_ARG, "Adam step: arrays overlap");
 
-  gsr::AdamDev a{};
+  a = gsr::AdamDev{};
   const double t = double(o.step);
   const double bc1 = 1.0 - std::pow(double(o.beta1), t);
   const double bc2 = 1.0 - std::pow(double(o.beta2), t);
@@ -774,9 +799,43 @@ gsr_status gsr_sparse_adam(gsr_context* ctx, int64_t n, int32_t sh_degree, const
   a.c2 = float(1.0 - double(o.beta2));
   a.eps = o.eps;
   a.inv_sqrt_bc2 = float(1.0 / std::sqrt(bc2));
+  return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_sparse_adam(gsr_context* ctx, int64_t n, int32_t sh_degree, const uint32_t* cluster_visible,
+                           const gsr_grads* params, const gsr_grads* grads, const gsr_grads* exp_avg,
+                           const gsr_grads* exp_avg_sq, const gsr_adam_options* opts, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (!grads) return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_sparse_adam");
+  gsr::AdamDev a;
+  gsr_status st = build_adam(ctx, n, sh_degree, params, grads, exp_avg, exp_avg_sq, opts, a);
+  if (st) return st;
+  if (n == 0) return GSR_OK;
   DeviceGuard guard(ctx->device);
   gsr::launch_sparse_adam(a, cluster_visible, static_cast<hipStream_t>(stream));
   return check_hip(ctx, hipGetLastError(), "sparse adam");
+}
+
+gsr_status gsr_backward_adam(gsr_context* ctx, const gsr_scene* scene, const gsr_camera* cams, int32_t V,
+                             const gsr_options* opts, void* workspace, size_t ws_bytes,
+                             const float* const* dL_dimages, const gsr_grads* exp_avg, const gsr_grads* exp_avg_sq,
+                             const gsr_adam_options* adam_opts, const gsr_stats* stats, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (!scene) return fail(ctx, GSR_ERR_INVALID_ARG, "scene is NULL");
+  gsr_grads params;
+  params.means = const_cast<float*>(scene->means);
+  params.log_scales = const_cast<float*>(scene->log_scales);
+  params.quats = const_cast<float*>(scene->quats);
+  params.opacity_logits = const_cast<float*>(scene->opacity_logits);
+  params.sh = const_cast<float*>(scene->sh);
+  gsr::AdamDev a;
+  gsr_status st = build_adam(ctx, scene->n, scene->sh_degree, &params, nullptr, exp_avg, exp_avg_sq, adam_opts, a);
+  if (st) return st;
+  return backward_impl(ctx, scene, cams, V, opts, workspace, ws_bytes, dL_dimages, nullptr, stats, &a, stream);
 }
 
 gsr_status gsr_densify_workspace_size(gsr_context* ctx, int64_t n, int64_t max_candidates, size_t* bytes) {

@@ -111,6 +111,7 @@ struct Frame {
   float* pix_T;             // [pixels]
   uint32_t* pix_last;       // [pixels]
   float* grad2d;            // [nrec][12]
+  float* dmean;              // [ncap][3] mean gradient between the two projection-backward kernels (fused Adam)
   unsigned long long* grad2d_fx;  // [nrec][12] fixed-point sums (deterministic backward), else null
   uint32_t split_len = kSplitLen;         // forward: tiles with longer lists are rastered as four bands
   uint32_t split_len_bwd = kSplitLenBwd;  // backward: tiles with longer lists are walked as two halves
@@ -162,8 +163,11 @@ void launch_cluster(const float* means, const float* log_scales, int64_t n, int 
 
 // preprocess.hip
 void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s);
+struct AdamDev;
+// adam null: gradients into g. adam set: no gradient leaves the kernels; the
+// Gaussians of kept clusters take the Adam step in place (adam's p, m, v arrays).
 void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
-                           const gsr_stats* stats, hipStream_t s);
+                           const gsr_stats* stats, const AdamDev* adam, hipStream_t s);
 
 // binning.hip (counts read from the frame header)
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
@@ -239,6 +243,18 @@ struct AdamDev {
 };
 // Every pointer 16-byte aligned; visible u32[ceil(n / GSR_CLUSTER)] or null (all).
 void launch_sparse_adam(const AdamDev& a, const uint32_t* visible, hipStream_t s);
+
+// One float of an Adam step (Kingma and Ba, Algorithm 1), the bias corrections folded
+// into step = lr / (1 - beta1^t) and inv_sqrt_bc2 = 1 / sqrt(1 - beta2^t):
+//   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,  p -= step m / (sqrt(v) inv_sqrt_bc2 + eps).
+// The separate kernel and the update fused into the projection backward share it, so
+// both give the same bits.
+__device__ __forceinline__ void adam_float(float& p, float g, float& m, float& v, float step, const AdamDev& a) {
+  m = fmaf(a.beta1, m, a.c1 * g);
+  v = fmaf(a.beta2, v, a.c2 * (g * g));
+  const float den = fmaf(sqrtf(v), a.inv_sqrt_bc2, a.eps);
+  p = p - step * (m / den);
+}
 
 // densify.hip: densification by the variance metric and opacity decay (Sec. 3.3).
 constexpr int kMaxDensCopy = 3 + 16;  // quaternions, opacity logits, SH and up to 16 state arrays

@@ -406,11 +406,52 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
 // FP64. One thread per Gaussian in the caller's order; Gaussians that no view
 // blends (including those of culled clusters) get zero. The SH coefficients and the
 // colour's dependence on the mean through the view direction follow in k_sh_bwd.
+// The projection backward's results for Gaussian i (compact slot j): the gradients,
+// or, with the fused Adam, the Adam step of its log-scales, quaternion and opacity
+// logit in place and its mean gradient, which k_sh_bwd completes, in dmean.
+template <bool kAdam>
+__device__ __forceinline__ void store_project_grads(const gsr_grads& gr, const AdamDev& adam, float* dmean, int64_t i,
+                                                    int64_t j, const float (&gm)[3], const float (&gl)[3],
+                                                    const float (&gq)[4], float go) {
+  if constexpr (kAdam) {
+    const AdamGroupDev& ql = adam.grp[1];
+    const AdamGroupDev& qq = adam.grp[2];
+    const AdamGroupDev& qo = adam.grp[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float p = ql.p[3 * i + a], m = ql.m[3 * i + a], v = ql.v[3 * i + a];
+      adam_float(p, gl[a], m, v, ql.step_head, adam);
+      ql.p[3 * i + a] = p, ql.m[3 * i + a] = m, ql.v[3 * i + a] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      float p = qq.p[4 * i + a], m = qq.m[4 * i + a], v = qq.v[4 * i + a];
+      adam_float(p, gq[a], m, v, qq.step_head, adam);
+      qq.p[4 * i + a] = p, qq.m[4 * i + a] = m, qq.v[4 * i + a] = v;
+    }
+    {
+      float p = qo.p[i], m = qo.m[i], v = qo.v[i];
+      adam_float(p, go, m, v, qo.step_head, adam);
+      qo.p[i] = p, qo.m[i] = m, qo.v[i] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dmean[3 * j + a] = gm[a];
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gr.means[3 * i + a] = gm[a], gr.log_scales[3 * i + a] = gl[a];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) gr.quats[4 * i + a] = gq[a];
+    gr.opacity_logits[i] = go;
+  }
+}
+
+template <bool kAdam>
 __global__ __launch_bounds__(kThreads) void k_project_bwd(
     gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, const uint32_t* __restrict__ visible,
     const uint32_t* __restrict__ cluster_offset, const uint32_t* __restrict__ tiles,
     float* __restrict__ grad2d, const unsigned long long* __restrict__ grad_fx, gsr_grads gr,
-    float* __restrict__ S, float* __restrict__ Mst, uint32_t* __restrict__ Cst) {
+    float* __restrict__ S, float* __restrict__ Mst, uint32_t* __restrict__ Cst, AdamDev adam,
+    float* __restrict__ dmean) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= sc.n) return;
   const int64_t c = i / GSR_CLUSTER;
@@ -517,13 +558,10 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
       for (int a = 0; a < 3; ++a) dm[a] += (double)W[a] * dt[0] + (double)W[3 + a] * dt[1] + (double)W[6 + a] * dt[2];
     }
   }
-  float* om = gr.means + 3 * i;
-  float* ol = gr.log_scales + 3 * i;
-  float* oq = gr.quats + 4 * i;
+  if (kAdam && !vis) return;  // a culled cluster keeps its parameters and moments
+  float gl[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, gm[3] = {0.f, 0.f, 0.f}, go = 0.f;
   if (!any) {
-    for (int a = 0; a < 3; ++a) om[a] = 0.0f, ol[a] = 0.0f;
-    for (int a = 0; a < 4; ++a) oq[a] = 0.0f;
-    gr.opacity_logits[i] = 0.0f;
+    store_project_grads<kAdam>(gr, adam, dmean, i, j, gm, gl, gq, go);
     return;
   }
   // Sigma = L L^T, L = R S: G_L = 2 G_Sigma L
@@ -542,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
   for (int k = 0; k < 3; ++k) {
     double ds = 0.0;
     for (int r = 0; r < 3; ++r) ds += GL[3 * r + k] * g.R[3 * r + k];
-    ol[k] = (float)(ds * g.s[k]);
+    gl[k] = (float)(ds * g.s[k]);
     for (int r = 0; r < 3; ++r) GR[3 * r + k] = GL[3 * r + k] * g.s[k];
   }
   const double w = g.q[0], x = g.q[1], y = g.q[2], z = g.q[3];
@@ -552,9 +590,10 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
   dq[2] = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] - 2 * y * GR[8]);
   dq[3] = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] + x * GR[6] + y * GR[7]);
   const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  for (int a = 0; a < 4; ++a) oq[a] = (float)((dq[a] - g.q[a] * qd) / g.qn);
-  for (int a = 0; a < 3; ++a) om[a] = (float)dm[a];
-  gr.opacity_logits[i] = (float)dlogit;
+  for (int a = 0; a < 4; ++a) gq[a] = (float)((dq[a] - g.q[a] * qd) / g.qn);
+  for (int a = 0; a < 3; ++a) gm[a] = (float)dm[a];
+  go = (float)dlogit;
+  store_project_grads<kAdam>(gr, adam, dmean, i, j, gm, gl, gq, go);
   if (S) {
     S[i] += (float)sS;
     Mst[i] += (float)sM;
@@ -567,12 +606,13 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
 // gradients and adds the direction term to the mean gradient that k_project_bwd
 // wrote. The clamp decision is taken in FP64 like the projection's; the gradients
 // accumulate in FP32.
-template <int DEG>
+template <int DEG, bool kAdam>
 __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev* __restrict__ views, int32_t V,
                                                      const uint32_t* __restrict__ visible,
                                                      const uint32_t* __restrict__ cluster_offset,
                                                      const uint32_t* __restrict__ tiles,
-                                                     const float* __restrict__ grad2d, gsr_grads gr) {
+                                                     const float* __restrict__ grad2d, gsr_grads gr, AdamDev adam,
+                                                     const float* __restrict__ dmean) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int R = 3 * K, S = R + 1;
   __shared__ float lsh[kThreads * S];  // the cluster's SH rows, then their gradients
@@ -582,7 +622,7 @@ __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev
   const int nrows = (int)min<int64_t>(kThreads, sc.n - i0);
   float* osh = gr.sh + i0 * R;
   if (visible[c] == 0) {  // a culled cluster: its SH gradient rows are zero (written, not accumulated)
-    zero_rows<R>(osh, nrows);
+    if (!kAdam) zero_rows<R>(osh, nrows);  // or, with the fused Adam, its parameters stay as they are
     return;
   }
   rows_to_lds<R>(lsh, sc.sh + i0 * R, nrows);
@@ -646,12 +686,40 @@ __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev
 #pragma unroll
   for (int q = 0; q < R; ++q) orow[q] = gsh[q];
   __syncthreads();
-  rows_from_lds<R>(osh, lsh, nrows);
-  if (DEG > 0 && written) {
-    float* om = gr.means + 3 * i;
-    om[0] += dmu[0];
-    om[1] += dmu[1];
-    om[2] += dmu[2];
+  if constexpr (kAdam) {
+    // the cluster's SH slice, coalesced: gradient from LDS, parameter and moments from HBM
+    const AdamGroupDev q = adam.grp[4];
+    const int64_t base = i0 * R;
+    for (int e = t; e < nrows * R; e += kThreads) {
+      const int row = e / R, col = e - row * R;
+      float pv = q.p[base + e], mv = q.m[base + e], vv = q.v[base + e];
+      adam_float(pv, lsh[row * S + col], mv, vv, col < q.head ? q.step_head : q.step_rest, adam);
+      q.p[base + e] = pv;
+      q.m[base + e] = mv;
+      q.v[base + e] = vv;
+    }
+    if (t < nrows) {  // the mean: the projection's part plus the colour's
+      const int64_t j = (int64_t)cluster_offset[c] * GSR_CLUSTER + t;
+      const AdamGroupDev qm = adam.grp[0];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float gmv = dmean[3 * j + a];
+        if (DEG > 0 && written) gmv += dmu[a];
+        float pv = qm.p[3 * i + a], mv = qm.m[3 * i + a], vv = qm.v[3 * i + a];
+        adam_float(pv, gmv, mv, vv, qm.step_head, adam);
+        qm.p[3 * i + a] = pv;
+        qm.m[3 * i + a] = mv;
+        qm.v[3 * i + a] = vv;
+      }
+    }
+  } else {
+    rows_from_lds<R>(osh, lsh, nrows);
+    if (DEG > 0 && written) {
+      float* om = gr.means + 3 * i;
+      om[0] += dmu[0];
+      om[1] += dmu[1];
+      om[2] += dmu[2];
+    }
   }
 }
 
@@ -719,16 +787,29 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
 }
 
 void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
-                           const gsr_stats* stats, hipStream_t s) {
+                           const gsr_stats* stats, const AdamDev* adam, hipStream_t s) {
   (void)cull;
   if (sc.n <= 0) return;
   const unsigned grid = (unsigned)((sc.n + kThreads - 1) / kThreads);
-  k_project_bwd<<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset, f.tiles_touched,
-                                          f.grad2d, f.grad2d_fx, g, stats ? stats->S : nullptr,
-                                          stats ? stats->M : nullptr, stats ? stats->C : nullptr);
-#define GSR_SH_BWD(D)                                                                                      \
-  k_sh_bwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset, f.tiles_touched, \
-                                        f.grad2d, g)
+  const AdamDev none{};
+  const AdamDev& a = adam ? *adam : none;
+  if (adam)
+    k_project_bwd<true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,
+                                                  f.tiles_touched, f.grad2d, f.grad2d_fx, g,
+                                                  stats ? stats->S : nullptr, stats ? stats->M : nullptr,
+                                                  stats ? stats->C : nullptr, a, f.dmean);
+  else
+    k_project_bwd<false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,
+                                                   f.tiles_touched, f.grad2d, f.grad2d_fx, g,
+                                                   stats ? stats->S : nullptr, stats ? stats->M : nullptr,
+                                                   stats ? stats->C : nullptr, a, f.dmean);
+#define GSR_SH_BWD(D)                                                                                            \
+  if (adam)                                                                                                      \
+    k_sh_bwd<D, true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,           \
+                                                f.tiles_touched, f.grad2d, g, a, f.dmean);                       \
+  else                                                                                                           \
+    k_sh_bwd<D, false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,          \
+                                                 f.tiles_touched, f.grad2d, g, a, f.dmean)
   switch (sc.sh_degree) {
     case 0: GSR_SH_BWD(0); break;
     case 1: GSR_SH_BWD(1); break;

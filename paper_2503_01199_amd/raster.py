@@ -301,6 +301,39 @@ class Rasterizer:
                     "gsr_backward")
         return grads
 
+    def backward_adam(self, frame: Frame, dL_dimages, exp_avg: dict, exp_avg_sq: dict, lr: dict, step: int,
+                      beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, stats=None):
+        """The backward with the Adam step of the frame's kept clusters fused in
+        (gsr_backward_adam): the frame's scene tensors are updated in place, with the
+        moments; no gradient is returned."""
+        V = len(frame.cameras)
+        sc = frame.scene.struct()
+        dl = [t.contiguous() for t in dL_dimages]
+        for t, c in zip(dl, frame.cameras):
+            if t.shape != (3, c.height, c.width) or t.dtype != torch.float32:
+                raise ValueError("dL/dimage must be float32 [3, H, W]")
+        dl_ptrs = (ctypes.c_void_p * V)(*[t.data_ptr() for t in dl])
+        sets = []
+        for d in (exp_avg, exp_avg_sq):
+            g = L.GsrGrads()
+            for k, t in zip(GRAD_KEYS, frame.scene.tensors()):
+                if d[k].shape != t.shape or d[k].dtype != torch.float32 or not d[k].is_contiguous():
+                    raise ValueError("moments must be contiguous float32 tensors shaped like the scene")
+                setattr(g, k, d[k].data_ptr())
+            sets.append(g)
+        st_ptr = None
+        if stats is not None:
+            s = L.GsrStats()
+            s.S, s.M, s.C = _ptr(stats["S"]), _ptr(stats["M"]), _ptr(stats["C"])
+            st_ptr = ctypes.byref(s)
+        o = L.GsrAdamOptions(lr["means"], lr["log_scales"], lr["quats"], lr["opacity_logits"], lr["sh_dc"],
+                             lr["sh_rest"], beta1, beta2, eps, 0, int(step))
+        ws = frame.workspace
+        self._check(self.lib.gsr_backward_adam(self.ctx, ctypes.byref(sc), frame.cam_structs, V,
+                                               ctypes.byref(frame.opts), ws.ptr, ws.nbytes, dl_ptrs,
+                                               ctypes.byref(sets[0]), ctypes.byref(sets[1]), ctypes.byref(o), st_ptr,
+                                               self._stream()), "gsr_backward_adam")
+
     # ------------------------------------------------------------------ inspection
     def inspect(self, frame: Frame, allow_overflow: bool = False) -> dict:
         """Tensor views (not copies) of the frame's intermediate buffers in the

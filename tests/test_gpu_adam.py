@@ -240,3 +240,49 @@ def test_room_size_sampled_against_oracle(rz):
             assert np.array_equal(a[~rows], b[~rows]), k
         _check(k, got, (rp[k], rm[k], rv[k]), (P[k][idx], G[k][idx], M[k][idx], V[k][idx]), 0.9, 0.999, 1e-15, t,
                rows)
+
+
+@pytest.mark.parametrize("which", ["spheres-sh3", "tiny-sh0"])
+def test_fused_backward_adam_equals_two_calls(rz, which):
+    """gsr_backward_adam against gsr_backward followed by gsr_sparse_adam on the
+    frame's cluster flags: bit for bit over two steps with carried moments (frames
+    in the deterministic mode, so both paths see the same gradient bits), culled
+    clusters untouched, and the statistic identical."""
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace, new_stats
+    if which == "tiny-sh0":
+        sc, cam = scenes.tiny_scene(3000, seed_salt=4), scenes.tiny_camera()
+    else:
+        sc = scenes.spheres_planes_scene(20_000, seed_salt=6)
+        _, perm = orc.morton(sc.means)
+        sc = sc.permuted(perm)
+        cam = scenes.orbit_camera(60.0, 10.0, radius=4.0, width=200, height=150)
+    _, _, M, V = scenes.adam_inputs(sc.n, sc.sh_degree, salt=12)
+    M["sh"] = M["sh"].reshape(sc.sh.shape)
+    V["sh"] = V["sh"].reshape(sc.sh.shape)
+    two = SceneTensors.from_scene(sc, rz.device)
+    fused = SceneTensors.from_scene(sc, rz.device)
+    m2, v2, mf, vf = _dev(M, rz), _dev(V, rz), _dev(M, rz), _dev(V, rz)
+    s2, sf = new_stats(sc.n, rz.device), new_stats(sc.n, rz.device)
+    print("fused backward + adam %s n=%d" % (which, sc.n), flush=True)
+    for t in (1, 2):
+        w, gt = scenes.l1_weights((3, cam.height, cam.width), config=0, salt=t)
+        w, gt = torch.as_tensor(w, device=rz.device), torch.as_tensor(gt, device=rz.device)
+        fa = rz.forward(two, [cam], workspace=Workspace(rz.device), deterministic=True)
+        fb = rz.forward(fused, [cam], workspace=Workspace(rz.device), deterministic=True)
+        assert torch.equal(fa.images[0], fb.images[0])
+        dl = rz.l1_grad(fa.images[0], w, gt)
+        grads = rz.backward(fa, [dl], stats=s2)
+        vis = rz.inspect(fa)["cluster_visible"][: fa.info["clusters"]].clone()
+        rz.sparse_adam(dict(zip(KEYS, two.tensors())), grads, m2, v2, vis, LR, t)
+        rz.backward_adam(fb, [dl], mf, vf, LR, t, stats=sf)
+        torch.cuda.synchronize()
+        flags = vis.cpu().numpy()
+        assert 0 < flags.sum() < flags.size or which == "tiny-sh0"
+    rows = np.repeat(flags != 0, 128)[: sc.n]
+    for k, a, b, p0 in zip(KEYS, two.tensors(), fused.tensors(), sc.arrays()):
+        assert torch.equal(a, b), k
+        assert torch.equal(m2[k], mf[k]) and torch.equal(v2[k], vf[k]), k
+        if (~rows).any():  # culled in both steps here: untouched (the view is the same)
+            assert np.array_equal(b.cpu().numpy()[~rows], np.asarray(p0)[~rows]), k
+    for k in ("S", "M", "C"):
+        assert torch.equal(s2[k], sf[k]), k
