@@ -55,8 +55,8 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                             "sources": ["paper_2503_01199_amd/csrc/raster_bwd.hip",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
-                            "sha1": "f7d932a9cbb13fc67235a33cee0db7f2702a75ba",
-                            "fetch_kib": 70605.0, "write_kib": 99531.0}}
+                            "sha1": "244bfe7373dccd28064c4a8a157a75c1edf94248",
+                            "fetch_kib": 70561.0, "write_kib": 99531.0}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
