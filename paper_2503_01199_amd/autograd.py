@@ -28,12 +28,13 @@ def default_rasterizer(device=None) -> Rasterizer:
 class GaussianRasterize(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, sh, cameras, sh_degree, rasterizer, precision,
-                cluster_cull, stats):
+                cluster_cull, stats, deterministic):
         st = SceneTensors(means.detach().contiguous(), log_scales.detach().contiguous(),
                           quats.detach().contiguous(), opacity_logits.detach().contiguous(),
                           sh.detach().contiguous(), int(sh_degree))
         frame = rasterizer.forward(st, cameras, precision=precision, cluster_cull=cluster_cull,
-                                   stats=stats is not None, workspace=Workspace(rasterizer.device))
+                                   stats=stats is not None, workspace=Workspace(rasterizer.device),
+                                   deterministic=deterministic)
         ctx.frame = frame
         ctx.rasterizer = rasterizer
         ctx.stats = stats
@@ -50,13 +51,14 @@ class GaussianRasterize(torch.autograd.Function):
         grads = ctx.rasterizer.backward(frame, dl, stats=ctx.stats)
         ctx.frame = None
         return (grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"],
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
 def rasterize(means, log_scales, quats, opacity_logits, sh, cameras, sh_degree, rasterizer=None,
-              precision=L.GSR_FP32, cluster_cull=True, stats=None):
-    """Differentiable render of `cameras` (a list); returns a list of [3, H, W] images."""
+              precision=L.GSR_FP32, cluster_cull=True, stats=None, deterministic=False):
+    """Differentiable render of `cameras` (a list); returns a list of [3, H, W] images.
+    deterministic: bitwise reproducible gradients (fixed-point per-tile sums)."""
     rz = rasterizer or default_rasterizer(means.device)
     out = GaussianRasterize.apply(means, log_scales, quats, opacity_logits, sh, list(cameras), sh_degree, rz,
-                                  precision, cluster_cull, stats)
+                                  precision, cluster_cull, stats, bool(deterministic))
     return list(out)

@@ -154,3 +154,22 @@ def test_raster_schedule_changes_nothing_but_time(rz, split):
     b_len = 512 if split[1] == 0 else split[1]
     assert ins["info"]["split_tiles"] == min(int((lens > f_len).sum()), cap)
     assert ins["info"]["split_tiles_bwd"] == min(int((lens > b_len).sum()), cap)
+
+
+def test_autograd_deterministic_gradients_repeat(rz):
+    """rasterize(..., deterministic=True): two loss.backward() calls leave the same
+    gradient bits in the parameter tensors."""
+    from paper_2503_01199_amd.autograd import rasterize
+    sc = scenes.tiny_scene(3000, seed_salt=3)
+    cams = [scenes.tiny_camera(96, 80), scenes.tiny_camera(64, 64)]
+    w = [torch.as_tensor(np.random.default_rng(v).uniform(-1, 1, (3, c.height, c.width)).astype(np.float32),
+                         device=rz.device) for v, c in enumerate(cams)]
+    runs = []
+    print("deterministic autograd n=%d" % sc.n, flush=True)
+    for _ in range(2):
+        params = [torch.as_tensor(a, device=rz.device).requires_grad_(True) for a in sc.arrays()]
+        imgs = rasterize(*params, cams, sc.sh_degree, rasterizer=rz, deterministic=True)
+        sum((img * wi).sum() for img, wi in zip(imgs, w)).backward()
+        runs.append([p.grad.detach().clone() for p in params])
+    for a, b in zip(*runs):
+        assert torch.equal(a, b)
