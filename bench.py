@@ -56,7 +56,8 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
                             "sha1": "244bfe7373dccd28064c4a8a157a75c1edf94248",
-                            "fetch_kib": 70561.0, "write_kib": 99531.0}}
+                            "fetch_kib": 70561.0, "write_kib": 99531.0,
+                            "valu_insts": 153793460}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
@@ -65,9 +66,9 @@ BWD_FLOP_EVAL = 7
 BWD_FLOP_FRAG = 41
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the recorded counters, or
-    None when they were taken on another workload or its sources have changed since."""
+def recorded_counters(kernel, workload):
+    """The counters recorded for `kernel` on `workload`, or None when they were taken
+    on another workload or its sources have changed since."""
     import hashlib
     t = TRAFFIC.get(kernel)
     if t is None or t["workload"] != workload:
@@ -76,9 +77,26 @@ def measured_traffic(kernel, workload):
     for f in t["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != t["sha1"]:
+    return t if h.hexdigest() == t["sha1"] else None
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the recorded FETCH_SIZE / WRITE_SIZE, or None."""
+    t = recorded_counters(kernel, workload)
+    if t is None:
         return None
     return int(round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024))
+
+
+def valu_issue_fraction(kernel, workload, launch_s):
+    """Share of the launch's VALU issue slots used: recorded SQ_INSTS_VALU (wave
+    instructions) x 4 cycles each (a wave64 instruction on a 16-lane SIMD; the
+    quarter-rate transcendentals take longer, so this is a lower bound) over
+    1,024 SIMDs x 2.4 GHz x the launch time measured now. None without a record."""
+    t = recorded_counters(kernel, workload)
+    if t is None or "valu_insts" not in t:
+        return None
+    return t["valu_insts"] * 4.0 / (1024 * 2.4e9 * launch_s)
 
 
 def log(msg):
@@ -538,6 +556,8 @@ def main():
         roof = {"bound": "hbm", "achieved": round(work / dur_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     roof["traffic"] = measured_traffic(roof_kernel, desc)
+    vi = valu_issue_fraction(roof_kernel, desc, dur_s)
+    roof["valu_issue_frac"] = None if vi is None else round(vi, 3)
     roof["kernel"] = roof_kernel
     roof["launch_ms"] = stages[dom]
     roof["work_per_launch"] = work
