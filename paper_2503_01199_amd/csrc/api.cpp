@@ -638,7 +638,7 @@ gsr_status backward_impl(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   {
     StageScope sc_(ctx, GSR_STAGE_PREPROCESS_BWD, s);
     const gsr_grads none{};
-    gsr::launch_preprocess_bwd(*scene, f, 1, adam ? none : *grads, use_stats ? stats : nullptr, adam, s);
+    gsr::launch_preprocess_bwd(*scene, f, adam ? none : *grads, use_stats ? stats : nullptr, adam, s);
   }
   fr.backwards++;
   return check_hip(ctx, hipGetLastError(), "backward");

@@ -166,8 +166,8 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s);
 struct AdamDev;
 // adam null: gradients into g. adam set: no gradient leaves the kernels; the
 // Gaussians of kept clusters take the Adam step in place (adam's p, m, v arrays).
-void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
-                           const gsr_stats* stats, const AdamDev* adam, hipStream_t s);
+void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads& g, const gsr_stats* stats,
+                           const AdamDev* adam, hipStream_t s);
 
 // binning.hip (counts read from the frame header)
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);

@@ -786,9 +786,8 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
 #undef GSR_PRE_FWD
 }
 
-void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, int cull, const gsr_grads& g,
-                           const gsr_stats* stats, const AdamDev* adam, hipStream_t s) {
-  (void)cull;
+void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads& g, const gsr_stats* stats,
+                           const AdamDev* adam, hipStream_t s) {
   if (sc.n <= 0) return;
   const unsigned grid = (unsigned)((sc.n + kThreads - 1) / kThreads);
   const AdamDev none{};
