@@ -55,8 +55,8 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                             "sources": ["paper_2503_01199_amd/csrc/raster_bwd.hip",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
-                            "sha1": "244bfe7373dccd28064c4a8a157a75c1edf94248",
-                            "fetch_kib": 70561.0, "write_kib": 99531.0,
+                            "sha1": "0dc43ef58e66037afc147dafcae2891af92677ec",
+                            "fetch_kib": 70572.0, "write_kib": 99531.0,
                             "valu_insts": 153793460}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
