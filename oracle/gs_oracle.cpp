@@ -16,9 +16,9 @@
 //   Sec. 3.2.2       clusters of 128 consecutive primitives with an AABB
 //   Sec. 3.3         opacity-gradient statistic S_i, M_i, C_i and S - M^2/C
 //   App. A.2, Eq. (7)-(9)  (a,b,c) form of the exponent and its scanline split
-// Points on which the paper is silent follow the readings listed in the design doc
-// (projection, pixel centres, alpha/T thresholds, support radius, ...); each
-// is restated where it is used.
+// Points on which the paper is silent (projection, pixel centres, alpha/T
+// thresholds, support radius, ...) take one reading each, restated where it is
+// used.
 //
 // Parity pins: every function here is pinned by tests under tests/ (closed
 // forms, invariants, brute force, finite differences, library routines).
