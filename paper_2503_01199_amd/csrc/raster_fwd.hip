@@ -97,7 +97,7 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
         const bool ok = a >= amin[j];
         if (!__any(ok)) continue;  // nobody in this band blends the entry
         bm[j] |= 1ull << k;
-        const float Tn = T[j] * (1.0f - a);
+        const float Tn = __builtin_fmaf(-T[j], a, T[j]);  // T (1 - a), one rounding
         const bool below = Tn < kTMin;  // one compare serves both outcomes
         const bool stop = ok && below;
         const bool blend = ok && !below;
