@@ -100,9 +100,10 @@ typedef struct {
                            instead of FP32 atomics (the integer reduction of Sec. 3.1.2,
                            carried to the device-wide sum), so gradients and statistic
                            are bitwise reproducible whatever the order in which tiles
-                           finish (for one raster schedule, gsr_set_raster_split). Each per-tile sum is rounded to a multiple of 2^-32
-                           and saturates at 2^31 in magnitude. The workspace grows by
-                           48 B per record; forward and backward must agree. 0: FP32
+                           finish (for one raster schedule, see gsr_set_raster_split).
+                           Each per-tile sum is rounded to a multiple of 2^-32 and
+                           saturates at 2^31 in magnitude. The workspace grows by 96 B
+                           per record; forward and backward must agree. 0: FP32
                            atomics. */
 } gsr_options;
 
@@ -340,8 +341,10 @@ gsr_status gsr_sparse_adam(gsr_context *ctx, int64_t n, int32_t sh_degree, const
  * frame read them before the update); exp_avg / exp_avg_sq are the moments, in
  * place. Same arguments and checks as gsr_backward (without grads) and
  * gsr_sparse_adam (with cluster_visible = the frame's flags); stats are accumulated
- * as by gsr_backward. The result equals gsr_backward followed by gsr_sparse_adam on
- * the frame's cluster_visible, bit for bit. */
+ * as by gsr_backward. Given the same gradients (a deterministic frame, where the
+ * backward's sums do not depend on the order of atomics), the result equals
+ * gsr_backward followed by gsr_sparse_adam on the frame's cluster_visible, bit for
+ * bit: both apply the same per-float update. */
 gsr_status gsr_backward_adam(gsr_context *ctx, const gsr_scene *scene, const gsr_camera *cams, int32_t V,
                              const gsr_options *opts, void *workspace, size_t ws_bytes,
                              const float *const *dL_dimages, const gsr_grads *exp_avg, const gsr_grads *exp_avg_sq,
