@@ -13,39 +13,83 @@
 namespace gsr {
 namespace {
 
-// One thread per sorted record k < (active records); writes its instances at its
-// scanned offset, tiles in row-major order of its rect. When the frame has more
-// instances than the workspace holds, the list is cut at the capacity (the record
-// that straddles it writes its first tiles only), so [0, kept) is always complete,
-// and the overflow flag is raised. The first threads also clear the per-tile ranges.
-__global__ void k_emit(const uint32_t* __restrict__ sorted_rec, const uint32_t* __restrict__ offsets,
-                       const uint32_t* __restrict__ tiles, const ushort4* __restrict__ rect,
-                       const ViewDev* __restrict__ views, int32_t V, uint32_t* __restrict__ header, int64_t cap,
-                       uint32_t* __restrict__ inst_tile, uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ ranges,
-                       int64_t ntiles) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t t = k; t < 2 * ntiles; t += (int64_t)gridDim.x * blockDim.x) ranges[t] = 0u;
+// One thread per sorted record k < (active records); its instances go to its
+// scanned offset, tiles in row-major order of its rect. A record with more than
+// kEmitAlone tiles is written by its whole wave instead, lanes on consecutive
+// positions, one such record after another (found by a ballot, broadcast by lane
+// reads): left to one lane, the largest rects hold their wave long after the others
+// are done (on 8 orbit views of a 3M-Gaussian scene the slowest lane's count
+// averages 4x a wave's mean). When the frame has more instances than the workspace
+// holds, the list is cut at the capacity (the record that straddles it writes its
+// first tiles only), so [0, kept) is always complete, and the overflow flag is
+// raised. The first threads also clear the per-tile ranges.
+constexpr int kEmitThreads = 128;
+constexpr uint32_t kEmitAlone = 16;
+
+__global__ __launch_bounds__(kEmitThreads) void k_emit(const uint32_t* __restrict__ sorted_rec,
+                                                       const uint32_t* __restrict__ offsets,
+                                                       const uint32_t* __restrict__ tiles,
+                                                       const ushort4* __restrict__ rect,
+                                                       const ViewDev* __restrict__ views, int32_t V,
+                                                       uint32_t* __restrict__ header, int64_t cap,
+                                                       uint32_t* __restrict__ inst_tile,
+                                                       uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ ranges,
+                                                       int64_t ntiles) {
+  const int64_t k = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
+  for (int64_t q = k; q < 2 * ntiles; q += (int64_t)gridDim.x * kEmitThreads) ranges[q] = 0u;
   if (k == 0) {
     const uint32_t M = header[kHdrInstances];
     header[kHdrInstancesKept] = (uint32_t)min((int64_t)M, cap);
     if ((int64_t)M > cap) header[kHdrOverflow] = 1u;
   }
-  if (k >= (int64_t)header[kHdrRecords]) return;
-  const uint32_t r = sorted_rec[k];
-  const uint32_t cnt = tiles[r];
-  int64_t o = offsets[k];
-  if (cnt == 0 || o >= cap) return;
-  const int64_t end = min(o + (int64_t)cnt, cap);
-  const ushort4 b = rect[r];
-  const int v = (int)(r % (uint32_t)V);
-  const int32_t base = views[v].tile_base;
-  const int32_t tx = views[v].tiles_x;
-  for (int y = b.z; y <= b.w && o < end; ++y)
-    for (int x = b.x; x <= b.y && o < end; ++x) {
-      inst_tile[o] = (uint32_t)(base + y * tx + x);
-      inst_rec[o] = r;
-      ++o;
+  const int64_t nrec = header[kHdrRecords];
+  if (k - (threadIdx.x & 63) >= nrec) return;  // the whole wave
+  uint32_t r = 0, cnt = 0;
+  int64_t o = 0;
+  if (k < nrec) {
+    r = sorted_rec[k];
+    cnt = tiles[r];
+    o = offsets[k];
+  }
+  const bool live = cnt > 0 && o < cap;
+  const bool alone = live && cnt > kEmitAlone;
+  ushort4 b = make_ushort4(0, 0, 0, 0);
+  int32_t base = 0, tx = 0;
+  if (live) {  // every lane loads its own rect and view first, large records too
+    b = rect[r];
+    const int v = (int)(r % (uint32_t)V);
+    base = views[v].tile_base;
+    tx = views[v].tiles_x;
+  }
+  if (live && !alone) {
+    const int64_t end = min(o + (int64_t)cnt, cap);
+    for (int y = b.z; y <= b.w && o < end; ++y)
+      for (int x = b.x; x <= b.y && o < end; ++x) {
+        inst_tile[o] = (uint32_t)(base + y * tx + x);
+        inst_rec[o] = r;
+        ++o;
+      }
+  }
+  uint64_t big = __builtin_amdgcn_ballot_w64(alone);
+  const int lane = (int)(threadIdx.x & 63);
+  while (big) {  // wave-uniform; every value comes from the owning lane's registers
+    const int src = __builtin_ctzll(big);
+    big &= big - 1;
+    const uint32_t rr = (uint32_t)__shfl((int)r, src, 64);
+    const int64_t o0 = (int64_t)(uint32_t)__shfl((int)(uint32_t)o, src, 64);
+    const int64_t n_here = min((int64_t)(uint32_t)__shfl((int)cnt, src, 64), cap - o0);
+    const int32_t x0 = __shfl((int)b.x, src, 64);
+    const int32_t y0 = __shfl((int)b.z, src, 64);
+    const uint32_t width = (uint32_t)(__shfl((int)b.y, src, 64) - x0 + 1);
+    const int32_t tbase = __shfl(base, src, 64);
+    const int32_t ttx = __shfl(tx, src, 64);
+    for (int64_t idx = lane; idx < n_here; idx += 64) {
+      const uint32_t row = (uint32_t)idx / width;
+      const uint32_t col = (uint32_t)idx - row * width;
+      inst_tile[o0 + idx] = (uint32_t)(tbase + (y0 + (int32_t)row) * ttx + x0 + (int32_t)col);
+      inst_rec[o0 + idx] = rr;
     }
+  }
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ header,
@@ -285,10 +329,10 @@ int64_t raster_max_items(int64_t tiles) { return max_items(tiles); }
 
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s) {
   int64_t n = std::max<int64_t>(f.nrec, 2 * f.tiles);
-  int64_t g = (n + 127) / 128;
+  int64_t g = (n + kEmitThreads - 1) / kEmitThreads;
   if (g < 1) g = 1;
-  k_emit<<<(unsigned)g, 128, 0, s>>>(sorted_rec, f.offsets, f.tiles_touched, f.rect, f.views, f.V, f.header,
-                                     f.inst_cap, f.ikey[0], f.ival[0], f.ranges, f.tiles);
+  k_emit<<<(unsigned)g, kEmitThreads, 0, s>>>(sorted_rec, f.offsets, f.tiles_touched, f.rect, f.views, f.V,
+                                              f.header, f.inst_cap, f.ikey[0], f.ival[0], f.ranges, f.tiles);
 }
 
 void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s) {

@@ -97,6 +97,37 @@ def _oracle_bins(scene, cams):
     return orc.bin_instances(views)
 
 
+def _large_footprint_scene():
+    """The 800-Gaussian tiny scene with every 7th Gaussian 7.4x larger (log-scale + 2):
+    footprints of tens of tiles up to whole small views."""
+    sc = scenes.tiny_scene(800, seed_salt=4)
+    big = np.arange(sc.n) % 7 == 0
+    sc.log_scales[big] = sc.log_scales[big] + np.float32(2.0)
+    return sc
+
+
+@pytest.mark.parametrize("sizes", [[(320, 240)], [(128, 128), (200, 120)]])
+def test_binning_bit_exact_large_footprints(rz, sizes):
+    """Records of more than 16 tiles are emitted by whole waves (lanes on consecutive
+    positions); the instance lists stay bit-exact."""
+    sc = _large_footprint_scene()
+    cams = [scenes.tiny_camera(w, h) for w, h in sizes]
+    fr = gpu_forward(rz, sc, cams)
+    ins = rz.inspect(fr)
+    tiles = ins["tiles"].cpu().numpy().view(np.uint32)
+    print("records with more than 16 tiles: %d (largest %d)" % ((tiles > 16).sum(), tiles.max()))
+    assert (tiles > 16).sum() > 20
+    keys, vals, ranges = _oracle_bins(sc, cams)
+    assert ins["info"]["instances"] == len(keys)
+    full, view = full_index_of_records(ins, len(cams))
+    it = ins["inst_tile"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    ir = ins["inst_record"].cpu().numpy().view(np.uint32).astype(np.int64)
+    dk = ins["depth_key"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal((it << np.uint64(32)) | dk[ir], keys)
+    assert np.array_equal(view[ir] * sc.n + full[ir], vals)
+    assert np.array_equal(ins["ranges"].cpu().numpy().view(np.uint32), ranges)
+
+
 @pytest.mark.parametrize("sizes", [[(128, 128)], [(100, 75)], [(128, 128), (72, 40)]])
 def test_binning_bit_exact(rz, sizes):
     sc = scenes.tiny_scene(800, seed_salt=4)
@@ -244,15 +275,18 @@ def test_views_beyond_one_argument_chunk(rz):
         check_image(fr, sc, cams[v], v=v, what="view %d of 20" % v)
 
 
-def test_instance_overflow_keeps_a_depth_prefix_and_reports(rz):
+@pytest.mark.parametrize("large", [False, True])
+def test_instance_overflow_keeps_a_depth_prefix_and_reports(rz, large):
     """A workspace that holds about half of the frame's instances: the forward cuts
     the list at the capacity, every tile keeps a prefix of its full list, and the
     frame check reports the workspace the frame needs; after growing, the frame is
-    whole again."""
+    whole again. With large footprints the cut can fall inside a record that a whole
+    wave emits."""
     import ctypes
     from paper_2503_01199_amd import _lib as L
     from paper_2503_01199_amd.raster import SceneTensors, Workspace, camera_struct
-    sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
+    sc = _large_footprint_scene() if large else scenes.tiny_scene()
+    cam = scenes.tiny_camera()
     st = SceneTensors.from_scene(sc, rz.device)
     full = rz.forward(st, [cam], workspace=Workspace(rz.device))
     fins = rz.inspect(full)
