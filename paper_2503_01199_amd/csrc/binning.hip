@@ -92,13 +92,31 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const uint32_t* __restric
   }
 }
 
+// Each thread takes four consecutive instances (one 16-byte load) and compares each
+// with its neighbours; the first and last instance of a tile write its range.
 __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ header,
                          uint32_t* __restrict__ ranges) {
+  constexpr uint32_t kNone = 0xffffffffu;  // no tile id (ids stay below 2^28)
   const int64_t M = header[kHdrInstancesKept];
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = inst_tile[k];
-    if (k == 0 || inst_tile[k - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)k;
-    if (k == M - 1 || inst_tile[k + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(k + 1);
+  const int64_t G = (M + 3) / 4;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < G; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k0 = 4 * q;
+    uint32_t t[6];  // instances k0 - 1 .. k0 + 4, kNone outside [0, M)
+    if (k0 + 4 <= M) {
+      const uint4 v = *reinterpret_cast<const uint4*>(inst_tile + k0);
+      t[1] = v.x, t[2] = v.y, t[3] = v.z, t[4] = v.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) t[1 + j] = k0 + j < M ? inst_tile[k0 + j] : kNone;
+    }
+    t[0] = k0 > 0 ? inst_tile[k0 - 1] : kNone;
+    t[5] = k0 + 4 < M ? inst_tile[k0 + 4] : kNone;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (t[1 + j] == kNone) break;
+      if (t[j] != t[1 + j]) ranges[2 * (int64_t)t[1 + j]] = (uint32_t)(k0 + j);
+      if (t[2 + j] != t[1 + j]) ranges[2 * (int64_t)t[1 + j] + 1] = (uint32_t)(k0 + j + 1);
+    }
   }
 }
 
@@ -338,7 +356,7 @@ void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream
 void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s) {
   if (M_max <= 0) return;
   // grid-stride over the count on the device; the grid covers typical frames in one sweep
-  const int64_t g = std::min<int64_t>((M_max + 255) / 256, 4096);
+  const int64_t g = std::min<int64_t>((M_max + 4 * 256 - 1) / (4 * 256), 4096);
   k_ranges<<<(unsigned)g, 256, 0, s>>>(inst_tile, f.header, f.ranges);
 }
 
