@@ -213,6 +213,7 @@ constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 items per tile
 constexpr int kHistBlocks = 512;
 constexpr int64_t kHistChunk = 8192;  // keys per histogram block at least
 constexpr int kMaxPasses = 8;
+constexpr int64_t kWideSortItems = int64_t(1) << 24;  // sorts of at least this capacity take 4096-item tiles
 
 // Lanes of the wave holding the same 8-bit digit d (restricted to `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -315,15 +316,16 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
 // scatters. The tile is first reordered by digit in LDS (reusing the counters'
 // space), so that consecutive threads store consecutive positions of each digit's
 // run: a direct per-item scatter writes 256 short runs from scattered lanes.
-template <typename K>
+template <typename K, int R>
 __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n_host, const uint32_t* __restrict__ n_dev,
                                                              int shift, const uint32_t* __restrict__ offs,
                                                              uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
-  __shared__ __align__(16) uint32_t cnt[kSortRounds][4][256];
+  constexpr int kTile = kSortThreads * R;  // items per tile: R rounds of one item per thread
+  __shared__ __align__(16) uint32_t cnt[R][4][256];
   __shared__ uint32_t gofs[256], ldig[256], wtot[4];
-  static_assert(sizeof(K) * kSortTile + 4 * kSortTile <= sizeof(uint32_t) * kSortRounds * 4 * 256,
+  static_assert(sizeof(K) * kTile + 4 * kTile <= sizeof(uint32_t) * R * 4 * 256,
                 "the staged tile fits in the counters' space");
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
@@ -331,35 +333,35 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
   const int lane = t & 63;
   {
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * kSortTile;
+    const int64_t base = tile * kTile;
     if (base >= n) return;  // uniform over the block
-    for (int r = 0; r < kSortRounds; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) cnt[r][q][t] = 0;
     __syncthreads();
-    K key[kSortRounds];
-    uint32_t val[kSortRounds];
-    uint32_t dig[kSortRounds];
-    uint32_t rank[kSortRounds];
+    K key[R];
+    uint32_t val[R];
+    uint32_t dig[R];
+    uint32_t rank[R];
     // every round's loads first (indices clamped into range, so none sits behind a
     // branch and their round trips overlap), then the ranking
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int64_t i = base + r * kSortThreads + t;
       key[r] = kin[i < n ? i : n - 1];
     }
     if (vin) {
 #pragma unroll
-      for (int r = 0; r < kSortRounds; ++r) {
+      for (int r = 0; r < R; ++r) {
         const int64_t i = base + r * kSortThreads + t;
         val[r] = vin[i < n ? i : n - 1];
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < kSortRounds; ++r) val[r] = (uint32_t)(base + r * kSortThreads + t);
+      for (int r = 0; r < R; ++r) val[r] = (uint32_t)(base + r * kSortThreads + t);
     }
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
+    for (int r = 0; r < R; ++r) {
       const int64_t i = base + r * kSortThreads + t;
       const bool valid = i < n;
       dig[r] = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
@@ -370,14 +372,14 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
     __syncthreads();
     // thread d: exclusive running count of digit d over (round, wave), then the tile total
     uint32_t run = 0;
-    for (int r = 0; r < kSortRounds; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t c = cnt[r][q][t];
         cnt[r][q][t] = run;
         run += c;
       }
-    const int64_t tiles = (n_host + kSortTile - 1) / kSortTile;
+    const int64_t tiles = (n_host + kTile - 1) / kTile;
     const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err);
     gofs[t] = offs[t] + prior;
     // tile-local digit offsets: exclusive scan over the digits of the tile's totals
@@ -388,22 +390,22 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
     for (int q = 0; q < w; ++q) woff += wtot[q];
     ldig[t] = woff + incl - run;
     __syncthreads();
-    uint32_t lpos[kSortRounds];  // position in the tile sorted by digit (stable)
+    uint32_t lpos[R];  // position in the tile sorted by digit (stable)
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r)
+    for (int r = 0; r < R; ++r)
       lpos[r] = dig[r] < 256u ? ldig[dig[r]] + cnt[r][w][dig[r]] + rank[r] : 0xffffffffu;
     __syncthreads();  // the counters are consumed: their space takes the staged tile
     K* s_key = reinterpret_cast<K*>(&cnt[0][0][0]);
-    uint32_t* s_val = reinterpret_cast<uint32_t*>(s_key + kSortTile);
+    uint32_t* s_val = reinterpret_cast<uint32_t*>(s_key + kTile);
 #pragma unroll
-    for (int r = 0; r < kSortRounds; ++r) {
-      if (lpos[r] < (uint32_t)kSortTile) {
+    for (int r = 0; r < R; ++r) {
+      if (lpos[r] < (uint32_t)kTile) {
         s_key[lpos[r]] = key[r];
         s_val[lpos[r]] = val[r];
       }
     }
     __syncthreads();
-    const int nv = (int)min<int64_t>(kSortTile, n - base);
+    const int nv = (int)min<int64_t>(kTile, n - base);
     for (int q = t; q < nv; q += kSortThreads) {
       const K k = s_key[q];
       const uint32_t d = (uint32_t)(k >> shift) & 255u;
@@ -423,7 +425,13 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   uint32_t* offs = ctl + kMaxPasses * 256;    // [passes][256]
   uint32_t* done = offs + kMaxPasses * 256;   // 1 word (padded to 64)
   uint32_t* pass_ctl = done + 64;             // per pass: 64 reserved words, tile then group status [.][256]
-  const int64_t tiles = (n_max + kSortTile - 1) / kSortTile;
+  // Large sorts take 4096-item tiles: each 8-bit digit of a tile then leaves in runs
+  // of ~16 items instead of ~8, and the look-back has half the tiles. Small sorts
+  // keep 2048, which gives more blocks. The control words are sized for 2048-item
+  // tiles, which bounds both.
+  const bool wide = n_max >= kWideSortItems;
+  const int64_t tile_items = wide ? 2 * kSortTile : kSortTile;
+  const int64_t tiles = (n_max + tile_items - 1) / tile_items;
   const int64_t pass_words = 64 + (tiles + (tiles + kGroup - 1) / kGroup) * 256;
   int64_t hb = (n_max + kHistChunk - 1) / kHistChunk;
   if (hb > kHistBlocks) hb = kHistBlocks;
@@ -436,8 +444,12 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   const uint32_t* vcur = vals_in;
   int out = 0;
   for (int p = 0; p < passes; ++p) {
-    k_os_scatter<K><<<(unsigned)tiles, kSortThreads, 0, s>>>(kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p,
-                                                             offs + p * 256, pass_ctl + p * pass_words, err);
+    if (wide)
+      k_os_scatter<K, 2 * kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
+          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err);
+    else
+      k_os_scatter<K, kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
+          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err);
     kcur = kb[out];
     vcur = vb[out];
     out ^= 1;

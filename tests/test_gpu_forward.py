@@ -151,6 +151,38 @@ def test_binning_bit_exact(rz, sizes):
     assert np.array_equal(gr, ranges)
 
 
+def test_binning_bit_exact_wide_sort_tiles(rz):
+    """A workspace sized for 2^24 + 5 instances: the tile sort takes its large-sort
+    tiles (4096 items per block) while the frame holds a few thousand instances. The
+    lists stay bit-exact."""
+    import ctypes
+    from paper_2503_01199_amd import _lib as L
+    from paper_2503_01199_amd.raster import SceneTensors, Workspace, camera_struct
+    sc = scenes.tiny_scene(800, seed_salt=4)
+    cams = [scenes.tiny_camera(128, 128), scenes.tiny_camera(72, 40)]
+    st = SceneTensors.from_scene(sc, rz.device)
+    cs = (L.GsrCamera * len(cams))(*[camera_struct(c) for c in cams])
+    nbytes = ctypes.c_size_t()
+    rz._check(rz.lib.gsr_workspace_size(rz.ctx, ctypes.byref(st.struct()), cs, len(cams),
+                                        ctypes.byref(rz.options(L.GSR_FP32, True, True, False)), (1 << 24) + 5,
+                                        ctypes.byref(nbytes)), "gsr_workspace_size")
+    ws = Workspace(rz.device)
+    ws.ensure(nbytes.value)
+    print("wide tile sort: workspace %d bytes" % nbytes.value, flush=True)
+    fr = rz.forward(st, cams, workspace=ws)
+    torch.cuda.synchronize()
+    ins = rz.inspect(fr)
+    keys, vals, ranges = _oracle_bins(sc, cams)
+    assert ins["info"]["instances"] == len(keys)
+    full, view = full_index_of_records(ins, len(cams))
+    it = ins["inst_tile"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    ir = ins["inst_record"].cpu().numpy().view(np.uint32).astype(np.int64)
+    dk = ins["depth_key"].cpu().numpy().view(np.uint32).astype(np.uint64)
+    assert np.array_equal((it << np.uint64(32)) | dk[ir], keys)
+    assert np.array_equal(view[ir] * sc.n + full[ir], vals)
+    assert np.array_equal(ins["ranges"].cpu().numpy().view(np.uint32), ranges)
+
+
 def test_pixel_state_matches_tiled_oracle(rz):
     sc, cam = scenes.tiny_scene(), scenes.tiny_camera()
     sc.opacity_logits[:] = sc.opacity_logits + 2.0  # reach the T stop on many pixels

@@ -29,6 +29,20 @@ def test_morton_codes_and_order_bit_exact(rz, n):
     assert np.array_equal(perm.cpu().numpy(), ref_perm)
 
 
+def test_morton_order_wide_sort_tiles(rz):
+    """2^24 + 3 points: the 64-bit code sort takes its large-sort tiles (4096 items
+    per block, 8 passes). Points on a coarse grid, so many codes repeat and the
+    stable order of equal codes is exercised in every pass."""
+    n = (1 << 24) + 3
+    rng = np.random.default_rng(11)
+    means = (rng.integers(0, 300, size=(n, 3)) * np.float32(0.01) - np.float32(1.5)).astype(np.float32)
+    print("morton n=%d" % n, flush=True)
+    perm, codes = rz.morton_order(torch.as_tensor(means, device=rz.device))
+    ref_codes, ref_perm = orc.morton(means)
+    assert np.array_equal(codes.cpu().numpy().view(np.uint64), ref_codes)
+    assert np.array_equal(perm.cpu().numpy(), ref_perm)
+
+
 def test_morton_degenerate_axis(rz):
     m = np.zeros((300, 3), np.float32)
     m[:, 0] = np.linspace(-1, 1, 300)  # y and z constant
