@@ -213,7 +213,7 @@ constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 items per tile
 constexpr int kHistBlocks = 512;
 constexpr int64_t kHistChunk = 8192;  // keys per histogram block at least
 constexpr int kMaxPasses = 8;
-constexpr int64_t kWideSortItems = int64_t(1) << 24;  // sorts of at least this capacity take 4096-item tiles
+constexpr int64_t kWideSortItems = int64_t(1) << 24;  // from this capacity: 4096-item tiles, 16-byte histogram loads
 
 // Lanes of the wave holding the same 8-bit digit d (restricted to `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -252,6 +252,40 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
   const int lane = t & 63;
   for (int p = 0; p < passes; ++p) h[p][t] = 0;
   __syncthreads();
+  if constexpr (!kRuns && sizeof(K) == 4) {
+    // Large sorts of 32-bit keys: four per 16-byte load, so a thread has 32 keys in
+    // flight (two blocks per CU with one key per load leave too few bytes in flight
+    // for HBM). Small sorts keep one key per load, which spreads them over more
+    // iterations.
+    if (n_host >= kWideSortItems && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+      constexpr int64_t kStep = (int64_t)kSortTile * 4;
+      for (int64_t base = (int64_t)blockIdx.x * kStep; base < n; base += nb * kStep) {
+        uint4 q[kSortRounds];
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+          const int64_t i = base + 4 * ((int64_t)r * kSortThreads + t);
+          if (i + 3 < n) {
+            q[r] = *reinterpret_cast<const uint4*>(keys + i);
+          } else {
+            q[r].x = (uint32_t)keys[i < n ? i : n - 1];
+            q[r].y = (uint32_t)keys[i + 1 < n ? i + 1 : n - 1];
+            q[r].z = (uint32_t)keys[i + 2 < n ? i + 2 : n - 1];
+            q[r].w = (uint32_t)keys[i + 3 < n ? i + 3 : n - 1];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kSortRounds; ++r) {
+          const int64_t i = base + 4 * ((int64_t)r * kSortThreads + t);
+          const uint32_t e[4] = {q[r].x, q[r].y, q[r].z, q[r].w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (i + c < n)
+              for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(e[c] >> (8 * p)) & 255u], 1u);
+        }
+      }
+      goto merge;
+    }
+  }
   for (int64_t base = (int64_t)blockIdx.x * kSortTile; base < n; base += nb * kSortTile) {
     if constexpr (!kRuns) {
       K key[kSortRounds];
@@ -289,6 +323,7 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
       if (run) atomicAdd(&h[p][prev], run);
     }
   }
+merge:
   __syncthreads();
   for (int p = 0; p < passes; ++p)
     if (h[p][t]) atomicAdd(&hist[p * 256 + t], h[p][t]);
