@@ -308,6 +308,8 @@ struct PixelResult {
   double T;
   int n_contrib;    // position of the last blended entry + 1 (0 if none)
   int n_blended;
+  int64_t last;     // Gaussian of the last blended entry (-1 if none)
+  int64_t stop;     // Gaussian whose blend would have taken T below 1e-4 (-1 if the list ran out)
   std::vector<Frag> blended;
   std::vector<int64_t> fragile_at;  // Gaussians whose decision here is within rounding
 };
@@ -329,6 +331,8 @@ void composite(const std::vector<Proj>& P, const std::vector<int64_t>& list, int
   r.T = 1.0;
   r.n_contrib = 0;
   r.n_blended = 0;
+  r.last = -1;
+  r.stop = -1;
   r.blended.clear();
   r.fragile_at.clear();
   for (int pos = 0; pos < (int)list.size(); ++pos) {
@@ -347,12 +351,16 @@ void composite(const std::vector<Proj>& P, const std::vector<int64_t>& list, int
     const double Tn = r.T * (1.0 - alpha);
     frag = frag || std::fabs(Tn / kTMin - 1.0) < kFragT;
     if (frag) r.fragile_at.push_back(list[pos]);
-    if (Tn < kTMin) break;
+    if (Tn < kTMin) {
+      r.stop = list[pos];
+      break;
+    }
     if (keep) r.blended.push_back(Frag{list[pos], pos, G, araw, alpha, r.T, dx, dy});
     for (int ch = 0; ch < 3; ++ch) r.rgb[ch] += r.T * alpha * p.rgb[ch];
     r.T = Tn;
     r.n_contrib = pos + 1;
     r.n_blended++;
+    r.last = list[pos];
   }
   for (int ch = 0; ch < 3; ++ch) r.rgb[ch] += r.T * cam.bg[ch];
 }
@@ -645,13 +653,25 @@ void orc_render(int64_t n, int deg, const float* means, const float* ls, const f
 //   d_means f64[n,3], d_log_scales f64[n,3], d_quats f64[n,4], d_logits f64[n],
 //   d_sh f64[n,K,3], g2d f64[n,9] (u, v, a, b, c, o, r, g, b),
 //   S f64[n], M f64[n], C i64[n] (opacity-gradient statistic, Sec. 3.3),
-//   gfrag u8[n] (1 if the Gaussian appears in the list of a fragile pixel).
+//   gfrag u8[n] (1 if the Gaussian appears in the list of a fragile pixel),
+//   C_slack i64[n] (by how much an FP32 walk may legitimately differ from C).
 // The statistic sums over blended (pixel, Gaussian) pairs; the per-pixel
 // gradient is taken w.r.t. the activated opacity o.
+//
+// C_slack: at a pixel with a fragile decision, an FP32 walk may take that decision
+// the other way. An alpha test or a T-stop test that flips adds or removes its own
+// entry. An alpha test or a 0.99 clamp that flips changes every later T of the
+// pixel by at most a factor (1 - 1/255) or 1 +- 2e-3, which can move the pixel's
+// stop by one entry: the last blended entry may become the stop, or the stop
+// entry may be blended (the next visible entry then stops, its T being within
+// rounding of 1e-4 times at most 1 - 1/255). Every other entry keeps its decision.
+// So each fragile pixel adds 1 to the slack of each of its fragile subjects, of
+// its last blended entry and of its stop entry (once per Gaussian per pixel).
 void orc_backward(int64_t n, int deg, const float* means, const float* ls, const float* q, const float* lo,
                   const float* sh, const double* camp, int mode, int x_lo, int x_hi, int y_lo, int y_hi,
                   int threads, const double* dL_dI, double* d_means, double* d_ls, double* d_q, double* d_logit,
-                  double* d_sh, double* g2d, double* S, double* M, int64_t* C, uint8_t* gfrag) {
+                  double* d_sh, double* g2d, double* S, double* M, int64_t* C, uint8_t* gfrag,
+                  int64_t* C_slack) {
   Scene sc = make_scene(n, deg, means, ls, q, lo, sh);
   Camera cam = unpack_camera(camp);
   std::vector<Proj> P;
@@ -662,6 +682,7 @@ void orc_backward(int64_t n, int deg, const float* means, const float* ls, const
   const int nt = n_threads(threads);
   std::vector<std::vector<Grad2D>> acc(nt, std::vector<Grad2D>(n, Grad2D{0, 0, 0, 0, 0, 0, {0, 0, 0}, 0, 0, 0}));
   std::vector<std::vector<uint8_t>> fr(nt, std::vector<uint8_t>(n, 0));
+  std::vector<std::vector<int64_t>> slack(nt, std::vector<int64_t>(n, 0));
   parallel_rows(y_lo, y_hi, nt, [&](int t, int py) {
     std::vector<int64_t> list;
     PixelResult r;
@@ -675,6 +696,12 @@ void orc_backward(int64_t n, int deg, const float* means, const float* ls, const
       if (!r.fragile_at.empty()) {
         for (int64_t g : r.fragile_at) fr[t][g] = 1;
         for (const Frag& f : r.blended) fr[t][f.g] = 1;
+        std::vector<int64_t> who(r.fragile_at);
+        if (r.last >= 0) who.push_back(r.last);
+        if (r.stop >= 0) who.push_back(r.stop);
+        std::sort(who.begin(), who.end());
+        who.erase(std::unique(who.begin(), who.end()), who.end());
+        for (int64_t g : who) slack[t][g] += 1;
       }
       const double gI[3] = {dL_dI[o], dL_dI[(size_t)H * W + o], dL_dI[(size_t)2 * H * W + o]};
       const int nb = (int)r.blended.size();
@@ -723,7 +750,9 @@ void orc_backward(int64_t n, int deg, const float* means, const float* ls, const
   for (int64_t i = 0; i < n; ++i) {
     Grad2D g{0, 0, 0, 0, 0, 0, {0, 0, 0}, 0, 0, 0};
     uint8_t f = 0;
+    C_slack[i] = 0;
     for (int t = 0; t < nt; ++t) {
+      C_slack[i] += slack[t][i];
       const Grad2D& a = acc[t][i];
       g.u += a.u; g.v += a.v; g.a += a.a; g.b += a.b; g.c += a.c; g.o += a.o;
       for (int ch = 0; ch < 3; ++ch) g.rgb[ch] += a.rgb[ch];

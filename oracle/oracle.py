@@ -117,7 +117,11 @@ def render(scene, cam, mode: int = 1, window=None, threads: int = 0) -> dict:
 
 
 def backward(scene, cam, dL_dI, mode: int = 1, window=None, threads: int = 0) -> dict:
-    """Analytic FP64 backward of render() for upstream gradient dL_dI [3,H,W]."""
+    """Analytic FP64 backward of render() for upstream gradient dL_dI [3,H,W].
+    Besides the gradients and the statistic (S, M, C), returns `fragile` (the
+    Gaussian is in the list of a pixel with a fragile decision) and `C_slack`, the
+    number of fragile pixels at which the Gaussian's blend decision may flip in FP32:
+    |C_fp32 - C| <= C_slack for every Gaussian."""
     lib = load()
     arrs, args = _scene_args(scene)
     n = arrs[0].shape[0]
@@ -126,13 +130,14 @@ def backward(scene, cam, dL_dI, mode: int = 1, window=None, threads: int = 0) ->
     assert g.shape == (3, cam.height, cam.width)
     out = dict(means=np.zeros((n, 3)), log_scales=np.zeros((n, 3)), quats=np.zeros((n, 4)),
                opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)), g2d=np.zeros((n, 9)),
-               S=np.zeros(n), M=np.zeros(n), C=np.zeros(n, dtype=np.int64), fragile=np.zeros(n, dtype=np.uint8))
+               S=np.zeros(n), M=np.zeros(n), C=np.zeros(n, dtype=np.int64), fragile=np.zeros(n, dtype=np.uint8),
+               C_slack=np.zeros(n, dtype=np.int64))
     ca = camera_array(cam)
     x0, x1, y0, y1 = _window(cam, window)
     lib.orc_backward(*args, _p(ca), ctypes.c_int(mode), ctypes.c_int(x0), ctypes.c_int(x1), ctypes.c_int(y0),
                      ctypes.c_int(y1), ctypes.c_int(threads), _p(g), _p(out["means"]), _p(out["log_scales"]),
                      _p(out["quats"]), _p(out["opacity_logits"]), _p(out["sh"]), _p(out["g2d"]), _p(out["S"]),
-                     _p(out["M"]), _p(out["C"]), _p(out["fragile"]))
+                     _p(out["M"]), _p(out["C"]), _p(out["fragile"]), _p(out["C_slack"]))
     out["fragile"] = out["fragile"].astype(bool)
     return out
 

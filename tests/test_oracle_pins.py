@@ -242,6 +242,117 @@ def test_footprint_contains_every_contributing_pixel(orc):
         assert tx.min() >= x0 and tx.max() <= x1 and ty.min() >= y0 and ty.max() <= y1
 
 
+def test_footprint_is_the_smallest_box_of_the_alpha_ellipse(orc):
+    """Rect minimality (App. A.1 tile culling; support reading: the rect is the tile
+    cover of the pixel-centre bounding box of the alpha >= 1/255 ellipse). Brute force
+    per pixel-centre column: the vertical line x = px + 1/2 meets the ellipse
+    d^T Q d <= 2 ln(255 o) exactly when the minimum of the quadratic form over y, taken
+    at dy = -b dx / c and evaluated from the conic, is within that bound; rows
+    likewise. The footprint must be exactly the range of such columns times the range
+    of such rows, clipped to the image: a wider rect (an off-by-one in a ceil or floor,
+    a 3-sigma radius, the other axis's variance) fails, as does a narrower one."""
+    sc = scenes.tiny_scene(400, seed_salt=6)
+    W, H = 96, 80
+    cam = scenes.tiny_camera(W, H)
+    pp = orc.preprocess(sc, cam)
+    cols = np.arange(W) + 0.5
+    rows = np.arange(H) + 0.5
+    checked = wide = 0
+    for i in range(sc.n):
+        if not (pp["tcam"][i, 2] > 0.2) or not (pp["opacity"][i] >= 1 / 255):
+            continue
+        a, b, c = pp["conic"][i]
+        if not (a > 0 and c > 0 and a * c - b * b > 0):
+            continue
+        K = 2.0 * math.log(255.0 * pp["opacity"][i])
+        dx = pp["u"][i] - cols
+        dys = -b * dx / c
+        qx = a * dx * dx + 2 * b * dx * dys + c * dys * dys
+        dy = pp["v"][i] - rows
+        dxs = -b * dy / a
+        qy = a * dxs * dxs + 2 * b * dxs * dy + c * dy * dy
+        if np.any(np.abs(qx - K) <= 1e-9 * K) or np.any(np.abs(qy - K) <= 1e-9 * K):
+            continue  # a column or row within rounding of the boundary
+        cin, rin = np.nonzero(qx <= K)[0], np.nonzero(qy <= K)[0]
+        if cin.size == 0 or rin.size == 0:
+            assert not pp["valid"][i], i
+            continue
+        assert pp["valid"][i], i
+        exp = (cin.min() // 16, cin.max() // 16, rin.min() // 16, rin.max() // 16)
+        assert tuple(pp["rect"][i]) == exp, (i, tuple(pp["rect"][i]), exp)
+        assert pp["tiles"][i] == (exp[1] - exp[0] + 1) * (exp[3] - exp[2] + 1)
+        wide += int(cin.max() - cin.min() >= 16 or rin.max() - rin.min() >= 16)
+        checked += 1
+    assert checked > 200 and wide > 20
+
+
+def _stack_scene(opacities, depths, log_scale=math.log(3.0)):
+    """Large flat Gaussians on the optical axis: G = 1 exactly at the centre pixel of
+    _cam(32, 32, f=32, cx=cy=16.5) (pixel 16's centre is on the axis)."""
+    n = len(opacities)
+    return _one_gaussian([[0, 0, d] for d in depths], log_scale, [1, 0, 0, 0], opacities, [[0.5, 0.5, 0.5]] * n)
+
+
+def _crossing(orc, sc, cam, idx, lo, hi, flipped):
+    """Adjacent FP32 opacity logits (x_a, x_b) of Gaussian idx between lo and hi across
+    which flipped(render) changes (bisection on the FP32 bit patterns)."""
+    f = lambda x: flipped(orc.render(_set(sc, "opacity_logits", idx, np.float32(x)), cam, mode=0, threads=1))  # noqa: E731
+    def key(x):  # integers ordered like the FP32 values
+        k = int(np.float32(x).view(np.int32))
+        return k if k >= 0 else -(k & 0x7FFFFFFF)
+
+    def val(k):
+        return np.int32(k if k >= 0 else (-k) | -0x80000000).view(np.float32)
+
+    a, b = np.float32(lo), np.float32(hi)
+    fa = f(a)
+    assert fa != f(b)
+    ia, ib = key(a), key(b)
+    while ib - ia > 1:
+        im = (ia + ib) // 2
+        if f(val(im)) == fa:
+            ia = im
+        else:
+            ib = im
+    return val(ia), val(ib)
+
+
+def _check_slack_across(orc, sc, cam, idx, xa, xb):
+    """Fragment counts on both sides of a flip differ by at most the slack either side
+    reports (C_slack), for every Gaussian; returns the total change."""
+    g = np.ones((3, cam.height, cam.width))
+    ba = orc.backward(_set(sc, "opacity_logits", idx, xa), cam, g, mode=0, threads=1)
+    bb = orc.backward(_set(sc, "opacity_logits", idx, xb), cam, g, mode=0, threads=1)
+    d = np.abs(ba["C"] - bb["C"])
+    assert np.all(d <= np.maximum(ba["C_slack"], bb["C_slack"])), (d, ba["C_slack"], bb["C_slack"])
+    return int(d.sum())
+
+
+def test_fragment_count_slack_covers_a_transmittance_stop_flip(orc):
+    """Four stacked Gaussians whose last one's blend takes T across 1e-4 at the centre
+    pixel as its opacity grows: at the flip the count of that Gaussian changes by one,
+    and C_slack (the FP32 allowance on C) covers it on both sides."""
+    cam = _cam(W=32, H=32, f=32.0, cx=16.5, cy=16.5)
+    sc = _stack_scene([0.8, 0.8, 0.8, 0.98], [2.0, 2.1, 2.2, 2.3])
+    xa, xb = _crossing(orc, sc, cam, 3, math.log(0.98 / 0.02), math.log(0.989 / 0.011),
+                       lambda r: int(r["n_blended"][16, 16]))
+    assert _check_slack_across(orc, sc, cam, 3, xa, xb) == 1
+
+
+def test_fragment_count_slack_covers_an_alpha_flip_that_moves_the_stop(orc):
+    """A faint Gaussian in front of a stack whose walk stops just after its 4th entry
+    (T' 0.2 % above 1e-4): when the faint one's alpha crosses 1/255 at the centre
+    pixel it is blended, which takes the stack's 4th T' below 1e-4, so two counts
+    change at once (the faint one's up, the 4th's down). C_slack covers both."""
+    cam = _cam(W=32, H=32, f=32.0, cx=16.5, cy=16.5)
+    o4 = 1.0 - 1.002e-4 / 0.2 ** 3
+    sc = _stack_scene([1.0 / 255, 0.8, 0.8, 0.8, o4], [1.9, 2.0, 2.1, 2.2, 2.3])
+    lo = math.log((0.99 / 255) / (1 - 0.99 / 255))
+    hi = math.log((1.01 / 255) / (1 - 1.01 / 255))
+    xa, xb = _crossing(orc, sc, cam, 0, lo, hi, lambda r: bool(r["T"][16, 16] < 1e-3))
+    assert _check_slack_across(orc, sc, cam, 0, xa, xb) == 2
+
+
 # ------------------------------------------------------------------ P5: scanline algebra
 def test_scanline_identity():
     """Basic + Linear j + Quad j^2 equals the exponent at (dx, dy - j) (App. A.2, Eq. (8)-(9))."""
