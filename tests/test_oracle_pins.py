@@ -132,6 +132,40 @@ def test_single_anisotropic_and_off_axis_closed_form(orc):
     assert pp["conic"][0] == pytest.approx([inv[0, 0], inv[0, 1], inv[1, 1]], rel=1e-12)
 
 
+def test_needle_closed_form(orc):
+    """A 1:100 needle on the optical axis, rotated about it by 30 degrees: its screen
+    covariance is (f/z)^2 R2 diag(s1^2, s2^2) R2^T + 0.3 I with R2 the in-plane
+    rotation (the Jacobian at an on-axis mean is diag(f/z, f/z) on x, y), so the
+    image is o exp(-d^T cov^-1 d / 2) c. The long axis spans 20 px, the short one
+    is set by the 0.3 px^2 dilation: the screen covariance's condition number is
+    about 1200, the FP32 conditioning case of the projection."""
+    z, f, th = 3.0, 64.0, math.radians(30.0)
+    s1 = 20.0 * z / f
+    q = [math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)]
+    sc = _one_gaussian([0, 0, z], [math.log(s1), math.log(s1 / 100), math.log(s1 / 100)], q, 0.8, [0.9, 0.4, 0.2])
+    cam = _cam(W=64, H=64, f=f)
+    out = orc.render(sc, cam, mode=0)
+    s = np.exp(sc.log_scales[0].astype(np.float64))
+    qq = sc.quats[0].astype(np.float64)
+    qq /= np.linalg.norm(qq)
+    c2, s2 = qq[0] ** 2 - qq[3] ** 2, 2 * qq[0] * qq[3]  # cos and sin of the in-plane angle
+    R2 = np.array([[c2, -s2], [s2, c2]])
+    zf = float(np.float32(z))
+    cov = (f / zf) ** 2 * R2 @ np.diag(s[:2] ** 2) @ R2.T + 0.3 * np.eye(2)
+    assert np.linalg.cond(cov) > 1000
+    inv = np.linalg.inv(cov)
+    py, px = np.mgrid[0:64, 0:64]
+    dx, dy = px + 0.5 - 32, py + 0.5 - 32
+    e = -0.5 * (inv[0, 0] * dx * dx + 2 * inv[0, 1] * dx * dy + inv[1, 1] * dy * dy)
+    o32 = 1 / (1 + math.exp(-float(sc.opacity_logits[0])))
+    a = o32 * np.exp(e)
+    a = np.where(a >= 1 / 255, np.minimum(a, 0.99), 0.0)
+    c32 = 0.5 + sc.sh[0, 0].astype(np.float64) / (2 * math.sqrt(math.pi))
+    assert np.abs(out["image"] - a[None] * c32[:, None, None]).max() < 1e-12
+    pp = orc.preprocess(sc, cam)
+    assert pp["cov"][0] == pytest.approx([cov[0, 0], cov[0, 1], cov[1, 1]], rel=1e-12)
+
+
 def test_rotated_gaussian_covariance(orc):
     # 90 degrees about z swaps the x and y scales
     q = [math.cos(math.pi / 4), 0, 0, math.sin(math.pi / 4)]
@@ -206,6 +240,37 @@ def test_alpha_skip_and_clamp(orc):
     out = orc.render(sc, cam, mode=0)
     assert out["image"].max() == 0.0
     assert not orc.preprocess(sc, cam)["valid"][0]
+
+
+def test_alpha_clamp_has_zero_derivative(orc):
+    """Where o G > 0.99 the clamp holds alpha at 0.99, so a loss over those pixels
+    alone does not change when the opacity or the mean moves a little: the
+    analytic gradient must vanish and central differences agree. A second
+    Gaussian behind makes the front alpha matter (it sets the back one's T)."""
+    cam = _cam(W=32, H=32, f=32.0, cx=16.5, cy=16.5, bg=(0.2, 0.3, 0.1))
+    sc = _one_gaussian([[0, 0, 2.0], [0.05, 0.0, 3.0]], math.log(3.0), [1, 0, 0, 0], [0.999, 0.6],
+                       [[0.9, 0.2, 0.4], [0.1, 0.8, 0.3]])
+    pp = orc.preprocess(sc, cam)
+    py, px = np.mgrid[0:32, 0:32]
+    dx, dy = px + 0.5 - pp["u"][0], py + 0.5 - pp["v"][0]
+    a, b, c = pp["conic"][0]
+    G = np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
+    clamped = pp["opacity"][0] * G > 0.995  # a margin past 0.99 that no small step crosses
+    assert clamped.sum() > 50
+    g = np.where(clamped[None], 1.0, 0.0) * np.array([0.7, -0.4, 0.9])[:, None, None]
+    bw = orc.backward(sc, cam, g, mode=0, threads=1)
+    for field in ("means", "opacity_logits"):
+        assert np.abs(bw[field][0]).max() < 1e-12, field
+        arr = getattr(sc, field)
+        for idx in range(arr[0].size):
+            flat = np.ravel_multi_index((0,) + np.unravel_index(idx, arr[0].shape), arr.shape) if arr.ndim > 1 else 0
+            x = np.float32(arr.reshape(-1)[flat])
+            h = np.float32(max(1.0, abs(float(x))) * 1e-4)
+            Lp, _ = _loss(orc, _set(sc, field, flat, np.float32(x + h)), cam, g)
+            Lm, _ = _loss(orc, _set(sc, field, flat, np.float32(x - h)), cam, g)
+            assert abs(Lp - Lm) < 1e-12, (field, idx, Lp - Lm)
+    # the back Gaussian's gradient does not vanish (the loss does see it)
+    assert np.abs(bw["opacity_logits"][1]) > 1e-3
 
 
 # ------------------------------------------------------------------ P4: brute force = tiled
