@@ -96,15 +96,17 @@ typedef struct {
                            frusta and compact the visible ones (Sec. 3.2.2); 0: keep all */
   int32_t stats;        /* 1: gsr_backward accumulates the statistic into gsr_stats */
   int32_t deterministic; /* 1: the backward adds the per-tile gradient sums (App. A.1's
-                           f_global) as 64-bit fixed-point integers with 32 fraction bits
-                           instead of FP32 atomics (the integer reduction of Sec. 3.1.2,
-                           carried to the device-wide sum), so gradients and statistic
-                           are bitwise reproducible whatever the order in which tiles
-                           finish (for one raster schedule, see gsr_set_raster_split).
-                           Each per-tile sum is rounded to a multiple of 2^-32 and
-                           saturates at 2^31 in magnitude. The workspace grows by 96 B
-                           per record; forward and backward must agree. 0: FP32
-                           atomics. */
+                           f_global) as 64-bit fixed-point integers instead of FP32
+                           atomics (the integer reduction of Sec. 3.1.2, carried to the
+                           device-wide sum, with one exponent shared by all tiles), so
+                           gradients and statistic are bitwise reproducible whatever
+                           the order in which tiles finish (for one raster schedule,
+                           see gsr_set_raster_split). With 2^E the power of two just
+                           above max |dL/dI| over the frame (E clamped to [-44, 44]),
+                           each per-tile sum is rounded to a multiple of 2^(E-32)
+                           (the statistic's square sum: 2^(2E-32)) and saturates at
+                           2^31 times that power. The workspace grows by 96 B per
+                           record; forward and backward must agree. 0: FP32 atomics. */
 } gsr_options;
 
 /* Parameter gradients, device memory, the shapes of gsr_scene's arrays. Overwritten
@@ -411,6 +413,26 @@ gsr_status gsr_opacity_decay(gsr_context *ctx, float *opacity_logits, int64_t n,
  * pixels exactly as the whole tile does); gradients only through rounding (a tile
  * walked as two halves adds two per-item sums instead of one). */
 gsr_status gsr_set_raster_split(gsr_context *ctx, uint32_t split_len, uint32_t split_len_bwd);
+
+/* Failure injection for tests of the error path (no caller needs it otherwise).
+ * The frames this context prepares from now on:
+ *   GSR_FAULT_NONE             render normally (the default);
+ *   GSR_FAULT_ABORT_BEFORE_SORT raise the abort bit of the frame's error word right
+ *                              before the depth sort;
+ *   GSR_FAULT_WITHHOLD_STATUS  in the first pass of the tile sort, the block of tile 1
+ *                              never publishes its look-back status, so every later
+ *                              tile's wait can only end by its time bound (100 ms).
+ * Every kernel still exits normally: device-wide waits are bounded by elapsed time,
+ * the first one to run out raises the abort bit, every other wait and every later
+ * kernel of the frame reads it and leaves, and gsr_frame_inspect then returns
+ * GSR_ERR_DEVICE. The next frame prepared on the workspace starts with a clear
+ * error word. Returns GSR_ERR_INVALID_ARG for an unknown mode. */
+typedef enum {
+  GSR_FAULT_NONE = 0,
+  GSR_FAULT_ABORT_BEFORE_SORT = 1,
+  GSR_FAULT_WITHHOLD_STATUS = 2
+} gsr_fault;
+gsr_status gsr_set_fault_injection(gsr_context *ctx, int32_t mode);
 
 /* Stages of gsr_forward and gsr_backward, in launch order. */
 typedef enum {

@@ -17,6 +17,9 @@ GSR_ERR_DEVICE = 3
 GSR_ERR_UNSUPPORTED = 4
 GSR_FP32 = 0
 GSR_FP16_BLEND = 1
+GSR_FAULT_NONE = 0
+GSR_FAULT_ABORT_BEFORE_SORT = 1
+GSR_FAULT_WITHHOLD_STATUS = 2
 GSR_TILE = 16
 GSR_CLUSTER = 128
 GSR_MAX_VIEWS = 64
@@ -120,6 +123,7 @@ EXPORTS = {
     "gsr_opacity_decay": (c_int32, [c_void_p, c_void_p, c_int64, c_float, c_void_p]),
     "gsr_set_raster_split": (c_int32, [c_void_p, ctypes.c_uint32, ctypes.c_uint32]),
     "gsr_set_profiling": (c_int32, [c_void_p, c_int32]),
+    "gsr_set_fault_injection": (c_int32, [c_void_p, c_int32]),
     "gsr_stage_times": (c_int32, [c_void_p, ctypes.POINTER(c_float)]),
 }
 

@@ -45,6 +45,7 @@ struct gsr_context {
   bool recorded[GSR_STAGE_COUNT] = {};
   uint32_t split_len = gsr::kSplitLen;          // raster schedules of the frames prepared from now on
   uint32_t split_len_bwd = gsr::kSplitLenBwd;
+  int32_t fault = GSR_FAULT_NONE;               // failure injection of the frames prepared from now on
 };
 
 namespace {
@@ -404,6 +405,7 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
     StageScope sc_(ctx, GSR_STAGE_DEPTH_SORT, s);
     uint32_t* kb[2] = {f.skey[0], f.skey[1]};
     uint32_t* vb[2] = {f.sval[0], f.sval[1]};
+    if (ctx->fault == GSR_FAULT_ABORT_BEFORE_SORT) gsr::raise_abort(err, s);
     const int r = gsr::radix_sort_u32_dev(f.dkey, nullptr, kb, vb, f.nrec, n_rec, 32, f.ctl_depth_sort, err, true, s);
     sorted_rec = r >= 0 ? vb[r] : vb[0];  // no pass only when there are no records
   }
@@ -422,7 +424,8 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
     uint32_t* ik[2] = {f.ikey[1], f.ikey[0]};
     uint32_t* iv[2] = {f.ival[1], f.ival[0]};
     const int ri = gsr::radix_sort_u32_dev(f.ikey[0], f.ival[0], ik, iv, cap, f.header + gsr::kHdrInstancesKept,
-                                           f.tile_bits, f.ctl_tile_sort, err, false, s);
+                                           f.tile_bits, f.ctl_tile_sort, err, false, s,
+                                           ctx->fault == GSR_FAULT_WITHHOLD_STATUS ? 1 : -1);
     f.inst_tile = ri >= 0 ? ik[ri] : f.ikey[0];
     f.inst_rec = ri >= 0 ? iv[ri] : f.ival[0];
     f.inst_mask = f.inst_rec == f.ival[0] ? f.ival[1] : f.ival[0];  // free once the sort is done
@@ -524,6 +527,7 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
       ip.p[views + v] = images[i][v];
     }
     gsr::FrameRef& r = tab.f[i];
+    r.header = f.header;
     r.views = f.views;
     r.ranges = f.ranges;
     r.inst_rec = f.inst_rec;
@@ -633,6 +637,11 @@ gsr_status backward_impl(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   for (int v = 0; v < V; ++v) dp.p[v] = dL_dimages[v];
   {
     StageScope sc_(ctx, GSR_STAGE_RASTER_BWD, s);
+    if (f.grad2d_fx) {  // the fixed-point scale follows the upstream gradient's size
+      gsr::ViewCounts counts{};
+      for (int v = 0; v < V; ++v) counts.n[v] = 3 * (int64_t)cams[v].width * cams[v].height;
+      gsr::launch_grad_absmax(f, dp, counts, s);
+    }
     gsr::launch_raster_bwd(f, dp, opts->precision, s);
   }
   {
@@ -703,7 +712,7 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
     }
   }
   if (h[gsr::kHdrError] & 2u) return fail(ctx, GSR_ERR_UNSUPPORTED, "the frame has 2^30 or more instances");
-  if (h[gsr::kHdrError]) return fail(ctx, GSR_ERR_DEVICE, "a device-wide scan or sort wait gave up");
+  if (h[gsr::kHdrError]) return fail(ctx, GSR_ERR_DEVICE, "a device-wide scan or sort wait gave up (frame aborted)");
   if (h[gsr::kHdrOverflow]) {
     ctx->required = bytes_for_instances(&fr.scene, fr.cams, f.V, M + M / 8 + 1024, f.grad2d_fx != nullptr);
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
@@ -959,6 +968,14 @@ gsr_status gsr_set_raster_split(gsr_context* ctx, uint32_t split_len, uint32_t s
   if (!ctx) return GSR_ERR_INVALID_ARG;
   ctx->split_len = split_len == 0 ? gsr::kSplitLen : split_len;
   ctx->split_len_bwd = split_len_bwd == 0 ? gsr::kSplitLenBwd : split_len_bwd;
+  return GSR_OK;
+}
+
+gsr_status gsr_set_fault_injection(gsr_context* ctx, int32_t mode) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (mode != GSR_FAULT_NONE && mode != GSR_FAULT_ABORT_BEFORE_SORT && mode != GSR_FAULT_WITHHOLD_STATUS)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "unknown fault injection mode %d", mode);
+  ctx->fault = mode;
   return GSR_OK;
 }
 

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const uint32_t* __restric
                                                        uint32_t* __restrict__ inst_tile,
                                                        uint32_t* __restrict__ inst_rec, uint32_t* __restrict__ ranges,
                                                        int64_t ntiles) {
+  if (frame_aborted(header)) return;  // the depth sort or offsets scan gave up
   const int64_t k = (int64_t)blockIdx.x * kEmitThreads + threadIdx.x;
   for (int64_t q = k; q < 2 * ntiles; q += (int64_t)gridDim.x * kEmitThreads) ranges[q] = 0u;
   if (k == 0) {
@@ -97,6 +98,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(const uint32_t* __restric
 __global__ void k_ranges(const uint32_t* __restrict__ inst_tile, const uint32_t* __restrict__ header,
                          uint32_t* __restrict__ ranges) {
   constexpr uint32_t kNone = 0xffffffffu;  // no tile id (ids stay below 2^28)
+  if (frame_aborted(header)) return;  // the tile sort gave up: tile ids may be out of range
   const int64_t M = header[kHdrInstancesKept];
   const int64_t G = (M + 3) / 4;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < G; q += (int64_t)gridDim.x * blockDim.x) {
@@ -145,13 +147,19 @@ __device__ __forceinline__ uint32_t order_bucket(uint32_t len) {
 // uniform search over the frames' first tiles).
 struct OneFrame {
   const uint32_t* ranges;
+  const uint32_t* header;
+  __device__ bool aborted() const { return frame_aborted(header); }
   __device__ uint32_t len(int64_t i) const { return ranges[2 * i + 1] - ranges[2 * i]; }
 };
+// A frame that gave up counts as empty here (its ranges may be garbage); the raster
+// skips its items.
 struct ManyFrames {
   FrameTable tab;
+  __device__ bool aborted() const { return false; }
   __device__ uint32_t len(int64_t i) const {
     int f = 0;
     while (f + 1 < tab.n && tab.first[f + 1] <= (uint32_t)i) ++f;
+    if (frame_aborted(tab.f[f].header)) return 0u;
     const int64_t t = i - tab.first[f];
     return tab.f[f].ranges[2 * t + 1] - tab.f[f].ranges[2 * t];
   }
@@ -189,6 +197,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   __shared__ uint32_t nlong[2];
   __shared__ uint32_t edge[2];  // bucket holding the forward's / backward's last split rank (none: kOrderBuckets)
   __shared__ uint32_t wcnt[2][kOrderThreads / 64];
+  if (L.aborted()) return;  // the item counts stay 0: no raster work
   const int t = threadIdx.x;
   for (int b = t; b < kOrderBuckets; b += kOrderThreads) h[b] = 0;
   if (t < 2) {
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
 
 bool launch_tile_order(const Frame& f, hipStream_t s, hipEvent_t done) {
   if (f.tiles <= 0) return false;
-  launch_tracked(k_tile_order<OneFrame>, 1, kOrderThreads, s, done, OneFrame{f.ranges}, (int64_t)f.tiles,
+  launch_tracked(k_tile_order<OneFrame>, 1, kOrderThreads, s, done, OneFrame{f.ranges, f.header}, (int64_t)f.tiles,
                  f.split_len, f.split_len_bwd, f.tile_order, f.header + kHdrItems, f.bwd_items,
                  f.header + kHdrItemsBwd);
   return true;

@@ -57,9 +57,12 @@ __global__ void k_dens_count(const uint32_t* __restrict__ skeys, int64_t n, int6
 }
 
 // Rank r < k: candidate svals[r] (svals null: the identity) is split or cloned.
+// Every kernel that indexes with sorted values or scanned positions leaves when a
+// device-wide wait of the round gave up (the error word): those may be garbage.
 __global__ void k_dens_mark(const uint32_t* __restrict__ svals, int64_t kmax, const uint32_t* __restrict__ hdr,
                             const float* __restrict__ log_scales, float split_ls, uint32_t* __restrict__ op,
-                            uint32_t* __restrict__ cc) {
+                            uint32_t* __restrict__ cc, const uint32_t* __restrict__ err) {
+  if (error_raised(err)) return;
   const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (r >= kmax) return;
   if (r >= (int64_t)hdr[kDhCandidates]) {
@@ -81,7 +84,9 @@ __global__ void k_dens_keep(const uint32_t* __restrict__ op, const float* __rest
 }
 
 __global__ void k_dens_map_kept(const uint32_t* __restrict__ keep, const uint32_t* __restrict__ pos, int64_t n,
-                                uint32_t* __restrict__ src, uint32_t* __restrict__ kind) {
+                                uint32_t* __restrict__ src, uint32_t* __restrict__ kind,
+                                const uint32_t* __restrict__ err) {
+  if (error_raised(err)) return;
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n || keep[i] == 0u) return;
   src[pos[i]] = (uint32_t)i;
@@ -93,12 +98,13 @@ __global__ void k_dens_map_new(const uint32_t* __restrict__ svals, const uint32_
                                const uint32_t* __restrict__ err, uint32_t* __restrict__ src,
                                uint32_t* __restrict__ kind, int64_t* __restrict__ n_out) {
   const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (r == 0) {
-    const uint32_t rows = hdr[kDhKept] + hdr[kDhChildren];
+  const bool bad = error_raised(err);
+  if (r == 0) {  // no output rows after a wait gave up: the later gathers do nothing
+    const uint32_t rows = bad ? 0u : hdr[kDhKept] + hdr[kDhChildren];
     hdr[kDhRows] = rows;
-    if (n_out) *n_out = err[0] != 0u ? -1 : (int64_t)rows;
+    if (n_out) *n_out = bad ? -1 : (int64_t)rows;
   }
-  if (r >= kmax || cc[r] == 0u) return;
+  if (bad || r >= kmax || cc[r] == 0u) return;
   const uint32_t i = svals ? svals[r] : (uint32_t)r;
   const uint32_t base = hdr[kDhKept] + coff[r];
   if (cc[r] == 1u) {
@@ -230,12 +236,12 @@ void densify(const DensifyArgs& a, uint32_t* ws, hipStream_t s) {
   k_dens_count<<<blocks_for(n), kThreads, 0, s>>>(skeys, n, K, hdr);
   if (K > 0)
     k_dens_mark<<<blocks_for(K), kThreads, 0, s>>>(svals, K, hdr, a.log_scales, a.split_log_scale, ws + L.op,
-                                                  ws + L.cc);
+                                                  ws + L.cc, err);
   k_dens_keep<<<blocks_for(n), kThreads, 0, s>>>(ws + L.op, a.opacity_logits, a.prune_logit, n, ws + L.keep);
   scan_u32(ws + L.keep, nullptr, ws + L.pos, n, nullptr, hdr + kDhKept, nullptr, ws + L.ctl_scan1, err, s);
   if (K > 0)
     scan_u32(ws + L.cc, nullptr, ws + L.coff, K, nullptr, hdr + kDhChildren, nullptr, ws + L.ctl_scan2, err, s);
-  k_dens_map_kept<<<blocks_for(n), kThreads, 0, s>>>(ws + L.keep, ws + L.pos, n, ws + L.src, ws + L.kind);
+  k_dens_map_kept<<<blocks_for(n), kThreads, 0, s>>>(ws + L.keep, ws + L.pos, n, ws + L.src, ws + L.kind, err);
   k_dens_map_new<<<blocks_for(std::max<int64_t>(K, 1)), kThreads, 0, s>>>(svals, ws + L.cc, ws + L.coff, K, hdr, err,
                                                                      ws + L.src, ws + L.kind, a.n_out);
   const int64_t rows_max = n + K;

@@ -70,10 +70,40 @@ enum HeaderWord {
   kHdrInstancesKept = 2,    // min(M, capacity): what the tile sort and raster use
   kHdrRecords = 3,          // active records = 128 * visible clusters * views
   kHdrOverflow = 4,         // 1 when M exceeded the workspace capacity
-  kHdrError = 5,            // bit 0: a look-back wait gave up; bit 1: a scanned count reached 2^30
+  kHdrError = 5,            // bit 0: abort (a device-wide wait ran out of time, or the host raised it);
+                            // bit 1: a scanned count reached 2^30
   kHdrItems = 6,            // forward raster work items (whole tiles plus the bands of split tiles)
   kHdrItemsBwd = 7,         // backward raster work items
+  kHdrGradMax = 8,          // deterministic backward: max |dL/dI| over the frame's views (FP32 bits)
 };
+
+// Fixed-point scale of the deterministic backward. A per-tile gradient sum is
+// rounded to a multiple of 2^(E - 32), E the binary exponent of max |dL/dI| over
+// the frame (max |dL/dI| < 2^E), and the statistic's square sum to a multiple of
+// 2^(2E - 32): the sums keep 32 bits below the size of the upstream gradient
+// whatever the scale of the loss, and saturate at 2^31 times it. E is clamped to
+// [-44, 44] so that both scales stay finite in FP32.
+constexpr int kFixedBits = 32;
+__device__ __forceinline__ int grad_exponent(const uint32_t* header) {
+  const float m = __uint_as_float(header[kHdrGradMax]);
+  int e = 0;
+  if (m > 0.0f) (void)frexpf(m, &e);
+  return e < -44 ? -44 : (e > 44 ? 44 : e);
+}
+
+// Error bits of the header's error word. Any set bit makes every later kernel of
+// the frame leave at once (frame_aborted): the scans and sorts it would read may
+// be incomplete, and indices read from them could point anywhere.
+constexpr uint32_t kErrAbort = 1u;
+constexpr uint32_t kErrCount = 2u;
+
+// The word is written by earlier kernels of the stream, or by blocks of a running
+// look-back kernel (which broadcast their own reading through LDS, since waves may
+// read it at different times): read once per wave into a scalar register.
+__device__ __forceinline__ bool error_raised(const uint32_t* err) {
+  return __builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+}
+__device__ __forceinline__ bool frame_aborted(const uint32_t* header) { return error_raised(header + kHdrError); }
 
 // Default list lengths above which the raster splits a tile into band items
 // (forward: four 16x4 bands; backward: two halves).
@@ -139,9 +169,13 @@ void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n
 // neighbouring keys tend to share their high bytes (the digit counting then adds
 // runs of equal digits at once).
 size_t sort_ctl_words(int64_t n_max, int bits);
+// withhold >= 0 (tests of the error path only): the first pass's block of that tile
+// never publishes its look-back status.
 int radix_sort_u32_dev(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2],
                        int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
-                       hipStream_t s);
+                       hipStream_t s, int64_t withhold = -1);
+// Raises the abort bit of an error word (tests of the error path).
+void raise_abort(uint32_t* err, hipStream_t s);
 int radix_sort_u64_dev(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2],
                        int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
                        hipStream_t s);
@@ -186,6 +220,7 @@ bool launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, h
 // Batched forward raster over several prepared frames (kernel-argument table).
 constexpr int kMaxBatch = GSR_MAX_BATCH;
 struct FrameRef {
+  const uint32_t* header;   // the frame's header (its error word: an aborted frame's tiles are skipped)
   const ViewDev* views;
   const uint32_t* ranges;
   const uint32_t* inst_rec;
@@ -211,6 +246,12 @@ void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32
 // Largest number of raster work items for `tiles` tiles (every split tile adds 3).
 int64_t raster_max_items(int64_t tiles);
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s);
+// Deterministic backward: header[kHdrGradMax] <- max |dL/dI| over the V images
+// (count[v] floats each).
+struct ViewCounts {
+  int64_t n[GSR_MAX_VIEWS];
+};
+void launch_grad_absmax(const Frame& f, const ConstImagePtrs& dL, const ViewCounts& counts, hipStream_t s);
 
 // morton.hip
 size_t morton_temp_words(int64_t n);

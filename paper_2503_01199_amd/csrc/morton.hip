@@ -93,9 +93,13 @@ __global__ void k_morton_encode(const float* __restrict__ means, int64_t n, cons
   if (codes_out) codes_out[i] = code;
 }
 
-__global__ void k_perm_out(const uint32_t* __restrict__ vals, int64_t n, int64_t* __restrict__ perm) {
+__global__ void k_perm_out(const uint32_t* __restrict__ vals, int64_t n, int64_t* __restrict__ perm,
+                           const uint32_t* __restrict__ err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) perm[i] = (int64_t)vals[i];
+  // a sort that gave up leaves the order as it is (the identity is a valid
+  // permutation, so a caller's gather stays in bounds)
+  const bool ok = !error_raised(err);
+  if (i < n) perm[i] = ok ? (int64_t)vals[i] : i;
 }
 
 __global__ void k_gather_rows(const int64_t* __restrict__ perm, int64_t n, const float* __restrict__ src,
@@ -144,7 +148,7 @@ bool morton_order(const float* means, int64_t n, uint32_t* temp, int64_t* perm, 
   k_bounds_final<<<1, 384, 0, s>>>(part, G, bounds);
   k_morton_encode<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(means, n, bounds, cin, codes);
   const int r = radix_sort_u64_dev(cin, nullptr, ck, vb, n, nullptr, 63, ctl, err, false, s);
-  k_perm_out<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(vb[r], n, perm);
+  k_perm_out<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(vb[r], n, perm, err);
   return true;
 }
 

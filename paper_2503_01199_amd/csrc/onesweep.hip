@@ -12,10 +12,15 @@
 // Grids hold one block per tile of the largest possible count; blocks past the
 // count on the device leave at once. A status word
 // is (flag << 30 | value): flag 0 = not ready, 1 = aggregate, 2 = inclusive
-// prefix. Values must stay below 2^30: a larger prefix sets bit 1 of the error word
-// (the result is then wrong but every access stays in bounds). The walk waits only
-// on blocks that have started, so it terminates; a bounded spin additionally sets
-// bit 0 of the error word instead of hanging.
+// prefix. Values must stay below 2^30: a larger prefix sets the count bit of the
+// error word (the result is then wrong but every access stays in bounds).
+//
+// Waits: every wait is bounded by elapsed time (kWaitTicks) and reads the error
+// word on each round. A wait that runs out raises the word's abort bit; any raised
+// bit ends every other wait at its next round and makes every block skip its
+// writes, and every later kernel of the frame checks the word at entry and leaves.
+// A protocol or scheduling failure therefore surfaces within one bound as an
+// error status of the frame, instead of as minutes of per-block spinning.
 #include <algorithm>
 
 #include "gsr_internal.h"
@@ -26,13 +31,42 @@ namespace {
 constexpr uint32_t kFlagAgg = 1u << 30;
 constexpr uint32_t kFlagPrefix = 2u << 30;
 constexpr uint32_t kValueMask = (1u << 30) - 1u;
-constexpr int kSpinLimit = 1 << 22;
+// s_memrealtime counts at a constant 100 MHz on gfx9 parts: 100 ms. A legitimate
+// wait lasts as long as earlier tiles take to publish (microseconds; at most the
+// pass itself, ~2 ms on the largest sorts here).
+constexpr uint64_t kWaitTicks = 100ull * 100000ull;
 
 __device__ __forceinline__ uint32_t ld_status(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_status(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Deadline of one wait. over(): the error word is raised (by another block, or by
+// the host), or the deadline has passed, in which case this wait raises the abort
+// bit itself.
+struct WaitBound {
+  uint64_t t0;
+  __device__ WaitBound() : t0(__builtin_amdgcn_s_memrealtime()) {}
+  __device__ bool over(uint32_t* err) const {
+    if (ld_status(err) != 0u) return true;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+      atomicOr(err, kErrAbort);
+      return true;
+    }
+    return false;
+  }
+};
+
+// Reads the error word once for the whole block (waves may otherwise read it at
+// different times while other blocks raise it); every thread must call it.
+__device__ __forceinline__ bool block_error(uint32_t* err) {
+  __shared__ uint32_t s_err;
+  __syncthreads();
+  if (threadIdx.x == 0) s_err = ld_status(err);
+  __syncthreads();
+  return s_err != 0u;
 }
 
 // Sum, in status column `col` (stride `stride` words between entries), of the
@@ -43,7 +77,7 @@ constexpr int kWindow = 16;
 
 __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride, int col, uint32_t* err) {
   uint32_t excl = 0;
-  int spins = 0;
+  const WaitBound bound;
   bool found = false;
   while (!found) {
     uint32_t st[kWindow];
@@ -62,10 +96,7 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
     if (found) break;
     b -= used;
     if (used < kWindow) {
-      if (++spins > kSpinLimit) {
-        atomicOr(err, 1u);
-        break;
-      }
+      if (bound.over(err)) break;
       __builtin_amdgcn_s_sleep(1);
     }
   }
@@ -81,18 +112,19 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
 // progress. tstat: [tiles][stride] per-tile aggregates; gstat: [groups][stride].
 constexpr int kGroup = 16;
 
+// publish = false (tests of the error path only): the tile never publishes.
 __device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t tile, int64_t stride, int col,
-                                      uint32_t agg, uint32_t* err) {
+                                      uint32_t agg, uint32_t* err, bool publish = true) {
   if (agg > kValueMask) {
-    atomicOr(err, 2u);
+    atomicOr(err, kErrCount);
     agg &= kValueMask;
   }
   const int64_t g = tile / kGroup, g0 = g * kGroup;
-  const bool last = tile % kGroup == kGroup - 1;
-  st_status(tstat + tile * stride + col, kFlagAgg | agg);
+  const bool last = publish && tile % kGroup == kGroup - 1;
+  if (publish) st_status(tstat + tile * stride + col, kFlagAgg | agg);
   // exclusive sum over the group's earlier tiles g0 .. tile - 1
   uint32_t E = 0;
-  int spins = 0;
+  const WaitBound bound;
   for (;;) {
     uint32_t v[kGroup - 1];
 #pragma unroll
@@ -112,8 +144,7 @@ __device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t 
       E = sum;
       break;
     }
-    if (++spins > kSpinLimit) {
-      atomicOr(err, 1u);
+    if (bound.over(err)) {
       E = sum;
       break;
     }
@@ -121,7 +152,7 @@ __device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t 
   }
   if (last) st_status(gstat + g * stride + col, kFlagAgg | ((E + agg) & kValueMask));
   const uint32_t X = g > 0 ? walk_back(gstat, g - 1, stride, col, err) : 0u;
-  if ((uint64_t)X + E + agg > kValueMask) atomicOr(err, 2u);
+  if ((uint64_t)X + E + agg > kValueMask) atomicOr(err, kErrCount);
   if (last) st_status(gstat + g * stride + col, kFlagPrefix | ((X + E + agg) & kValueMask));
   return X + E;
 }
@@ -151,6 +182,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
                                                        uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
   __shared__ uint32_t wsum[kScanThreads / 64];
   __shared__ uint32_t s_excl;
+  if (block_error(err)) return;  // an earlier stage gave up: its counts and indices may be garbage
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
   const int64_t tile = blockIdx.x;
@@ -192,7 +224,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     const int64_t tiles = max<int64_t>(1, (n_host + kScanTile - 1) / kScanTile);
     s_excl = look_back_grouped(ctl + 1, ctl + 1 + tiles, tile, 1, 0, agg, err);
   }
-  __syncthreads();
+  if (block_error(err)) return;  // a wait gave up: the prefix may be partial
   uint32_t run = s_excl + off + incl - sum;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
@@ -239,10 +271,11 @@ template <typename K, bool kRuns>
 __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ keys, int64_t n_host,
                                                           const uint32_t* __restrict__ n_dev, int passes,
                                                           uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
-                                                          uint32_t* __restrict__ done) {
+                                                          uint32_t* __restrict__ done, const uint32_t* __restrict__ err) {
   __shared__ uint32_t h[kMaxPasses][256];
   __shared__ uint32_t wsum[kSortThreads / 64];
   __shared__ bool last;
+  if (error_raised(err)) return;  // set by an earlier kernel only: the same for every wave
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   int64_t nb = (n + kHistChunk - 1) / kHistChunk;
   if (nb < 1) nb = 1;
@@ -356,12 +389,14 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n_host, const uint32_t* __restrict__ n_dev,
                                                              int shift, const uint32_t* __restrict__ offs,
-                                                             uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
+                                                             uint32_t* __restrict__ ctl, uint32_t* __restrict__ err,
+                                                             int64_t withhold) {
   constexpr int kTile = kSortThreads * R;  // items per tile: R rounds of one item per thread
   __shared__ __align__(16) uint32_t cnt[R][4][256];
   __shared__ uint32_t gofs[256], ldig[256], wtot[4];
   static_assert(sizeof(K) * kTile + 4 * kTile <= sizeof(uint32_t) * R * 4 * 256,
                 "the staged tile fits in the counters' space");
+  if (block_error(err)) return;
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
   const int w = t >> 6;
@@ -415,7 +450,9 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
         run += c;
       }
     const int64_t tiles = (n_host + kTile - 1) / kTile;
-    const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err);
+    const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err,
+                                             tile != withhold);
+    if (block_error(err)) return;  // a wait gave up: the prefixes may be partial
     gofs[t] = offs[t] + prior;
     // tile-local digit offsets: exclusive scan over the digits of the tile's totals
     const uint32_t incl = wave_incl_scan(run);
@@ -453,7 +490,8 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
 
 template <typename K>
 int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t* vb[2], int64_t n_max,
-                  const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool runs, hipStream_t s) {
+                  const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool runs, hipStream_t s,
+                  int64_t withhold = -1) {
   const int passes = (bits + 7) / 8;
   if (n_max <= 0 || passes == 0) return -1;
   uint32_t* hist = ctl;                       // [passes][256]
@@ -472,19 +510,20 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
   if (runs)
-    k_os_hist<K, true><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
+    k_os_hist<K, true><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done, err);
   else
-    k_os_hist<K, false><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done);
+    k_os_hist<K, false><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done, err);
   const K* kcur = keys_in;
   const uint32_t* vcur = vals_in;
   int out = 0;
   for (int p = 0; p < passes; ++p) {
+    const int64_t wh = p == 0 ? withhold : -1;
     if (wide)
       k_os_scatter<K, 2 * kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
-          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err);
+          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
     else
       k_os_scatter<K, kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
-          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err);
+          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
     kcur = kb[out];
     vcur = vb[out];
     out ^= 1;
@@ -513,9 +552,15 @@ void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n
 
 int radix_sort_u32_dev(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* kb[2], uint32_t* vb[2],
                        int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,
-                       hipStream_t s) {
-  return radix_sort_os<uint32_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, spatial, s);
+                       hipStream_t s, int64_t withhold) {
+  return radix_sort_os<uint32_t>(keys_in, vals_in, kb, vb, n_max, n_dev, bits, ctl, err, spatial, s, withhold);
 }
+
+namespace {
+__global__ void k_raise_abort(uint32_t* err) { atomicOr(err, kErrAbort); }
+}  // namespace
+
+void raise_abort(uint32_t* err, hipStream_t s) { k_raise_abort<<<1, 1, 0, s>>>(err); }
 
 int radix_sort_u64_dev(const uint64_t* keys_in, const uint32_t* vals_in, uint64_t* kb[2], uint32_t* vb[2],
                        int64_t n_max, const uint32_t* n_dev, int bits, uint32_t* ctl, uint32_t* err, bool spatial,

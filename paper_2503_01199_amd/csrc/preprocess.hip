@@ -309,6 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
                                                              unsigned long long* __restrict__ grad_fx) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float lsh[kThreads * (3 * K + 1)];  // the cluster's SH rows
+  if (frame_aborted(header)) return;  // the cluster scan gave up: its list may be garbage
   const int64_t j = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // block = compact slot p (grid covers ncap)
   const uint32_t nvis = header[kHdrVisibleClusters];
   if (j == 0) header[kHdrRecords] = nvis * GSR_CLUSTER * (uint32_t)V;
@@ -447,11 +448,12 @@ __device__ __forceinline__ void store_project_grads(const gsr_grads& gr, const A
 
 template <bool kAdam>
 __global__ __launch_bounds__(kThreads) void k_project_bwd(
-    gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, const uint32_t* __restrict__ visible,
-    const uint32_t* __restrict__ cluster_offset, const uint32_t* __restrict__ tiles,
-    float* __restrict__ grad2d, const unsigned long long* __restrict__ grad_fx, gsr_grads gr,
-    float* __restrict__ S, float* __restrict__ Mst, uint32_t* __restrict__ Cst, AdamDev adam,
+    gsr_scene sc, const ViewDev* __restrict__ views, int32_t V, const uint32_t* __restrict__ header,
+    const uint32_t* __restrict__ visible, const uint32_t* __restrict__ cluster_offset,
+    const uint32_t* __restrict__ tiles, float* __restrict__ grad2d, const unsigned long long* __restrict__ grad_fx,
+    gsr_grads gr, float* __restrict__ S, float* __restrict__ Mst, uint32_t* __restrict__ Cst, AdamDev adam,
     float* __restrict__ dmean) {
+  if (frame_aborted(header)) return;  // the frame's scans may be garbage: nothing is written
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= sc.n) return;
   const int64_t c = i / GSR_CLUSTER;
@@ -478,11 +480,15 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
         // SH backward (and inspection) reads
         float x[kGrad2D];
         const ulonglong2* fq = reinterpret_cast<const ulonglong2*>(grad_fx + r * kGrad2D);
+        const int E = grad_exponent(header);
 #pragma unroll
         for (int k = 0; k < kGrad2D / 2; ++k) {
           const ulonglong2 w2 = fq[k];
-          x[2 * k] = (float)((double)(long long)w2.x * 0x1p-32);
-          x[2 * k + 1] = (float)((double)(long long)w2.y * 0x1p-32);
+          // slot 9: square sum (scale 2^(2E - 32)); slot 10: fragment count (2^-32)
+          const int e0 = 2 * k == 10 ? -kFixedBits : E - kFixedBits;
+          const int e1 = 2 * k + 1 == 9 ? 2 * E - kFixedBits : E - kFixedBits;
+          x[2 * k] = (float)ldexp((double)(long long)w2.x, e0);
+          x[2 * k + 1] = (float)ldexp((double)(long long)w2.y, e1);
         }
         q0 = make_float4(x[0], x[1], x[2], x[3]);
         q1 = make_float4(x[4], x[5], x[6], x[7]);
@@ -608,6 +614,7 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
 // accumulate in FP32.
 template <int DEG, bool kAdam>
 __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev* __restrict__ views, int32_t V,
+                                                     const uint32_t* __restrict__ header,
                                                      const uint32_t* __restrict__ visible,
                                                      const uint32_t* __restrict__ cluster_offset,
                                                      const uint32_t* __restrict__ tiles,
@@ -616,6 +623,7 @@ __global__ __launch_bounds__(kThreads) void k_sh_bwd(gsr_scene sc, const ViewDev
   constexpr int K = (DEG + 1) * (DEG + 1);
   constexpr int R = 3 * K, S = R + 1;
   __shared__ float lsh[kThreads * S];  // the cluster's SH rows, then their gradients
+  if (frame_aborted(header)) return;
   const int t = threadIdx.x;
   const int64_t c = blockIdx.x;  // one cluster per block
   const int64_t i0 = c * GSR_CLUSTER;
@@ -793,21 +801,21 @@ void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads&
   const AdamDev none{};
   const AdamDev& a = adam ? *adam : none;
   if (adam)
-    k_project_bwd<true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,
+    k_project_bwd<true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,
                                                   f.tiles_touched, f.grad2d, f.grad2d_fx, g,
                                                   stats ? stats->S : nullptr, stats ? stats->M : nullptr,
                                                   stats ? stats->C : nullptr, a, f.dmean);
   else
-    k_project_bwd<false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,
+    k_project_bwd<false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,
                                                    f.tiles_touched, f.grad2d, f.grad2d_fx, g,
                                                    stats ? stats->S : nullptr, stats ? stats->M : nullptr,
                                                    stats ? stats->C : nullptr, a, f.dmean);
 #define GSR_SH_BWD(D)                                                                                            \
   if (adam)                                                                                                      \
-    k_sh_bwd<D, true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,           \
+    k_sh_bwd<D, true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,           \
                                                 f.tiles_touched, f.grad2d, g, a, f.dmean);                       \
   else                                                                                                           \
-    k_sh_bwd<D, false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.cluster_visible, f.cluster_offset,          \
+    k_sh_bwd<D, false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,          \
                                                  f.tiles_touched, f.grad2d, g, a, f.dmean)
   switch (sc.sh_degree) {
     case 0: GSR_SH_BWD(0); break;

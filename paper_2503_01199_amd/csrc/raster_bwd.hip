@@ -23,6 +23,8 @@
 // unit. f_global is ONE atomic add per gradient per tile, issued as three 4-lane
 // atomic instructions on the record's contiguous 48-byte row (FP32), or, for a
 // bitwise reproducible backward, on its 96-byte row of 64-bit fixed-point sums.
+#include <algorithm>
+
 #include "raster_common.h"
 
 namespace gsr {
@@ -30,12 +32,11 @@ namespace {
 
 constexpr int kBatch = 64;  // records per LDS batch
 
-// Deterministic backward: per-tile sums become two's-complement fixed point with
-// kFixedBits fraction bits (round to nearest, saturating), so that the device-wide
-// integer sum does not depend on the order in which tiles add.
-constexpr int kFixedBits = 32;
-__device__ __forceinline__ unsigned long long to_fixed(float v) {
-  const float x = fminf(fmaxf(v * 0x1p32f, -0x1p63f), 0x1.fffffep62f);
+// Deterministic backward: per-tile sums become two's-complement fixed point (round
+// to nearest, saturating) at the frame's scale (grad_exponent), so that the
+// device-wide integer sum does not depend on the order in which tiles add.
+__device__ __forceinline__ unsigned long long to_fixed(float v, float scale) {
+  const float x = fminf(fmaxf(v * scale, -0x1p63f), 0x1.fffffep62f);
   return (unsigned long long)(long long)__builtin_rintf(x);
 }
 using BwdBatch = BatchLDS<kBatch>;
@@ -99,7 +100,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
                                                 const Record* __restrict__ rec, const ConstImagePtrs& dL,
                                                 const float* __restrict__ pix_T,
                                                 const uint32_t* __restrict__ pix_last, float* __restrict__ grad2d,
-                                                unsigned long long* __restrict__ grad_fx) {
+                                                unsigned long long* __restrict__ grad_fx, float fx_lin, float fx_sq) {
   const int v = view_of_tile(views, V, gt);
   const ViewDev& w = views[v];
   const int W = w.width, H = w.height;
@@ -240,9 +241,12 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
         const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
         if constexpr (kFixed) {
           unsigned long long* dst = grad_fx + (int64_t)cur_rec[k] * kGrad2D + sub;
-          atomicAdd(dst, to_fixed(tot[0]));
-          atomicAdd(dst + 4, to_fixed(tot[1]));
-          if (sub != 3) atomicAdd(dst + 8, sub == 2 ? (unsigned long long)nfrag << kFixedBits : to_fixed(tot[2]));
+          atomicAdd(dst, to_fixed(tot[0], fx_lin));
+          atomicAdd(dst + 4, to_fixed(tot[1], fx_lin));
+          // slot 9 is the square sum of the statistic, slot 10 the fragment count
+          if (sub != 3)
+            atomicAdd(dst + 8, sub == 2 ? (unsigned long long)nfrag << kFixedBits
+                                        : to_fixed(tot[2], sub == 1 ? fx_sq : fx_lin));
         } else {
           float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D + sub;
           unsafeAtomicAdd(dst, tot[0]);
@@ -261,7 +265,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
 template <int P, bool kFixed>
 __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ views, int32_t V,
                                                    const uint32_t* __restrict__ items,
-                                                   const uint32_t* __restrict__ n_items,
+                                                   const uint32_t* __restrict__ header,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
                                                    const uint32_t* __restrict__ inst_mask,
@@ -272,27 +276,58 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    unsigned long long* __restrict__ grad_fx) {
   __shared__ BwdBatch bufA, bufB;  // two objects, so reads of one never wait on loads into the other
   __shared__ uint32_t recA[kBatch], recB[kBatch];
-  if (blockIdx.x >= *n_items) return;
+  if (blockIdx.x >= header[kHdrItemsBwd] || frame_aborted(header)) return;
   const uint32_t item = items[blockIdx.x];
   const uint32_t gt = item >> 3;
   const uint32_t code = item & 7u;
+  float fx_lin = 0.0f, fx_sq = 0.0f;
+  if constexpr (kFixed) {
+    const int E = grad_exponent(header);
+    fx_lin = __builtin_ldexpf(1.0f, kFixedBits - E);
+    fx_sq = __builtin_ldexpf(1.0f, kFixedBits - 2 * E);
+  }
   if (code == kItemWhole)
     raster_bwd_item<P, 4, kFixed>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL,
-                                  pix_T, pix_last, grad2d, grad_fx);
+                                  pix_T, pix_last, grad2d, grad_fx, fx_lin, fx_sq);
   else  // half of a split tile
     raster_bwd_item<P, 2, kFixed>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges,
-                                  inst_rec, inst_mask, rec, dL, pix_T, pix_last, grad2d, grad_fx);
+                                  inst_rec, inst_mask, rec, dL, pix_T, pix_last, grad2d, grad_fx, fx_lin, fx_sq);
+}
+
+// max |dL/dI| over the views' images into header[kHdrGradMax] (zeroed before): the
+// bits of a non-negative float order as unsigned integers, so an atomic max on them
+// is the maximum whatever the order of the blocks.
+__global__ __launch_bounds__(256) void k_grad_absmax(ConstImagePtrs dL, ViewCounts counts, int32_t V,
+                                                     uint32_t* __restrict__ header) {
+  if (frame_aborted(header)) return;
+  float m = 0.0f;
+  for (int v = 0; v < V; ++v) {
+    const float* g = dL.p[v];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < counts.n[v]; i += (int64_t)gridDim.x * 256)
+      m = fmaxf(m, fabsf(g[i]));
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(header + kHdrGradMax, __float_as_uint(m));
 }
 
 template <int P, bool kFixed>
 void launch_bwd(const Frame& f, const ConstImagePtrs& dL, hipStream_t s) {
   const unsigned grid = (unsigned)max_items(f.tiles);
-  k_raster_bwd<P, kFixed><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, f.header + kHdrItemsBwd, f.ranges,
+  k_raster_bwd<P, kFixed><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, f.header, f.ranges,
                                               f.inst_rec, f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d,
                                               f.grad2d_fx);
 }
 
 }  // namespace
+
+void launch_grad_absmax(const Frame& f, const ConstImagePtrs& dL, const ViewCounts& counts, hipStream_t s) {
+  fill_u32(f.header + kHdrGradMax, 1, 0u, s);
+  int64_t total = 0;
+  for (int v = 0; v < f.V; ++v) total += counts.n[v];
+  const int64_t g = std::min<int64_t>(std::max<int64_t>((total + 255) / 256, 1), 2048);
+  k_grad_absmax<<<(unsigned)g, 256, 0, s>>>(dL, counts, f.V, f.header);
+}
 
 void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s) {
   if (f.tiles <= 0) return;

@@ -168,14 +168,14 @@ __device__ __forceinline__ void raster_fwd_work(FwdBatch& bufA, FwdBatch& bufB, 
 template <int P>
 __global__ __launch_bounds__(64) void k_raster_fwd(const ViewDev* __restrict__ views, int32_t V,
                                                    const uint32_t* __restrict__ items,
-                                                   const uint32_t* __restrict__ n_items,
+                                                   const uint32_t* __restrict__ header,
                                                    const uint32_t* __restrict__ ranges,
                                                    const uint32_t* __restrict__ inst_rec,
                                                    uint32_t* __restrict__ inst_mask,
                                                    const Record* __restrict__ rec, ImagePtrs images,
                                                    float* __restrict__ pix_T, uint32_t* __restrict__ pix_last) {
   __shared__ FwdBatch bufA, bufB;  // two objects, so reads of one never wait on loads into the other
-  if (blockIdx.x >= *n_items) return;
+  if (blockIdx.x >= header[kHdrItems] || frame_aborted(header)) return;
   raster_fwd_work<P>(bufA, bufB, views, V, items[blockIdx.x], 0, ranges, inst_rec, inst_mask, rec, images, 0,
                      pix_T, pix_last);
 }
@@ -192,6 +192,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd_batch(FrameTable tab, const u
   int f = 0;
   while (f + 1 < tab.n && tab.first[f + 1] <= g) ++f;
   const FrameRef& fr = tab.f[f];
+  if (frame_aborted(fr.header)) return;  // that frame gave up: its lists may be garbage
   raster_fwd_work<P>(bufA, bufB, fr.views, fr.V, item, tab.first[f], fr.ranges, fr.inst_rec, fr.inst_mask, fr.rec,
                      images, fr.img_base, fr.pix_T, fr.pix_last);
 }
@@ -213,14 +214,14 @@ bool launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const
 bool launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, hipStream_t s, hipEvent_t done) {
   if (f.tiles <= 0) return false;
   const unsigned grid = (unsigned)max_items(f.tiles);
-  const uint32_t* n_items = f.header + kHdrItems;
+  const uint32_t* header = f.header;
   if (precision == GSR_FP16_BLEND)
     launch_tracked(k_raster_fwd<GSR_FP16_BLEND>, grid, 64, s, done, (const ViewDev*)f.views, f.V,
-                   (const uint32_t*)f.tile_order, n_items, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
+                   (const uint32_t*)f.tile_order, header, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
                    f.inst_mask, (const Record*)f.rec, images, f.pix_T, f.pix_last);
   else
     launch_tracked(k_raster_fwd<GSR_FP32>, grid, 64, s, done, (const ViewDev*)f.views, f.V,
-                   (const uint32_t*)f.tile_order, n_items, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
+                   (const uint32_t*)f.tile_order, header, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
                    f.inst_mask, (const Record*)f.rec, images, f.pix_T, f.pix_last);
   return true;
 }

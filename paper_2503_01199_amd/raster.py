@@ -470,6 +470,11 @@ class Rasterizer:
         self._check(self.lib.gsr_set_raster_split(self.ctx, int(split_len), int(split_len_bwd)),
                     "gsr_set_raster_split")
 
+    def set_fault_injection(self, mode: int):
+        """Failure injection of the frames prepared from now on (tests of the error
+        path): L.GSR_FAULT_NONE, GSR_FAULT_ABORT_BEFORE_SORT or GSR_FAULT_WITHHOLD_STATUS."""
+        self._check(self.lib.gsr_set_fault_injection(self.ctx, int(mode)), "gsr_set_fault_injection")
+
     def set_profiling(self, enable: bool):
         self._check(self.lib.gsr_set_profiling(self.ctx, 1 if enable else 0), "gsr_set_profiling")
 

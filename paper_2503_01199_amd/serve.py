@@ -200,6 +200,7 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=rasterizer.device) for _ in range(slots)]
         self.raster_stream = torch.cuda.Stream(device=rasterizer.device)
         self.margin = instance_margin
+        self.max_device_retries = 3
         self.density = {}  # instances per pixel of each scene, from one probe view
 
     def calibrate(self, name, camera):
@@ -262,6 +263,10 @@ class GpuExecutor:
             cam = h.req.camera
             seen = 1.1 * info["instances"] / float(cam.width * cam.height) / self.margin
             self.density[h.req.scene] = max(self.density.get(h.req.scene, 0.0), seen)
+        elif st == self.L.GSR_ERR_DEVICE and h.req.retries < self.max_device_retries:
+            # the frame's device-wide waits ran out of time and were abandoned (frames
+            # prepared on concurrent streams can starve each other's look-back): render again
+            need = h.req.nbytes
         elif st != self.L.GSR_OK:
             self.rz._check(st, "gsr_frame_inspect")
         h.ws._release()
