@@ -88,15 +88,27 @@ def measured_traffic(kernel, workload):
     return int(round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024))
 
 
-def valu_issue_fraction(kernel, workload, launch_s):
-    """Share of the launch's VALU issue slots used: recorded SQ_INSTS_VALU (wave
-    instructions) x 4 cycles each (a wave64 instruction on a 16-lane SIMD; the
-    quarter-rate transcendentals take longer, so this is a lower bound) over
-    1,024 SIMDs x 2.4 GHz x the launch time measured now. None without a record."""
+def recorded_valu(kernel, workload):
+    """VALU figures of the kernel from its recorded counters (rocprofv3 --pmc runs of
+    this bench, same sources): wave instructions issued (SQ_INSTS_VALU) and VALU
+    busy, the share of the SIMDs' cycles spent issuing VALU instructions while the
+    GPU was active (rocprofv3's derived VALUBusy = SQ_ACTIVE_INST_VALU x 4 / SIMDs /
+    GRBM_GUI_ACTIVE). Empty without a record."""
     t = recorded_counters(kernel, workload)
-    if t is None or "valu_insts" not in t:
-        return None
-    return t["valu_insts"] * 4.0 / (1024 * 2.4e9 * launch_s)
+    if t is None:
+        return {}
+    return {k: t[k] for k in ("valu_insts", "valu_busy", "valu_utilization") if k in t}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def log(msg):
@@ -108,6 +120,67 @@ def percentile(xs, p):
     k = (len(s) - 1) * p / 100.0
     lo, hi = math.floor(k), math.ceil(k)
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
+
+
+def stage_bytes(info, st_n, sh_degree, views, pixels, stats=True):
+    """Algorithmic HBM bytes of each stage of one step in this library's layouts (the
+    bytes the stage must move once; re-reads, cache hits and atomics' read-modify-
+    write traffic are not counted). R records = visible slots x views, M instances,
+    T tiles, P pixels; parameter rows of pb = 4 (11 + 3K) bytes."""
+    K = (sh_degree + 1) ** 2
+    pb = 4 * (3 + 3 + 4 + 1 + 3 * K)
+    nv = info["n_visible_slots"]
+    R = nv * views
+    M = info["instances"]
+    T = info["tiles"]
+    P = pixels
+    nc = info["clusters"]
+    tile_bits = max(1, int(math.ceil(math.log2(max(T, 2)))))
+    passes = (tile_bits + 7) // 8
+    return {
+        # means and log-scales read; bounds (8 floats) and the flag written; the scan
+        "cluster": st_n * 24 + nc * (32 + 4) + nc * 12,
+        # visible clusters' parameter rows read (the compaction is fused); record,
+        # depth key, tile count, rect, compact index and the zeroed gradient row written
+        "preprocess": nv * pb + R * (48 + 4 + 4 + 8 + 48) + nv * 4,
+        # 4 passes of 8 bits over (key, value): histogram read, then per pass the pair
+        # read (keys only in the first) and written
+        "depth_sort": R * 4 + R * (4 + 8) + 3 * R * 16,
+        # index, gathered tile count and offset
+        "offsets": R * 12,
+        # per record its index, count, offset and rect; per instance (tile, record)
+        "emit": R * 20 + M * 8,
+        "tile_sort": M * 4 + passes * M * 16,
+        "ranges": M * 4 + T * 8,
+        # per instance its record index, record and band mask; per pixel image, T, last
+        "raster_fwd": M * (4 + 48 + 4) + P * 20,
+        # per instance index, record and mask; per pixel dL/dI, T, last
+        "raster_bwd": M * (4 + 48 + 4) + P * 20,
+        # parameter rows and screen gradient rows read, every parameter gradient
+        # written, statistic read and written
+        "preprocess_bwd": nv * pb + R * 48 + st_n * pb + (st_n * 24 if stats else 0),
+    }
+
+
+def step_roofline(stages, nbytes, work_fwd, work_bwd, l1_bytes, ms_per_step):
+    """Roofline of the whole step: each stage's lower bound max(bytes / HBM peak,
+    FLOPs / FP32 peak), summed over stages (and the loss-gradient kernel), over the
+    measured step time. Also each stage's achieved GB/s and its own bound's fraction."""
+    flops = {"raster_fwd": work_fwd, "raster_bwd": work_bwd}
+    per = {}
+    t_min = l1_bytes / (HBM_PEAK_GBS * 1e9)
+    for k, b in nbytes.items():
+        ms = stages.get(k)
+        if ms is None or ms <= 0:
+            continue
+        tb = b / (HBM_PEAK_GBS * 1e9)
+        tf = flops.get(k, 0) / (FP32_PEAK_TFLOPS * 1e12)
+        t = max(tb, tf)
+        t_min += t
+        per[k] = {"ms": ms, "bytes": int(b), "GBs": round(b / (ms * 1e-3) / 1e9, 1),
+                  "bound": "alu" if tf > tb else "hbm", "frac": round(t / (ms * 1e-3), 4)}
+    return {"t_min_ms": round(t_min * 1e3, 4), "frac": round(t_min * 1e3 / ms_per_step, 4), "stages": per,
+            "loss_grad_bytes": int(l1_bytes)}
 
 
 def build_workload(name, n_override=None):
@@ -266,6 +339,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 3 times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-rates", default="200,1000,3000",
+                    help="arrival rates (req/s) of the serving sweep; the first is the reported stream")
+    ap.add_argument("--order", default="morton", choices=["morton", "shuffled"],
+                    help="Gaussian order of the scene (shuffled: a random permutation, for cache counters)")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="warm up, time the steps and stop (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -302,7 +381,20 @@ def main():
     arrays = rz.apply_permutation(perm, list(st.tensors()))
     t1.record()
     torch.cuda.synchronize()
-    morton_ms = t0.elapsed_time(t1)
+    morton_cold_ms = t0.elapsed_time(t1)
+    # warm: the same reorder again (workspaces in place), median of 10
+    warm = []
+    for _ in range(10):
+        t0.record()
+        perm, _ = rz.morton_order(st.means)
+        arrays = rz.apply_permutation(perm, list(st.tensors()))
+        t1.record()
+        t1.synchronize()
+        warm.append(t0.elapsed_time(t1))
+    morton_ms = sorted(warm)[len(warm) // 2]
+    if args.order == "shuffled":
+        perm = torch.randperm(st.n, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+        arrays = rz.apply_permutation(perm, list(st.tensors()))
     st = SceneTensors(*arrays, st.sh_degree)
     scene_sorted = scene.permuted(perm.cpu().numpy())
 
@@ -352,6 +444,10 @@ def main():
     wall = time.perf_counter() - wall0
     rz.check_frame(fr)  # the frame's instances fitted the workspace
     ms_per_step = wall * 1e3 / args.steps
+    if args.only_steps:
+        print(json.dumps({"workload": desc, "order": args.order, "cluster_cull": cull, "ms_per_step":
+                          round(ms_per_step, 4), "steps": args.steps, "instances": info["instances"]}), flush=True)
+        return
 
     # per-step latency: each step alone on the device, timed by events around it
     log("latency over %d single steps" % args.latency_iters)
@@ -556,22 +652,30 @@ def main():
         roof = {"bound": "hbm", "achieved": round(work / dur_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     roof["traffic"] = measured_traffic(roof_kernel, desc)
-    vi = valu_issue_fraction(roof_kernel, desc, dur_s)
-    roof["valu_issue_frac"] = None if vi is None else round(vi, 3)
+    roof.update(recorded_valu(roof_kernel, desc))
     roof["kernel"] = roof_kernel
     roof["launch_ms"] = stages[dom]
     roof["work_per_launch"] = work
+    pixels = sum(c.width * c.height for c in cams)
+    nbytes = stage_bytes(info, st.n, st.sh_degree, len(cams), pixels)
+    step_roof = step_roofline(stages, nbytes, FWD_FLOP_EVAL * E + FWD_FLOP_FRAG * F,
+                              BWD_FLOP_EVAL * E + BWD_FLOP_FRAG * F, 48 * pixels, ms_per_step)
 
     serving = None
     if not args.no_serving:
         from paper_2503_01199_amd.serve import serve_benchmark
-        serving = serve_benchmark(rz, n_warmup=200, n_measured=args.serve_requests, rate=200.0, log=log)
+        rates = [float(r) for r in args.serve_rates.split(",") if r.strip()]
+        # the first rate is the reported stream; the others go past capacity
+        serving = serve_benchmark(rz, n_warmup=200, n_measured=args.serve_requests, rate=rates[0], log=log,
+                                  more_rates=tuple(rates[1:]))
 
     cpu = None
     if not args.no_cpu_baseline and len(cams) == 1:
         threads = min(16, os.cpu_count() or 1)
         log("timing the FP64 oracle on the whole view, %d runs on %d threads" % (args.cpu_repeats, threads))
         cpu = cpu_baseline(scene_sorted, cam, args.cpu_repeats, threads)
+        cpu["host_cpus"] = os.cpu_count()
+        cpu["cpu_model"] = cpu_model()
 
     out = {
         "metric": METRIC,
@@ -593,6 +697,7 @@ def main():
         "p99_ms": round(percentile(times, 99), 4),
         "stages_ms": stages,
         "morton_reorder_ms": round(morton_ms, 3),
+        "morton_reorder_cold_ms": round(morton_cold_ms, 3),
         "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
@@ -604,6 +709,7 @@ def main():
         "densify": dens,
         "serving": serving,
         "roofline": roof,
+        "step_roofline": step_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

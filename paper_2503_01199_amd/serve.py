@@ -319,25 +319,35 @@ def resident_scenes(rasterizer, sizes=(100_000, 500_000, 1_000_000, 2_000_000)):
 
 
 def serve_benchmark(rasterizer, n_warmup=200, n_measured=3000, rate=200.0, budget_bytes=4 << 30, slots=8,
-                    sizes=(100_000, 500_000, 1_000_000, 2_000_000), log=None):
+                    sizes=(100_000, 500_000, 1_000_000, 2_000_000), log=None, more_rates=()):
     """The serving stream: resident scenes, Poisson arrivals, FP16-blend forward;
-    returns the latency / throughput summary over the measured requests."""
+    returns the latency / throughput summary over the measured requests. more_rates:
+    further streams over the same resident scenes at other arrival rates (past
+    capacity, views/s saturates and batches grow), summarised under "rate_sweep"."""
     from . import scenes as S
     res, radii = resident_scenes(rasterizer, sizes)
     ex = GpuExecutor(rasterizer, res, slots=slots)
     for name in res:
         for az in (0.0, 90.0, 180.0, 270.0):
             ex.calibrate(name, S.orbit_camera(az, 10.0, radius=radii[name], width=512, height=512, fov_x=60.0))
-    reqs = request_stream(radii, n_warmup + n_measured, rate)
-    if log:
-        log("serving %d requests at %.0f/s over %d scenes (budget %.1f GiB, %d slots)"
-            % (len(reqs), rate, len(res), budget_bytes / 2 ** 30, slots))
-    sched = Scheduler(ex, budget_bytes, slots=slots)
-    stats = sched.run(reqs)
-    out = stats.summary(warmup=n_warmup)
-    out["rate_per_s"] = rate
-    out["budget_bytes"] = int(budget_bytes)
-    out["scenes"] = sorted(res)
+    out = None
+    sweep = []
+    for r in (rate,) + tuple(more_rates):
+        reqs = request_stream(radii, n_warmup + n_measured, r)
+        if log:
+            log("serving %d requests at %.0f/s over %d scenes (budget %.1f GiB, %d slots)"
+                % (len(reqs), r, len(res), budget_bytes / 2 ** 30, slots))
+        sched = Scheduler(ex, budget_bytes, slots=slots)
+        stats = sched.run(reqs)
+        summ = stats.summary(warmup=n_warmup)
+        summ["rate_per_s"] = r
+        if out is None:
+            out = summ
+            out["budget_bytes"] = int(budget_bytes)
+            out["scenes"] = sorted(res)
+        else:
+            sweep.append(summ)
+    out["rate_sweep"] = sweep
     return out
 
 

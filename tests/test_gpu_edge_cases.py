@@ -48,23 +48,23 @@ def _with_background(sc_front, n=300, salt=0, W=32, H=32):
 
 
 def test_alpha_clamp_forward_and_zero_derivative(rz):
-    """Two large Gaussians with opacity 0.999 (alpha clamped to 0.99 wherever
-    o G > 0.99) in front of random ones: the clamped pixels' opacity derivative is
-    zero on both sides, and the front Gaussians' opacity gradients come only from
-    the rim where the clamp does not hold."""
+    """A large Gaussian with opacity 0.999 (alpha clamped to 0.99 wherever
+    o G > 0.99, about a hundred pixels) and one of opacity 0.7 behind it, in front
+    of random ones: at the clamped pixels the front Gaussian's opacity derivative is
+    zero on both sides, so its opacity gradient comes only from the rim where the
+    clamp does not hold. (Two clamped Gaussians in a row would leave T exactly at
+    the 1e-4 stop, a fragile decision.)"""
     cam = camera(W=32, H=32, f=32.0, cx=16.5, cy=16.5, bg=(0.2, 0.3, 0.1))
-    front = gaussians([[0, 0, 2.0], [0.3, -0.2, 2.5]], [math.log(0.8), math.log(0.5), math.log(0.6)],
-                      [0.9, 0.1, -0.2, 0.3], [0.999, 0.999], [[0.9, 0.2, 0.4], [0.1, 0.8, 0.3]])
+    front = gaussians([[0, 0, 2.0], [0.3, -0.2, 2.5]], [math.log(3.0), math.log(2.5), math.log(2.8)],
+                      [0.9, 0.1, -0.2, 0.3], [0.999, 0.7], [[0.9, 0.2, 0.4], [0.1, 0.8, 0.3]])
     sc = _with_background(front, salt=1)
     pp = orc.preprocess(sc, cam)
     py, px = np.mgrid[0:32, 0:32]
-    clamped = np.zeros((32, 32), bool)
-    for i in range(2):
-        dx, dy = px + 0.5 - pp["u"][i], py + 0.5 - pp["v"][i]
-        a, b, c = pp["conic"][i]
-        clamped |= pp["opacity"][i] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)) > 0.99
+    dx, dy = px + 0.5 - pp["u"][0], py + 0.5 - pp["v"][0]
+    a, b, c = pp["conic"][0]
+    clamped = pp["opacity"][0] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy)) > 0.99
     print("clamped pixels: %d" % clamped.sum())
-    assert clamped.sum() > 100
+    assert clamped.sum() > 80
     full_parity(rz, sc, [cam], "alpha clamp", salt=1)
 
 
