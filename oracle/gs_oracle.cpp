@@ -59,6 +59,7 @@ struct Camera {
   double t[3];
   double near_plane;
   double bg[3];
+  int radius_mode;  // tile membership: 0 the alpha >= 1/255 ellipse's box, 1 the 3-sigma square
 };
 
 Camera unpack_camera(const double* c) {
@@ -70,6 +71,7 @@ Camera unpack_camera(const double* c) {
   for (int i = 0; i < 3; ++i) k.t[i] = c[15 + i];
   k.near_plane = c[18];
   for (int i = 0; i < 3; ++i) k.bg[i] = c[19 + i];
+  k.radius_mode = (int)c[22];
   return k;
 }
 
@@ -265,17 +267,29 @@ void project(const Scene& sc, int64_t i, const Camera& cam, Proj& p) {
     p.rgb[ch] = p.rgb_raw[ch] < 0 ? 0.0 : p.rgb_raw[ch];
   }
   if (p.o < kAlphaMin) return;
-  // Support: alpha = min(0.99, o G) >= 1/255 exactly where the quadratic form
-  // d^T Q d <= 2 ln(255 o). The axis-aligned box of that ellipse has half
-  // widths sqrt(2 ln(255 o) cov_xx) and sqrt(2 ln(255 o) cov_yy); a pixel
+  auto near_int = [](double a) { return std::fabs(a - std::nearbyint(a)) < kFragRect; };
+  // Support (App. A.1 tile culling: tiles where the Gaussian has decayed to almost
+  // nothing are left out). radius_mode 0: alpha = min(0.99, o G) >= 1/255 exactly
+  // where the quadratic form d^T Q d <= 2 ln(255 o); the axis-aligned box of that
+  // ellipse has half widths sqrt(2 ln(255 o) cov_xx) and sqrt(2 ln(255 o) cov_yy).
+  // radius_mode 1: the square of half width r = ceil(3 sqrt(lambda_max)), lambda_max
+  // the larger eigenvalue of the screen covariance (the 3-sigma bound). A pixel
   // (px, py) has its centre at (px + 1/2, py + 1/2).
-  const double Kq = 2.0 * std::log(255.0 * p.o);
-  const double rx = std::sqrt(Kq * p.cov[0]);
-  const double ry = std::sqrt(Kq * p.cov[2]);
+  double rx, ry;
+  if (cam.radius_mode == 1) {
+    const double m = 0.5 * (p.cov[0] + p.cov[2]);
+    const double lam = m + std::sqrt(std::max(0.0, m * m - det));
+    const double r3 = 3.0 * std::sqrt(lam);
+    rx = ry = std::ceil(r3);
+    p.rect_fragile = near_int(r3);
+  } else {
+    const double Kq = 2.0 * std::log(255.0 * p.o);
+    rx = std::sqrt(Kq * p.cov[0]);
+    ry = std::sqrt(Kq * p.cov[2]);
+  }
   const double ex0 = p.u - rx - 0.5, ex1 = p.u + rx - 0.5;
   const double ey0 = p.v - ry - 0.5, ey1 = p.v + ry - 0.5;
-  auto near_int = [](double a) { return std::fabs(a - std::nearbyint(a)) < kFragRect; };
-  p.rect_fragile = near_int(ex0) || near_int(ex1) || near_int(ey0) || near_int(ey1);
+  p.rect_fragile = p.rect_fragile || near_int(ex0) || near_int(ex1) || near_int(ey0) || near_int(ey1);
   double x0 = std::ceil(ex0), x1 = std::floor(ex1), y0 = std::ceil(ey0), y1 = std::floor(ey1);
   x0 = std::max(x0, 0.0); y0 = std::max(y0, 0.0);
   x1 = std::min(x1, (double)(cam.W - 1)); y1 = std::min(y1, (double)(cam.H - 1));
@@ -285,6 +299,16 @@ void project(const Scene& sc, int64_t i, const Camera& cam, Proj& p) {
   p.rect[2] = p.pxr[2] / kTile; p.rect[3] = p.pxr[3] / kTile;
   p.tiles = (p.rect[1] - p.rect[0] + 1) * (p.rect[3] - p.rect[2] + 1);
   p.valid = 1;
+  if (cam.radius_mode == 1) {
+    // The 3-sigma square can cut through the alpha >= 1/255 set, so membership is
+    // no longer implied by alpha: the rasterizer evaluates a Gaussian at every
+    // pixel of the tiles its rect covers, and nowhere else. The pixel footprint
+    // becomes those tiles' pixels, which every candidate list below applies.
+    p.pxr[0] = p.rect[0] * kTile;
+    p.pxr[1] = std::min(p.rect[1] * kTile + kTile - 1, cam.W - 1);
+    p.pxr[2] = p.rect[2] * kTile;
+    p.pxr[3] = std::min(p.rect[3] * kTile + kTile - 1, cam.H - 1);
+  }
 }
 
 // Exponent of Eq. (2)/(7) at pixel (px, py): E = -1/2 (a dx^2 + 2 b dx dy + c dy^2),
@@ -372,6 +396,7 @@ void composite(const std::vector<Proj>& P, const std::vector<int64_t>& list, int
 // give the same image; mode 2 gives list positions comparable to a tiled walk.
 struct Lists {
   int mode;
+  bool membership;  // radius_mode 1: a Gaussian belongs to the pixels of its rect's tiles only
   std::vector<int64_t> all;                  // mode 0, depth-sorted
   std::vector<std::vector<int64_t>> rows;    // mode 1, per row (unsorted)
   std::vector<std::vector<int64_t>> tiles;   // mode 2, per tile, depth-sorted
@@ -380,6 +405,7 @@ struct Lists {
 
 void build_lists(const std::vector<Proj>& P, const Camera& cam, int mode, int y_lo, int y_hi, Lists& L) {
   L.mode = mode;
+  L.membership = cam.radius_mode == 1;
   const int64_t n = (int64_t)P.size();
   if (mode == 0) {
     for (int64_t i = 0; i < n; ++i)
@@ -412,7 +438,13 @@ void build_lists(const std::vector<Proj>& P, const Camera& cam, int mode, int y_
 void pixel_list(const std::vector<Proj>& P, const Lists& L, int px, int py, std::vector<int64_t>& out) {
   out.clear();
   if (L.mode == 0) {
-    out = L.all;
+    if (!L.membership) {
+      out = L.all;
+    } else {  // the 3-sigma bound's tile membership applies to the brute force as well
+      for (int64_t i : L.all)
+        if (P[i].valid && P[i].pxr[0] <= px && px <= P[i].pxr[1] && P[i].pxr[2] <= py && py <= P[i].pxr[3])
+          out.push_back(i);
+    }
   } else if (L.mode == 1) {
     for (int64_t i : L.rows[py])
       if (P[i].pxr[0] <= px && px <= P[i].pxr[1]) out.push_back(i);

@@ -418,6 +418,99 @@ def test_fragment_count_slack_covers_an_alpha_flip_that_moves_the_stop(orc):
     assert _check_slack_across(orc, sc, cam, 0, xa, xb) == 2
 
 
+# ------------------------------------------------------------------ 3-sigma tile membership (radius_mode 1)
+def test_three_sigma_rect_by_brute_force(orc):
+    """radius_mode 1: the tile rect covers the pixels whose centres lie in the square
+    of half width ceil(3 sqrt(lambda_max)) around the screen mean, lambda_max from
+    numpy's eigenvalues of the screen covariance; brute force over pixel centres."""
+    sc = scenes.tiny_scene(400, seed_salt=12)
+    cam = scenes.tiny_camera(100, 75)
+    pp = orc.preprocess(sc, cam, radius_mode=1)
+    checked = 0
+    for i in range(sc.n):
+        if not pp["valid"][i] or pp["rect_fragile"][i]:
+            continue
+        a, b, c = pp["cov"][i]
+        lam = np.linalg.eigvalsh(np.array([[a, b], [b, c]])).max()
+        r = math.ceil(3 * math.sqrt(lam))
+        xs = [x for x in range(cam.width) if abs(x + 0.5 - pp["u"][i]) <= r]
+        ys = [y for y in range(cam.height) if abs(y + 0.5 - pp["v"][i]) <= r]
+        assert xs and ys
+        assert list(pp["rect"][i]) == [xs[0] // 16, xs[-1] // 16, ys[0] // 16, ys[-1] // 16], i
+        checked += 1
+    assert checked > 200
+    # the opacity-aware box is wider for opaque Gaussians, narrower for faint ones
+    p0 = orc.preprocess(sc, cam)
+    both = p0["valid"] & pp["valid"]
+    w1 = (pp["rect"][:, 1] - pp["rect"][:, 0])[both]
+    w0 = (p0["rect"][:, 1] - p0["rect"][:, 0])[both]
+    assert (w1 != w0).any()
+
+
+@pytest.mark.parametrize("W,H,salt", [(128, 128, 0), (100, 75, 1)])
+def test_three_sigma_brute_force_equals_footprint_and_tiled(orc, W, H, salt):
+    """Under radius_mode 1 the brute force applies the rects' tile membership too:
+    brute force, per-pixel footprint and per-tile lists give one image."""
+    sc = scenes.tiny_scene(600, seed_salt=salt)
+    cam = scenes.tiny_camera(W, H)
+    imgs = [orc.render(sc, cam, mode=m, radius_mode=1)["image"] for m in (0, 1, 2)]
+    assert np.abs(imgs[0] - imgs[1]).max() < 1e-13
+    assert np.abs(imgs[0] - imgs[2]).max() < 1e-13
+    # and the bound matters on this scene
+    assert np.abs(imgs[0] - orc.render(sc, cam, mode=0)["image"]).max() > 1e-3
+
+
+def test_three_sigma_truncates_at_the_rect(orc):
+    """An opaque Gaussian (o = 0.99: alpha >= 1/255 out to 3.33 sigma) whose 3-sigma
+    square ends inside the image: pixels of tiles beyond the rect get nothing under
+    radius_mode 1 although their alpha passes 1/255, while pixels of covered tiles are
+    unchanged."""
+    cam = _cam(W=128, H=128, f=64.0, cx=64.0, cy=64.0)
+    # screen sigma 15 px: the 3-sigma square [19.5, 108.5] stays in tiles 1..6 while
+    # alpha >= 1/255 reaches 3.33 sigma, into tiles 0 and 7
+    s = math.sqrt(15.0 ** 2 - 0.3) * 2.0 / 64.0
+    sc = _one_gaussian([0, 0, 2.0], math.log(s), [1, 0, 0, 0], 0.99, [0.8, 0.6, 0.4])
+    pp = orc.preprocess(sc, cam, radius_mode=1)
+    x0, x1, y0, y1 = pp["rect"][0]
+    assert [x0, x1, y0, y1] == [1, 6, 1, 6] and list(orc.preprocess(sc, cam)["rect"][0]) == [0, 7, 0, 7]
+    full = orc.render(sc, cam, mode=0)["image"]
+    cut = orc.render(sc, cam, mode=0, radius_mode=1)["image"]
+    inside = np.zeros((128, 128), bool)
+    inside[16 * y0:16 * (y1 + 1), 16 * x0:16 * (x1 + 1)] = True
+    assert np.array_equal(cut[:, inside], full[:, inside])
+    assert cut[:, ~inside].max() == 0.0 and full[:, ~inside].max() > 1e-3
+
+
+def test_three_sigma_gradients_by_central_differences(orc):
+    """The backward under radius_mode 1 walks the same lists: FP64 analytic gradient
+    against central differences (stencils that change a blended set skipped)."""
+    sc, cam = _small_scene(24, 0, 7)
+    rng = np.random.default_rng(19)
+    g = rng.uniform(-1, 1, (3, cam.height, cam.width))
+    bw = orc.backward(sc, cam, g, mode=0, threads=1, radius_mode=1)
+
+    def loss(s):
+        out = orc.render(s, cam, mode=0, threads=1, radius_mode=1)
+        return float(np.sum(out["image"] * g)), out["n_blended"]
+    checked = 0
+    for field in ("means", "log_scales", "opacity_logits", "sh"):
+        arr = getattr(sc, field).reshape(-1)
+        grad = bw[field].reshape(-1)
+        for idx in rng.choice(arr.size, size=min(arr.size, 16), replace=False):
+            x = np.float32(arr[idx])
+            h = np.float32(max(1.0, abs(float(x))) * 3e-5)
+            xp, xm = np.float32(x + h), np.float32(x - h)
+            Lp, nbp = loss(_set(sc, field, idx, xp))
+            Lm, nbm = loss(_set(sc, field, idx, xm))
+            if not np.array_equal(nbp, nbm):
+                continue
+            fd = (Lp - Lm) / (float(xp) - float(xm))
+            scale = max(abs(grad[idx]), 1e-3 * np.abs(grad).max(), 1e-8)
+            assert abs(fd - grad[idx]) <= 2e-5 * scale + 1e-10, (field, idx, fd, grad[idx])
+            checked += 1
+    assert checked > 30
+
+
 # ------------------------------------------------------------------ P5: scanline algebra
 def test_scanline_identity():
     """Basic + Linear j + Quad j^2 equals the exponent at (dx, dy - j) (App. A.2, Eq. (8)-(9))."""
