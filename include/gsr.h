@@ -237,6 +237,21 @@ gsr_status gsr_raster_batch_workspace_size(gsr_context *ctx, int32_t n, const vo
 gsr_status gsr_raster_batch(gsr_context *ctx, int32_t n, const void *const *workspaces, float *const *const *images,
                             int32_t precision, void *batch_ws, size_t batch_ws_bytes, void *stream);
 
+/* gsr_raster_batch for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * launch, with the work-item list in a device-resident scratch array of the library
+ * instead of a batch workspace, so the call allocates nothing (the frames' own
+ * workspaces, prepared by gsr_prepare, and the images are still the caller's).
+ * The scratch holds the items of at most GSR_NOALLOC_MAX_TILES tiles over all n
+ * frames (1.8 MB per GPU, held until the process ends); a larger batch returns
+ * GSR_ERR_INVALID_ARG before any launch. Every call on one GPU shares that GPU's
+ * scratch and leaves its contents there: calls that overlap on one GPU (on
+ * different streams, unordered) race and must not be issued. Everything else is
+ * as gsr_raster_batch, whose images it reproduces bit for bit. */
+#define GSR_NOALLOC_MAX_TILES 262144
+gsr_status gsr_raster_batch_noalloc(gsr_context *ctx, int32_t n, const void *const *workspaces,
+                                    float *const *const *images, int32_t precision, void *stream);
+
 /* Backward of the last gsr_forward on `workspace` with the same scene, cameras and
  * options (Sec. 3, Eq. (3); App. A.1-A.2). dL_dimages[v] is a device pointer to
  * f32 [3, height_v, width_v]. grads are overwritten; stats (nullable; used when

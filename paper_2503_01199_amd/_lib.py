@@ -24,6 +24,7 @@ GSR_TILE = 16
 GSR_CLUSTER = 128
 GSR_MAX_VIEWS = 64
 GSR_MAX_BATCH = 16
+GSR_NOALLOC_MAX_TILES = 262144
 
 STATUS_NAMES = {0: "GSR_OK", 1: "GSR_ERR_INVALID_ARG", 2: "GSR_ERR_WORKSPACE_TOO_SMALL", 3: "GSR_ERR_DEVICE",
                 4: "GSR_ERR_UNSUPPORTED"}
@@ -102,6 +103,8 @@ EXPORTS = {
                                                   ctypes.POINTER(c_size_t)]),
     "gsr_raster_batch": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p), ctypes.POINTER(ctypes.POINTER(c_void_p)),
                                    c_int32, c_void_p, c_size_t, c_void_p]),
+    "gsr_raster_batch_noalloc": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p),
+                                           ctypes.POINTER(ctypes.POINTER(c_void_p)), c_int32, c_void_p]),
     "gsr_variance": (c_int32, [c_void_p, ctypes.POINTER(GsrStats), c_int64, c_void_p, c_void_p]),
     "gsr_morton_workspace_size": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_size_t)]),
     "gsr_morton_order": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),

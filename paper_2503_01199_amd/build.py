@@ -24,7 +24,7 @@ LIB = os.path.join(PKG, "libgsr.so")
 ARCH = "gfx950"
 
 SOURCES = ["scan.hip", "onesweep.hip", "cluster.hip", "preprocess.hip", "binning.hip", "raster_fwd.hip", "adam.hip", "densify.hip",
-           "raster_bwd.hip", "morton.hip", "api.cpp"]
+           "raster_bwd.hip", "morton.hip", "noalloc.hip", "api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

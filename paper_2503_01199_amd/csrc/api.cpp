@@ -296,6 +296,8 @@ gsr_status gsr_context_create(int device, gsr_context** out) {
   *out = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return GSR_ERR_DEVICE;
+  // the device's copy of the no-allocation scratch, looked up once per device
+  if (gsr::noalloc_init(device) != hipSuccess) return GSR_ERR_DEVICE;
   gsr_context* ctx = new gsr_context();
   ctx->device = device;
   *out = ctx;
@@ -499,8 +501,15 @@ gsr_status gsr_raster_batch_workspace_size(gsr_context* ctx, int32_t n, const vo
   return GSR_OK;
 }
 
-gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* workspaces, float* const* const* images,
-                            int32_t precision, void* batch_ws, size_t batch_ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One batched raster over n prepared frames. With batch_ws set, the work-item list
+// lives in the caller's batch workspace; with batch_ws null (the no-allocation
+// entry point), in the device-resident scratch of ctx's device.
+gsr_status raster_batch_impl(gsr_context* ctx, int32_t n, const void* const* workspaces, float* const* const* images,
+                             int32_t precision, void* batch_ws, size_t batch_ws_bytes, bool resident, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   if (n < 1 || n > gsr::kMaxBatch || !workspaces || !images)
     return fail(ctx, GSR_ERR_INVALID_ARG, "n = %d not in [1, %d] or NULL arrays", n, gsr::kMaxBatch);
@@ -545,16 +554,30 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
   if (tiles >= ((uint64_t)1 << 28)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles in a batch (limit 2^28)");
   tab.first[n] = (uint32_t)tiles;
   tab.n = n;
-  const size_t need = batch_workspace_bytes(tiles);
-  if (!batch_ws || batch_ws_bytes < need) {
-    ctx->required = need;
-    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "batch workspace of %zu bytes < %zu", batch_ws_bytes, need);
+  uint32_t* order = nullptr;
+  uint32_t* n_items = nullptr;
+  if (resident) {
+    if ((int64_t)tiles > gsr::noalloc_max_tiles())
+      return fail(ctx, GSR_ERR_INVALID_ARG, "%llu tiles exceed the %lld of the device-resident scratch",
+                  (unsigned long long)tiles, (long long)gsr::noalloc_max_tiles());
+    size_t words = 0;
+    order = gsr::noalloc_scratch(ctx->device, &words);
+    if (!order) return fail(ctx, GSR_ERR_DEVICE, "the device-resident scratch was not set up");
+    n_items = order + batch_items_words(tiles);
+    if (batch_items_words(tiles) + 1 > words) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: scratch too small");
+  } else {
+    const size_t need = batch_workspace_bytes(tiles);
+    if (!batch_ws || batch_ws_bytes < need) {
+      ctx->required = need;
+      return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "batch workspace of %zu bytes < %zu", batch_ws_bytes, need);
+    }
+    if (((uintptr_t)batch_ws & (kAlign - 1)) != 0)
+      return fail(ctx, GSR_ERR_INVALID_ARG, "batch workspace not aligned");
+    order = static_cast<uint32_t*>(batch_ws);
+    n_items = order + batch_items_words(tiles);
   }
-  if (((uintptr_t)batch_ws & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "batch workspace not aligned");
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  uint32_t* order = static_cast<uint32_t*>(batch_ws);
-  uint32_t* n_items = order + batch_items_words(tiles);
   gsr::launch_batch_tile_order(tab, (uint32_t)tiles, ctx->split_len, order, n_items, s);
   const bool attached = gsr::launch_raster_fwd_batch(tab, order, n_items, (uint32_t)tiles, ip, precision, s,
                                                      frs[0]->done);
@@ -565,6 +588,20 @@ gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* work
     frs[i]->precision = precision;
   }
   return GSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_status gsr_raster_batch(gsr_context* ctx, int32_t n, const void* const* workspaces, float* const* const* images,
+                            int32_t precision, void* batch_ws, size_t batch_ws_bytes, void* stream) {
+  return raster_batch_impl(ctx, n, workspaces, images, precision, batch_ws, batch_ws_bytes, false, stream);
+}
+
+gsr_status gsr_raster_batch_noalloc(gsr_context* ctx, int32_t n, const void* const* workspaces,
+                                    float* const* const* images, int32_t precision, void* stream) {
+  return raster_batch_impl(ctx, n, workspaces, images, precision, nullptr, 0, true, stream);
 }
 
 gsr_status gsr_frame_release(gsr_context* ctx, const void* workspace) {

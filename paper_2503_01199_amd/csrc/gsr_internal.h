@@ -240,6 +240,13 @@ static_assert(sizeof(FrameTable) + sizeof(ImagePtrs) <= 3584, "the batch table t
 bool launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const uint32_t* n_items,
                              uint32_t total_tiles, const ImagePtrs& images, int precision, hipStream_t s,
                              hipEvent_t done);
+// noalloc.hip: the device-resident scratch of gsr_raster_batch_noalloc (work items
+// of at most noalloc_max_tiles() tiles, then their count). noalloc_init(device)
+// looks up the device's copy once (hipGetSymbolAddress with the device current);
+// noalloc_scratch returns it (null before init) and its size in words.
+int64_t noalloc_max_tiles();
+hipError_t noalloc_init(int device);
+uint32_t* noalloc_scratch(int device, size_t* words);
 // Raster work items of the concatenated tiles of a batch of frames (n_items <- count).
 void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32_t split_len, uint32_t* order,
                              uint32_t* n_items, hipStream_t s);

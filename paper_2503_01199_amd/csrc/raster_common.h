@@ -33,7 +33,7 @@ constexpr int kStripStep = 4;
 constexpr uint32_t kItemWhole = 4;
 constexpr uint32_t kItemHalf = 5;
 constexpr int64_t kSplitShare = 4;
-__host__ __device__ inline int64_t max_items(int64_t tiles) { return tiles + 3 * ((tiles + kSplitShare - 1) / kSplitShare); }
+__host__ __device__ constexpr int64_t max_items(int64_t tiles) { return tiles + 3 * ((tiles + kSplitShare - 1) / kSplitShare); }
 // Row offsets s_j of the strip's pixels from its anchor, the centre row of the strip
 // (anchoring at the centre halves the largest offset, and so the extrapolation of the
 // scanline form, against anchoring at the first pixel).
