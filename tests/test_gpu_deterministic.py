@@ -65,7 +65,9 @@ def test_deterministic_gradients_match_oracle(rz, which):
     grads = {k: out[k] for k in GROUPS}
     stats = {k: out["stat_" + k] for k in ("S", "M", "C")}
     if which in ("mean-loss", "room-mean-loss"):
-        assert np.abs(ref["S"]).max() < 1e-8  # the scale at which a fixed 2^-32 step lost S
+        # per-tile square sums far below a fixed 2^-32 step, which rounded them to 0
+        print("oracle S: max %.3g" % np.abs(ref["S"]).max())
+        assert max(float(np.abs(g).max()) for g in gI) < 1e-4
     compare(grads, stats, ref, "deterministic %s" % which, logits=sc.opacity_logits)
 
 
