@@ -411,9 +411,9 @@ def main():
 
     from paper_2503_01199_amd import _lib as L
 
-    def step(check=False, precision=L.GSR_FP32, deterministic=False):
+    def step(check=False, precision=L.GSR_FP32, deterministic=False, radius_mode=0):
         fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision,
-                        deterministic=deterministic)
+                        deterministic=deterministic, radius_mode=radius_mode)
         for img, (w, gt), dl in zip(fr.images, wgt, dls):
             rz.l1_grad(img, w, gt, out=dl)
         rz.backward(fr, dls, grads=grads, stats=stats)
@@ -522,6 +522,33 @@ def main():
     std = {k: round(sum(v) / len(v), 4) for k, v in accd.items()}
     det = {"ms_per_step": round(det_ms, 4), "raster_bwd_ms": std.get("raster_bwd"),
            "zero_grad_ms": std.get("zero_grad")}
+
+    # the 3-sigma tile-membership bound instead of the exact alpha >= 1/255 box (a
+    # different image: every pixel of a covered tile, and only those, evaluates the
+    # Gaussian), same protocol
+    log("timing %d steps with the 3-sigma bound" % args.steps)
+    fr3 = step(check=True, radius_mode=1)
+    inst3 = int(fr3.info["instances"])
+    for _ in range(max(args.warmup, 1)):
+        step(radius_mode=1)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        fr3 = step(radius_mode=1)
+    torch.cuda.synchronize()
+    r3_ms = (time.perf_counter() - wall0) * 1e3 / args.steps
+    rz.check_frame(fr3)
+    rz.set_profiling(True)
+    acc3 = {}
+    for _ in range(args.steps):
+        step(radius_mode=1)
+        for k, v in rz.stage_times().items():
+            if v >= 0:
+                acc3.setdefault(k, []).append(v)
+    rz.set_profiling(False)
+    st3 = {k: round(sum(v) / len(v), 4) for k, v in acc3.items()}
+    radius3 = {"ms_per_step": round(r3_ms, 4), "instances": inst3, "stages_ms": st3}
+    step(check=True)  # back to the default bound's frame
 
     # raster schedule sweep (F4): the list length above which a tile is rastered as
     # band items, 1 pixel per lane in the forward's four 16x4 bands, 2 in the
@@ -702,6 +729,7 @@ def main():
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
         "deterministic": det,
+        "radius_3sigma": radius3,
         "schedule_sweep": sweep,
         "view_cycle": cycle,
         "sparse_adam": adam,

@@ -107,6 +107,14 @@ typedef struct {
                            (the statistic's square sum: 2^(2E-32)) and saturates at
                            2^31 times that power. The workspace grows by 96 B per
                            record; forward and backward must agree. 0: FP32 atomics. */
+  int32_t radius_mode;  /* tile membership of a Gaussian (App. A.1 tile culling leaves out
+                           tiles where it has decayed to almost nothing): 0 (default) the
+                           tiles of the pixel-centre box of its alpha >= 1/255 ellipse, so
+                           tiling is exact; 1 the tiles of the pixel-centre box of the square
+                           of half width ceil(3 sqrt(lambda_max)), lambda_max the larger
+                           eigenvalue of the screen covariance (the 3-sigma bound, which cuts
+                           through the alpha >= 1/255 set of opaque Gaussians: a pixel blends
+                           a Gaussian only if its tile is in the rect). */
 } gsr_options;
 
 /* Parameter gradients, device memory, the shapes of gsr_scene's arrays. Overwritten

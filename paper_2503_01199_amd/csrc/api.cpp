@@ -149,6 +149,7 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   if (o->stats != 0 && o->stats != 1) return fail(ctx, GSR_ERR_INVALID_ARG, "stats must be 0 or 1");
   if (o->deterministic != 0 && o->deterministic != 1)
     return fail(ctx, GSR_ERR_INVALID_ARG, "deterministic must be 0 or 1");
+  if (o->radius_mode != 0 && o->radius_mode != 1) return fail(ctx, GSR_ERR_INVALID_ARG, "radius_mode must be 0 or 1");
   return GSR_OK;
 }
 
@@ -364,6 +365,7 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   const size_t total = plan_frame(scene, cams, V, cap, fixed, workspace, f);
   f.split_len = ctx->split_len;
   f.split_len_bwd = ctx->split_len_bwd;
+  f.radius_mode = opts->radius_mode;
   if (total > ws_bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "internal: workspace plan exceeds its size");
 
   FrameRecord& fr = ctx->frames[workspace];

@@ -145,6 +145,7 @@ struct Frame {
   unsigned long long* grad2d_fx;  // [nrec][12] fixed-point sums (deterministic backward), else null
   uint32_t split_len = kSplitLen;         // forward: tiles with longer lists are rastered as four bands
   uint32_t split_len_bwd = kSplitLenBwd;  // backward: tiles with longer lists are walked as two halves
+  int32_t radius_mode = 0;                // tile membership: 0 the alpha >= 1/255 box, 1 the 3-sigma square
   uint32_t* ctl;            // look-back / histogram control words, cleared with the header
   size_t ctl_words;
   uint32_t *ctl_cluster_scan, *ctl_depth_sort, *ctl_offsets_scan, *ctl_tile_sort;

@@ -306,7 +306,8 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
                                                              uint32_t* __restrict__ tiles,
                                                              ushort4* __restrict__ rect,
                                                              float* __restrict__ grad2d,
-                                                             unsigned long long* __restrict__ grad_fx) {
+                                                             unsigned long long* __restrict__ grad_fx,
+                                                             int radius_mode) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   __shared__ float lsh[kThreads * (3 * K + 1)];  // the cluster's SH rows
   if (frame_aborted(header)) return;  // the cluster scan gave up: its list may be garbage
@@ -344,10 +345,18 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
     int x0 = 0, x1 = -1, y0 = 0, y1 = -1;
     if (ok) {
       // support box of d^T Q d <= 2 ln(255 o): half widths sqrt(K cov_xx), sqrt(K cov_yy);
+      // or (radius_mode 1) the 3-sigma square, half width ceil(3 sqrt(lambda_max));
       // pixel px covers the centre px + 1/2
-      const double Kq = 2.0 * log(255.0 * g.o);
-      const double rx = sqrt(Kq * pr.cov[0]);
-      const double ry = sqrt(Kq * pr.cov[2]);
+      double rx, ry;
+      if (radius_mode == 1) {
+        const double m = 0.5 * (pr.cov[0] + pr.cov[2]);
+        const double lam = m + sqrt(fmax(0.0, m * m - pr.det));
+        rx = ry = ceil(3.0 * sqrt(lam));
+      } else {
+        const double Kq = 2.0 * log(255.0 * g.o);
+        rx = sqrt(Kq * pr.cov[0]);
+        ry = sqrt(Kq * pr.cov[2]);
+      }
       double fx0 = ceil((pr.u - rx) - 0.5), fx1 = floor((pr.u + rx) - 0.5);
       double fy0 = ceil((pr.v - ry) - 0.5), fy1 = floor((pr.v + ry) - 0.5);
       fx0 = fmax(fx0, 0.0);
@@ -784,7 +793,8 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
   const unsigned grid = (unsigned)((f.ncap + kThreads - 1) / kThreads);
 #define GSR_PRE_FWD(D)                                                                                          \
   k_preprocess_fwd<D><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.ncap, f.header, f.cluster_list, f.compact2full, \
-                                                f.rec, f.dkey, f.tiles_touched, f.rect, f.grad2d, f.grad2d_fx)
+                                                f.rec, f.dkey, f.tiles_touched, f.rect, f.grad2d, f.grad2d_fx, \
+                                                f.radius_mode)
   switch (sc.sh_degree) {
     case 0: GSR_PRE_FWD(0); break;
     case 1: GSR_PRE_FWD(1); break;

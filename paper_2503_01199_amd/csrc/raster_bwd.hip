@@ -296,19 +296,36 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
 
 // max |dL/dI| over the views' images into header[kHdrGradMax] (zeroed before): the
 // bits of a non-negative float order as unsigned integers, so an atomic max on them
-// is the maximum whatever the order of the blocks.
+// is the maximum whatever the order of the blocks. A few blocks (one per CU) each
+// reduce a strided share with 16-byte loads and add one atomic: same-address
+// atomics serialise, so one per wave cost tens of microseconds.
+constexpr int kAbsMaxBlocks = 256;
 __global__ __launch_bounds__(256) void k_grad_absmax(ConstImagePtrs dL, ViewCounts counts, int32_t V,
                                                      uint32_t* __restrict__ header) {
+  __shared__ float wmax[4];
   if (frame_aborted(header)) return;
   float m = 0.0f;
+  const int64_t stride = (int64_t)gridDim.x * 256;
   for (int v = 0; v < V; ++v) {
     const float* g = dL.p[v];
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < counts.n[v]; i += (int64_t)gridDim.x * 256)
-      m = fmaxf(m, fabsf(g[i]));
+    const int64_t n = counts.n[v];
+    const bool aligned = (reinterpret_cast<uintptr_t>(g) & 15u) == 0;
+    const int64_t n4 = aligned ? n / 4 : 0;
+    const float4* g4 = reinterpret_cast<const float4*>(g);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+      const float4 x = g4[i];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+    }
+    for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) m = fmaxf(m, fabsf(g[i]));
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
-  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(header + kHdrGradMax, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    if (m > 0.0f) atomicMax(header + kHdrGradMax, __float_as_uint(m));
+  }
 }
 
 template <int P, bool kFixed>
@@ -325,7 +342,7 @@ void launch_grad_absmax(const Frame& f, const ConstImagePtrs& dL, const ViewCoun
   fill_u32(f.header + kHdrGradMax, 1, 0u, s);
   int64_t total = 0;
   for (int v = 0; v < f.V; ++v) total += counts.n[v];
-  const int64_t g = std::min<int64_t>(std::max<int64_t>((total + 255) / 256, 1), 2048);
+  const int64_t g = std::min<int64_t>(std::max<int64_t>((total + 1023) / 1024, 1), kAbsMaxBlocks);
   k_grad_absmax<<<(unsigned)g, 256, 0, s>>>(dL, counts, f.V, f.header);
 }
 

@@ -4,7 +4,7 @@
 // launch's duration; a band item walks the same list for a quarter of the pixels).
 //
 // Each lane walks its 4-pixel strip with the scanline exponent (App. A.2). The
-// tile's Gaussian records are staged through LDS in batches of 64 (one gather per
+// tile's Gaussian records are staged through LDS in batches of 32 (one gather per
 // lane, coalesced on the instance list, loaded straight into LDS and double
 // buffered so the next batch arrives during the current one), then read by the
 // whole wave as a broadcast. A pixel skips alpha < 1/255, clamps alpha at 0.99 and stops at the

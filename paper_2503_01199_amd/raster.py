@@ -164,27 +164,30 @@ class Rasterizer:
         return torch.cuda.current_stream(self.device).cuda_stream
 
     @staticmethod
-    def options(precision=L.GSR_FP32, cluster_cull=True, stats=True, deterministic=False) -> L.GsrOptions:
+    def options(precision=L.GSR_FP32, cluster_cull=True, stats=True, deterministic=False,
+                radius_mode=0) -> L.GsrOptions:
         o = L.GsrOptions()
         o.precision = int(precision)
         o.cluster_cull = 1 if cluster_cull else 0
         o.stats = 1 if stats else 0
         o.deterministic = 1 if deterministic else 0
+        o.radius_mode = int(radius_mode)
         return o
 
     # ------------------------------------------------------------------ forward / backward
     def forward(self, scene: SceneTensors, cameras, precision=L.GSR_FP32, cluster_cull=True, stats=True,
                 workspace: Workspace | None = None, images=None, check: bool = True,
-                deterministic: bool = False) -> Frame:
+                deterministic: bool = False, radius_mode: int = 0) -> Frame:
         """Renders the views. With check (the default) waits for the frame's counters
         and, when its instances did not fit the workspace, grows it and renders
         again; check=False returns right after enqueueing (info is then empty: call
         check_frame to wait, read the counters and learn whether it fitted).
         deterministic: the frame's backward sums per-tile gradients in fixed point
-        (bitwise reproducible gradients)."""
+        (bitwise reproducible gradients). radius_mode: 0 the exact alpha >= 1/255 tile
+        membership, 1 the 3-sigma bound."""
         V = len(cameras)
         cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
-        opts = self.options(precision, cluster_cull, stats, deterministic)
+        opts = self.options(precision, cluster_cull, stats, deterministic, radius_mode)
         sc = scene.struct()
         ws = workspace if workspace is not None else self.default_workspace
         if images is None:
@@ -217,12 +220,13 @@ class Rasterizer:
         raise L.GsrError(L.GSR_ERR_WORKSPACE_TOO_SMALL, "gsr_forward: workspace did not converge")
 
     def prepare(self, scene: SceneTensors, cameras, cluster_cull=True, stats=True,
-                workspace: Workspace | None = None, stream=None, deterministic: bool = False) -> Frame:
+                workspace: Workspace | None = None, stream=None, deterministic: bool = False,
+                radius_mode: int = 0) -> Frame:
         """Enqueues every stage before the raster (gsr_prepare) on `stream` (a
         torch.cuda.Stream; default the current stream); render with raster_batch."""
         V = len(cameras)
         cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
-        opts = self.options(L.GSR_FP32, cluster_cull, stats, deterministic)
+        opts = self.options(L.GSR_FP32, cluster_cull, stats, deterministic, radius_mode)
         sc = scene.struct()
         ws = workspace if workspace is not None else Workspace(self.device)
         if ws.buf is None:

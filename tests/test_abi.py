@@ -34,16 +34,26 @@ def test_binding_declares_every_symbol():
     assert set(header_functions()) == set(L.EXPORTS)
 
 
-def test_struct_layouts_match_header_sizes():
+STRUCTS = {"GsrScene": "gsr_scene", "GsrCamera": "gsr_camera", "GsrOptions": "gsr_options",
+           "GsrFrameInfo": "gsr_frame_info", "GsrFrameBuffers": "gsr_frame_buffers",
+           "GsrAdamOptions": "gsr_adam_options", "GsrDensifyOptions": "gsr_densify_options"}
+
+
+def test_struct_layouts_match_header_sizes(tmp_path):
+    """The binding's ctypes structures have the sizes the C compiler gives the
+    header's structures (compiled here with gcc against include/gsr.h)."""
+    import subprocess
     from paper_2503_01199_amd import _lib as L
-    # sizes follow from the header's field lists on LP64
-    assert ctypes.sizeof(L.GsrScene) == 8 + 8 + 5 * 8
-    assert ctypes.sizeof(L.GsrCamera) == 4 * (2 + 4 + 9 + 3 + 1 + 3)
-    assert ctypes.sizeof(L.GsrOptions) == 16
-    assert ctypes.sizeof(L.GsrFrameInfo) == 5 * 8 + 6 * 4
-    assert ctypes.sizeof(L.GsrFrameBuffers) == 13 * 8 + 2 * 64 * 8
-    assert ctypes.sizeof(L.GsrAdamOptions) == 9 * 4 + 4 + 8
-    assert ctypes.sizeof(L.GsrDensifyOptions) == 4 * 4 + 8
+    src = tmp_path / "sizes.c"
+    src.write_text("#include <stdio.h>\n#include \"gsr.h\"\nint main(void) {\n"
+                   + "".join('  printf("%%s %%zu\\n", "%s", sizeof(%s));\n' % (c, c) for c in STRUCTS.values())
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    sizes = dict((a, int(b)) for a, b in (ln.split() for ln in subprocess.check_output([str(exe)], text=True).split("\n")
+                                          if ln.strip()))
+    for py, c in STRUCTS.items():
+        assert ctypes.sizeof(getattr(L, py)) == sizes[c], (py, ctypes.sizeof(getattr(L, py)), sizes[c])
 
 
 def _scene(n=10, deg=0):
