@@ -295,9 +295,14 @@ def densify_leg(rz, st, stats, steps):
     return out
 
 
-def cpu_baseline(scene, cam, repeats, threads):
+def cpu_baseline(scene, cam, repeats, threads, gpu_forms=None):
     """The FP64 oracle's forward + backward of the whole view (the same scene, camera
-    and loss as the GPU step), timed `repeats` times; the median is reported."""
+    and loss as the GPU step; the loss gradient is zeroed on the pixels the oracle
+    flags as fragile), timed `repeats` times; the median is reported. With gpu_forms
+    (a callable taking that upstream gradient and returning, per GPU form, its image
+    and parameter gradients), the error of each form against the oracle's last run:
+    image max abs and normwise on non-fragile pixels; per gradient group normwise and
+    the largest element error relative to max(|g*|, 1e-3 of the group's largest)."""
     import numpy as np
     import oracle
     from paper_2503_01199_amd import scenes
@@ -309,12 +314,31 @@ def cpu_baseline(scene, cam, repeats, threads):
         t = time.perf_counter()
         r = oracle.render(scene, cam, mode=1, threads=threads)
         g = oracle.l1_grad(r["image"], w, gt)
-        oracle.backward(scene, cam, g, mode=1, threads=threads)
+        g[:, r["fragile"]] = 0.0
+        b = oracle.backward(scene, cam, g, mode=1, threads=threads)
         times.append(time.perf_counter() - t)
     med = sorted(times)[len(times) // 2]
-    return {"value": round(med * 1e3, 1), "unit": "ms/iter", "cores": threads, "kind": "oracle",
-            "sample": "FP64 oracle forward + backward of the whole %dx%d view, median of %d runs (%s s)"
-                      % (W, H, repeats, ", ".join("%.2f" % x for x in times))}
+    out = {"value": round(med * 1e3, 1), "unit": "ms/iter", "cores": threads, "kind": "oracle",
+           "sample": "FP64 oracle forward + backward of the whole %dx%d view, median of %d runs (%s s)"
+                     % (W, H, repeats, ", ".join("%.2f" % x for x in times))}
+    errors = None
+    if gpu_forms is not None:
+        keep = ~r["fragile"]
+        errors = {}
+        for name, (img, grads) in gpu_forms(g.astype(np.float32)).items():
+            d = (np.asarray(img, np.float64) - r["image"])[:, keep]
+            e = {"image_max_abs": float(np.abs(d).max()),
+                 "image_normwise": float(np.linalg.norm(d) / max(np.linalg.norm(r["image"][:, keep]), 1e-30))}
+            for k, ga in grads.items():
+                ref = b[k].reshape(ga.shape[0], -1)
+                gg = np.asarray(ga, np.float64).reshape(ref.shape)
+                floor = 1e-3 * max(np.abs(ref).max(), 1e-30)
+                e[k + "_normwise"] = float(np.linalg.norm(gg - ref) / max(np.linalg.norm(ref), 1e-30))
+                e[k + "_max_rel"] = float((np.abs(gg - ref) / np.maximum(np.abs(ref), floor)).max())
+            errors[name] = {k: float("%.3g" % v) for k, v in e.items()}
+        errors["pixels"] = int(keep.sum())
+        errors["fragile_pixels"] = int((~keep).sum())
+    return out, errors
 
 
 def main():
@@ -384,14 +408,14 @@ def main():
     morton_cold_ms = t0.elapsed_time(t1)
     # warm: the same reorder again (workspaces in place), median of 10
     warm = []
-    for _ in range(10):
+    for _ in range(0 if args.only_steps else 10):
         t0.record()
         perm, _ = rz.morton_order(st.means)
         arrays = rz.apply_permutation(perm, list(st.tensors()))
         t1.record()
         t1.synchronize()
         warm.append(t0.elapsed_time(t1))
-    morton_ms = sorted(warm)[len(warm) // 2]
+    morton_ms = sorted(warm)[len(warm) // 2] if warm else morton_cold_ms
     if args.order == "shuffled":
         perm = torch.randperm(st.n, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
         arrays = rz.apply_permutation(perm, list(st.tensors()))
@@ -411,9 +435,9 @@ def main():
 
     from paper_2503_01199_amd import _lib as L
 
-    def step(check=False, precision=L.GSR_FP32, deterministic=False, radius_mode=0):
+    def step(check=False, precision=L.GSR_FP32, deterministic=False, radius_mode=0, half_reduction=False):
         fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision,
-                        deterministic=deterministic, radius_mode=radius_mode)
+                        deterministic=deterministic, radius_mode=radius_mode, half_reduction=half_reduction)
         for img, (w, gt), dl in zip(fr.images, wgt, dls):
             rz.l1_grad(img, w, gt, out=dl)
         rz.backward(fr, dls, grads=grads, stats=stats)
@@ -424,6 +448,19 @@ def main():
     for _ in range(max(args.warmup - 1, 0)):
         fr = step()
     torch.cuda.synchronize()
+
+    if args.only_steps:  # profiler runs: the timed steps only
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        for _ in range(args.steps):
+            fr = step()
+        torch.cuda.synchronize()
+        info = rz.check_frame(fr)
+        print(json.dumps({"workload": desc, "order": args.order, "cluster_cull": cull, "ms_per_step":
+                          round((time.perf_counter() - wall0) * 1e3 / args.steps, 4), "steps": args.steps,
+                          "frames": 1 + max(args.warmup - 1, 0) + args.steps,
+                          "instances": info["instances"]}), flush=True)
+        return
 
     # algorithmic work of one step, from the frame state (outside the timed region)
     ins = rz.inspect(fr)
@@ -444,10 +481,6 @@ def main():
     wall = time.perf_counter() - wall0
     rz.check_frame(fr)  # the frame's instances fitted the workspace
     ms_per_step = wall * 1e3 / args.steps
-    if args.only_steps:
-        print(json.dumps({"workload": desc, "order": args.order, "cluster_cull": cull, "ms_per_step":
-                          round(ms_per_step, 4), "steps": args.steps, "instances": info["instances"]}), flush=True)
-        return
 
     # per-step latency: each step alone on the device, timed by events around it
     log("latency over %d single steps" % args.latency_iters)
@@ -500,6 +533,29 @@ def main():
     fp16 = {"ms_per_step": round(fp16_ms, 4), "raster_fwd_ms": st16.get("raster_fwd"),
             "raster_bwd_ms": st16.get("raster_bwd")}
 
+    # the FP16 blend with the forward's T in FP16 as well, same protocol
+    log("timing %d FP16-T steps" % args.steps)
+    for _ in range(max(args.warmup, 1)):
+        step(precision=L.GSR_FP16_BLEND_T)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        fr16t = step(precision=L.GSR_FP16_BLEND_T)
+    torch.cuda.synchronize()
+    fp16t_ms = (time.perf_counter() - wall0) * 1e3 / args.steps
+    rz.check_frame(fr16t)
+    rz.set_profiling(True)
+    acc16t = {}
+    for _ in range(args.steps):
+        step(precision=L.GSR_FP16_BLEND_T)
+        for k, v in rz.stage_times().items():
+            if v >= 0:
+                acc16t.setdefault(k, []).append(v)
+    rz.set_profiling(False)
+    st16t = {k: round(sum(v) / len(v), 4) for k, v in acc16t.items()}
+    fp16t = {"ms_per_step": round(fp16t_ms, 4), "raster_fwd_ms": st16t.get("raster_fwd"),
+             "raster_bwd_ms": st16t.get("raster_bwd")}
+
     # the deterministic backward (fixed-point per-tile sums) on the same protocol
     log("timing %d deterministic steps" % args.steps)
     step(check=True, deterministic=True)  # grows the workspace by the fixed-point rows
@@ -522,6 +578,29 @@ def main():
     std = {k: round(sum(v) / len(v), 4) for k, v in accd.items()}
     det = {"ms_per_step": round(det_ms, 4), "raster_bwd_ms": std.get("raster_bwd"),
            "zero_grad_ms": std.get("zero_grad")}
+
+    # the half2-packed colour/opacity gradient reduction (Sec. 3.1.2), same protocol
+    log("timing %d steps with the half2 gradient reduction" % args.steps)
+    step(check=True, half_reduction=True)
+    for _ in range(max(args.warmup, 1)):
+        step(half_reduction=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(half_reduction=True)
+    torch.cuda.synchronize()
+    h_ms = (time.perf_counter() - wall0) * 1e3 / args.steps
+    rz.set_profiling(True)
+    acch = {}
+    for _ in range(args.steps):
+        step(half_reduction=True)
+        for k, v in rz.stage_times().items():
+            if v >= 0:
+                acch.setdefault(k, []).append(v)
+    rz.set_profiling(False)
+    sth = {k: round(sum(v) / len(v), 4) for k, v in acch.items()}
+    half_red = {"ms_per_step": round(h_ms, 4), "raster_bwd_ms": sth.get("raster_bwd"),
+                "preprocess_bwd_ms": sth.get("preprocess_bwd")}
 
     # the 3-sigma tile-membership bound instead of the exact alpha >= 1/255 box (a
     # different image: every pixel of a covered tile, and only those, evaluates the
@@ -697,10 +776,25 @@ def main():
                                   more_rates=tuple(rates[1:]))
 
     cpu = None
+    err_report = None
     if not args.no_cpu_baseline and len(cams) == 1:
         threads = min(16, os.cpu_count() or 1)
         log("timing the FP64 oracle on the whole view, %d runs on %d threads" % (args.cpu_repeats, threads))
-        cpu = cpu_baseline(scene_sorted, cam, args.cpu_repeats, threads)
+
+        def gpu_forms(g):
+            """The GPU path's image and gradients for the oracle's upstream gradient, per
+            form: FP32, the FP16 blend, the FP16 blend with FP16 T, the half2 reduction."""
+            gd = torch.as_tensor(g, device=dev)
+            res = {}
+            for name, prec, half in (("fp32", L.GSR_FP32, False), ("fp16_blend", L.GSR_FP16_BLEND, False),
+                                     ("fp16_blend_t", L.GSR_FP16_BLEND_T, False),
+                                     ("half_reduction", L.GSR_FP32, True)):
+                f_ = rz.forward(st, cams, cluster_cull=cull, workspace=ws, precision=prec, half_reduction=half)
+                gr = rz.backward(f_, [gd])
+                torch.cuda.synchronize()
+                res[name] = (f_.images[0].cpu().numpy(), {k: v.cpu().numpy() for k, v in gr.items()})
+            return res
+        cpu, err_report = cpu_baseline(scene_sorted, cam, args.cpu_repeats, threads, gpu_forms)
         cpu["host_cpus"] = os.cpu_count()
         cpu["cpu_model"] = cpu_model()
 
@@ -728,8 +822,10 @@ def main():
         "frame": {"visible_slots": info["n_visible_slots"], "instances": info["instances"],
                   "evaluations_E": E, "fragments_F": F, "tiles": info["tiles"]},
         "fp16_blend": fp16,
+        "fp16_blend_t": fp16t,
         "deterministic": det,
         "radius_3sigma": radius3,
+        "half_reduction": half_red,
         "schedule_sweep": sweep,
         "view_cycle": cycle,
         "sparse_adam": adam,
@@ -739,6 +835,7 @@ def main():
         "roofline": roof,
         "step_roofline": step_roof,
         "cpu_baseline": cpu,
+        "error_vs_oracle": err_report,
     }
     print(json.dumps(out), flush=True)
 

@@ -45,10 +45,16 @@ typedef enum {
 
 typedef enum {
   GSR_FP32 = 0,        /* every raster quantity in FP32 */
-  GSR_FP16_BLEND = 1   /* packed-FP16 blend (Sec. 3.1.2): exponents computed in FP32 and rounded
+  GSR_FP16_BLEND = 1,  /* packed-FP16 blend (Sec. 3.1.2): exponents computed in FP32 and rounded
                           toward zero to FP16; G = 2^e and alpha = min(0.99, o G) in packed FP16
                           (clamp point 0.99 rounded to FP16); T, colour and all gradients FP32.
                           An approximation: its error against FP32 is measured, not bounded. */
+  GSR_FP16_BLEND_T = 2 /* as GSR_FP16_BLEND, and the forward's transmittance T is also kept in
+                          FP16 (T (1 - alpha) one FP16 fused multiply-add, the 1e-4 stop tested
+                          on that FP16 value, the blend weight alpha T formed in FP16): Sec. 3.1.2 keeps
+                          G, T and c in half precision; colour accumulates in FP32 here. The
+                          backward is that of GSR_FP16_BLEND, starting from the FP16 final T.
+                          An approximation whose error is measured, not bounded. */
 } gsr_precision;
 
 #define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile, or per
@@ -115,6 +121,13 @@ typedef struct {
                            eigenvalue of the screen covariance (the 3-sigma bound, which cuts
                            through the alpha >= 1/255 set of opaque Gaussians: a pixel blends
                            a Gaussian only if its tile is in the rect). */
+  int32_t half_reduction; /* 1: the backward packs each pixel strip's colour and opacity
+                           gradient sums as FP16 pairs (Sec. 3.1.2: half2 to move more
+                           gradient data per reduction step), reduces them over the wave
+                           in packed FP16 and adds them across tiles with packed FP16
+                           atomics; the geometry gradients and the statistic's square
+                           sum stay FP32. An approximation whose error is reported, not
+                           bounded; not with deterministic = 1. 0: all FP32. */
 } gsr_options;
 
 /* Parameter gradients, device memory, the shapes of gsr_scene's arrays. Overwritten

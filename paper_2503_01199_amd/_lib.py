@@ -17,6 +17,7 @@ GSR_ERR_DEVICE = 3
 GSR_ERR_UNSUPPORTED = 4
 GSR_FP32 = 0
 GSR_FP16_BLEND = 1
+GSR_FP16_BLEND_T = 2
 GSR_FAULT_NONE = 0
 GSR_FAULT_ABORT_BEFORE_SORT = 1
 GSR_FAULT_WITHHOLD_STATUS = 2
@@ -46,7 +47,7 @@ class GsrCamera(ctypes.Structure):
 
 class GsrOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("cluster_cull", c_int32), ("stats", c_int32), ("deterministic", c_int32),
-                ("radius_mode", c_int32)]
+                ("radius_mode", c_int32), ("half_reduction", c_int32)]
 
 
 class GsrGrads(ctypes.Structure):

@@ -23,7 +23,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libgsr.so")
 ARCH = "gfx950"
 
-SOURCES = ["scan.hip", "onesweep.hip", "cluster.hip", "preprocess.hip", "binning.hip", "raster_fwd.hip", "adam.hip", "densify.hip",
+SOURCES = ["fill.hip", "onesweep.hip", "cluster.hip", "preprocess.hip", "binning.hip", "raster_fwd.hip", "adam.hip", "densify.hip",
            "raster_bwd.hip", "morton.hip", "noalloc.hip", "api.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",

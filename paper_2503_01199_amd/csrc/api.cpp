@@ -142,7 +142,7 @@ gsr_status validate_records(gsr_context* ctx, const gsr_scene* sc, int32_t V) {
 
 gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   if (!o) return fail(ctx, GSR_ERR_INVALID_ARG, "options are NULL");
-  if (o->precision != GSR_FP32 && o->precision != GSR_FP16_BLEND)
+  if (o->precision != GSR_FP32 && o->precision != GSR_FP16_BLEND && o->precision != GSR_FP16_BLEND_T)
     return fail(ctx, GSR_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->cluster_cull != 0 && o->cluster_cull != 1)
     return fail(ctx, GSR_ERR_INVALID_ARG, "cluster_cull must be 0 or 1");
@@ -150,6 +150,10 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
   if (o->deterministic != 0 && o->deterministic != 1)
     return fail(ctx, GSR_ERR_INVALID_ARG, "deterministic must be 0 or 1");
   if (o->radius_mode != 0 && o->radius_mode != 1) return fail(ctx, GSR_ERR_INVALID_ARG, "radius_mode must be 0 or 1");
+  if (o->half_reduction != 0 && o->half_reduction != 1)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "half_reduction must be 0 or 1");
+  if (o->half_reduction && o->deterministic)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "half_reduction and deterministic exclude each other");
   return GSR_OK;
 }
 
@@ -515,7 +519,7 @@ gsr_status raster_batch_impl(gsr_context* ctx, int32_t n, const void* const* wor
   if (!ctx) return GSR_ERR_INVALID_ARG;
   if (n < 1 || n > gsr::kMaxBatch || !workspaces || !images)
     return fail(ctx, GSR_ERR_INVALID_ARG, "n = %d not in [1, %d] or NULL arrays", n, gsr::kMaxBatch);
-  if (precision != GSR_FP32 && precision != GSR_FP16_BLEND)
+  if (precision != GSR_FP32 && precision != GSR_FP16_BLEND && precision != GSR_FP16_BLEND_T)
     return fail(ctx, GSR_ERR_INVALID_ARG, "unknown precision %d", precision);
   gsr::FrameTable tab;
   std::memset(&tab, 0, sizeof(tab));
@@ -681,12 +685,13 @@ gsr_status backward_impl(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
       for (int v = 0; v < V; ++v) counts.n[v] = 3 * (int64_t)cams[v].width * cams[v].height;
       gsr::launch_grad_absmax(f, dp, counts, s);
     }
-    gsr::launch_raster_bwd(f, dp, opts->precision, s);
+    gsr::launch_raster_bwd(f, dp, opts->precision, opts->half_reduction != 0, s);
   }
   {
     StageScope sc_(ctx, GSR_STAGE_PREPROCESS_BWD, s);
     const gsr_grads none{};
-    gsr::launch_preprocess_bwd(*scene, f, adam ? none : *grads, use_stats ? stats : nullptr, adam, s);
+    gsr::launch_preprocess_bwd(*scene, f, adam ? none : *grads, use_stats ? stats : nullptr, adam,
+                               opts->half_reduction != 0, s);
   }
   fr.backwards++;
   return check_hip(ctx, hipGetLastError(), "backward");

@@ -152,7 +152,7 @@ struct Frame {
 };
 
 // ---------------------------------------------------------------- launchers
-// scan.hip
+// fill.hip
 void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 void fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
@@ -201,8 +201,10 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s);
 struct AdamDev;
 // adam null: gradients into g. adam set: no gradient leaves the kernels; the
 // Gaussians of kept clusters take the Adam step in place (adam's p, m, v arrays).
+// half: the backward raster left the colour and opacity sums as FP16 pairs in slots 6
+// and 7 of each gradient row (half_reduction).
 void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads& g, const gsr_stats* stats,
-                           const AdamDev* adam, hipStream_t s);
+                           const AdamDev* adam, bool half, hipStream_t s);
 
 // binning.hip (counts read from the frame header)
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
@@ -253,7 +255,7 @@ void launch_batch_tile_order(const FrameTable& tab, uint32_t total_tiles, uint32
                              uint32_t* n_items, hipStream_t s);
 // Largest number of raster work items for `tiles` tiles (every split tile adds 3).
 int64_t raster_max_items(int64_t tiles);
-void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s);
+void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, bool half, hipStream_t s);
 // Deterministic backward: header[kHdrGradMax] <- max |dL/dI| over the V images
 // (count[v] floats each).
 struct ViewCounts {

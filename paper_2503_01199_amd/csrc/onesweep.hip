@@ -246,15 +246,13 @@ constexpr int kHistBlocks = 512;
 constexpr int64_t kHistChunk = 8192;  // keys per histogram block at least
 constexpr int kMaxPasses = 8;
 constexpr int64_t kWideSortItems = int64_t(1) << 24;  // from this capacity: 4096-item tiles, 16-byte histogram loads
-constexpr int64_t kSmallSortItems = int64_t(1) << 21;  // below this capacity: 1024-item tiles
 
-// Items per one-sweep tile for a sort of capacity n_max. Small sorts take 1024-item
-// tiles so that a pass launches enough blocks to occupy every CU (the room's depth
-// sort of 409k records has 200 tiles of 2048 for 256 CUs); large ones 4096, whose
-// digits leave in longer runs and whose look-back has fewer tiles.
-inline int64_t sort_tile_items(int64_t n_max) {
-  return n_max >= kWideSortItems ? 2 * kSortTile : (n_max < kSmallSortItems ? kSortTile / 2 : kSortTile);
-}
+// Items per one-sweep tile for a sort of capacity n_max: 4096 from kWideSortItems on
+// (digits leave in longer runs, the look-back has fewer tiles), else 2048. 1024-item
+// tiles, which give small sorts more blocks than CUs (the room's depth sort of 409k
+// records has 200 tiles of 2048 for 256 CUs), measured slower: 12.7 against 11.5 us
+// per depth-sort pass (the look-back chain doubles).
+inline int64_t sort_tile_items(int64_t n_max) { return n_max >= kWideSortItems ? 2 * kSortTile : kSortTile; }
 
 // Lanes of the wave holding the same 8-bit digit d (restricted to `valid` lanes).
 __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
@@ -508,8 +506,8 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   uint32_t* done = offs + kMaxPasses * 256;   // 1 word (padded to 64)
   uint32_t* pass_ctl = done + 64;             // per pass: 64 reserved words, tile then group status [.][256]
   // Large sorts take 4096-item tiles: each 8-bit digit of a tile then leaves in runs
-  // of ~16 items instead of ~8, and the look-back has half the tiles. Small sorts
-  // take 1024, which gives more blocks (sort_ctl_words sizes the control words for
+  // of ~16 items instead of ~8, and the look-back has half the tiles. Smaller sorts
+  // keep 2048, which gives more blocks (sort_ctl_words sizes the control words for
   // the same choice).
   const int64_t tile_items = sort_tile_items(n_max);
   const int64_t tiles = (n_max + tile_items - 1) / tile_items;
@@ -529,11 +527,8 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
     if (tile_items == 2 * kSortTile)
       k_os_scatter<K, 2 * kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
           kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
-    else if (tile_items == kSortTile)
-      k_os_scatter<K, kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
-          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
     else
-      k_os_scatter<K, kSortRounds / 2><<<(unsigned)tiles, kSortThreads, 0, s>>>(
+      k_os_scatter<K, kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
           kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
     kcur = kb[out];
     vcur = vb[out];

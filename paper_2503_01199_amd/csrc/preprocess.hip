@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
     const uint32_t* __restrict__ visible, const uint32_t* __restrict__ cluster_offset,
     const uint32_t* __restrict__ tiles, float* __restrict__ grad2d, const unsigned long long* __restrict__ grad_fx,
     gsr_grads gr, float* __restrict__ S, float* __restrict__ Mst, uint32_t* __restrict__ Cst, AdamDev adam,
-    float* __restrict__ dmean) {
+    float* __restrict__ dmean, int half) {
   if (frame_aborted(header)) return;  // the frame's scans may be garbage: nothing is written
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= sc.n) return;
@@ -509,6 +509,16 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
         q0 = gg4[0];
         q1 = gg4[1];
         q2 = gg4[2];
+        if (half) {
+          // half_reduction: slots 6 and 7 hold (red, green) and (blue, opacity) as FP16
+          // pairs; the FP32 row the SH backward (and inspection) reads is rewritten
+          typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+          const h2 rg = __builtin_bit_cast(h2, q1.z), bo = __builtin_bit_cast(h2, q1.w);
+          q1 = make_float4(q1.x, (float)bo.y, (float)rg.x, (float)rg.y);
+          q2.x = (float)bo.x;
+          gg4[1] = q1;
+          gg4[2] = q2;
+        }
       }
       const double du = q0.x, dv = q0.y, da = q0.z, db = q0.w, dc = q1.x, dop = q1.y;
       sS += q2.y;
@@ -805,7 +815,7 @@ void launch_preprocess_fwd(const gsr_scene& sc, const Frame& f, hipStream_t s) {
 }
 
 void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads& g, const gsr_stats* stats,
-                           const AdamDev* adam, hipStream_t s) {
+                           const AdamDev* adam, bool half, hipStream_t s) {
   if (sc.n <= 0) return;
   const unsigned grid = (unsigned)((sc.n + kThreads - 1) / kThreads);
   const AdamDev none{};
@@ -814,12 +824,12 @@ void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads&
     k_project_bwd<true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,
                                                   f.tiles_touched, f.grad2d, f.grad2d_fx, g,
                                                   stats ? stats->S : nullptr, stats ? stats->M : nullptr,
-                                                  stats ? stats->C : nullptr, a, f.dmean);
+                                                  stats ? stats->C : nullptr, a, f.dmean, half ? 1 : 0);
   else
     k_project_bwd<false><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,
                                                    f.tiles_touched, f.grad2d, f.grad2d_fx, g,
                                                    stats ? stats->S : nullptr, stats ? stats->M : nullptr,
-                                                   stats ? stats->C : nullptr, a, f.dmean);
+                                                   stats ? stats->C : nullptr, a, f.dmean, half ? 1 : 0);
 #define GSR_SH_BWD(D)                                                                                            \
   if (adam)                                                                                                      \
     k_sh_bwd<D, true><<<grid, kThreads, 0, s>>>(sc, f.views, f.V, f.header, f.cluster_visible, f.cluster_offset,           \

@@ -89,9 +89,67 @@ __device__ __forceinline__ void wave_reduce10(const float v[10], float w[3]) {
   for (int i = 0; i < 3; ++i) w[i] += dpp_row_shr<0x118>(w[i]);
 }
 
+__device__ __forceinline__ void swap32u(uint32_t& a, uint32_t& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  a = r[0];
+  b = r[1];
+}
+__device__ __forceinline__ void swap16u(uint32_t& a, uint32_t& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+  a = r[0];
+  b = r[1];
+}
+__device__ __forceinline__ half2_t as_h2(uint32_t x) { return __builtin_bit_cast(half2_t, x); }
+__device__ __forceinline__ uint32_t as_u32(half2_t x) { return __builtin_bit_cast(uint32_t, x); }
+
+// The same transposed reduction for the half_reduction layout: 6 FP32 values v (the
+// screen-mean and conic gradients and the square sum) and 2 packed FP16 pairs h0
+// (red, green), h1 (blue, opacity). On return, in lanes 15, 31, 47 and 63: w0 holds
+// v0, v2, v1, v3; w1 holds v4, 0, v5, 0; w2 holds h0, 0, h1, 0 (packed FP16 sums).
+__device__ __forceinline__ void wave_reduce_half(const float v[6], half2_t h0, half2_t h1, float& w0, float& w1,
+                                                 half2_t& w2) {
+  float u[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    float a = v[2 * i], b = v[2 * i + 1];
+    swap32(a, b);
+    u[i] = a + b;
+  }
+  uint32_t pa = as_u32(h0), pb = as_u32(h1);
+  swap32u(pa, pb);
+  const half2_t u3 = as_h2(pa) + as_h2(pb);
+  {
+    float a = u[0], b = u[1];
+    swap16(a, b);
+    w0 = a + b;
+  }
+  {
+    float a = u[2], b = 0.0f;
+    swap16(a, b);
+    w1 = a + b;
+  }
+  {
+    uint32_t a = as_u32(u3), b = 0u;
+    swap16u(a, b);
+    w2 = as_h2(a) + as_h2(b);
+  }
+  w0 += dpp_row_shr<0x111>(w0);
+  w1 += dpp_row_shr<0x111>(w1);
+  w2 = w2 + as_h2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)as_u32(w2), 0x111, 0xf, 0xf, true));
+  w0 += dpp_row_shr<0x112>(w0);
+  w1 += dpp_row_shr<0x112>(w1);
+  w2 = w2 + as_h2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)as_u32(w2), 0x112, 0xf, 0xf, true));
+  w0 += dpp_row_shr<0x114>(w0);
+  w1 += dpp_row_shr<0x114>(w1);
+  w2 = w2 + as_h2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)as_u32(w2), 0x114, 0xf, 0xf, true));
+  w0 += dpp_row_shr<0x118>(w0);
+  w1 += dpp_row_shr<0x118>(w1);
+  w2 = w2 + as_h2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)as_u32(w2), 0x118, 0xf, 0xf, true));
+}
+
 // One work item: tile gt whole (NB = 4 pixels per lane), or its two bands from
 // `band` on (NB = 2, at their row offsets from the whole strip's anchor).
-template <int P, int NB, bool kFixed>
+template <int P, int NB, bool kFixed, bool kHalf>
 __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, uint32_t* recA, uint32_t* recB,
                                                 const ViewDev* __restrict__ views, int32_t V, uint32_t gt, int band,
                                                 const uint32_t* __restrict__ ranges,
@@ -230,6 +288,29 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
       const float ga = -0.5f * dx * dx * S0;
       const float gb = __builtin_fmaf(dx, S1, -dx * dy * S0);
       const float gcn = __builtin_fmaf(dy, S1, __builtin_fmaf(-0.5f * dy * dy, S0, -0.5f * S2));
+      if constexpr (kHalf) {
+        // colour and opacity sums as FP16 pairs (round to nearest), reduced packed
+        const float v6[6] = {gu, gv, ga, gb, gcn, ss};
+        const half2_t h0 = {(_Float16)dcr, (_Float16)dcg};
+        const half2_t h1 = {(_Float16)dcb, (_Float16)dop};
+        float t0, t1;
+        half2_t t2;
+        wave_reduce_half(v6, h0, h1, t0, t1, t2);
+        P1 = P2 = dcr = dcg = dcb = dop = ss = 0.f;
+        if ((lane & 15) == 15) {
+          const int row = lane >> 4;
+          const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+          float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D;
+          unsafeAtomicAdd(dst + sub, t0);
+          // t1 rows: conic c (slot 4), padding (the fragment count goes there: slot 10),
+          // square sum (slot 9); t2 rows: (red, green) into slot 6, (blue, opacity) into 7
+          if (row != 3) unsafeAtomicAdd(dst + (row == 0 ? 4 : row == 1 ? 10 : 9), row == 1 ? (float)nfrag : t1);
+          if (row == 0 || row == 2)
+            __builtin_amdgcn_global_atomic_fadd_v2f16(
+                (__attribute__((address_space(1))) half2_t*)(reinterpret_cast<half2_t*>(dst + (row == 0 ? 6 : 7))), t2);
+        }
+        continue;
+      }
       const float vals[10] = {gu, gv, ga, gb, gcn, dop, dcr, dcg, dcb, ss};
       float tot[3];
       wave_reduce10(vals, tot);
@@ -262,7 +343,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
   }
 }
 
-template <int P, bool kFixed>
+template <int P, bool kFixed, bool kHalf>
 __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ views, int32_t V,
                                                    const uint32_t* __restrict__ items,
                                                    const uint32_t* __restrict__ header,
@@ -287,10 +368,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
     fx_sq = __builtin_ldexpf(1.0f, kFixedBits - 2 * E);
   }
   if (code == kItemWhole)
-    raster_bwd_item<P, 4, kFixed>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL,
+    raster_bwd_item<P, 4, kFixed, kHalf>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL,
                                   pix_T, pix_last, grad2d, grad_fx, fx_lin, fx_sq);
   else  // half of a split tile
-    raster_bwd_item<P, 2, kFixed>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges,
+    raster_bwd_item<P, 2, kFixed, kHalf>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges,
                                   inst_rec, inst_mask, rec, dL, pix_T, pix_last, grad2d, grad_fx, fx_lin, fx_sq);
 }
 
@@ -328,10 +409,10 @@ __global__ __launch_bounds__(256) void k_grad_absmax(ConstImagePtrs dL, ViewCoun
   }
 }
 
-template <int P, bool kFixed>
+template <int P, bool kFixed, bool kHalf = false>
 void launch_bwd(const Frame& f, const ConstImagePtrs& dL, hipStream_t s) {
   const unsigned grid = (unsigned)max_items(f.tiles);
-  k_raster_bwd<P, kFixed><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, f.header, f.ranges,
+  k_raster_bwd<P, kFixed, kHalf><<<grid, 64, 0, s>>>(f.views, f.V, f.bwd_items, f.header, f.ranges,
                                               f.inst_rec, f.inst_mask, f.rec, dL, f.pix_T, f.pix_last, f.grad2d,
                                               f.grad2d_fx);
 }
@@ -346,9 +427,17 @@ void launch_grad_absmax(const Frame& f, const ConstImagePtrs& dL, const ViewCoun
   k_grad_absmax<<<(unsigned)g, 256, 0, s>>>(dL, counts, f.V, f.header);
 }
 
-void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, hipStream_t s) {
+void launch_raster_bwd(const Frame& f, const ConstImagePtrs& dL, int precision, bool half, hipStream_t s) {
   if (f.tiles <= 0) return;
+  if (precision == GSR_FP16_BLEND_T) precision = GSR_FP16_BLEND;  // the same alphas; T restarts from the final T
   const bool fixed = f.grad2d_fx != nullptr;
+  if (half && !fixed) {
+    if (precision == GSR_FP16_BLEND)
+      launch_bwd<GSR_FP16_BLEND, false, true>(f, dL, s);
+    else
+      launch_bwd<GSR_FP32, false, true>(f, dL, s);
+    return;
+  }
   if (precision == GSR_FP16_BLEND)
     fixed ? launch_bwd<GSR_FP16_BLEND, true>(f, dL, s) : launch_bwd<GSR_FP16_BLEND, false>(f, dL, s);
   else

@@ -120,10 +120,11 @@ __device__ __forceinline__ void strip_alpha_h(float o, const float e[NB], float 
   }
 }
 
-// Alpha of the NB strip pixels at precision P (GSR_FP32 or GSR_FP16_BLEND).
+// Alpha of the NB strip pixels at precision P (GSR_FP32, or the FP16 blend of
+// GSR_FP16_BLEND and GSR_FP16_BLEND_T).
 template <int P, int NB>
 __device__ __forceinline__ void strip_alpha(float o, const float e[NB], float a[NB], float G[NB], float araw[NB]) {
-  if constexpr (P == GSR_FP16_BLEND) {
+  if constexpr (P == GSR_FP16_BLEND || P == GSR_FP16_BLEND_T) {
     strip_alpha_h<NB>(o, e, a, G, araw);
   } else {
 #pragma unroll
@@ -135,7 +136,7 @@ __device__ __forceinline__ void strip_alpha(float o, const float e[NB], float a[
 // strip_alpha gives that pixel (the FP16 pair operations act elementwise).
 template <int P>
 __device__ __forceinline__ float pixel_alpha(float o, float e, float& G, float& araw) {
-  if constexpr (P == GSR_FP16_BLEND) {
+  if constexpr (P == GSR_FP16_BLEND || P == GSR_FP16_BLEND_T) {
     const half2_t eh = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(e, e));
     const _Float16 g = __ocml_exp2_f16(eh.x);
     const _Float16 r = (_Float16)o * g;
@@ -151,7 +152,7 @@ __device__ __forceinline__ float pixel_alpha(float o, float e, float& G, float& 
 // The value of o G above which alpha is clamped (and its derivative is 0).
 template <int P>
 constexpr float alpha_clamp() {
-  return P == GSR_FP16_BLEND ? kAlphaMaxH : kAlphaMax;
+  return P == GSR_FP32 ? kAlphaMax : kAlphaMaxH;
 }
 
 // A batch of B records (B a power of two, at most 64) in LDS, stored as three

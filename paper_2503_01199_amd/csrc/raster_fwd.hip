@@ -97,11 +97,21 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
         const bool ok = a >= amin[j];
         if (!__any(ok)) continue;  // nobody in this band blends the entry
         bm[j] |= 1ull << k;
-        const float Tn = __builtin_fmaf(-T[j], a, T[j]);  // T (1 - a), one rounding
+        float Tn, wt0;
+        if constexpr (P == GSR_FP16_BLEND_T) {
+          // T kept in FP16 (T[j] holds an FP16 value; a is one too): T (1 - a) and a T
+          // each one FP16 operation
+          const _Float16 Th = (_Float16)T[j], ah = (_Float16)a;
+          Tn = (float)__builtin_fmaf16(-Th, ah, Th);
+          wt0 = (float)(ah * Th);
+        } else {
+          Tn = __builtin_fmaf(-T[j], a, T[j]);  // T (1 - a), one rounding
+          wt0 = a * T[j];
+        }
         const bool below = Tn < kTMin;  // one compare serves both outcomes
         const bool stop = ok && below;
         const bool blend = ok && !below;
-        const float wt = blend ? a * T[j] : 0.0f;
+        const float wt = blend ? wt0 : 0.0f;
         cr[j] = __builtin_fmaf(wt, g.r2.y, cr[j]);
         cg[j] = __builtin_fmaf(wt, g.r2.z, cg[j]);
         cb[j] = __builtin_fmaf(wt, g.r2.w, cb[j]);
@@ -206,6 +216,8 @@ bool launch_raster_fwd_batch(const FrameTable& tab, const uint32_t* order, const
   const unsigned grid = (unsigned)max_items(total_tiles);
   if (precision == GSR_FP16_BLEND)
     launch_tracked(k_raster_fwd_batch<GSR_FP16_BLEND>, grid, 64, s, done, tab, order, n_items, images);
+  else if (precision == GSR_FP16_BLEND_T)
+    launch_tracked(k_raster_fwd_batch<GSR_FP16_BLEND_T>, grid, 64, s, done, tab, order, n_items, images);
   else
     launch_tracked(k_raster_fwd_batch<GSR_FP32>, grid, 64, s, done, tab, order, n_items, images);
   return true;
@@ -217,6 +229,10 @@ bool launch_raster_fwd(const Frame& f, const ImagePtrs& images, int precision, h
   const uint32_t* header = f.header;
   if (precision == GSR_FP16_BLEND)
     launch_tracked(k_raster_fwd<GSR_FP16_BLEND>, grid, 64, s, done, (const ViewDev*)f.views, f.V,
+                   (const uint32_t*)f.tile_order, header, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
+                   f.inst_mask, (const Record*)f.rec, images, f.pix_T, f.pix_last);
+  else if (precision == GSR_FP16_BLEND_T)
+    launch_tracked(k_raster_fwd<GSR_FP16_BLEND_T>, grid, 64, s, done, (const ViewDev*)f.views, f.V,
                    (const uint32_t*)f.tile_order, header, (const uint32_t*)f.ranges, (const uint32_t*)f.inst_rec,
                    f.inst_mask, (const Record*)f.rec, images, f.pix_T, f.pix_last);
   else

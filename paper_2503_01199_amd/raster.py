@@ -165,29 +165,31 @@ class Rasterizer:
 
     @staticmethod
     def options(precision=L.GSR_FP32, cluster_cull=True, stats=True, deterministic=False,
-                radius_mode=0) -> L.GsrOptions:
+                radius_mode=0, half_reduction=False) -> L.GsrOptions:
         o = L.GsrOptions()
         o.precision = int(precision)
         o.cluster_cull = 1 if cluster_cull else 0
         o.stats = 1 if stats else 0
         o.deterministic = 1 if deterministic else 0
         o.radius_mode = int(radius_mode)
+        o.half_reduction = 1 if half_reduction else 0
         return o
 
     # ------------------------------------------------------------------ forward / backward
     def forward(self, scene: SceneTensors, cameras, precision=L.GSR_FP32, cluster_cull=True, stats=True,
                 workspace: Workspace | None = None, images=None, check: bool = True,
-                deterministic: bool = False, radius_mode: int = 0) -> Frame:
+                deterministic: bool = False, radius_mode: int = 0, half_reduction: bool = False) -> Frame:
         """Renders the views. With check (the default) waits for the frame's counters
         and, when its instances did not fit the workspace, grows it and renders
         again; check=False returns right after enqueueing (info is then empty: call
         check_frame to wait, read the counters and learn whether it fitted).
         deterministic: the frame's backward sums per-tile gradients in fixed point
         (bitwise reproducible gradients). radius_mode: 0 the exact alpha >= 1/255 tile
-        membership, 1 the 3-sigma bound."""
+        membership, 1 the 3-sigma bound. half_reduction: the frame's backward reduces
+        colour and opacity gradients as packed FP16 pairs."""
         V = len(cameras)
         cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
-        opts = self.options(precision, cluster_cull, stats, deterministic, radius_mode)
+        opts = self.options(precision, cluster_cull, stats, deterministic, radius_mode, half_reduction)
         sc = scene.struct()
         ws = workspace if workspace is not None else self.default_workspace
         if images is None:
