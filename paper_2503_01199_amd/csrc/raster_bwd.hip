@@ -31,6 +31,9 @@ namespace gsr {
 namespace {
 
 constexpr int kBatch = 64;  // records per LDS batch
+// Entries whose wave totals are staged in LDS before one pass turns them into
+// gradients and issues their atomics (a divisor of kBatch).
+constexpr int kGroup = 16;
 
 // Deterministic backward: per-tile sums become two's-complement fixed point (round
 // to nearest, saturating) at the frame's scale (grad_exponent), so that the
@@ -147,10 +150,19 @@ __device__ __forceinline__ void wave_reduce_half(const float v[6], half2_t h0, h
   w2 = w2 + as_h2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)as_u32(w2), 0x118, 0xf, 0xf, true));
 }
 
+// The work-group is one wave and its LDS instructions execute in issue order, so
+// lanes exchange data through LDS behind a compiler-level barrier alone.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One work item: tile gt whole (NB = 4 pixels per lane), or its two bands from
 // `band` on (NB = 2, at their row offsets from the whole strip's anchor).
 template <int P, int NB, bool kFixed, bool kHalf>
 __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, uint32_t* recA, uint32_t* recB,
+                                                float4* __restrict__ stage,
                                                 const ViewDev* __restrict__ views, int32_t V, uint32_t gt, int band,
                                                 const uint32_t* __restrict__ ranges,
                                                 const uint32_t* __restrict__ inst_rec,
@@ -201,6 +213,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) mymax = max(mymax, (uint32_t)__shfl_xor((int)mymax, d, 64));
+  mymax = (uint32_t)__builtin_amdgcn_readfirstlane((int)mymax);  // equal in every lane: keep the loop bounds scalar
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = min(ranges[2 * gt + 1], s + mymax);
   if (e <= s) return;
@@ -227,6 +240,60 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
   // gradients g_o are summed against s^0 (dop), s^1 and s^2; times o they are the
   // exponent-gradient sums S0, S1, S2.
   float P1 = 0.f, P2 = 0.f, dcr = 0.f, dcg = 0.f, dcb = 0.f, dop = 0.f, ss = 0.f;
+
+  // Gradients of a group of staged entries (FP32 path). Each lane reduces, against
+  // its pixels' offsets X = dx, Y_j = dy - s_j from the Gaussian's mean, the sums
+  // (dop, sum g_o X, sum g_o Y, sum g_o X^2, sum g_o X Y, sum g_o Y^2, dcr, dcg, dcb,
+  // ss); row r of an entry's stage holds their wave totals in slots (sub, sub + 4,
+  // sub + 8), sub = 0, 2, 1, 3 for r = 0..3, slot 10 being the fragment count.
+  // Lane i converts entry k0 + i: with the exponent E = -1/2 (a X^2 + 2 b X Y +
+  // c Y^2) and w = o g_o,
+  //   dL/du = -(a sum wX + b sum wY), dL/dv = -(b sum wX + c sum wY),
+  //   dL/da = -1/2 sum wX^2, dL/db = -sum wXY, dL/dc = -1/2 sum wY^2:
+  // the per-pixel chain rule with its linear pieces taken after the wave sum (o and
+  // the conic are the entry's). The entry's 12 output slots go back to its stage;
+  // then four lanes per entry add one 16-byte quarter of its gradient row each (one
+  // atomic per gradient per tile).
+  auto flush = [&](const BwdBatch& cur, const uint32_t* cur_rec, int k0, uint32_t stg) __attribute__((always_inline)) {
+    wave_lds_sync();
+    if (lane < kGroup && ((stg >> lane) & 1u)) {
+      const Record g = batch_get(cur, k0 + lane);
+      float4* st = stage + 4 * lane;
+      const float4 q0 = st[0], q1 = st[1], q2 = st[2], q3 = st[3];
+      const float o = g.r2.x;
+      const float wX = o * q2.x, wY = o * q1.x, wXX = o * q3.x, wXY = o * q0.y, wYY = o * q2.y;
+      const float ca = -2.0f * (float)kLn2 * g.r1.x;
+      const float cb = ca * g.r1.y;
+      const float cc = -2.0f * (float)kLn2 * g.r1.w;
+      const float gu = -__builtin_fmaf(ca, wX, cb * wY);
+      const float gv = -__builtin_fmaf(cb, wX, cc * wY);
+      st[0] = make_float4(gu, gv, -0.5f * wXX, -wXY);
+      st[1] = make_float4(-0.5f * wYY, q0.x, q1.y, q3.y);  // conic c, opacity, red, green
+      st[2] = make_float4(q0.z, q2.z, q1.z, 0.0f);         // blue, square sum, count
+    }
+    wave_lds_sync();
+    const int e = lane >> 2, sub = lane & 3;
+    if ((stg >> e) & 1u) {
+      const float* sv = reinterpret_cast<const float*>(stage + 4 * e) + sub;
+      const int64_t row = (int64_t)cur_rec[k0 + e] * kGrad2D + sub;
+      if constexpr (kFixed) {
+        unsigned long long* dst = grad_fx + row;
+        atomicAdd(dst, to_fixed(sv[0], fx_lin));
+        atomicAdd(dst + 4, to_fixed(sv[4], fx_lin));
+        // slot 9 is the square sum of the statistic, slot 10 the fragment count
+        if (sub != 3)
+          atomicAdd(dst + 8, sub == 2 ? (unsigned long long)(uint32_t)sv[8] << kFixedBits
+                                      : to_fixed(sv[8], sub == 1 ? fx_sq : fx_lin));
+      } else {
+        float* dst = grad2d + row;
+        unsafeAtomicAdd(dst, sv[0]);
+        unsafeAtomicAdd(dst + 4, sv[4]);
+        if (sub != 3) unsafeAtomicAdd(dst + 8, sv[8]);
+      }
+    }
+    wave_lds_sync();  // the group's stage is read before the next group writes it
+  };
+
   auto run_batch = [&](const BwdBatch& cur, const uint32_t* cur_rec, uint32_t cur_mask, BwdBatch& nxt,
                        uint32_t* nxt_rec, uint32_t& nxt_mask, uint32_t b0) __attribute__((always_inline)) {
     __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
@@ -238,101 +305,101 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
     }
     r_next = (batch_lane && b0 >= s + 2 * kBatch) ? inst_rec[b0 - 2 * kBatch + lane] : 0u;
     const int cnt = (int)min((uint32_t)kBatch, e - b0);
+    uint32_t stg = 0;  // entries of the current group staged (scalar)
     for (int k = cnt - 1; k >= 0; --k) {
       const uint32_t m = ((uint32_t)__builtin_amdgcn_readlane((int)cur_mask, k) >> mask_shift) & mask_keep;
-      if (m == 0) continue;  // no pixel of the item blends this entry
-      const Record g = batch_get(cur, k);
-      float dx, dy;
-      const StripTerms et = strip_terms(g, pxc, pyc, dx, dy);
-      const uint32_t pos = b0 - s + (uint32_t)k;
-      const float o = g.r2.x;
-      uint32_t nfrag = 0;  // blended pixels of this entry over the wave (scalar)
+      if (m != 0) {  // else no pixel of the item blends this entry
+        const Record g = batch_get(cur, k);
+        float dx, dy;
+        const StripTerms et = strip_terms(g, pxc, pyc, dx, dy);
+        const uint32_t pos = b0 - s + (uint32_t)k;
+        const float o = g.r2.x;
+        uint32_t nfrag = 0;  // blended pixels of this entry over the wave (scalar)
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (((m >> (8 * j)) & 0xFFu) == 0) continue;  // no pixel of band j blends it
-        float G, araw;
-        const float a = pixel_alpha<P>(o, et.at(soff[j]), G, araw);
-        const bool before = pos < last[j], visible = a >= kAlphaMin;
-        const bool blend = before && visible;
-        nfrag += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(before) &
-                                                __builtin_amdgcn_ballot_w64(visible));
-        if (blend) {
-          const float inv = __builtin_amdgcn_rcpf(1.0f - a);
-          const float Tb = T[j] * inv;  // T before this entry
-          const float wt = a * Tb;
-          const float gc = __builtin_fmaf(gI[j][2], g.r2.w, __builtin_fmaf(gI[j][1], g.r2.z, gI[j][0] * g.r2.y));
-          dcr = __builtin_fmaf(wt, gI[j][0], dcr);
-          dcg = __builtin_fmaf(wt, gI[j][1], dcg);
-          dcb = __builtin_fmaf(wt, gI[j][2], dcb);
-          // dL/dalpha = T (g . c) - (g . colour behind) / (1 - alpha)
-          const float dA = __builtin_fmaf(Tb, gc, -gR[j] * inv);
-          const float go = (araw <= alpha_clamp<P>()) ? dA * G : 0.0f;
-          dop += go;
-          P1 = __builtin_fmaf(soff[j], go, P1);
-          P2 = __builtin_fmaf(soff[j] * soff[j], go, P2);
-          ss = __builtin_fmaf(go, go, ss);
-          gR[j] = __builtin_fmaf(wt, gc, gR[j]);  // now the colour behind the previous entry
-          T[j] = Tb;
+        for (int j = 0; j < NB; ++j) {
+          if (((m >> (8 * j)) & 0xFFu) == 0) continue;  // no pixel of band j blends it
+          float G, araw;
+          const float a = pixel_alpha<P>(o, et.at(soff[j]), G, araw);
+          const bool before = pos < last[j], visible = a >= kAlphaMin;
+          const bool blend = before && visible;
+          nfrag += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(before) &
+                                                  __builtin_amdgcn_ballot_w64(visible));
+          if (blend) {
+            const float inv = __builtin_amdgcn_rcpf(1.0f - a);
+            const float Tb = T[j] * inv;  // T before this entry
+            const float wt = a * Tb;
+            const float gc = __builtin_fmaf(gI[j][2], g.r2.w, __builtin_fmaf(gI[j][1], g.r2.z, gI[j][0] * g.r2.y));
+            dcr = __builtin_fmaf(wt, gI[j][0], dcr);
+            dcg = __builtin_fmaf(wt, gI[j][1], dcg);
+            dcb = __builtin_fmaf(wt, gI[j][2], dcb);
+            // dL/dalpha = T (g . c) - (g . colour behind) / (1 - alpha)
+            const float dA = __builtin_fmaf(Tb, gc, -gR[j] * inv);
+            const float go = (araw <= alpha_clamp<P>()) ? dA * G : 0.0f;
+            dop += go;
+            P1 = __builtin_fmaf(soff[j], go, P1);
+            P2 = __builtin_fmaf(soff[j] * soff[j], go, P2);
+            ss = __builtin_fmaf(go, go, ss);
+            gR[j] = __builtin_fmaf(wt, gc, gR[j]);  // now the colour behind the previous entry
+            T[j] = Tb;
+          }
+        }
+        if constexpr (kHalf) {
+          if (nfrag != 0) {
+            const float S0 = o * dop, S1 = o * P1, S2 = o * P2;  // dL/dE sums
+            // exponent -> conic (a, b, c) and mean (u, v) gradients at the strip
+            // anchor (pixel j is s_j rows below it):
+            //   E_j = -1/2 (a dx^2 + 2 b dx (dy - s_j) + c (dy - s_j)^2), d = mean - anchor
+            const float ca = -2.0f * (float)kLn2 * g.r1.x;
+            const float cb = ca * g.r1.y;
+            const float cc = -2.0f * (float)kLn2 * g.r1.w;
+            const float gu = __builtin_fmaf(cb, S1, -__builtin_fmaf(ca, dx, cb * dy) * S0);
+            const float gv = __builtin_fmaf(cc, S1, -__builtin_fmaf(cb, dx, cc * dy) * S0);
+            const float ga = -0.5f * dx * dx * S0;
+            const float gb = __builtin_fmaf(dx, S1, -dx * dy * S0);
+            const float gcn = __builtin_fmaf(dy, S1, __builtin_fmaf(-0.5f * dy * dy, S0, -0.5f * S2));
+            // colour and opacity sums as FP16 pairs (round to nearest), reduced packed
+            const float v6[6] = {gu, gv, ga, gb, gcn, ss};
+            const half2_t h0 = {(_Float16)dcr, (_Float16)dcg};
+            const half2_t h1 = {(_Float16)dcb, (_Float16)dop};
+            float t0, t1;
+            half2_t t2;
+            wave_reduce_half(v6, h0, h1, t0, t1, t2);
+            P1 = P2 = dcr = dcg = dcb = dop = ss = 0.f;
+            if ((lane & 15) == 15) {
+              const int row = lane >> 4;
+              const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+              float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D;
+              unsafeAtomicAdd(dst + sub, t0);
+              // t1 rows: conic c (slot 4), padding (the fragment count goes there: slot
+              // 10), square sum (slot 9); t2 rows: (red, green) into slot 6, (blue,
+              // opacity) into 7
+              if (row != 3) unsafeAtomicAdd(dst + (row == 0 ? 4 : row == 1 ? 10 : 9), row == 1 ? (float)nfrag : t1);
+              if (row == 0 || row == 2)
+                __builtin_amdgcn_global_atomic_fadd_v2f16(
+                    (__attribute__((address_space(1))) half2_t*)(reinterpret_cast<half2_t*>(dst + (row == 0 ? 6 : 7))),
+                    t2);
+            }
+          }
+        } else if (nfrag != 0) {
+          // sums against the offsets X = dx, Y_j = dy - s_j of the lane's pixels
+          const float wX = dx * dop;
+          const float wY = __builtin_fmaf(dy, dop, -P1);
+          const float wYY = __builtin_fmaf(dy, wY, __builtin_fmaf(-dy, P1, P2));
+          const float vals[10] = {dop, wX, wY, dx * wX, dx * wY, wYY, dcr, dcg, dcb, ss};
+          float tot[3];
+          wave_reduce10(vals, tot);
+          P1 = P2 = dcr = dcg = dcb = dop = ss = 0.f;
+          if ((lane & 15) == 15) {
+            const int row = lane >> 4;
+            stage[4 * (k & (kGroup - 1)) + row] = make_float4(tot[0], tot[1], row == 1 ? (float)nfrag : tot[2], 0.0f);
+          }
+          stg |= 1u << (k & (kGroup - 1));
         }
       }
-      if (nfrag == 0) continue;  // nobody blended this entry
-      const float S0 = o * dop, S1 = o * P1, S2 = o * P2;  // dL/dE sums
-      // exponent -> conic (a, b, c) and mean (u, v) gradients at the strip anchor
-      // (pixel j is s_j rows below it):
-      //   E_j = -1/2 (a dx^2 + 2 b dx (dy - s_j) + c (dy - s_j)^2), d = mean - anchor
-      const float ca = -2.0f * (float)kLn2 * g.r1.x;
-      const float cb = ca * g.r1.y;
-      const float cc = -2.0f * (float)kLn2 * g.r1.w;
-      const float gu = __builtin_fmaf(cb, S1, -__builtin_fmaf(ca, dx, cb * dy) * S0);
-      const float gv = __builtin_fmaf(cc, S1, -__builtin_fmaf(cb, dx, cc * dy) * S0);
-      const float ga = -0.5f * dx * dx * S0;
-      const float gb = __builtin_fmaf(dx, S1, -dx * dy * S0);
-      const float gcn = __builtin_fmaf(dy, S1, __builtin_fmaf(-0.5f * dy * dy, S0, -0.5f * S2));
-      if constexpr (kHalf) {
-        // colour and opacity sums as FP16 pairs (round to nearest), reduced packed
-        const float v6[6] = {gu, gv, ga, gb, gcn, ss};
-        const half2_t h0 = {(_Float16)dcr, (_Float16)dcg};
-        const half2_t h1 = {(_Float16)dcb, (_Float16)dop};
-        float t0, t1;
-        half2_t t2;
-        wave_reduce_half(v6, h0, h1, t0, t1, t2);
-        P1 = P2 = dcr = dcg = dcb = dop = ss = 0.f;
-        if ((lane & 15) == 15) {
-          const int row = lane >> 4;
-          const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-          float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D;
-          unsafeAtomicAdd(dst + sub, t0);
-          // t1 rows: conic c (slot 4), padding (the fragment count goes there: slot 10),
-          // square sum (slot 9); t2 rows: (red, green) into slot 6, (blue, opacity) into 7
-          if (row != 3) unsafeAtomicAdd(dst + (row == 0 ? 4 : row == 1 ? 10 : 9), row == 1 ? (float)nfrag : t1);
-          if (row == 0 || row == 2)
-            __builtin_amdgcn_global_atomic_fadd_v2f16(
-                (__attribute__((address_space(1))) half2_t*)(reinterpret_cast<half2_t*>(dst + (row == 0 ? 6 : 7))), t2);
-        }
-        continue;
-      }
-      const float vals[10] = {gu, gv, ga, gb, gcn, dop, dcr, dcg, dcb, ss};
-      float tot[3];
-      wave_reduce10(vals, tot);
-      P1 = P2 = dcr = dcg = dcb = dop = ss = 0.f;
-      // lanes 15, 31, 47, 63 of tot[i] hold slots 4i, 4i+2, 4i+1, 4i+3; slot 10 (the
-      // fragment count, lane 31 of tot[2]) comes from the scalar count, 11 is padding
-      if ((lane & 15) == 15) {
-        const int row = lane >> 4;
-        const int sub = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-        if constexpr (kFixed) {
-          unsigned long long* dst = grad_fx + (int64_t)cur_rec[k] * kGrad2D + sub;
-          atomicAdd(dst, to_fixed(tot[0], fx_lin));
-          atomicAdd(dst + 4, to_fixed(tot[1], fx_lin));
-          // slot 9 is the square sum of the statistic, slot 10 the fragment count
-          if (sub != 3)
-            atomicAdd(dst + 8, sub == 2 ? (unsigned long long)nfrag << kFixedBits
-                                        : to_fixed(tot[2], sub == 1 ? fx_sq : fx_lin));
-        } else {
-          float* dst = grad2d + (int64_t)cur_rec[k] * kGrad2D + sub;
-          unsafeAtomicAdd(dst, tot[0]);
-          unsafeAtomicAdd(dst + 4, tot[1]);
-          if (sub != 3) unsafeAtomicAdd(dst + 8, sub == 2 ? (float)nfrag : tot[2]);
+      if constexpr (!kHalf) {
+        if ((k & (kGroup - 1)) == 0 && stg != 0) {
+          flush(cur, cur_rec, k, stg);
+          stg = 0;
         }
       }
     }
@@ -357,6 +424,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
                                                    unsigned long long* __restrict__ grad_fx) {
   __shared__ BwdBatch bufA, bufB;  // two objects, so reads of one never wait on loads into the other
   __shared__ uint32_t recA[kBatch], recB[kBatch];
+  __shared__ float4 stage[kHalf ? 1 : 4 * kGroup];
   if (blockIdx.x >= header[kHdrItemsBwd] || frame_aborted(header)) return;
   const uint32_t item = items[blockIdx.x];
   const uint32_t gt = item >> 3;
@@ -368,10 +436,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(const ViewDev* __restrict__ v
     fx_sq = __builtin_ldexpf(1.0f, kFixedBits - 2 * E);
   }
   if (code == kItemWhole)
-    raster_bwd_item<P, 4, kFixed, kHalf>(bufA, bufB, recA, recB, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL,
+    raster_bwd_item<P, 4, kFixed, kHalf>(bufA, bufB, recA, recB, stage, views, V, gt, 0, ranges, inst_rec, inst_mask, rec, dL,
                                   pix_T, pix_last, grad2d, grad_fx, fx_lin, fx_sq);
   else  // half of a split tile
-    raster_bwd_item<P, 2, kFixed, kHalf>(bufA, bufB, recA, recB, views, V, gt, 2 * (int)(code - kItemHalf), ranges,
+    raster_bwd_item<P, 2, kFixed, kHalf>(bufA, bufB, recA, recB, stage, views, V, gt, 2 * (int)(code - kItemHalf), ranges,
                                   inst_rec, inst_mask, rec, dL, pix_T, pix_last, grad2d, grad_fx, fx_lin, fx_sq);
 }
 
