@@ -181,7 +181,12 @@ typedef struct {
  *   grad2d      f32[R][12] (after gsr_backward): d/du, d/dv, d/da, d/db, d/dc, d/do,
  *                 d/dred, d/dgreen, d/dblue, S, C, 0 of each record
  *   cluster_bounds f32[clusters][8] : min xyz, max xyz, max log-scale, 0
- *   cluster_visible u32[clusters] */
+ *   cluster_visible u32[clusters]
+ *   fwd_items   u32[tiles + 3 split_tiles], bwd_items u32[tiles + split_tiles_bwd]:
+ *                 the raster schedules, one work item per entry, (global tile << 3) |
+ *                 code with code 4 the whole tile, 0..3 a 16x4 band of a tile split
+ *                 four ways, 5 and 6 the two halves of a tile split two ways; split
+ *                 tiles first, each group in non-increasing list length */
 typedef struct {
   const float *record;
   const uint32_t *depth_key;
@@ -198,6 +203,8 @@ typedef struct {
   const uint32_t *cluster_visible;
   int64_t pixel_base[GSR_MAX_VIEWS]; /* first pixel of each view in the pixel arrays */
   int64_t tile_base[GSR_MAX_VIEWS];  /* first global tile id of each view */
+  const uint32_t *fwd_items;
+  const uint32_t *bwd_items;
 } gsr_frame_buffers;
 
 /* Context on HIP device `device`. Returns GSR_ERR_DEVICE if the device cannot be used. */

@@ -81,7 +81,8 @@ class GsrFrameBuffers(ctypes.Structure):
                 ("compact2full", c_void_p), ("inst_tile", c_void_p), ("inst_record", c_void_p),
                 ("ranges", c_void_p), ("pixel_T", c_void_p), ("pixel_last", c_void_p),
                 ("grad2d", c_void_p), ("cluster_bounds", c_void_p), ("cluster_visible", c_void_p),
-                ("pixel_base", c_int64 * GSR_MAX_VIEWS), ("tile_base", c_int64 * GSR_MAX_VIEWS)]
+                ("pixel_base", c_int64 * GSR_MAX_VIEWS), ("tile_base", c_int64 * GSR_MAX_VIEWS),
+                ("fwd_items", c_void_p), ("bwd_items", c_void_p)]
 
 
 EXPORTS = {

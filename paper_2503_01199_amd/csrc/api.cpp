@@ -207,7 +207,8 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   const size_t w_depth = up(gsr::sort_ctl_words(f.nrec, 32));
   const size_t w_offsets = up(gsr::scan_ctl_words(f.nrec));
   const size_t w_tiles = up(gsr::sort_ctl_words(std::max<int64_t>(inst_cap, 1), f.tile_bits));
-  f.ctl_words = w_cluster + w_depth + w_offsets + w_tiles;
+  const size_t w_order = up(gsr::tile_order_ctl_words(f.tiles));
+  f.ctl_words = w_cluster + w_depth + w_offsets + w_tiles + w_order;
   f.header = P.take<uint32_t>(64 + f.ctl_words);
   if (f.header) {
     f.ctl = f.header + 64;
@@ -215,6 +216,7 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
     f.ctl_depth_sort = f.ctl_cluster_scan + w_cluster;
     f.ctl_offsets_scan = f.ctl_depth_sort + w_depth;
     f.ctl_tile_sort = f.ctl_offsets_scan + w_offsets;
+    f.ctl_tile_order = w_order ? f.ctl_tile_sort + w_tiles : nullptr;
   }
   for (int b = 0; b < 2; ++b) {
     f.ikey[b] = P.take<uint32_t>((size_t)std::max<int64_t>(inst_cap, 1));
@@ -750,6 +752,8 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
     bufs->grad2d = f.grad2d;
     bufs->cluster_bounds = f.cluster_bounds;
     bufs->cluster_visible = f.cluster_visible;
+    bufs->fwd_items = f.tile_order;
+    bufs->bwd_items = f.bwd_items;
     for (int v = 0; v < f.V; ++v) {
       bufs->tile_base[v] = fr.tile_base[v];
       bufs->pixel_base[v] = fr.pixel_base[v];

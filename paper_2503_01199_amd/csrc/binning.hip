@@ -343,10 +343,197 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   }
 }
 
+// Frames of more than kStageTiles tiles: the same schedule from three launches over
+// many blocks (one block storing the items of the 65k tiles of 8 full-HD views took
+// 155 us). Block g takes the chunk of kOrderChunk tiles from g kOrderChunk. Control
+// words: bucket starts [4096], meta [64] (ns, ns_b, the edge buckets), then per
+// block its bucket counts [4096] and long-list counts [2].
+constexpr int64_t kOrderChunk = 4096;  // tiles per block: 4 per thread
+constexpr int kOrderMeta = kOrderBuckets;
+constexpr int kOrderBlk = kOrderBuckets + 64;
+constexpr int kOrderBlkWords = kOrderBuckets + 2;
+
+// The chunk's count per length bucket and of long lists (written whole: no atomics
+// across blocks).
+template <class Len>
+__global__ __launch_bounds__(kOrderThreads) void k_order_count(Len L, int64_t T, uint32_t split_len,
+                                                               uint32_t split_len_bwd, uint32_t* __restrict__ ctl) {
+  __shared__ uint32_t h[kOrderBuckets];
+  __shared__ uint32_t nl[2];
+  if (L.aborted()) return;
+  const int t = threadIdx.x;
+  for (int b = t; b < kOrderBuckets; b += kOrderThreads) h[b] = 0;
+  if (t < 2) nl[t] = 0;
+  __syncthreads();
+  const int64_t c0 = (int64_t)blockIdx.x * kOrderChunk;
+  uint32_t my_long = 0, my_long_b = 0;
+  uint32_t len[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = c0 + q * kOrderThreads + t;
+    len[q] = L.len(i < T ? i : T - 1);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (c0 + q * kOrderThreads + t >= T) continue;
+    atomicAdd(&h[order_bucket(len[q])], 1u);
+    my_long += len[q] > split_len ? 1u : 0u;
+    my_long_b += len[q] > split_len_bwd ? 1u : 0u;
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    my_long += __shfl_xor(my_long, d, 64);
+    my_long_b += __shfl_xor(my_long_b, d, 64);
+  }
+  if ((t & 63) == 0) {
+    atomicAdd(&nl[0], my_long);
+    atomicAdd(&nl[1], my_long_b);
+  }
+  __syncthreads();
+  uint32_t* blk = ctl + kOrderBlk + (int64_t)blockIdx.x * kOrderBlkWords;
+  for (int b = t; b < kOrderBuckets; b += kOrderThreads) blk[b] = h[b];
+  if (t < 2) blk[kOrderBuckets + t] = nl[t];
+}
+
+// Bucket starts (exclusive scan of the totals), the split counts, the edge buckets
+// and the item counts (one block).
+template <class Len>
+__global__ __launch_bounds__(kOrderThreads) void k_order_scan(Len L, int64_t T, uint32_t* __restrict__ ctl,
+                                                              uint32_t* __restrict__ n_items,
+                                                              uint32_t* __restrict__ n_bwd) {
+  __shared__ uint32_t wsum[kOrderThreads / 64];
+  __shared__ uint32_t edge[2];
+  __shared__ uint32_t nl[2];
+  if (L.aborted()) return;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int64_t G = (T + kOrderChunk - 1) / kOrderChunk;
+  if (t < 2) {
+    edge[t] = kOrderBuckets;
+    uint32_t c = 0;
+    for (int64_t g = 0; g < G; ++g) c += ctl[kOrderBlk + g * kOrderBlkWords + kOrderBuckets + t];
+    nl[t] = c;
+  }
+  uint32_t v[4] = {0, 0, 0, 0}, sum = 0;
+  for (int64_t g = 0; g < G; ++g) {
+    const uint32_t* blk = ctl + kOrderBlk + g * kOrderBlkWords;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] += blk[4 * t + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) sum += v[q];
+  uint32_t incl = sum;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) wsum[t >> 6] = incl;
+  __syncthreads();
+  const uint32_t cap = (uint32_t)((T + kSplitShare - 1) / kSplitShare);
+  const uint32_t ns = min(nl[0], cap);
+  const uint32_t ns_b = min(nl[1], cap);
+  uint32_t off = incl - sum;
+  for (int w = 0; w < (t >> 6); ++w) off += wsum[w];
+  for (int q = 0; q < 4; ++q) {
+    if (ns > 0 && off < ns && ns < off + v[q]) edge[0] = 4 * t + q;
+    if (n_bwd && ns_b > 0 && off < ns_b && ns_b < off + v[q]) edge[1] = 4 * t + q;
+    ctl[4 * t + q] = off;
+    off += v[q];
+  }
+  __syncthreads();
+  if (t == 0) {
+    ctl[kOrderMeta + 0] = ns;
+    ctl[kOrderMeta + 1] = ns_b;
+    ctl[kOrderMeta + 2] = edge[0];
+    ctl[kOrderMeta + 3] = edge[1];
+    *n_items = (uint32_t)T + 3 * ns;
+    if (n_bwd) *n_bwd = (uint32_t)T + ns_b;
+  }
+}
+
+// Places the block's chunk: thread t takes its tiles 4t .. 4t + 3. A tile's rank is
+// its bucket's start, plus the bucket's tiles in the chunks before (their counts),
+// plus its rank within the chunk: in index order in an edge bucket (a block scan),
+// in no particular order in any other (LDS atomics).
+template <class Len>
+__global__ __launch_bounds__(kOrderThreads) void k_order_place(Len L, int64_t T, const uint32_t* __restrict__ ctl,
+                                                               uint32_t* __restrict__ items,
+                                                               uint32_t* __restrict__ bwd) {
+  __shared__ uint32_t base[kOrderBuckets];  // the block's first rank per bucket
+  __shared__ uint32_t h[kOrderBuckets];     // chunk ranks handed out per bucket
+  __shared__ uint32_t wsum[2][kOrderThreads / 64];
+  if (L.aborted()) return;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const uint32_t ns = ctl[kOrderMeta + 0], ns_b = ctl[kOrderMeta + 1];
+  const uint32_t e0 = ctl[kOrderMeta + 2], e1 = ctl[kOrderMeta + 3];
+  const int64_t g = blockIdx.x;
+  for (int b = t; b < kOrderBuckets; b += kOrderThreads) {
+    uint32_t x = ctl[b];
+    for (int64_t q = 0; q < g; ++q) x += ctl[kOrderBlk + q * kOrderBlkWords + b];
+    base[b] = x;
+    h[b] = 0;
+  }
+  __syncthreads();
+  const int64_t i0 = g * kOrderChunk + 4 * (int64_t)t;
+  uint32_t bk[4], rk[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) bk[q] = order_bucket(L.len(i0 + q < T ? i0 + q : T - 1));
+  uint32_t c_e0 = 0, c_e1 = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    rk[q] = 0;
+    if (i0 + q >= T) continue;
+    if (bk[q] == e0) rk[q] = c_e0++;
+    else if (bk[q] == e1) rk[q] = c_e1++;
+    else rk[q] = atomicAdd(&h[bk[q]], 1u);
+  }
+  // ranks of the edge tiles of lower threads (index order)
+  uint32_t x0 = c_e0, x1 = c_e1;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y0 = __shfl_up(x0, d, 64), y1 = __shfl_up(x1, d, 64);
+    if (lane >= d) {
+      x0 += y0;
+      x1 += y1;
+    }
+  }
+  if (lane == 63) {
+    wsum[0][t >> 6] = x0;
+    wsum[1][t >> 6] = x1;
+  }
+  __syncthreads();
+  uint32_t r0 = x0 - c_e0, r1 = x1 - c_e1;
+  for (int w = 0; w < (t >> 6); ++w) {
+    r0 += wsum[0][w];
+    r1 += wsum[1][w];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = i0 + q;
+    if (i >= T) continue;
+    const uint32_t pos = base[bk[q]] + rk[q] + (bk[q] == e0 ? r0 : bk[q] == e1 ? r1 : 0u);
+    place_items(items, (uint32_t)i, pos, ns, 4);
+    if (bwd) place_items(bwd, (uint32_t)i, pos, ns_b, 2);
+  }
+}
+
 }  // namespace
+
+size_t tile_order_ctl_words(int64_t tiles) {
+  return tiles > kStageTiles ? kOrderBlk + (size_t)((tiles + kOrderChunk - 1) / kOrderChunk) * kOrderBlkWords : 0;
+}
 
 bool launch_tile_order(const Frame& f, hipStream_t s, hipEvent_t done) {
   if (f.tiles <= 0) return false;
+  if (f.tiles > kStageTiles && f.ctl_tile_order) {
+    const OneFrame L{f.ranges, f.header};
+    const unsigned g = (unsigned)((f.tiles + kOrderChunk - 1) / kOrderChunk);
+    k_order_count<<<g, kOrderThreads, 0, s>>>(L, (int64_t)f.tiles, f.split_len, f.split_len_bwd, f.ctl_tile_order);
+    k_order_scan<<<1, kOrderThreads, 0, s>>>(L, (int64_t)f.tiles, f.ctl_tile_order, f.header + kHdrItems,
+                                             f.header + kHdrItemsBwd);
+    launch_tracked(k_order_place<OneFrame>, g, kOrderThreads, s, done, L, (int64_t)f.tiles, f.ctl_tile_order,
+                   f.tile_order, f.bwd_items);
+    return true;
+  }
   launch_tracked(k_tile_order<OneFrame>, 1, kOrderThreads, s, done, OneFrame{f.ranges, f.header}, (int64_t)f.tiles,
                  f.split_len, f.split_len_bwd, f.tile_order, f.header + kHdrItems, f.bwd_items,
                  f.header + kHdrItemsBwd);

@@ -149,6 +149,7 @@ struct Frame {
   uint32_t* ctl;            // look-back / histogram control words, cleared with the header
   size_t ctl_words;
   uint32_t *ctl_cluster_scan, *ctl_depth_sort, *ctl_offsets_scan, *ctl_tile_sort;
+  uint32_t* ctl_tile_order = nullptr;  // multi-block raster schedule of large frames (tile_order_ctl_words)
 };
 
 // ---------------------------------------------------------------- launchers
@@ -210,6 +211,9 @@ void launch_preprocess_bwd(const gsr_scene& sc, const Frame& f, const gsr_grads&
 void launch_emit_instances(const Frame& f, const uint32_t* sorted_rec, hipStream_t s);
 void launch_tile_ranges(const Frame& f, const uint32_t* inst_tile, int64_t M_max, hipStream_t s);
 bool launch_tile_order(const Frame& f, hipStream_t s, hipEvent_t done);
+// Control words the raster schedule of a frame of `tiles` tiles needs (zero when one
+// block builds it); they must be zero on entry.
+size_t tile_order_ctl_words(int64_t tiles);
 
 // raster_fwd.hip / raster_bwd.hip
 struct ImagePtrs {

@@ -385,24 +385,33 @@ merge:
   }
 }
 
-// One pass: block b takes tile b of 2048 items (8 coalesced rounds of 256), ranks
-// them stably within the tile (ballot match per wave, counts per (round, wave,
-// digit) in LDS), learns the per-digit counts of all earlier tiles by look-back and
-// scatters. The tile is first reordered by digit in LDS (reusing the counters'
-// space), so that consecutive threads store consecutive positions of each digit's
-// run: a direct per-item scatter writes 256 short runs from scattered lanes.
+// One pass: block b takes tile b of kTile items. Wave w owns the contiguous quarter
+// [w kTile/4, (w+1) kTile/4) of the tile and ranks it round by round (64 consecutive
+// items per round, coalesced): the lanes holding the same 8-bit digit find each
+// other by ballots, and a per-wave running count per digit in LDS gives each item
+// its rank among the wave's earlier items of that digit. Ordering by (wave, round,
+// lane) is the input order, so the ranks are stable. The block then learns the
+// per-digit counts of all earlier tiles by look-back and scatters; the tile is first
+// reordered by digit in LDS, so that consecutive threads store consecutive positions
+// of each digit's run (a direct per-item scatter writes 256 short runs from
+// scattered lanes). The per-wave counters take 4 KB of LDS whatever the tile size,
+// so more blocks fit on a CU than with per-round counters; the tile is staged
+// before the look-back, so that keys and values leave the registers first. A
+// 4096-item tile of 32-bit keys is held to 128 registers: four blocks per CU.
 template <typename K, int R>
-__global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R > 8 && sizeof(K) == 4 ? 4 : 1))) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n_host, const uint32_t* __restrict__ n_dev,
                                                              int shift, const uint32_t* __restrict__ offs,
                                                              uint32_t* __restrict__ ctl, uint32_t* __restrict__ err,
                                                              int64_t withhold) {
   constexpr int kTile = kSortThreads * R;  // items per tile: R rounds of one item per thread
-  __shared__ __align__(16) uint32_t cnt[R][4][256];
-  __shared__ uint32_t gofs[256], ldig[256], wtot[4];
-  static_assert(sizeof(K) * kTile + 4 * kTile <= sizeof(uint32_t) * R * 4 * 256,
-                "the staged tile fits in the counters' space");
+  constexpr int kWaves = kSortThreads / 64;
+  constexpr int kQuarter = kTile / kWaves;  // items per wave
+  __shared__ uint32_t wcnt[kWaves][256];    // running count, then exclusive offset, per (wave, digit)
+  __shared__ __align__(16) K s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
+  __shared__ uint32_t gofs[256], ldig[256], wtot[kWaves];
   if (block_error(err)) return;
   const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
   const int t = threadIdx.x;
@@ -412,55 +421,57 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kTile;
     if (base >= n) return;  // uniform over the block
-    for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cnt[r][q][t] = 0;
-    __syncthreads();
+    for (int q = 0; q < 4; ++q) wcnt[w][lane + 64 * q] = 0;
+    const int64_t wbase = base + (int64_t)w * kQuarter + lane;  // round r: item wbase + 64 r
     K key[R];
-    uint32_t val[R];
-    uint32_t dig[R];
-    uint32_t rank[R];
+    uint32_t rd[R];  // rank among the wave's items of the same digit, | digit << 16 (256: past the end)
     // every round's loads first (indices clamped into range, so none sits behind a
     // branch and their round trips overlap), then the ranking
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int64_t i = base + r * kSortThreads + t;
+      const int64_t i = wbase + 64 * r;
       key[r] = kin[i < n ? i : n - 1];
     }
+    // the wave's counters are zero before its first read (LDS runs a wave's
+    // instructions in order)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool valid = wbase + 64 * r < n;
+      const uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
+      const uint64_t peers = match_digit(d & 255u, valid);
+      const uint32_t before = valid ? wcnt[w][d] : 0u;
+      const uint32_t below = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+      rd[r] = (before + below) | (d << 16);
+      if (valid && below == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+      // the next round reads what this one wrote (in order within the wave)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    uint32_t val[R];  // loaded once the ranking no longer holds registers
     if (vin) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int64_t i = base + r * kSortThreads + t;
+        const int64_t i = wbase + 64 * r;
         val[r] = vin[i < n ? i : n - 1];
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < R; ++r) val[r] = (uint32_t)(base + r * kSortThreads + t);
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t i = base + r * kSortThreads + t;
-      const bool valid = i < n;
-      dig[r] = valid ? (uint32_t)(key[r] >> shift) & 255u : 256u;
-      const uint64_t peers = match_digit(dig[r] & 255u, valid);
-      rank[r] = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
-      if (valid && rank[r] == 0) cnt[r][w][dig[r]] = (uint32_t)__popcll(peers);
+      for (int r = 0; r < R; ++r) val[r] = (uint32_t)(wbase + 64 * r);
     }
     __syncthreads();
-    // thread d: exclusive running count of digit d over (round, wave), then the tile total
+    // thread d: exclusive offsets of digit d over the waves, then the tile total
     uint32_t run = 0;
-    for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t c = cnt[r][q][t];
-        cnt[r][q][t] = run;
-        run += c;
-      }
-    const int64_t tiles = (n_host + kTile - 1) / kTile;
-    const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err,
-                                             tile != withhold);
-    if (block_error(err)) return;  // a wait gave up: the prefixes may be partial
-    gofs[t] = offs[t] + prior;
+    for (int q = 0; q < kWaves; ++q) {
+      const uint32_t c = wcnt[q][t];
+      wcnt[q][t] = run;
+      run += c;
+    }
     // tile-local digit offsets: exclusive scan over the digits of the tile's totals
     const uint32_t incl = wave_incl_scan(run);
     if (lane == 63) wtot[w] = incl;
@@ -469,21 +480,22 @@ __global__ __launch_bounds__(kSortThreads) void k_os_scatter(const K* __restrict
     for (int q = 0; q < w; ++q) woff += wtot[q];
     ldig[t] = woff + incl - run;
     __syncthreads();
-    uint32_t lpos[R];  // position in the tile sorted by digit (stable)
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      lpos[r] = dig[r] < 256u ? ldig[dig[r]] + cnt[r][w][dig[r]] + rank[r] : 0xffffffffu;
-    __syncthreads();  // the counters are consumed: their space takes the staged tile
-    K* s_key = reinterpret_cast<K*>(&cnt[0][0][0]);
-    uint32_t* s_val = reinterpret_cast<uint32_t*>(s_key + kTile);
+    // the tile sorted by digit (stable) in LDS; its place in the output needs only
+    // the earlier tiles' counts, learnt next
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (lpos[r] < (uint32_t)kTile) {
-        s_key[lpos[r]] = key[r];
-        s_val[lpos[r]] = val[r];
+      const uint32_t d = rd[r] >> 16;
+      if (d < 256u) {
+        const uint32_t lpos = ldig[d] + wcnt[w][d] + (rd[r] & 0xFFFFu);
+        s_key[lpos] = key[r];
+        s_val[lpos] = val[r];
       }
     }
-    __syncthreads();
+    const int64_t tiles = (n_host + kTile - 1) / kTile;
+    const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err,
+                                             tile != withhold);
+    gofs[t] = offs[t] + prior;
+    if (block_error(err)) return;  // a wait gave up: the prefixes may be partial (also orders the LDS writes)
     const int nv = (int)min<int64_t>(kTile, n - base);
     for (int q = t; q < nv; q += kSortThreads) {
       const K k = s_key[q];

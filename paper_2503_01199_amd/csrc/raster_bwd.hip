@@ -34,6 +34,7 @@ constexpr int kBatch = 64;  // records per LDS batch
 // Entries whose wave totals are staged in LDS before one pass turns them into
 // gradients and issues their atomics (a divisor of kBatch).
 constexpr int kGroup = 16;
+static_assert(kBatch % kGroup == 0 && kGroup <= 16, "a group's atomics take one pass of four lanes per entry");
 
 // Deterministic backward: per-tile sums become two's-complement fixed point (round
 // to nearest, saturating) at the frame's scale (grad_exponent), so that the

@@ -375,6 +375,8 @@ class Rasterizer:
             grad2d=ws.view(b.grad2d, 12 * R, f32).view(R, 12),
             cluster_bounds=ws.view(b.cluster_bounds, 8 * max(info.clusters, 1), f32).view(-1, 8),
             cluster_visible=ws.view(b.cluster_visible, max(info.clusters, 1), u32),
+            fwd_items=ws.view(b.fwd_items, info.tiles + 3 * info.split_tiles, u32),
+            bwd_items=ws.view(b.bwd_items, info.tiles + info.split_tiles_bwd, u32),
             pixel_base=[b.pixel_base[v] for v in range(V)],
             tile_base=[b.tile_base[v] for v in range(V)],
             info=info_d,
