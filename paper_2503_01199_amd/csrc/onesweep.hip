@@ -72,17 +72,24 @@ __device__ __forceinline__ bool block_error(uint32_t* err) {
 // Sum, in status column `col` (stride `stride` words between entries), of the
 // values from entry b down to the nearest inclusive prefix, that prefix included
 // (entries below 0 count as an empty prefix). The walk reads kWindow entries per
-// round trip and consumes them in order, waiting on entries not yet published.
+// round trip (kFirstWindow in the first: the nearest prefix is usually the entry
+// just below, and every status read goes past the XCD's L2) and consumes them in
+// order, waiting on entries not yet published.
 constexpr int kWindow = 16;
+constexpr int kFirstWindow = 4;
 
 __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride, int col, uint32_t* err) {
   uint32_t excl = 0;
   const WaitBound bound;
   bool found = false;
+  int win = kFirstWindow;
   while (!found) {
     uint32_t st[kWindow];
 #pragma unroll
-    for (int q = 0; q < kWindow; ++q) st[q] = b - q >= 0 ? ld_status(status + (b - q) * stride + col) : kFlagPrefix;
+    for (int q = 0; q < kWindow; ++q)
+      st[q] = q >= win ? 0u : b - q >= 0 ? ld_status(status + (b - q) * stride + col) : kFlagPrefix;
+    const int read = win;
+    win = kWindow;
     int used = 0;
 #pragma unroll
     for (int q = 0; q < kWindow; ++q) {
@@ -95,7 +102,7 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
     }
     if (found) break;
     b -= used;
-    if (used < kWindow) {
+    if (used < read) {  // stopped at a status not yet published: wait a little
       if (bound.over(err)) break;
       __builtin_amdgcn_s_sleep(1);
     }
@@ -128,10 +135,9 @@ __device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t 
   for (;;) {
     uint32_t v[kGroup - 1];
 #pragma unroll
-    for (int q = 0; q < kGroup - 1; ++q) {  // clamped index: all loads in flight at once
+    for (int q = 0; q < kGroup - 1; ++q) {  // all loads in flight at once (the condition is uniform)
       const int64_t j = tile - 1 - q;
-      const uint32_t x = ld_status(tstat + (j >= g0 ? j : g0) * stride + col);
-      v[q] = j >= g0 ? x : kFlagAgg;
+      v[q] = j >= g0 ? ld_status(tstat + j * stride + col) : kFlagAgg;
     }
     bool ready = true;
     uint32_t sum = 0;
