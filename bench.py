@@ -55,9 +55,9 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                             "sources": ["paper_2503_01199_amd/csrc/raster_bwd.hip",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
-                            "sha1": "0dc43ef58e66037afc147dafcae2891af92677ec",
-                            "fetch_kib": 70572.0, "write_kib": 99531.0,
-                            "valu_insts": 153793460}}
+                            "sha1": "528fa3cc62ed14eca22bf522a9fcab76da172d2c",
+                            "fetch_kib": 70449.6, "write_kib": 99531.2,
+                            "valu_insts": 128924690, "valu_busy": 0.9189, "valu_utilization": 0.7306}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
@@ -369,6 +369,8 @@ def main():
                     help="Gaussian order of the scene (shuffled: a random permutation, for cache counters)")
     ap.add_argument("--only-steps", action="store_true",
                     help="warm up, time the steps and stop (for profiler runs)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "fp16t"],
+                    help="blend precision of the steps of an --only-steps run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -450,13 +452,15 @@ def main():
     torch.cuda.synchronize()
 
     if args.only_steps:  # profiler runs: the timed steps only
+        prec = {"fp32": L.GSR_FP32, "fp16": L.GSR_FP16_BLEND, "fp16t": L.GSR_FP16_BLEND_T}[args.precision]
         torch.cuda.synchronize()
         wall0 = time.perf_counter()
         for _ in range(args.steps):
-            fr = step()
+            fr = step(precision=prec)
         torch.cuda.synchronize()
         info = rz.check_frame(fr)
-        print(json.dumps({"workload": desc, "order": args.order, "cluster_cull": cull, "ms_per_step":
+        print(json.dumps({"workload": desc, "order": args.order, "cluster_cull": cull, "precision": args.precision,
+                          "ms_per_step":
                           round((time.perf_counter() - wall0) * 1e3 / args.steps, 4), "steps": args.steps,
                           "frames": 1 + max(args.warmup - 1, 0) + args.steps,
                           "instances": info["instances"]}), flush=True)
