@@ -319,6 +319,24 @@ gsr_status gsr_morton_workspace_size(gsr_context *ctx, int64_t n, size_t *bytes)
 gsr_status gsr_morton_order(gsr_context *ctx, const float *means, int64_t n, void *workspace, size_t ws_bytes,
                             int64_t *perm, uint64_t *codes, void *stream);
 
+/* Workspace bytes for gsr_sort_u32 on n keys of `bits` bits (ctx may be NULL). */
+gsr_status gsr_sort_workspace_size(gsr_context *ctx, int64_t n, int32_t bits, size_t *bytes);
+
+/* Stable LSD radix sort of n (< 2^30) 32-bit keys on their low `bits` bits (1..32),
+ * 8 bits per one-sweep pass: the sort that orders the records by depth and the
+ * instances by tile (App. A.1's binning, in the sorted order Eq. (1) composites).
+ * keys [n] (device, each below 2^bits: the passes take whole bytes, so bits above
+ * are not ignored) and vals [n] (device; NULL: the values are the positions
+ * 0..n-1) are read only; out_keys [n], out_vals [n] (device) receive the keys in
+ * ascending order, equal ones in input order, and their values;
+ * outputs must not overlap the inputs or each other. Pointers need 4-byte
+ * alignment only. workspace: gsr_sort_workspace_size bytes, 256-byte aligned. The
+ * call does not wait: the first 32-bit word of the workspace is nonzero once the
+ * stream has passed the sort if a device-wide wait gave up (the output is then
+ * incomplete); it is zero otherwise. */
+gsr_status gsr_sort_u32(gsr_context *ctx, const uint32_t *keys, const uint32_t *vals, int64_t n, int32_t bits,
+                        uint32_t *out_keys, uint32_t *out_vals, void *workspace, size_t ws_bytes, void *stream);
+
 /* Gathers rows: dst[a][i, :] = src[a][perm[i], :] for n_arrays arrays of n rows of
  * row_floats[a] floats (device memory; dst and src must not overlap). Applies a
  * Morton order to the parameters and to any optimiser state. */

@@ -111,6 +111,9 @@ EXPORTS = {
     "gsr_variance": (c_int32, [c_void_p, ctypes.POINTER(GsrStats), c_int64, c_void_p, c_void_p]),
     "gsr_morton_workspace_size": (c_int32, [c_void_p, c_int64, ctypes.POINTER(c_size_t)]),
     "gsr_morton_order": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "gsr_sort_workspace_size": (c_int32, [c_void_p, c_int64, c_int32, ctypes.POINTER(c_size_t)]),
+    "gsr_sort_u32": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_size_t,
+                               c_void_p]),
     "gsr_apply_permutation": (c_int32, [c_void_p, c_void_p, c_int64, c_int32, ctypes.POINTER(c_void_p),
                                         ctypes.POINTER(c_void_p), ctypes.POINTER(c_int32), c_void_p]),
     "gsr_l1_grad": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),

@@ -1076,6 +1076,61 @@ gsr_status gsr_morton_order(gsr_context* ctx, const float* means, int64_t n, voi
   return check_hip(ctx, hipGetLastError(), "morton order");
 }
 
+namespace {
+// Sort workspace: the error word (padded to 64 words), the control words, then one
+// key and one value buffer of n for the passes that do not write the output.
+size_t sort_ws_words(int64_t n, int bits) {
+  const size_t ctl = (gsr::sort_ctl_words(std::max<int64_t>(n, 1), bits) + 63) & ~(size_t)63;
+  return 64 + ctl + 2 * (((size_t)std::max<int64_t>(n, 1) + 63) & ~(size_t)63);
+}
+}  // namespace
+
+gsr_status gsr_sort_workspace_size(gsr_context* ctx, int64_t n, int32_t bits, size_t* bytes) {
+  if (!bytes || n < 0 || n >= ((int64_t)1 << 30) || bits < 1 || bits > 32)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_sort_workspace_size");
+  *bytes = sort_ws_words(n, bits) * 4;
+  return GSR_OK;
+}
+
+gsr_status gsr_sort_u32(gsr_context* ctx, const uint32_t* keys, const uint32_t* vals, int64_t n, int32_t bits,
+                        uint32_t* out_keys, uint32_t* out_vals, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx) return GSR_ERR_INVALID_ARG;
+  if (n < 0 || n >= ((int64_t)1 << 30) || bits < 1 || bits > 32 ||
+      (n > 0 && (!keys || !out_keys || !out_vals || !workspace)))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "bad arguments to gsr_sort_u32");
+  const uintptr_t all = (uintptr_t)keys | (uintptr_t)vals | (uintptr_t)out_keys | (uintptr_t)out_vals;
+  if ((all & 3u) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sort_u32: arrays need 4-byte alignment");
+  auto overlap = [n](const void* a, const void* b) {
+    const char *x = static_cast<const char*>(a), *y = static_cast<const char*>(b);
+    return a && b && x < y + 4 * n && y < x + 4 * n;
+  };
+  if (overlap(out_keys, out_vals) || overlap(out_keys, keys) || overlap(out_keys, vals) ||
+      overlap(out_vals, keys) || overlap(out_vals, vals))
+    return fail(ctx, GSR_ERR_INVALID_ARG, "gsr_sort_u32: outputs overlap the inputs or each other");
+  const size_t need = sort_ws_words(n, bits) * 4;
+  if (ws_bytes < need) {
+    ctx->required = need;
+    return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "sort workspace %zu < %zu", ws_bytes, need);
+  }
+  if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (n == 0) return GSR_OK;
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* err = static_cast<uint32_t*>(workspace);
+  const size_t ctl_words = (gsr::sort_ctl_words(n, bits) + 63) & ~(size_t)63;
+  uint32_t* ctl = err + 64;
+  uint32_t* tk = ctl + ctl_words;
+  uint32_t* tv = tk + ((n + 63) & ~(int64_t)63);
+  gsr::fill_u32(err, 64 + (int64_t)ctl_words, 0u, s);
+  // the last pass writes the outputs: pass p writes buffer p & 1
+  const int passes = (bits + 7) / 8;
+  const int last = (passes - 1) & 1;
+  uint32_t* kb[2] = {last == 0 ? out_keys : tk, last == 1 ? out_keys : tk};
+  uint32_t* vb[2] = {last == 0 ? out_vals : tv, last == 1 ? out_vals : tv};
+  gsr::radix_sort_u32_dev(keys, vals, kb, vb, n, nullptr, bits, ctl, err, false, s);
+  return check_hip(ctx, hipGetLastError(), "sort");
+}
+
 gsr_status gsr_apply_permutation(gsr_context* ctx, const int64_t* perm, int64_t n, int32_t n_arrays,
                                  const float* const* src, float* const* dst, const int32_t* row_floats, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;

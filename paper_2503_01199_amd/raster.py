@@ -398,6 +398,29 @@ class Rasterizer:
                                               self._stream()), "gsr_morton_order")
         return perm, codes
 
+    def sort_u32(self, keys: torch.Tensor, vals: torch.Tensor | None = None, bits: int = 32,
+                 workspace: Workspace | None = None):
+        """Stable radix sort of 32-bit keys (int32 tensors holding the bits) on their low
+        `bits` bits with their values (None: positions), gsr_sort_u32. Keys and values
+        may start at any 4-byte offset. Returns (keys, values) and raises if a
+        device-wide wait gave up."""
+        n = int(keys.numel())
+        assert keys.dtype == torch.int32 and keys.is_contiguous()
+        assert vals is None or (vals.dtype == torch.int32 and vals.is_contiguous() and vals.numel() == n)
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.gsr_sort_workspace_size(self.ctx, n, int(bits), ctypes.byref(nbytes)),
+                    "gsr_sort_workspace_size")
+        ws = workspace if workspace is not None else Workspace(self.device)
+        ws.ensure(nbytes.value)
+        out_k = torch.empty(n, dtype=torch.int32, device=self.device)
+        out_v = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(self.lib.gsr_sort_u32(self.ctx, keys.data_ptr(), vals.data_ptr() if vals is not None else None, n,
+                                          int(bits), out_k.data_ptr(), out_v.data_ptr(), ws.ptr, ws.nbytes,
+                                          self._stream()), "gsr_sort_u32")
+        if n > 0 and int(ws.view(ws.ptr, 1, torch.int32).item()) != 0:
+            raise L.GsrError(L.GSR_ERR_DEVICE, "gsr_sort_u32: a device-wide wait gave up")
+        return out_k, out_v
+
     def apply_permutation(self, perm: torch.Tensor, arrays):
         """New tensors dst[i] = src[perm[i]] for each array (rows along dim 0)."""
         n = int(perm.shape[0])
