@@ -59,14 +59,38 @@ struct WaitBound {
   }
 };
 
-// Reads the error word once for the whole block (waves may otherwise read it at
-// different times while other blocks raise it); every thread must call it.
-__device__ __forceinline__ bool block_error(uint32_t* err) {
+// Block entry: the error word and the item count (n_dev, or n_host when null), read
+// once for the whole block by one thread, both loads in one round trip (waves could
+// otherwise read the word at different times while other blocks raise it). A raised
+// word means an earlier stage gave up and the count may be garbage: the caller
+// leaves without using it. Every thread must call it; it also clears the block's
+// incomplete-wait flag (block_incomplete).
+struct BlockStart {
+  bool error;
+  int64_t n;
+};
+__device__ __forceinline__ BlockStart block_start(uint32_t* err, const uint32_t* n_dev, int64_t n_host,
+                                                  uint32_t& s_incomplete) {
   __shared__ uint32_t s_err;
+  __shared__ int64_t s_n;
+  if (threadIdx.x == 0) {
+    const uint32_t e = ld_status(err);
+    const int64_t n = n_dev ? (int64_t)ld_status(n_dev) : n_host;
+    s_err = e;
+    s_n = n;
+    s_incomplete = 0u;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) s_err = ld_status(err);
+  return {s_err != 0u, s_n};
+}
+
+// After the look-back: whether any thread's waits ended before its prefix was
+// complete (they end early only when the error word is raised). Every thread must
+// call it with its own look-back's completion; it synchronises the block.
+__device__ __forceinline__ bool block_incomplete(bool complete, uint32_t& s_incomplete) {
+  if (!complete) s_incomplete = 1u;
   __syncthreads();
-  return s_err != 0u;
+  return s_incomplete != 0u;
 }
 
 // Sum, in status column `col` (stride `stride` words between entries), of the
@@ -78,7 +102,8 @@ __device__ __forceinline__ bool block_error(uint32_t* err) {
 constexpr int kWindow = 16;
 constexpr int kFirstWindow = 4;
 
-__device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride, int col, uint32_t* err) {
+__device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride, int col, uint32_t* err,
+                              bool& complete) {
   uint32_t excl = 0;
   const WaitBound bound;
   bool found = false;
@@ -107,6 +132,7 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
       __builtin_amdgcn_s_sleep(1);
     }
   }
+  complete = found;
   return excl;
 }
 
@@ -119,16 +145,26 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
 // progress. tstat: [tiles][stride] per-tile aggregates; gstat: [groups][stride].
 constexpr int kGroup = 16;
 
-// publish = false (tests of the error path only): the tile never publishes.
-__device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t tile, int64_t stride, int col,
-                                      uint32_t agg, uint32_t* err, bool publish = true) {
+// The look-back in two steps, so that a caller can do other work between them
+// while its aggregate reaches the later tiles: look_back_publish publishes the
+// tile's aggregate (returned, clipped to the value range); look_back_gather then
+// waits for the exclusive prefix. publish = false (tests of the error path only):
+// the tile never publishes. complete: the prefix found is whole (false only when a
+// wait gave up).
+__device__ __forceinline__ uint32_t look_back_publish(uint32_t* tstat, int64_t tile, int64_t stride, int col,
+                                                      uint32_t agg, uint32_t* err, bool publish = true) {
   if (agg > kValueMask) {
     atomicOr(err, kErrCount);
     agg &= kValueMask;
   }
+  if (publish) st_status(tstat + tile * stride + col, kFlagAgg | agg);
+  return agg;
+}
+
+__device__ uint32_t look_back_gather(uint32_t* tstat, uint32_t* gstat, int64_t tile, int64_t stride, int col,
+                                     uint32_t agg, uint32_t* err, bool& complete, bool publish = true) {
   const int64_t g = tile / kGroup, g0 = g * kGroup;
   const bool last = publish && tile % kGroup == kGroup - 1;
-  if (publish) st_status(tstat + tile * stride + col, kFlagAgg | agg);
   // exclusive sum over the group's earlier tiles g0 .. tile - 1
   uint32_t E = 0;
   const WaitBound bound;
@@ -152,15 +188,25 @@ __device__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t 
     }
     if (bound.over(err)) {
       E = sum;
-      break;
+      complete = false;
+      return E;  // the prefix is partial: publish nothing further
     }
     __builtin_amdgcn_s_sleep(1);
   }
   if (last) st_status(gstat + g * stride + col, kFlagAgg | ((E + agg) & kValueMask));
-  const uint32_t X = g > 0 ? walk_back(gstat, g - 1, stride, col, err) : 0u;
+  bool walked = true;
+  const uint32_t X = g > 0 ? walk_back(gstat, g - 1, stride, col, err, walked) : 0u;
+  complete = walked;
   if ((uint64_t)X + E + agg > kValueMask) atomicOr(err, kErrCount);
-  if (last) st_status(gstat + g * stride + col, kFlagPrefix | ((X + E + agg) & kValueMask));
+  if (last && walked) st_status(gstat + g * stride + col, kFlagPrefix | ((X + E + agg) & kValueMask));
   return X + E;
+}
+
+__device__ __forceinline__ uint32_t look_back_grouped(uint32_t* tstat, uint32_t* gstat, int64_t tile, int64_t stride,
+                                                      int col, uint32_t agg, uint32_t* err, bool& complete,
+                                                      bool publish = true) {
+  agg = look_back_publish(tstat, tile, stride, col, agg, err, publish);
+  return look_back_gather(tstat, gstat, tile, stride, col, agg, err, complete, publish);
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
@@ -187,9 +233,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
                                                        uint32_t* __restrict__ total, uint32_t* __restrict__ list,
                                                        uint32_t* __restrict__ ctl, uint32_t* __restrict__ err) {
   __shared__ uint32_t wsum[kScanThreads / 64];
-  __shared__ uint32_t s_excl;
-  if (block_error(err)) return;  // an earlier stage gave up: its counts and indices may be garbage
-  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  __shared__ uint32_t s_excl, s_incomplete;
+  const BlockStart bs = block_start(err, n_dev, n_host, s_incomplete);
+  if (bs.error) return;  // an earlier stage gave up: its counts and indices may be garbage
+  const int64_t n = bs.n;
   const int t = threadIdx.x;
   const int64_t tile = blockIdx.x;
   const int64_t base = tile * kScanTile;
@@ -226,11 +273,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const uint32_t* __restric
     off += (w < (t >> 6)) ? wsum[w] : 0u;
     agg += wsum[w];
   }
+  bool complete = true;
   if (t == 0) {
     const int64_t tiles = max<int64_t>(1, (n_host + kScanTile - 1) / kScanTile);
-    s_excl = look_back_grouped(ctl + 1, ctl + 1 + tiles, tile, 1, 0, agg, err);
+    s_excl = look_back_grouped(ctl + 1, ctl + 1 + tiles, tile, 1, 0, agg, err, complete);
   }
-  if (block_error(err)) return;  // a wait gave up: the prefix may be partial
+  if (block_incomplete(complete, s_incomplete)) return;  // a wait gave up: the prefix may be partial
   uint32_t run = s_excl + off + incl - sum;
 #pragma unroll
   for (int q = 0; q < kScanItems; ++q) {
@@ -288,8 +336,11 @@ __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ 
   __shared__ uint32_t h[kMaxPasses][256];
   __shared__ uint32_t wsum[kSortThreads / 64];
   __shared__ bool last;
-  if (error_raised(err)) return;  // set by an earlier kernel only: the same for every wave
-  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  // the error word (set by an earlier kernel only: the same for every wave) and the
+  // count, loaded together; a raised word means the count may be garbage
+  const uint32_t e = ld_status(err);
+  const int64_t n = n_dev ? (int64_t)ld_status(n_dev) : n_host;
+  if (e != 0u) return;
   int64_t nb = (n + kHistChunk - 1) / kHistChunk;
   if (nb < 1) nb = 1;
   if (nb > gridDim.x) nb = gridDim.x;
@@ -418,8 +469,10 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
   __shared__ __align__(16) K s_key[kTile];
   __shared__ uint32_t s_val[kTile];
   __shared__ uint32_t gofs[256], ldig[256], wtot[kWaves];
-  if (block_error(err)) return;
-  const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+  __shared__ uint32_t s_incomplete;
+  const BlockStart bs = block_start(err, n_dev, n_host, s_incomplete);
+  if (bs.error) return;  // an earlier stage gave up: its counts may be garbage
+  const int64_t n = bs.n;
   const int t = threadIdx.x;
   const int w = t >> 6;
   const int lane = t & 63;
@@ -432,13 +485,32 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
     const int64_t wbase = base + (int64_t)w * kQuarter + lane;  // round r: item wbase + 64 r
     K key[R];
     uint32_t rd[R];  // rank among the wave's items of the same digit, | digit << 16 (256: past the end)
+    uint32_t val[R];
     // every round's loads first (indices clamped into range, so none sits behind a
-    // branch and their round trips overlap), then the ranking
+    // branch and their round trips overlap), then the ranking; tiles of up to 2048
+    // items load their values with the keys too, larger ones after the ranking (so
+    // that the ranking's registers are not held by them)
+    constexpr bool kEarlyVals = R <= 8;
+    // the digit's offset, needed after the look-back, loaded with the keys (small tiles)
+    const uint32_t digit_off = kEarlyVals ? offs[t] : 0u;
+    auto load_vals = [&]() __attribute__((always_inline)) {
+      if (vin) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int64_t i = wbase + 64 * r;
+          val[r] = vin[i < n ? i : n - 1];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) val[r] = (uint32_t)(wbase + 64 * r);
+      }
+    };
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int64_t i = wbase + 64 * r;
       key[r] = kin[i < n ? i : n - 1];
     }
+    if constexpr (kEarlyVals) load_vals();
     // the wave's counters are zero before its first read (LDS runs a wave's
     // instructions in order)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -458,19 +530,10 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    uint32_t val[R];  // loaded once the ranking no longer holds registers
-    if (vin) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int64_t i = wbase + 64 * r;
-        val[r] = vin[i < n ? i : n - 1];
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) val[r] = (uint32_t)(wbase + 64 * r);
-    }
+    if constexpr (!kEarlyVals) load_vals();
     __syncthreads();
-    // thread d: exclusive offsets of digit d over the waves, then the tile total
+    // thread d: exclusive offsets of digit d over the waves, then the tile total,
+    // published at once (the staging below overlaps its way to the later tiles)
     uint32_t run = 0;
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) {
@@ -478,6 +541,8 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
       wcnt[q][t] = run;
       run += c;
     }
+    const int64_t tiles = (n_host + kTile - 1) / kTile;
+    const uint32_t agg = look_back_publish(ctl + 64, tile, 256, t, run, err, tile != withhold);
     // tile-local digit offsets: exclusive scan over the digits of the tile's totals
     const uint32_t incl = wave_incl_scan(run);
     if (lane == 63) wtot[w] = incl;
@@ -497,11 +562,12 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
         s_val[lpos] = val[r];
       }
     }
-    const int64_t tiles = (n_host + kTile - 1) / kTile;
-    const uint32_t prior = look_back_grouped(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, run, err,
-                                             tile != withhold);
-    gofs[t] = offs[t] + prior;
-    if (block_error(err)) return;  // a wait gave up: the prefixes may be partial (also orders the LDS writes)
+    bool complete = true;
+    const uint32_t prior = look_back_gather(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, agg, err, complete,
+                                            tile != withhold);
+    gofs[t] = (kEarlyVals ? digit_off : offs[t]) + prior;
+    // a wait gave up: the prefixes may be partial (the barrier also orders the LDS writes)
+    if (block_incomplete(complete, s_incomplete)) return;
     const int nv = (int)min<int64_t>(kTile, n - base);
     for (int q = t; q < nv; q += kSortThreads) {
       const K k = s_key[q];
