@@ -533,7 +533,10 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
       if (!project_view(g, w, p)) continue;
       dlogit += dop * g.o * (1.0 - g.o);
       // conic -> screen covariance: G_cov = -Q G_Q Q, G_Q = [[da, db/2], [db/2, dc]]
-      const double qa = p.cov[2] / p.det, qb = -p.cov[1] / p.det, qc = p.cov[0] / p.det;
+      // (one reciprocal per divisor; the products are within an FP64 ulp or two of the
+      // quotients, far below the FP32 gradients they feed)
+      const double idet = 1.0 / p.det;
+      const double qa = p.cov[2] * idet, qb = -p.cov[1] * idet, qc = p.cov[0] * idet;
       const double h = 0.5 * db;
       const double t00 = da * qa + h * qb, t01 = da * qb + h * qc;
       const double t10 = h * qa + dc * qb, t11 = h * qb + dc * qc;
@@ -561,25 +564,25 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
       const double gJ02 = GMf[0] * W[6] + GMf[1] * W[7] + GMf[2] * W[8];
       const double gJ11 = GMf[3] * W[3] + GMf[4] * W[4] + GMf[5] * W[5];
       const double gJ12 = GMf[3] * W[6] + GMf[4] * W[7] + GMf[5] * W[8];
-      const double fx = w.fx, fy = w.fy, tz = p.tz, tz2 = p.tz * p.tz;
+      const double fx = w.fx, fy = w.fy, itz = 1.0 / p.tz, itz2 = itz * itz, itz3 = itz2 * itz;
       double dt[3] = {0, 0, 0};
-      dt[2] += -gJ00 * fx / tz2 - gJ11 * fy / tz2;
+      dt[2] += -gJ00 * fx * itz2 - gJ11 * fy * itz2;
       if (p.clx) {
-        dt[2] += gJ02 * fx * p.xt / tz2;
+        dt[2] += gJ02 * fx * p.xt * itz2;
       } else {
-        dt[0] += -gJ02 * fx / tz2;
-        dt[2] += gJ02 * 2.0 * fx * p.tx / (tz2 * tz);
+        dt[0] += -gJ02 * fx * itz2;
+        dt[2] += gJ02 * 2.0 * fx * p.tx * itz3;
       }
       if (p.cly) {
-        dt[2] += gJ12 * fy * p.yt / tz2;
+        dt[2] += gJ12 * fy * p.yt * itz2;
       } else {
-        dt[1] += -gJ12 * fy / tz2;
-        dt[2] += gJ12 * 2.0 * fy * p.ty / (tz2 * tz);
+        dt[1] += -gJ12 * fy * itz2;
+        dt[2] += gJ12 * 2.0 * fy * p.ty * itz3;
       }
       // screen mean
-      dt[0] += du * fx / tz;
-      dt[1] += dv * fy / tz;
-      dt[2] += -du * fx * p.tx / tz2 - dv * fy * p.ty / tz2;
+      dt[0] += du * fx * itz;
+      dt[1] += dv * fy * itz;
+      dt[2] += -du * fx * p.tx * itz2 - dv * fy * p.ty * itz2;
       for (int a = 0; a < 3; ++a) dm[a] += (double)W[a] * dt[0] + (double)W[3 + a] * dt[1] + (double)W[6 + a] * dt[2];
     }
   }
@@ -615,7 +618,8 @@ __global__ __launch_bounds__(kThreads) void k_project_bwd(
   dq[2] = 2 * (-2 * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7] - 2 * y * GR[8]);
   dq[3] = 2 * (-2 * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2 * z * GR[4] + y * GR[5] + x * GR[6] + y * GR[7]);
   const double qd = w * dq[0] + x * dq[1] + y * dq[2] + z * dq[3];
-  for (int a = 0; a < 4; ++a) gq[a] = (float)((dq[a] - g.q[a] * qd) / g.qn);
+  const double iqn = 1.0 / g.qn;
+  for (int a = 0; a < 4; ++a) gq[a] = (float)((dq[a] - g.q[a] * qd) * iqn);
   for (int a = 0; a < 3; ++a) gm[a] = (float)dm[a];
   go = (float)dlogit;
   store_project_grads<kAdam>(gr, adam, dmean, i, j, gm, gl, gq, go);
