@@ -392,14 +392,20 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   {
     // frame start, then Cluster-Cull-Compact
     StageScope sc_(ctx, GSR_STAGE_CLUSTER, s);
-    for (int v0 = 0; v0 < V; v0 += gsr::kViewChunk) {
-      gsr::ViewChunk chunk;
-      const int nv = std::min(gsr::kViewChunk, V - v0);
-      std::memcpy(chunk.v, hv + v0, sizeof(ViewDev) * nv);
-      gsr::launch_frame_begin(chunk, v0, nv, f.views, f.header, v0 == 0 ? (int64_t)(64 + f.ctl_words) : 0, s);
+    gsr::ViewChunk first;
+    std::memcpy(first.v, hv, sizeof(ViewDev) * std::min(gsr::kViewChunk, (int)V));
+    if (!gsr::launch_cluster_begin(first, V, f.views, f.header, (int64_t)(64 + f.ctl_words), scene->means,
+                                   scene->log_scales, scene->n, opts->cluster_cull, f.cluster_bounds,
+                                   f.cluster_visible, s)) {
+      for (int v0 = 0; v0 < V; v0 += gsr::kViewChunk) {
+        gsr::ViewChunk chunk;
+        const int nv = std::min(gsr::kViewChunk, V - v0);
+        std::memcpy(chunk.v, hv + v0, sizeof(ViewDev) * nv);
+        gsr::launch_frame_begin(chunk, v0, nv, f.views, f.header, v0 == 0 ? (int64_t)(64 + f.ctl_words) : 0, s);
+      }
+      gsr::launch_cluster(scene->means, scene->log_scales, scene->n, opts->cluster_cull, f.views, V,
+                          f.cluster_bounds, f.cluster_visible, s);
     }
-    gsr::launch_cluster(scene->means, scene->log_scales, scene->n, opts->cluster_cull, f.views, V, f.cluster_bounds,
-                        f.cluster_visible, s);
     gsr::scan_u32(f.cluster_visible, nullptr, f.cluster_offset, f.nclusters, nullptr,
                   f.header + gsr::kHdrVisibleClusters, f.cluster_list, f.ctl_cluster_scan, f.header + gsr::kHdrError,
                   s);

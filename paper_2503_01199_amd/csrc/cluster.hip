@@ -78,12 +78,27 @@ __device__ bool cluster_visible_in(const ViewDev& w, const float* lo, const floa
 
 // One wave per cluster of 128 Gaussians (two per lane): min/max of the means and the
 // largest log-scale (output [8]: min xyz, max xyz, max log-scale, 0), then the
-// frustum test against every view.
+// frustum test against every view. kBegin (frames of at most kViewChunk views): the
+// kernel also starts the frame, as k_frame_begin would: the views come from the
+// kernel arguments (block 0 copies them to `views` for the later kernels) and the
+// blocks clear the header and control words, which no block of this kernel reads.
+template <bool kBegin>
 __global__ __launch_bounds__(64) void k_cluster(const float* __restrict__ means, const float* __restrict__ log_scales,
                                                 int64_t n, int cull, const ViewDev* __restrict__ views, int32_t V,
-                                                float* __restrict__ bounds, uint32_t* __restrict__ visible) {
+                                                float* __restrict__ bounds, uint32_t* __restrict__ visible,
+                                                ViewChunk chunk, ViewDev* __restrict__ views_out,
+                                                uint32_t* __restrict__ zero, int64_t zero_words) {
   const int64_t c = blockIdx.x;
   const int lane = threadIdx.x;
+  if constexpr (kBegin) {
+    constexpr int kWords = sizeof(ViewDev) / 4;
+    if (c == 0) {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(chunk.v);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(views_out);
+      for (int k = lane; k < V * kWords; k += 64) dst[k] = src[k];
+    }
+    for (int64_t k = c * 64 + lane; k < zero_words; k += (int64_t)gridDim.x * 64) zero[k] = 0u;
+  }
   float lo[3] = {INFINITY, INFINITY, INFINITY};
   float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   float mls = -INFINITY;
@@ -121,7 +136,8 @@ __global__ __launch_bounds__(64) void k_cluster(const float* __restrict__ means,
     if (cull) {
       vis = 0;
       const float smax = expf(mls);
-      for (int v = 0; v < V && !vis; ++v) vis = cluster_visible_in(views[v], lo, hi, smax) ? 1u : 0u;
+      for (int v = 0; v < V && !vis; ++v)
+        vis = cluster_visible_in(kBegin ? chunk.v[v] : views[v], lo, hi, smax) ? 1u : 0u;
     }
     visible[c] = vis;
   }
@@ -140,7 +156,19 @@ void launch_frame_begin(const ViewChunk& chunk, int v0, int nv, ViewDev* views, 
 void launch_cluster(const float* means, const float* log_scales, int64_t n, int cull, const ViewDev* views, int32_t V,
                     float* bounds, uint32_t* visible, hipStream_t s) {
   const int64_t nc = (n + GSR_CLUSTER - 1) / GSR_CLUSTER;
-  if (nc > 0) k_cluster<<<(unsigned)nc, 64, 0, s>>>(means, log_scales, n, cull, views, V, bounds, visible);
+  if (nc > 0)
+    k_cluster<false><<<(unsigned)nc, 64, 0, s>>>(means, log_scales, n, cull, views, V, bounds, visible, ViewChunk{},
+                                                 nullptr, nullptr, 0);
+}
+
+bool launch_cluster_begin(const ViewChunk& chunk, int32_t V, ViewDev* views, uint32_t* zero, int64_t zero_words,
+                          const float* means, const float* log_scales, int64_t n, int cull, float* bounds,
+                          uint32_t* visible, hipStream_t s) {
+  const int64_t nc = (n + GSR_CLUSTER - 1) / GSR_CLUSTER;
+  if (nc <= 0 || V > kViewChunk) return false;
+  k_cluster<true><<<(unsigned)nc, 64, 0, s>>>(means, log_scales, n, cull, views, V, bounds, visible, chunk, views,
+                                              zero, zero_words);
+  return true;
 }
 
 }  // namespace gsr

@@ -194,6 +194,12 @@ void launch_frame_begin(const ViewChunk& chunk, int v0, int nv, ViewDev* views, 
                         hipStream_t s);
 // Per cluster: bounds (min/max of the means, largest log-scale) and, when cull is
 // set, the frustum test against every view (else every cluster is visible).
+// The frame start (views and cleared words, as launch_frame_begin) fused into the
+// cluster kernel; false (nothing launched) for an empty scene or more than
+// kViewChunk views, which take launch_frame_begin + launch_cluster.
+bool launch_cluster_begin(const ViewChunk& chunk, int32_t V, ViewDev* views, uint32_t* zero, int64_t zero_words,
+                          const float* means, const float* log_scales, int64_t n, int cull, float* bounds,
+                          uint32_t* visible, hipStream_t s);
 void launch_cluster(const float* means, const float* log_scales, int64_t n, int cull, const ViewDev* views, int32_t V,
                     float* bounds, uint32_t* visible, hipStream_t s);
 
