@@ -319,9 +319,9 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
   return peers;
 }
 
-// Digit histograms of every pass in one read of the keys; the last block to finish
-// turns them into per-pass exclusive digit offsets (offs[p][d]). Counting needs no
-// ranks. With kRuns (keys in spatial order, whose high bytes repeat), each thread
+// Digit histograms of every pass in one read of the keys, merged into hist[p][d]
+// (which starts at zero); each scatter block scans its pass's 256 counts into digit
+// offsets itself. Counting needs no ranks. With kRuns (keys in spatial order, whose high bytes repeat), each thread
 // takes 8 consecutive keys and adds each run of equal digits to its LDS counter
 // with one atomic, since per-key atomics on one address would serialise within an
 // instruction; otherwise each key adds 1 directly.
@@ -331,11 +331,8 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 template <typename K, bool kRuns>
 __global__ __launch_bounds__(kSortThreads) void k_os_hist(const K* __restrict__ keys, int64_t n_host,
                                                           const uint32_t* __restrict__ n_dev, int passes,
-                                                          uint32_t* __restrict__ hist, uint32_t* __restrict__ offs,
-                                                          uint32_t* __restrict__ done, const uint32_t* __restrict__ err) {
+                                                          uint32_t* __restrict__ hist, const uint32_t* __restrict__ err) {
   __shared__ uint32_t h[kMaxPasses][256];
-  __shared__ uint32_t wsum[kSortThreads / 64];
-  __shared__ bool last;
   // the error word (set by an earlier kernel only: the same for every wave) and the
   // count, loaded together; a raised word means the count may be garbage
   const uint32_t e = ld_status(err);
@@ -424,22 +421,6 @@ merge:
   __syncthreads();
   for (int p = 0; p < passes; ++p)
     if (h[p][t]) atomicAdd(&hist[p * 256 + t], h[p][t]);
-  __threadfence();
-  __syncthreads();
-  if (t == 0) last = atomicAdd(done, 1u) == (uint32_t)(nb - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  for (int p = 0; p < passes; ++p) {
-    const uint32_t x = __hip_atomic_load(&hist[p * 256 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t incl = wave_incl_scan(x);
-    if (lane == 63) wsum[t >> 6] = incl;
-    __syncthreads();
-    uint32_t off = 0;
-    for (int w = 0; w < (t >> 6); ++w) off += wsum[w];
-    offs[p * 256 + t] = off + incl - x;
-    __syncthreads();
-  }
 }
 
 // One pass: block b takes tile b of kTile items. Wave w owns the contiguous quarter
@@ -459,7 +440,7 @@ template <typename K, int R>
 __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R > 8 && sizeof(K) == 4 ? 4 : 1))) void k_os_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                              K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n_host, const uint32_t* __restrict__ n_dev,
-                                                             int shift, const uint32_t* __restrict__ offs,
+                                                             int shift, const uint32_t* __restrict__ hist,
                                                              uint32_t* __restrict__ ctl, uint32_t* __restrict__ err,
                                                              int64_t withhold) {
   constexpr int kTile = kSortThreads * R;  // items per tile: R rounds of one item per thread
@@ -468,7 +449,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
   __shared__ uint32_t wcnt[kWaves][256];    // running count, then exclusive offset, per (wave, digit)
   __shared__ __align__(16) K s_key[kTile];
   __shared__ uint32_t s_val[kTile];
-  __shared__ uint32_t gofs[256], ldig[256], wtot[kWaves];
+  __shared__ uint32_t gofs[256], ldig[256], wtot[kWaves], htot[kWaves];
   __shared__ uint32_t s_incomplete;
   const BlockStart bs = block_start(err, n_dev, n_host, s_incomplete);
   if (bs.error) return;  // an earlier stage gave up: its counts may be garbage
@@ -491,8 +472,9 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
     // items load their values with the keys too, larger ones after the ranking (so
     // that the ranking's registers are not held by them)
     constexpr bool kEarlyVals = R <= 8;
-    // the digit's offset, needed after the look-back, loaded with the keys (small tiles)
-    const uint32_t digit_off = kEarlyVals ? offs[t] : 0u;
+    // the pass's count of digit t over all keys (loaded with the values); its
+    // exclusive scan over the digits is the digit's first output position
+    uint32_t hcount = kEarlyVals ? hist[t] : 0u;
     auto load_vals = [&]() __attribute__((always_inline)) {
       if (vin) {
 #pragma unroll
@@ -530,7 +512,10 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if constexpr (!kEarlyVals) load_vals();
+    if constexpr (!kEarlyVals) {
+      load_vals();
+      hcount = hist[t];
+    }
     __syncthreads();
     // thread d: exclusive offsets of digit d over the waves, then the tile total,
     // published at once (the staging below overlaps its way to the later tiles)
@@ -543,13 +528,22 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
     }
     const int64_t tiles = (n_host + kTile - 1) / kTile;
     const uint32_t agg = look_back_publish(ctl + 64, tile, 256, t, run, err, tile != withhold);
-    // tile-local digit offsets: exclusive scan over the digits of the tile's totals
+    // exclusive scans over the digits: the tile's totals (tile-local digit offsets)
+    // and the pass's counts (the digits' output offsets)
     const uint32_t incl = wave_incl_scan(run);
-    if (lane == 63) wtot[w] = incl;
+    const uint32_t hincl = wave_incl_scan(hcount);
+    if (lane == 63) {
+      wtot[w] = incl;
+      htot[w] = hincl;
+    }
     __syncthreads();
-    uint32_t woff = 0;
-    for (int q = 0; q < w; ++q) woff += wtot[q];
+    uint32_t woff = 0, hoff = 0;
+    for (int q = 0; q < w; ++q) {
+      woff += wtot[q];
+      hoff += htot[q];
+    }
     ldig[t] = woff + incl - run;
+    const uint32_t digit_off = hoff + hincl - hcount;
     __syncthreads();
     // the tile sorted by digit (stable) in LDS; its place in the output needs only
     // the earlier tiles' counts, learnt next
@@ -565,7 +559,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(R 
     bool complete = true;
     const uint32_t prior = look_back_gather(ctl + 64, ctl + 64 + tiles * 256, tile, 256, t, agg, err, complete,
                                             tile != withhold);
-    gofs[t] = (kEarlyVals ? digit_off : offs[t]) + prior;
+    gofs[t] = digit_off + prior;
     // a wait gave up: the prefixes may be partial (the barrier also orders the LDS writes)
     if (block_incomplete(complete, s_incomplete)) return;
     const int nv = (int)min<int64_t>(kTile, n - base);
@@ -585,10 +579,8 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
                   int64_t withhold = -1) {
   const int passes = (bits + 7) / 8;
   if (n_max <= 0 || passes == 0) return -1;
-  uint32_t* hist = ctl;                       // [passes][256]
-  uint32_t* offs = ctl + kMaxPasses * 256;    // [passes][256]
-  uint32_t* done = offs + kMaxPasses * 256;   // 1 word (padded to 64)
-  uint32_t* pass_ctl = done + 64;             // per pass: 64 reserved words, tile then group status [.][256]
+  uint32_t* hist = ctl;                        // [passes][256]
+  uint32_t* pass_ctl = ctl + kMaxPasses * 256;  // per pass: 64 reserved words, tile then group status [.][256]
   // Large sorts take 4096-item tiles: each 8-bit digit of a tile then leaves in runs
   // of ~16 items instead of ~8, and the look-back has half the tiles. Smaller sorts
   // keep 2048, which gives more blocks (sort_ctl_words sizes the control words for
@@ -600,9 +592,9 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
   if (hb > kHistBlocks) hb = kHistBlocks;
   if (hb < 1) hb = 1;
   if (runs)
-    k_os_hist<K, true><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done, err);
+    k_os_hist<K, true><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, err);
   else
-    k_os_hist<K, false><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, offs, done, err);
+    k_os_hist<K, false><<<(unsigned)hb, kSortThreads, 0, s>>>(keys_in, n_max, n_dev, passes, hist, err);
   const K* kcur = keys_in;
   const uint32_t* vcur = vals_in;
   int out = 0;
@@ -610,10 +602,10 @@ int radix_sort_os(const K* keys_in, const uint32_t* vals_in, K* kb[2], uint32_t*
     const int64_t wh = p == 0 ? withhold : -1;
     if (tile_items == 2 * kSortTile)
       k_os_scatter<K, 2 * kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
-          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
+          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, hist + p * 256, pass_ctl + p * pass_words, err, wh);
     else
       k_os_scatter<K, kSortRounds><<<(unsigned)tiles, kSortThreads, 0, s>>>(
-          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, offs + p * 256, pass_ctl + p * pass_words, err, wh);
+          kcur, vcur, kb[out], vb[out], n_max, n_dev, 8 * p, hist + p * 256, pass_ctl + p * pass_words, err, wh);
     kcur = kb[out];
     vcur = vb[out];
     out ^= 1;
@@ -632,7 +624,7 @@ size_t sort_ctl_words(int64_t n_max, int bits) {
   const int passes = (bits + 7) / 8;
   const int64_t tile_items = sort_tile_items(n_max);
   const int64_t tiles = (n_max + tile_items - 1) / tile_items;
-  return 2 * kMaxPasses * 256 + 64 + (size_t)passes * (64 + (tiles + (tiles + kGroup - 1) / kGroup) * 256);
+  return kMaxPasses * 256 + (size_t)passes * (64 + (tiles + (tiles + kGroup - 1) / kGroup) * 256);
 }
 
 void scan_u32(const uint32_t* src, const uint32_t* idx, uint32_t* out, int64_t n_max, const uint32_t* n_dev,
