@@ -221,8 +221,8 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 
 // ------------------------------------------------------------------ scan
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 2048
 
 // out[k] = sum_{i<k} in(i) for k < n, n = *n_dev (or n_host when n_dev is null).
 // in(i) = src[idx ? idx[i] : i]. total (nullable) receives the sum of all n items;
@@ -297,7 +297,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 2048 items per tile
 constexpr int kHistBlocks = 512;
-constexpr int64_t kHistChunk = 8192;  // keys per histogram block at least
+constexpr int64_t kHistChunk = 4096;  // keys per histogram block at least
 constexpr int kMaxPasses = 8;
 constexpr int64_t kWideSortItems = int64_t(1) << 24;  // from this capacity: 4096-item tiles, 16-byte histogram loads
 
