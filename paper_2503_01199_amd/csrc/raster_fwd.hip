@@ -27,6 +27,15 @@ namespace {
 constexpr int kBatch = 32;
 using FwdBatch = BatchLDS<kBatch>;
 
+// Exponent bound below which no pixel can reach alpha >= 1/255: o 2^e >= 1/255 needs
+// e >= log2(1/255) - log2(o). The FP32 walk tests a band's exponents against this
+// bound, less a margin of 2^-10 (a relative 6.8e-4 in o 2^e, far above the few ulp by
+// which v_log_f32, v_exp_f32 and the product round), before it evaluates alpha: a
+// band that fails for every lane cannot blend (its exact test would fail too), so it
+// skips the quarter-rate exponential and the alpha arithmetic. The bound is computed
+// once per batch, lane k for entry k, and read per entry from that lane.
+constexpr float kLog2AlphaMinLessMargin = -7.99435343685885793f - 0.0009765625f;
+
 // One work item of a frame (views, ranges, lists and records of that frame): tile
 // gt whole (NB = 4 pixels per lane) or its band `band` (NB = 1); its image planes
 // are images.p[img_base + view].
@@ -62,11 +71,17 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
     cr[j] = cg[j] = cb[j] = 0.0f;
     last[j] = 0;
   }
-  auto any_live = [&]() __attribute__((always_inline)) {
-    float m = amin[0];
+  // lm[j]: the lanes whose pixel j is live, as a wave mask (scalar registers),
+  // refreshed by the bands that blend, so that the test for a wave with no live
+  // pixel left takes no vector instruction
+  uint64_t lm[NB];
 #pragma unroll
-    for (int j = 1; j < NB; ++j) m = fminf(m, amin[j]);
-    return __any(m < 1.0f);
+  for (int j = 0; j < NB; ++j) lm[j] = __ballot(amin[j] < 1.0f);
+  auto any_live = [&]() __attribute__((always_inline)) {
+    uint64_t m = lm[0];
+#pragma unroll
+    for (int j = 1; j < NB; ++j) m |= lm[j];
+    return m != 0;
   };
   const uint32_t s = ranges[2 * gt];
   const uint32_t e = ranges[2 * gt + 1];
@@ -74,9 +89,13 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
   // Pipeline: record ids two batches ahead, records one batch ahead (in LDS).
   if (s < e) batch_fetch(bufA, rec, (lane < kBatch && s + lane < e) ? inst_rec[s + lane] : 0u);
   uint32_t r_next = (lane < kBatch && s + kBatch + lane < e) ? inst_rec[s + kBatch + lane] : 0u;
+  constexpr bool kPrefilter = P == GSR_FP32;
   auto run_batch = [&](const FwdBatch& cur, FwdBatch& nxt, uint32_t b0) __attribute__((always_inline)) {
     __builtin_amdgcn_s_waitcnt(0);  // this batch's records have landed in LDS
     __syncthreads();
+    // lane k: the exponent bound of entry k (lanes past the batch repeat an entry)
+    const float eth_lane =
+        kPrefilter ? kLog2AlphaMinLessMargin - __builtin_amdgcn_logf(cur.part[2][lane & (kBatch - 1)].x) : 0.0f;
     if (b0 + kBatch < e) batch_fetch(nxt, rec, r_next);
     r_next = (lane < kBatch && b0 + 2 * kBatch + lane < e) ? inst_rec[b0 + 2 * kBatch + lane] : 0u;
     const int cnt = (int)min((uint32_t)kBatch, e - b0);
@@ -90,9 +109,17 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
       uint32_t pos1 = b0 - s + (uint32_t)k + 1u;
       asm volatile("" : "+v"(pos1));  // one register copy per entry, not one per band select
       float av[NB], Gv[NB], arv[NB];
-      strip_alpha<P, NB>(g.r2.x, ev, av, Gv, arv);
+      float eth = 0.0f;
+      if constexpr (kPrefilter)
+        eth = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, eth_lane), k));
+      else
+        strip_alpha<P, NB>(g.r2.x, ev, av, Gv, arv);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
+        if constexpr (kPrefilter) {
+          if (!__any(ev[j] >= eth)) continue;  // no pixel of the band can reach 1/255
+          av[j] = alpha_of(g.r2.x, ev[j], Gv[j], arv[j]);
+        }
         const float a = av[j];
         const bool ok = a >= amin[j];
         if (!__any(ok)) continue;  // nobody in this band blends the entry
@@ -118,6 +145,7 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
         T[j] = blend ? Tn : T[j];
         last[j] = blend ? pos1 : last[j];
         amin[j] = stop ? 2.0f : amin[j];
+        lm[j] = __ballot(amin[j] < 1.0f);
       }
       if (!any_live()) {
         live = false;
