@@ -151,14 +151,6 @@ __device__ __forceinline__ void wave_reduce_half(const float v[6], half2_t h0, h
   w2 = w2 + as_h2((uint32_t)__builtin_amdgcn_update_dpp(0, (int)as_u32(w2), 0x118, 0xf, 0xf, true));
 }
 
-// The work-group is one wave and its LDS instructions execute in issue order, so
-// lanes exchange data through LDS behind a compiler-level barrier alone.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // One work item: tile gt whole (NB = 4 pixels per lane), or its two bands from
 // `band` on (NB = 2, at their row offsets from the whole strip's anchor).
 template <int P, int NB, bool kFixed, bool kHalf>

@@ -187,6 +187,14 @@ __device__ __forceinline__ Record batch_get(const BatchLDS<B>& b, int k) {
   return g;
 }
 
+// A wave's LDS instructions execute in issue order, so its lanes exchange data
+// through LDS behind a compiler-level barrier alone.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Locate the view of global tile gt (views are few; the loop is wave-uniform).
 __device__ __forceinline__ int view_of_tile(const ViewDev* views, int32_t V, uint32_t gt) {
   int v = 0;
