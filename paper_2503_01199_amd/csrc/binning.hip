@@ -24,7 +24,7 @@ namespace {
 // first tiles only), so [0, kept) is always complete, and the overflow flag is
 // raised. The first threads also clear the per-tile ranges.
 constexpr int kEmitThreads = 128;
-constexpr uint32_t kEmitAlone = 16;
+constexpr uint32_t kEmitAlone = 4;
 
 __global__ __launch_bounds__(kEmitThreads) void k_emit(const uint32_t* __restrict__ sorted_rec,
                                                        const uint32_t* __restrict__ offsets,
