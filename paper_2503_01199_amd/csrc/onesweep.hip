@@ -6,7 +6,7 @@
 // the dispatcher has placed before it (workgroups are dispatched in id order; an
 // atomic ticket per block would cost a serialised device-scope atomic per block on
 // one address, ~20 us per pass here). A block publishes its tile aggregate, adds
-// the aggregates of the earlier tiles of its group of 16, and walks back over the
+// the aggregates of the earlier tiles of its group of 32, and walks back over the
 // groups' status words until it meets an inclusive prefix; a group's last tile
 // publishes the group's aggregate and then its inclusive prefix (look_back_grouped).
 // Grids hold one block per tile of the largest possible count; blocks past the
@@ -143,7 +143,7 @@ __device__ uint32_t walk_back(const uint32_t* status, int64_t b, int64_t stride,
 // prefix thus reaches kWindow * kGroup tiles further per round trip, instead of
 // kWindow. Every wait is on a lower tile, so in-order dispatch guarantees
 // progress. tstat: [tiles][stride] per-tile aggregates; gstat: [groups][stride].
-constexpr int kGroup = 16;
+constexpr int kGroup = 32;
 
 // The look-back in two steps, so that a caller can do other work between them
 // while its aggregate reaches the later tiles: look_back_publish publishes the

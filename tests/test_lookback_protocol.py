@@ -3,7 +3,7 @@ run under adversarial schedules.
 
 The model restates the protocol of the HIP kernels (it shares no code with them):
 tile t publishes its aggregate, sums the aggregates of the earlier tiles of its
-group of 16, and walks back over the groups' status words, 16 per round trip,
+group of 32, and walks back over the groups' status words, 16 per round trip,
 until it meets an inclusive prefix; a group's last tile publishes the group's
 aggregate and then its inclusive prefix. A status word carries flag and value
 together, so a reader never sees one without the other.
@@ -32,7 +32,7 @@ import random
 
 import pytest
 
-GROUP = 16
+GROUP = 32
 WINDOW = 16
 XCDS = 8
 AGG, PREFIX = 1, 2
@@ -216,7 +216,7 @@ def exclusive(vals):
     return out
 
 
-@pytest.mark.parametrize("T,slots", [(1, 1), (17, 1), (40, 2), (300, 3), (700, 8)])
+@pytest.mark.parametrize("T,slots", [(1, 1), (17, 1), (40, 2), (70, 2), (300, 3), (700, 8)])
 def test_one_kernel_always_terminates_exactly(T, slots):
     for seed in range(6):
         rng = random.Random(seed * 1000 + T)
