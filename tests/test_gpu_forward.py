@@ -108,8 +108,8 @@ def _large_footprint_scene():
 
 @pytest.mark.parametrize("sizes", [[(320, 240)], [(128, 128), (200, 120)]])
 def test_binning_bit_exact_large_footprints(rz, sizes):
-    """Records of more than 16 tiles are emitted by whole waves (lanes on consecutive
-    positions); the instance lists stay bit-exact."""
+    """Records of more than 4 tiles are emitted by whole waves (lanes on consecutive
+    positions), several per wave here; the instance lists stay bit-exact."""
     sc = _large_footprint_scene()
     cams = [scenes.tiny_camera(w, h) for w, h in sizes]
     fr = gpu_forward(rz, sc, cams)
