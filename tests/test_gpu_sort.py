@@ -2,8 +2,8 @@
 bit: 2^24 + 3 random 32-bit keys (the path of 4096-item tiles and 16-byte histogram
 loads that sorts of 16M or more items take), the same keys from an address 4 bytes
 past a 16-byte boundary (the histogram's per-key fallback), 16-bit keys with heavy
-ties (tile ids: stability decides the order), ragged small sizes and argument
-errors."""
+ties (tile ids: stability decides the order), ragged small sizes (also either
+side of a full look-back group) and argument errors."""
 import numpy as np
 import pytest
 import torch
@@ -53,7 +53,10 @@ def test_sort_large_tile_ids_stable(rz):
     _check(rz, keys, None, 16)
 
 
-@pytest.mark.parametrize("n,bits", [(1, 32), (7, 8), (2049, 13), (4097, 24), (300_001, 32)])
+# 2048-item tiles below 2^24 items, in look-back groups of 32 tiles: 65,536 items
+# fill exactly one group, one more item opens a second group with one tile
+@pytest.mark.parametrize("n,bits", [(1, 32), (7, 8), (2049, 13), (4097, 24), (65_535, 32), (65_536, 32),
+                                    (65_537, 16), (131_073, 32), (300_001, 32)])
 def test_sort_small_and_ragged(rz, n, bits):
     rng = np.random.default_rng(13 + n)
     keys = rng.integers(0, 1 << bits, size=n, dtype=np.uint64).astype(np.uint32)
