@@ -182,6 +182,7 @@ __device__ __forceinline__ void place_items(W* items, uint32_t i, uint32_t pos, 
 // then stored with coalesced writes (one CU issuing ~3 scattered 4-byte stores per
 // tile is otherwise the kernel's bottleneck); larger frames store items directly.
 constexpr int64_t kStageTiles = 8192;
+static_assert(kStageTiles <= (int64_t)kOrderThreads * kOrderUnroll, "a staged frame is counted in one round");
 constexpr int kStageItems = (int)(kStageTiles + 3 * ((kStageTiles + kSplitShare - 1) / kSplitShare));
 
 template <class Len>
@@ -206,6 +207,9 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   }
   __syncthreads();
   uint32_t my_long = 0, my_long_b = 0;
+  // a staged frame (T <= kOrderThreads * kOrderUnroll) takes one round, whose lengths
+  // the placement below reuses instead of loading them again
+  uint32_t kept[kOrderUnroll];
   for (int64_t i0 = t; i0 < T; i0 += (int64_t)kOrderThreads * kOrderUnroll) {
     uint32_t len[kOrderUnroll];
 #pragma unroll
@@ -213,6 +217,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
       const int64_t i = i0 + (int64_t)q * kOrderThreads;
       const uint32_t l = L.len(i < T ? i : T - 1);
       len[q] = i < T ? l : 0u;
+      kept[q] = len[q];
     }
 #pragma unroll
     for (int q = 0; q < kOrderUnroll; ++q) {
@@ -309,9 +314,9 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(Len L, int64_t T, 
   for (int64_t i0 = t; i0 < T; i0 += (int64_t)kOrderThreads * kOrderUnroll) {
     uint32_t len[kOrderUnroll];
 #pragma unroll
-    for (int q = 0; q < kOrderUnroll; ++q) {  // unconditional loads (index clamped), so all are in flight at once
+    for (int q = 0; q < kOrderUnroll; ++q) {  // larger frames: unconditional loads again (index clamped)
       const int64_t i = i0 + (int64_t)q * kOrderThreads;
-      const uint32_t l = L.len(i < T ? i : T - 1);
+      const uint32_t l = staged ? kept[q] : L.len(i < T ? i : T - 1);
       len[q] = i < T ? l : 0u;
     }
 #pragma unroll
