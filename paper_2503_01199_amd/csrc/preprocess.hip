@@ -763,16 +763,21 @@ __global__ void k_variance(const float* __restrict__ S, const float* __restrict_
   out[i] = c > 0.0 ? (float)((double)S[i] - m * m / c) : 0.0f;
 }
 
-__global__ void k_l1_grad(const float4* __restrict__ img, const float4* __restrict__ w,
-                          const float4* __restrict__ gt, int64_t n4, float4* __restrict__ out) {
+// Streaming loads and stores (non-temporal): every value is touched once, and the
+// gradient planes are read back by the backward raster only after the caches have
+// turned over.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void k_l1_grad(const f32x4* __restrict__ img, const f32x4* __restrict__ w,
+                          const f32x4* __restrict__ gt, int64_t n4, f32x4* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
-    const float4 a = img[i], b = w[i], c = gt[i];
-    float4 r;
+    const f32x4 a = __builtin_nontemporal_load(img + i), b = __builtin_nontemporal_load(w + i),
+                c = __builtin_nontemporal_load(gt + i);
+    f32x4 r;
     r.x = a.x > c.x ? b.x : (a.x < c.x ? -b.x : 0.0f);
     r.y = a.y > c.y ? b.y : (a.y < c.y ? -b.y : 0.0f);
     r.z = a.z > c.z ? b.z : (a.z < c.z ? -b.z : 0.0f);
     r.w = a.w > c.w ? b.w : (a.w < c.w ? -b.w : 0.0f);
-    out[i] = r;
+    __builtin_nontemporal_store(r, out + i);
   }
 }
 
@@ -791,8 +796,8 @@ void launch_l1_grad(const float* image, const float* w, const float* gt, int64_t
   if (n4 > 0) {
     int64_t g = (n4 + 255) / 256;
     if (g > 8192) g = 8192;
-    k_l1_grad<<<(unsigned)g, 256, 0, s>>>(reinterpret_cast<const float4*>(image), reinterpret_cast<const float4*>(w),
-                                          reinterpret_cast<const float4*>(gt), n4, reinterpret_cast<float4*>(out));
+    k_l1_grad<<<(unsigned)g, 256, 0, s>>>(reinterpret_cast<const f32x4*>(image), reinterpret_cast<const f32x4*>(w),
+                                          reinterpret_cast<const f32x4*>(gt), n4, reinterpret_cast<f32x4*>(out));
   }
   const int64_t rest = n - 4 * n4;
   if (rest > 0) {
