@@ -26,11 +26,15 @@ namespace {
 constexpr int kThreads = 128;
 static_assert(kThreads == GSR_CLUSTER, "the SH kernels take one cluster (a run of consecutive Gaussians) per block");
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // SH rows (R floats per Gaussian) of a block's consecutive Gaussians move between
 // global memory and LDS with coalesced float4 accesses (a wave moves 1 KB per
 // instruction), instead of one strided 4- or 16-byte access per thread and row. In
 // LDS a row has stride R + 1 floats (odd for R = 12, 48), so the threads' walks
-// along their own rows hit distinct banks.
+// along their own rows hit distinct banks. Gradient rows leave with streaming
+// (non-temporal) stores: nothing in the step reads them again, and written through
+// the caches they would evict the scene data that the next frame reads first.
 template <int R>
 __device__ __forceinline__ void rows_to_lds(float* lds, const float* __restrict__ src, int nrows) {
   constexpr int S = R + 1;
@@ -62,12 +66,13 @@ __device__ __forceinline__ void rows_from_lds(float* __restrict__ dst, const flo
   const int t = threadIdx.x;
   if constexpr (R % 4 == 0) {
     if (nrows == kThreads) {
-      float4* d4 = reinterpret_cast<float4*>(dst);
+      f32x4* d4 = reinterpret_cast<f32x4*>(dst);
 #pragma unroll
       for (int m = 0; m < R / 4; ++m) {
         const int e = 4 * (m * kThreads + t);
         const float* s = lds + (e / R) * S + e % R;
-        d4[m * kThreads + t] = make_float4(s[0], s[1], s[2], s[3]);
+        const f32x4 x = {s[0], s[1], s[2], s[3]};
+        __builtin_nontemporal_store(x, d4 + m * kThreads + t);
       }
       return;
     }
@@ -80,9 +85,10 @@ __device__ __forceinline__ void zero_rows(float* __restrict__ dst, int nrows) {
   const int t = threadIdx.x;
   if constexpr (R % 4 == 0) {
     if (nrows == kThreads) {
-      float4* d4 = reinterpret_cast<float4*>(dst);
+      f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+      const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int m = 0; m < R / 4; ++m) d4[m * kThreads + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int m = 0; m < R / 4; ++m) __builtin_nontemporal_store(z, d4 + m * kThreads + t);
       return;
     }
   }
@@ -447,11 +453,15 @@ __device__ __forceinline__ void store_project_grads(const gsr_grads& gr, const A
 #pragma unroll
     for (int a = 0; a < 3; ++a) dmean[3 * j + a] = gm[a];
   } else {
+    // streaming stores but for the mean, to which the SH backward adds its term
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gr.means[3 * i + a] = gm[a], gr.log_scales[3 * i + a] = gl[a];
+    for (int a = 0; a < 3; ++a) {
+      gr.means[3 * i + a] = gm[a];
+      __builtin_nontemporal_store(gl[a], gr.log_scales + 3 * i + a);
+    }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) gr.quats[4 * i + a] = gq[a];
-    gr.opacity_logits[i] = go;
+    for (int a = 0; a < 4; ++a) __builtin_nontemporal_store(gq[a], gr.quats + 4 * i + a);
+    __builtin_nontemporal_store(go, gr.opacity_logits + i);
   }
 }
 
@@ -766,7 +776,6 @@ __global__ void k_variance(const float* __restrict__ S, const float* __restrict_
 // Streaming loads and stores (non-temporal): every value is touched once, and the
 // gradient planes are read back by the backward raster only after the caches have
 // turned over.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 __global__ void k_l1_grad(const f32x4* __restrict__ img, const f32x4* __restrict__ w,
                           const f32x4* __restrict__ gt, int64_t n4, f32x4* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
