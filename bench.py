@@ -56,8 +56,8 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
                             "sha1": "b36274112defe3a02c76255173ff2e85f31df09d",
-                            "fetch_kib": 70514.4, "write_kib": 99531.2,
-                            "valu_insts": 128924690, "valu_busy": 0.9162, "valu_utilization": 0.7306}}
+                            "fetch_kib": 70414.6, "write_kib": 99531.2,
+                            "valu_insts": 128924690, "valu_busy": 0.904, "valu_utilization": 0.7306}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
