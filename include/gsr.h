@@ -167,9 +167,10 @@ typedef struct {
 
 /* Device pointers into a workspace after gsr_forward, for inspection and tests.
  * Records are indexed r = slot * views + view, slot = compact position.
- *   record      f32[R][12] : u_hi, v_hi, u_lo, v_lo, k1, r, k2, quad, o, red, green, blue
+ *   record      f32[R][12] : u_hi, v_hi, u_lo, v_lo, k1, r, k2, quad4, o, red, green, blue
  *                (screen mean as a float-float pair; exponent in log2 units
- *                 E2 = k1 (dx + r dy)^2 + k2 dy^2, quad = E2's coefficient of j^2)
+ *                 E2 = k1 (dx + r dy)^2 + k2 dy^2, quad4 = a quarter of E2's
+ *                 coefficient of j^2)
  *   depth_key   u32[R]     : FP32 bits of the camera-space depth (0xffffffff: invalid)
  *   tiles       u32[R]     : tiles touched
  *   rect        u16[R][4]  : tile rect x0, x1, y0, y1 (inclusive)

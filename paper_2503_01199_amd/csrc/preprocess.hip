@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
     const float uh = (float)pr.u, vh = (float)pr.v;
     out.r0 = make_float4(uh, vh, (float)(pr.u - (double)uh), (float)(pr.v - (double)vh));
     out.r1 = make_float4((float)(-0.5 * a * kLog2e), (float)ratio, (float)(-0.5 / pr.cov[2] * kLog2e),
-                         (float)(-0.5 * c * kLog2e));
+                         (float)(-0.125 * c * kLog2e));  // a quarter of the j^2 coefficient
     out.r2 = make_float4((float)g.o, (float)fmax(col[0], 0.0), (float)fmax(col[1], 0.0), (float)fmax(col[2], 0.0));
     rec[r] = out;
     if (grad_fx) {  // cleared for the backward's atomics: fixed-point sums, or FP32 sums

@@ -175,8 +175,9 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
   const int py0 = ys + kStripStep * band;      // rows py0 + 4 j
   const float pxc = (float)px + 0.5f;
   const float pyc = (float)ys + kStripAnchor + 0.5f;
-  float soff[NB];
+  float soff[NB], sg[NB];
   strip_offsets<NB>(band, soff);
+  strip_sigmas<NB>(soff, sg);
   const int64_t plane = (int64_t)W * H;
   const float* g_img = dL.p[v];
 
@@ -257,7 +258,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
       const float wX = o * q2.x, wY = o * q1.x, wXX = o * q3.x, wXY = o * q0.y, wYY = o * q2.y;
       const float ca = -2.0f * (float)kLn2 * g.r1.x;
       const float cb = ca * g.r1.y;
-      const float cc = -2.0f * (float)kLn2 * g.r1.w;
+      const float cc = -8.0f * (float)kLn2 * g.r1.w;  // the record holds c / (-8 ln 2)
       const float gu = -__builtin_fmaf(ca, wX, cb * wY);
       const float gv = -__builtin_fmaf(cb, wX, cc * wY);
       st[0] = make_float4(gu, gv, -0.5f * wXX, -wXY);
@@ -312,7 +313,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
         for (int j = 0; j < NB; ++j) {
           if (((m >> (8 * j)) & 0xFFu) == 0) continue;  // no pixel of band j blends it
           float G, araw;
-          const float a = pixel_alpha<P>(o, et.at(soff[j]), G, araw);
+          const float a = pixel_alpha<P>(o, et.at(sg[j]), G, araw);
           const bool before = pos < last[j], visible = a >= kAlphaMin;
           const bool blend = before && visible;
           nfrag += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(before) &
@@ -344,7 +345,7 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
             //   E_j = -1/2 (a dx^2 + 2 b dx (dy - s_j) + c (dy - s_j)^2), d = mean - anchor
             const float ca = -2.0f * (float)kLn2 * g.r1.x;
             const float cb = ca * g.r1.y;
-            const float cc = -2.0f * (float)kLn2 * g.r1.w;
+            const float cc = -8.0f * (float)kLn2 * g.r1.w;  // the record holds c / (-8 ln 2)
             const float gu = __builtin_fmaf(cb, S1, -__builtin_fmaf(ca, dx, cb * dy) * S0);
             const float gv = __builtin_fmaf(cc, S1, -__builtin_fmaf(cb, dx, cc * dy) * S0);
             const float ga = -0.5f * dx * dx * S0;

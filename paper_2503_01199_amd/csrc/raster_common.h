@@ -36,7 +36,8 @@ constexpr int64_t kSplitShare = 4;
 __host__ __device__ constexpr int64_t max_items(int64_t tiles) { return tiles + 3 * ((tiles + kSplitShare - 1) / kSplitShare); }
 // Row offsets s_j of the strip's pixels from its anchor, the centre row of the strip
 // (anchoring at the centre halves the largest offset, and so the extrapolation of the
-// scanline form, against anchoring at the first pixel).
+// scanline form, against anchoring at the first pixel). The exponent is evaluated at
+// the scaled offsets sigma_j = -2 s_j (strip_sigmas).
 constexpr float kStripOffset[4] = {-6.0f, -2.0f, 2.0f, 6.0f};
 constexpr float kStripAnchor = 6.0f;  // anchor row minus first row
 
@@ -49,16 +50,27 @@ __device__ __forceinline__ void strip_offsets(int band, float s[NB]) {
     s[j] = NB == 4 ? kStripOffset[j] : (float)(kStripStep * (band + j)) - kStripAnchor;
 }
 
+template <int NB>
+__device__ __forceinline__ void strip_sigmas(const float s[NB], float sg[NB]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) sg[j] = -2.0f * s[j];
+}
+
 // Exponent of the 2-D Gaussian (Eq. (2)) in log2 units at row offsets s[j] from a
 // strip anchor whose pixel centre is (pxc, pyc). Following the scanline split of
 // App. A.2 (Eq. (8)-(9)), it is Basic + Linear s + Quad s^2, with Basic and Linear
 // computed once per strip from the factored form
 //   E2 = k1 (dx + r dy)^2 + k2 dy^2,   d = screen mean - anchor centre,
-// whose two terms never cancel; the per-pixel cost is two FMAs.
+// whose two terms never cancel; the per-pixel cost is two FMAs. In the scaled offset
+// sigma = -2 s the form is Basic + sigma (L + sigma Q/4) with L = -Linear/2: the record
+// holds Q/4 and L needs no product by -2, and since the scalings are by powers of two
+// the value is the same, bit for bit, as Basic + s (Linear + s Q).
 struct StripTerms {
-  float basic, lin, quad;
-  // exponent at row offset s from the anchor
-  __device__ __forceinline__ float at(float s) const { return __builtin_fmaf(s, __builtin_fmaf(s, quad, lin), basic); }
+  float basic, lin, quad4;
+  // exponent at scaled row offset sg = -2 s from the anchor
+  __device__ __forceinline__ float at(float sg) const {
+    return __builtin_fmaf(sg, __builtin_fmaf(sg, quad4, lin), basic);
+  }
 };
 
 __device__ __forceinline__ StripTerms strip_terms(const Record& g, float pxc, float pyc, float& dx, float& dy) {
@@ -69,17 +81,17 @@ __device__ __forceinline__ StripTerms strip_terms(const Record& g, float pxc, fl
   const float t2 = g.r1.z * dy;
   StripTerms t;
   t.basic = __builtin_fmaf(t1, D, t2 * dy);
-  t.lin = -2.0f * __builtin_fmaf(t1, g.r1.y, t2);
-  t.quad = g.r1.w;
+  t.lin = __builtin_fmaf(t1, g.r1.y, t2);
+  t.quad4 = g.r1.w;
   return t;
 }
 
 template <int NB>
-__device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, const float s[NB],
+__device__ __forceinline__ void strip_exponents(const Record& g, float pxc, float pyc, const float sg[NB],
                                                 float e[NB], float& dx, float& dy) {
   const StripTerms t = strip_terms(g, pxc, pyc, dx, dy);
 #pragma unroll
-  for (int j = 0; j < NB; ++j) e[j] = t.at(s[j]);
+  for (int j = 0; j < NB; ++j) e[j] = t.at(sg[j]);
 }
 
 // G = 2^e (v_exp_f32) and alpha = min(0.99, o G); araw = o G before the clamp.

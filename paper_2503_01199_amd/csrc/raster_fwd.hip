@@ -57,8 +57,9 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
   const int py0 = ys + kStripStep * band;      // rows py0 + 4 j
   const float pxc = (float)px + 0.5f;
   const float pyc = (float)ys + kStripAnchor + 0.5f;
-  float soff[NB];
+  float soff[NB], sg[NB];
   strip_offsets<NB>(band, soff);
+  strip_sigmas<NB>(soff, sg);
 
   // A pixel blends an entry when alpha >= amin; amin is 1/255 while the pixel is
   // live and 2 (unreachable) once it has stopped or lies outside the image.
@@ -105,7 +106,7 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
     for (int k = 0; k < cnt; ++k) {
       const Record g = batch_get(cur, k);
       float ev[NB], dx, dy;
-      strip_exponents<NB>(g, pxc, pyc, soff, ev, dx, dy);
+      strip_exponents<NB>(g, pxc, pyc, sg, ev, dx, dy);
       uint32_t pos1 = b0 - s + (uint32_t)k + 1u;
       asm volatile("" : "+v"(pos1));  // one register copy per entry, not one per band select
       float av[NB], Gv[NB], arv[NB];

@@ -56,13 +56,14 @@ def normwise(g, ref):
 
 def decode_records(rec):
     """Screen mean (FP64 from the float-float pair) and conic (a, b, c) from records
-    f32[R,12] = (u_hi, v_hi, u_lo, v_lo, k1, r, k2, quad, o, rgb): the exponent in log2
-    units is k1 (dx + r dy)^2 + k2 dy^2 = -log2(e)/2 (a dx^2 + 2 b dx dy + c dy^2)."""
+    f32[R,12] = (u_hi, v_hi, u_lo, v_lo, k1, r, k2, quad4, o, rgb): the exponent in log2
+    units is k1 (dx + r dy)^2 + k2 dy^2 = -log2(e)/2 (a dx^2 + 2 b dx dy + c dy^2), and
+    quad4 is a quarter of its coefficient of dy^2, -log2(e) c / 8."""
     rec = np.asarray(rec, np.float64)
     u = rec[:, 0] + rec[:, 2]
     v = rec[:, 1] + rec[:, 3]
     ln2 = np.log(2.0)
     a = -2.0 * ln2 * rec[:, 4]
     b = a * rec[:, 5]
-    c = -2.0 * ln2 * rec[:, 7]
+    c = -8.0 * ln2 * rec[:, 7]
     return u, v, np.stack([a, b, c], 1), rec[:, 8], rec[:, 9:12]
