@@ -42,7 +42,7 @@ constexpr double kAlphaMax = 0.99;
 constexpr double kTMin = 1e-4;
 constexpr double kDilation = 0.3;
 constexpr double kFovClamp = 1.3;
-constexpr int kTile = 16;
+constexpr int kTilePixels = 256;  // pixels per tile: 16x16 by default, or 4x64, 8x32, 32x8, 64x4
 constexpr double kPi = 3.14159265358979323846;
 
 // Fragility tolerances: a discrete decision within this distance of its
@@ -60,6 +60,7 @@ struct Camera {
   double near_plane;
   double bg[3];
   int radius_mode;  // tile membership: 0 the alpha >= 1/255 ellipse's box, 1 the 3-sigma square
+  int tw, th;       // tile width and height in pixels (tw th = 256)
 };
 
 Camera unpack_camera(const double* c) {
@@ -72,6 +73,8 @@ Camera unpack_camera(const double* c) {
   k.near_plane = c[18];
   for (int i = 0; i < 3; ++i) k.bg[i] = c[19 + i];
   k.radius_mode = (int)c[22];
+  k.tw = c[23] > 0 ? (int)c[23] : 16;
+  k.th = kTilePixels / k.tw;
   return k;
 }
 
@@ -295,8 +298,8 @@ void project(const Scene& sc, int64_t i, const Camera& cam, Proj& p) {
   x1 = std::min(x1, (double)(cam.W - 1)); y1 = std::min(y1, (double)(cam.H - 1));
   if (x0 > x1 || y0 > y1) return;
   p.pxr[0] = (int)x0; p.pxr[1] = (int)x1; p.pxr[2] = (int)y0; p.pxr[3] = (int)y1;
-  p.rect[0] = p.pxr[0] / kTile; p.rect[1] = p.pxr[1] / kTile;
-  p.rect[2] = p.pxr[2] / kTile; p.rect[3] = p.pxr[3] / kTile;
+  p.rect[0] = p.pxr[0] / cam.tw; p.rect[1] = p.pxr[1] / cam.tw;
+  p.rect[2] = p.pxr[2] / cam.th; p.rect[3] = p.pxr[3] / cam.th;
   p.tiles = (p.rect[1] - p.rect[0] + 1) * (p.rect[3] - p.rect[2] + 1);
   p.valid = 1;
   if (cam.radius_mode == 1) {
@@ -304,10 +307,10 @@ void project(const Scene& sc, int64_t i, const Camera& cam, Proj& p) {
     // no longer implied by alpha: the rasterizer evaluates a Gaussian at every
     // pixel of the tiles its rect covers, and nowhere else. The pixel footprint
     // becomes those tiles' pixels, which every candidate list below applies.
-    p.pxr[0] = p.rect[0] * kTile;
-    p.pxr[1] = std::min(p.rect[1] * kTile + kTile - 1, cam.W - 1);
-    p.pxr[2] = p.rect[2] * kTile;
-    p.pxr[3] = std::min(p.rect[3] * kTile + kTile - 1, cam.H - 1);
+    p.pxr[0] = p.rect[0] * cam.tw;
+    p.pxr[1] = std::min(p.rect[1] * cam.tw + cam.tw - 1, cam.W - 1);
+    p.pxr[2] = p.rect[2] * cam.th;
+    p.pxr[3] = std::min(p.rect[3] * cam.th + cam.th - 1, cam.H - 1);
   }
 }
 
@@ -391,7 +394,7 @@ void composite(const std::vector<Proj>& P, const std::vector<int64_t>& list, int
 
 // Candidate lists. mode 0: every valid Gaussian (brute force, no filter);
 // mode 1: Gaussians whose pixel footprint contains the pixel (an exact superset
-// of the alpha >= 1/255 set); mode 2: the pixel's 16x16 tile list, i.e. every
+// of the alpha >= 1/255 set); mode 2: the pixel's tile list, i.e. every
 // Gaussian whose tile rect covers the tile, in (depth, index) order. All three
 // give the same image; mode 2 gives list positions comparable to a tiled walk.
 struct Lists {
@@ -400,7 +403,8 @@ struct Lists {
   std::vector<int64_t> all;                  // mode 0, depth-sorted
   std::vector<std::vector<int64_t>> rows;    // mode 1, per row (unsorted)
   std::vector<std::vector<int64_t>> tiles;   // mode 2, per tile, depth-sorted
-  int tx, ty;
+  int tx, ty;  // mode 2: tiles per row and column
+  int tw, th;  // mode 2: tile width and height in pixels
 };
 
 void build_lists(const std::vector<Proj>& P, const Camera& cam, int mode, int y_lo, int y_hi, Lists& L) {
@@ -420,13 +424,15 @@ void build_lists(const std::vector<Proj>& P, const Camera& cam, int mode, int y_
         L.rows[y].push_back(i);
     }
   } else {
-    L.tx = (cam.W + kTile - 1) / kTile;
-    L.ty = (cam.H + kTile - 1) / kTile;
+    L.tw = cam.tw;
+    L.th = cam.th;
+    L.tx = (cam.W + cam.tw - 1) / cam.tw;
+    L.ty = (cam.H + cam.th - 1) / cam.th;
     L.tiles.assign((size_t)L.tx * L.ty, {});
     for (int64_t i = 0; i < n; ++i) {
       if (!P[i].valid) continue;
       for (int y = P[i].rect[2]; y <= P[i].rect[3]; ++y) {
-        if ((y + 1) * kTile <= y_lo || y * kTile >= y_hi) continue;
+        if ((y + 1) * cam.th <= y_lo || y * cam.th >= y_hi) continue;
         for (int x = P[i].rect[0]; x <= P[i].rect[1]; ++x) L.tiles[(size_t)y * L.tx + x].push_back(i);
       }
     }
@@ -450,7 +456,7 @@ void pixel_list(const std::vector<Proj>& P, const Lists& L, int px, int py, std:
       if (P[i].pxr[0] <= px && px <= P[i].pxr[1]) out.push_back(i);
     std::sort(out.begin(), out.end(), [&](int64_t a, int64_t b) { return depth_less(P, a, b); });
   } else {
-    out = L.tiles[(size_t)(py / kTile) * L.tx + px / kTile];
+    out = L.tiles[(size_t)(py / L.th) * L.tx + px / L.tw];
   }
 }
 

@@ -54,17 +54,21 @@ def _scene_args(scene):
     return arrs, [ctypes.c_int64(arrs[0].shape[0]), ctypes.c_int(int(scene.sh_degree))] + [_p(a) for a in arrs]
 
 
-def camera_array(cam, radius_mode: int = 0) -> np.ndarray:
-    """23 doubles: W, H, fx, fy, cx, cy, R (9, row-major), t (3), near, bg (3), and the
+def camera_array(cam, radius_mode: int = 0, tile_width: int = 0) -> np.ndarray:
+    """24 doubles: W, H, fx, fy, cx, cy, R (9, row-major), t (3), near, bg (3), the
     tile-membership bound (0: the alpha >= 1/255 ellipse's box, 1: the 3-sigma
-    square). The float fields are rounded to FP32 first, exactly as the GPU library
+    square) and the tile width in pixels (4, 8, 16, 32 or 64, the height 256 / width;
+    0: 16). The float fields are rounded to FP32 first, exactly as the GPU library
     receives them."""
+    if tile_width not in (0, 4, 8, 16, 32, 64):
+        raise ValueError("tile_width must be 0, 4, 8, 16, 32 or 64")
     f32 = lambda x: float(np.float32(x))  # noqa: E731
     R = np.asarray(cam.R, dtype=np.float32).reshape(9).astype(np.float64)
     t = np.asarray(cam.t, dtype=np.float32).reshape(3).astype(np.float64)
     bg = np.asarray(cam.bg, dtype=np.float32).reshape(3).astype(np.float64)
     out = np.array([cam.width, cam.height, f32(cam.fx), f32(cam.fy), f32(cam.cx), f32(cam.cy)]
-                   + list(R) + list(t) + [f32(cam.near)] + list(bg) + [int(radius_mode)], dtype=np.float64)
+                   + list(R) + list(t) + [f32(cam.near)] + list(bg) + [int(radius_mode), int(tile_width)],
+                   dtype=np.float64)
     return out
 
 
@@ -78,14 +82,14 @@ def sh_basis(deg: int, direction):
     return Y, dY
 
 
-def preprocess(scene, cam, radius_mode: int = 0) -> dict:
+def preprocess(scene, cam, radius_mode: int = 0, tile_width: int = 0) -> dict:
     lib = load()
     arrs, args = _scene_args(scene)
     n = arrs[0].shape[0]
     f = np.zeros((n, 16))
     iv = np.zeros((n, 8), dtype=np.int32)
     db = np.zeros(n, dtype=np.uint32)
-    ca = camera_array(cam, radius_mode)
+    ca = camera_array(cam, radius_mode, tile_width)
     lib.orc_preprocess(*args, _p(ca), _p(f), _p(iv), _p(db))
     return dict(u=f[:, 0], v=f[:, 1], conic=f[:, 2:5], cov=f[:, 5:8], opacity=f[:, 8], rgb=f[:, 9:12],
                 depth=f[:, 12], tcam=f[:, 13:16], valid=iv[:, 0].astype(bool), rect=iv[:, 1:5],
@@ -99,7 +103,8 @@ def _window(cam, window):
     return int(x0), int(x1), int(y0), int(y1)
 
 
-def render(scene, cam, mode: int = 1, window=None, threads: int = 0, radius_mode: int = 0) -> dict:
+def render(scene, cam, mode: int = 1, window=None, threads: int = 0, radius_mode: int = 0,
+           tile_width: int = 0) -> dict:
     """Forward render. mode 0 = brute force over all Gaussians, 1 = per-pixel
     footprint filter, 2 = per-tile lists (list positions comparable to a tiled walk).
     Returns image f64[3,H,W], T f64[H,W], n_contrib, n_blended i32[H,W], fragile bool."""
@@ -111,14 +116,15 @@ def render(scene, cam, mode: int = 1, window=None, threads: int = 0, radius_mode
     nc = np.zeros((H, W), dtype=np.int32)
     nb = np.zeros((H, W), dtype=np.int32)
     fr = np.zeros((H, W), dtype=np.uint8)
-    ca = camera_array(cam, radius_mode)
+    ca = camera_array(cam, radius_mode, tile_width)
     x0, x1, y0, y1 = _window(cam, window)
     lib.orc_render(*args, _p(ca), ctypes.c_int(mode), ctypes.c_int(x0), ctypes.c_int(x1), ctypes.c_int(y0),
                    ctypes.c_int(y1), ctypes.c_int(threads), _p(img), _p(T), _p(nc), _p(nb), _p(fr))
     return dict(image=img, T=T, n_contrib=nc, n_blended=nb, fragile=fr.astype(bool))
 
 
-def backward(scene, cam, dL_dI, mode: int = 1, window=None, threads: int = 0, radius_mode: int = 0) -> dict:
+def backward(scene, cam, dL_dI, mode: int = 1, window=None, threads: int = 0, radius_mode: int = 0,
+             tile_width: int = 0) -> dict:
     """Analytic FP64 backward of render() for upstream gradient dL_dI [3,H,W].
     Besides the gradients and the statistic (S, M, C), returns `fragile` (the
     Gaussian is in the list of a pixel with a fragile decision) and `C_slack`, the
@@ -134,7 +140,7 @@ def backward(scene, cam, dL_dI, mode: int = 1, window=None, threads: int = 0, ra
                opacity_logits=np.zeros(n), sh=np.zeros((n, K, 3)), g2d=np.zeros((n, 9)),
                S=np.zeros(n), M=np.zeros(n), C=np.zeros(n, dtype=np.int64), fragile=np.zeros(n, dtype=np.uint8),
                C_slack=np.zeros(n, dtype=np.int64))
-    ca = camera_array(cam, radius_mode)
+    ca = camera_array(cam, radius_mode, tile_width)
     x0, x1, y0, y1 = _window(cam, window)
     lib.orc_backward(*args, _p(ca), ctypes.c_int(mode), ctypes.c_int(x0), ctypes.c_int(x1), ctypes.c_int(y0),
                      ctypes.c_int(y1), ctypes.c_int(threads), _p(g), _p(out["means"]), _p(out["log_scales"]),

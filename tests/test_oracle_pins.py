@@ -307,7 +307,8 @@ def test_footprint_contains_every_contributing_pixel(orc):
         assert tx.min() >= x0 and tx.max() <= x1 and ty.min() >= y0 and ty.max() <= y1
 
 
-def test_footprint_is_the_smallest_box_of_the_alpha_ellipse(orc):
+@pytest.mark.parametrize("tw", [16, 4, 8, 32, 64])
+def test_footprint_is_the_smallest_box_of_the_alpha_ellipse(orc, tw):
     """Rect minimality (App. A.1 tile culling; support reading: the rect is the tile
     cover of the pixel-centre bounding box of the alpha >= 1/255 ellipse). Brute force
     per pixel-centre column: the vertical line x = px + 1/2 meets the ellipse
@@ -315,11 +316,14 @@ def test_footprint_is_the_smallest_box_of_the_alpha_ellipse(orc):
     at dy = -b dx / c and evaluated from the conic, is within that bound; rows
     likewise. The footprint must be exactly the range of such columns times the range
     of such rows, clipped to the image: a wider rect (an off-by-one in a ceil or floor,
-    a 3-sigma radius, the other axis's variance) fails, as does a narrower one."""
+    a 3-sigma radius, the other axis's variance) fails, as does a narrower one. For
+    every tile shape of 256 pixels (Sec. 3.1: the tile shape is a free parameter) the
+    rect is that box's cover by tw x (256 / tw) tiles."""
+    th = 256 // tw
     sc = scenes.tiny_scene(400, seed_salt=6)
     W, H = 96, 80
     cam = scenes.tiny_camera(W, H)
-    pp = orc.preprocess(sc, cam)
+    pp = orc.preprocess(sc, cam, tile_width=tw)
     cols = np.arange(W) + 0.5
     rows = np.arange(H) + 0.5
     checked = wide = 0
@@ -343,12 +347,31 @@ def test_footprint_is_the_smallest_box_of_the_alpha_ellipse(orc):
             assert not pp["valid"][i], i
             continue
         assert pp["valid"][i], i
-        exp = (cin.min() // 16, cin.max() // 16, rin.min() // 16, rin.max() // 16)
+        exp = (cin.min() // tw, cin.max() // tw, rin.min() // th, rin.max() // th)
         assert tuple(pp["rect"][i]) == exp, (i, tuple(pp["rect"][i]), exp)
         assert pp["tiles"][i] == (exp[1] - exp[0] + 1) * (exp[3] - exp[2] + 1)
-        wide += int(cin.max() - cin.min() >= 16 or rin.max() - rin.min() >= 16)
+        wide += int(exp[1] > exp[0] or exp[3] > exp[2])
         checked += 1
     assert checked > 200 and wide > 20
+
+
+@pytest.mark.parametrize("tw", [4, 8, 32, 64])
+def test_tile_lists_of_every_tile_shape_give_the_brute_force_image(orc, tw):
+    """The per-tile lists (mode 2) of tw x (256 / tw) tiles hold, for each pixel, every
+    Gaussian whose alpha can reach 1/255 there, in depth order, so the image equals
+    the brute force over all Gaussians (mode 0) whatever the tile shape; and so do the
+    per-Gaussian gradients (Sec. 3.1: the shape changes the work, not the result)."""
+    sc = scenes.tiny_scene(600, seed_salt=8)
+    cam = scenes.tiny_camera(80, 72)
+    ref = orc.render(sc, cam, mode=0)["image"]
+    img = orc.render(sc, cam, mode=2, tile_width=tw)["image"]
+    assert np.max(np.abs(img - ref)) < 1e-12
+    g = np.random.default_rng(5).uniform(-1, 1, size=ref.shape)
+    b0 = orc.backward(sc, cam, g, mode=0)
+    b2 = orc.backward(sc, cam, g, mode=2, tile_width=tw)
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "S", "M"):
+        assert np.max(np.abs(b2[k] - b0[k])) <= 1e-12 * (1 + np.max(np.abs(b0[k]))), k
+    assert np.array_equal(b2["C"], b0["C"])
 
 
 def _stack_scene(opacities, depths, log_scale=math.log(3.0)):
