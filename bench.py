@@ -369,6 +369,8 @@ def main():
                     help="Gaussian order of the scene (shuffled: a random permutation, for cache counters)")
     ap.add_argument("--only-steps", action="store_true",
                     help="warm up, time the steps and stop (for profiler runs)")
+    ap.add_argument("--tile-width", type=int, default=0, choices=[0, 4, 8, 16, 32, 64],
+                    help="with --only-steps: tiles of 256 pixels this wide (0: 16x16)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "fp16t"],
                     help="blend precision of the steps of an --only-steps run")
     args = ap.parse_args()
@@ -437,18 +439,21 @@ def main():
 
     from paper_2503_01199_amd import _lib as L
 
-    def step(check=False, precision=L.GSR_FP32, deterministic=False, radius_mode=0, half_reduction=False):
+    def step(check=False, precision=L.GSR_FP32, deterministic=False, radius_mode=0, half_reduction=False,
+             tile_width=0):
         fr = rz.forward(st, cams, cluster_cull=cull, workspace=ws, check=check, precision=precision,
-                        deterministic=deterministic, radius_mode=radius_mode, half_reduction=half_reduction)
+                        deterministic=deterministic, radius_mode=radius_mode, half_reduction=half_reduction,
+                        tile_width=tile_width)
         for img, (w, gt), dl in zip(fr.images, wgt, dls):
             rz.l1_grad(img, w, gt, out=dl)
         rz.backward(fr, dls, grads=grads, stats=stats)
         return fr
 
     log("warmup %d steps" % args.warmup)
-    fr = step(check=True)  # sizes the workspace for this frame's instance count
+    tw0 = args.tile_width if args.only_steps else 0
+    fr = step(check=True, tile_width=tw0)  # sizes the workspace for this frame's instance count
     for _ in range(max(args.warmup - 1, 0)):
-        fr = step()
+        fr = step(tile_width=tw0)
     torch.cuda.synchronize()
 
     if args.only_steps:  # profiler runs: the timed steps only
@@ -456,7 +461,7 @@ def main():
         torch.cuda.synchronize()
         wall0 = time.perf_counter()
         for _ in range(args.steps):
-            fr = step(precision=prec)
+            fr = step(precision=prec, tile_width=tw0)
         torch.cuda.synchronize()
         info = rz.check_frame(fr)
         print(json.dumps({"workload": desc, "order": args.order, "cluster_cull": cull, "precision": args.precision,
@@ -632,6 +637,37 @@ def main():
     st3 = {k: round(sum(v) / len(v), 4) for k, v in acc3.items()}
     radius3 = {"ms_per_step": round(r3_ms, 4), "instances": inst3, "stages_ms": st3}
     step(check=True)  # back to the default bound's frame
+
+    # tile shapes of 256 pixels other than 16x16 (F4): 4x64, 8x32, 32x8 and 64x4
+    # tiles, one wave64 per tile with 4 pixels per lane, same protocol
+    shapes = {}
+    for tw in (4, 8, 32, 64):
+        log("timing %d steps with %dx%d tiles" % (args.steps, tw, 256 // tw))
+        frs = step(check=True, tile_width=tw)
+        inst_s = int(frs.info["instances"])
+        for _ in range(max(args.warmup, 1)):
+            step(tile_width=tw)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        for _ in range(args.steps):
+            frs = step(tile_width=tw)
+        torch.cuda.synchronize()
+        s_ms = (time.perf_counter() - wall0) * 1e3 / args.steps
+        rz.check_frame(frs)
+        rz.set_profiling(True)
+        accs = {}
+        for _ in range(args.steps):
+            step(tile_width=tw)
+            for k, v in rz.stage_times().items():
+                if v >= 0:
+                    accs.setdefault(k, []).append(v)
+        rz.set_profiling(False)
+        sts = {k: round(sum(v) / len(v), 4) for k, v in accs.items()}
+        shapes["%dx%d" % (tw, 256 // tw)] = {"ms_per_step": round(s_ms, 4), "instances": inst_s,
+                                             "raster_fwd_ms": sts.get("raster_fwd"),
+                                             "raster_bwd_ms": sts.get("raster_bwd"),
+                                             "tile_sort_ms": sts.get("tile_sort"), "emit_ms": sts.get("emit")}
+    step(check=True)  # back to 16x16 tiles
 
     # raster schedule sweep (F4): the list length above which a tile is rastered as
     # band items, 1 pixel per lane in the forward's four 16x4 bands, 2 in the
@@ -829,6 +865,7 @@ def main():
         "fp16_blend_t": fp16t,
         "deterministic": det,
         "radius_3sigma": radius3,
+        "tile_shapes": shapes,
         "half_reduction": half_red,
         "schedule_sweep": sweep,
         "view_cycle": cycle,

@@ -57,8 +57,9 @@ typedef enum {
                           An approximation whose error is measured, not bounded. */
 } gsr_precision;
 
-#define GSR_TILE 16          /* render tile edge in pixels: one wave64 per 16x16 tile, or per
-                                16x4 band of a tile with a long list; at most 2^28 tiles per call */
+#define GSR_TILE 16          /* default render tile edge in pixels: one wave64 per 16x16 tile, or
+                                per 16x4 band of a tile with a long list (other shapes of 256
+                                pixels: gsr_options.tile_width); at most 2^28 tiles per call */
 #define GSR_CLUSTER 128      /* primitives per cluster (Sec. 3.2.2) */
 #define GSR_MAX_VIEWS 64     /* views per gsr_forward / gsr_backward call, and per gsr_raster_batch */
 #define GSR_MAX_BATCH 16     /* prepared frames per gsr_raster_batch call */
@@ -128,6 +129,14 @@ typedef struct {
                            atomics; the geometry gradients and the statistic's square
                            sum stay FP32. An approximation whose error is reported, not
                            bounded; not with deterministic = 1. 0: all FP32. */
+  int32_t tile_width;   /* tile shape (Sec. 3.1: tile shape and pixels per thread are
+                           parameters of the raster): the width in pixels of a tile of
+                           256 pixels, 4, 8, 16, 32 or 64 (height 256 / width: 4x64,
+                           8x32, 16x16, 32x8, 64x4); 0 selects 16 (16x16, GSR_TILE). One
+                           wave64 walks a tile's list with 4 pixels per lane: lane l owns
+                           column l mod width and rows r + S j, j = 0..3, S = min(4,
+                           height / 4), r = l / width, or in tiles taller than 16 rows
+                           16 (r / 4) + r mod 4. Forward and backward must agree. */
 } gsr_options;
 
 /* Parameter gradients, device memory, the shapes of gsr_scene's arrays. Overwritten

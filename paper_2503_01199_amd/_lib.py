@@ -47,7 +47,7 @@ class GsrCamera(ctypes.Structure):
 
 class GsrOptions(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("cluster_cull", c_int32), ("stats", c_int32), ("deterministic", c_int32),
-                ("radius_mode", c_int32), ("half_reduction", c_int32)]
+                ("radius_mode", c_int32), ("half_reduction", c_int32), ("tile_width", c_int32)]
 
 
 class GsrGrads(ctypes.Structure):

@@ -108,13 +108,30 @@ gsr_status validate_scene(gsr_context* ctx, const gsr_scene* sc) {
   return GSR_OK;
 }
 
-gsr_status validate_views(gsr_context* ctx, const gsr_camera* cams, int32_t V) {
+// log2 of the tile width selected by gsr_options.tile_width (validated; 0 means 16)
+int tile_wl_of(const gsr_options* o) {
+  switch (o->tile_width) {
+    case 4: return 2;
+    case 8: return 3;
+    case 32: return 5;
+    case 64: return 6;
+    default: return 4;
+  }
+}
+
+// Tiles of a view under tiles 2^wl wide and 256 >> wl high.
+int64_t view_tiles(const gsr_camera& c, int wl) {
+  const int tw = 1 << wl, th = 256 >> wl;
+  return (int64_t)((c.width + tw - 1) / tw) * ((c.height + th - 1) / th);
+}
+
+gsr_status validate_views(gsr_context* ctx, const gsr_camera* cams, int32_t V, int wl) {
   if (!cams) return fail(ctx, GSR_ERR_INVALID_ARG, "cameras are NULL");
   if (V < 1 || V > GSR_MAX_VIEWS) return fail(ctx, GSR_ERR_INVALID_ARG, "V = %d not in [1, %d]", V, GSR_MAX_VIEWS);
   int64_t tiles = 0;
   for (int v = 0; v < V; ++v) {
     const gsr_camera& c = cams[v];
-    if (c.width < 1 || c.height < 1 || c.width > 65535 * GSR_TILE || c.height > 65535 * GSR_TILE)
+    if (c.width < 1 || c.height < 1 || c.width > 65535 * (1 << wl) || c.height > 65535 * (256 >> wl))
       return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: image %dx%d out of range", v, c.width, c.height);
     if (!(c.fx > 0.0f) || !(c.fy > 0.0f) || !std::isfinite(c.fx) || !std::isfinite(c.fy) ||
         !std::isfinite(c.cx) || !std::isfinite(c.cy))
@@ -125,7 +142,7 @@ gsr_status validate_views(gsr_context* ctx, const gsr_camera* cams, int32_t V) {
     for (int k = 0; k < 3; ++k)
       if (!std::isfinite(c.t[k]) || !std::isfinite(c.bg[k]))
         return fail(ctx, GSR_ERR_INVALID_ARG, "view %d: t or bg not finite", v);
-    tiles += (int64_t)((c.width + GSR_TILE - 1) / GSR_TILE) * ((c.height + GSR_TILE - 1) / GSR_TILE);
+    tiles += view_tiles(c, wl);
   }
   // raster work items carry the tile index in their upper 29 bits
   if (tiles >= ((int64_t)1 << 28)) return fail(ctx, GSR_ERR_INVALID_ARG, "too many tiles (limit 2^28)");
@@ -154,6 +171,9 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
     return fail(ctx, GSR_ERR_INVALID_ARG, "half_reduction must be 0 or 1");
   if (o->half_reduction && o->deterministic)
     return fail(ctx, GSR_ERR_INVALID_ARG, "half_reduction and deterministic exclude each other");
+  if (o->tile_width != 0 && o->tile_width != 4 && o->tile_width != 8 && o->tile_width != 16 && o->tile_width != 32 &&
+      o->tile_width != 64)
+    return fail(ctx, GSR_ERR_INVALID_ARG, "tile_width %d not 0, 4, 8, 16, 32 or 64", o->tile_width);
   return GSR_OK;
 }
 
@@ -161,8 +181,8 @@ gsr_status validate_opts(gsr_context* ctx, const gsr_options* o) {
 // room for inst_cap instances. Returns the total bytes. Layout: per-scene and
 // per-pixel buffers, then the header and control words (cleared together at the
 // frame start; their size grows with inst_cap), then the instance buffers.
-size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t inst_cap, bool fixed, void* ws,
-                  Frame& f) {
+size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int wl, int64_t inst_cap, bool fixed,
+                  void* ws, Frame& f) {
   std::memset(&f, 0, sizeof(f));
   f.n = sc->n;
   f.V = V;
@@ -172,10 +192,11 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   f.tiles = 0;
   f.pixels = 0;
   for (int v = 0; v < V; ++v) {
-    f.tiles += (int64_t)((cams[v].width + GSR_TILE - 1) / GSR_TILE) * ((cams[v].height + GSR_TILE - 1) / GSR_TILE);
+    f.tiles += view_tiles(cams[v], wl);
     f.pixels += (int64_t)cams[v].width * cams[v].height;
   }
   f.tile_bits = bits_for(f.tiles);
+  f.tile_wl = wl;
   f.inst_cap = inst_cap;
   Planner P{static_cast<char*>(ws)};
   const size_t nr = (size_t)f.nrec, nc = (size_t)std::max(f.nclusters, 1);
@@ -225,18 +246,19 @@ size_t plan_frame(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_
   return (P.off + kAlign - 1) & ~(kAlign - 1);
 }
 
-size_t bytes_for_instances(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int64_t m, bool fixed) {
+size_t bytes_for_instances(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int wl, int64_t m, bool fixed) {
   Frame f;
-  return plan_frame(sc, cams, V, m, fixed, nullptr, f);
+  return plan_frame(sc, cams, V, wl, m, fixed, nullptr, f);
 }
 
 // Largest instance capacity whose layout fits in ws_bytes (-1 if not even 0 fits).
-int64_t instances_for_bytes(const gsr_scene* sc, const gsr_camera* cams, int32_t V, size_t ws_bytes, bool fixed) {
-  if (bytes_for_instances(sc, cams, V, 0, fixed) > ws_bytes) return -1;
+int64_t instances_for_bytes(const gsr_scene* sc, const gsr_camera* cams, int32_t V, int wl, size_t ws_bytes,
+                            bool fixed) {
+  if (bytes_for_instances(sc, cams, V, wl, 0, fixed) > ws_bytes) return -1;
   int64_t lo = 0, hi = (int64_t)(ws_bytes / 16) + 1;
   while (lo < hi) {
     const int64_t mid = lo + (hi - lo + 1) / 2;
-    if (bytes_for_instances(sc, cams, V, mid, fixed) <= ws_bytes) lo = mid;
+    if (bytes_for_instances(sc, cams, V, wl, mid, fixed) <= ws_bytes) lo = mid;
     else hi = mid - 1;
   }
   return lo;
@@ -262,7 +284,7 @@ void release_frame(FrameRecord& fr) {
   fr.done = nullptr;
 }
 
-void fill_views(const gsr_camera* cams, int32_t V, ViewDev* out) {
+void fill_views(const gsr_camera* cams, int32_t V, int wl, ViewDev* out) {
   int64_t tile_base = 0, pixel_base = 0;
   for (int v = 0; v < V; ++v) {
     const gsr_camera& c = cams[v];
@@ -285,8 +307,9 @@ void fill_views(const gsr_camera* cams, int32_t V, ViewDev* out) {
     w.campos[2] = -(R[2] * t[0] + R[5] * t[1] + R[8] * t[2]);
     w.width = c.width;
     w.height = c.height;
-    w.tiles_x = (c.width + GSR_TILE - 1) / GSR_TILE;
-    w.tiles_y = (c.height + GSR_TILE - 1) / GSR_TILE;
+    w.tiles_x = (c.width + (1 << wl) - 1) >> wl;
+    w.tiles_y = (c.height + (256 >> wl) - 1) / (256 >> wl);
+    w.tile_wl = wl;
     w.tile_base = (int32_t)tile_base;
     w.pixel_base = pixel_base;
     tile_base += (int64_t)w.tiles_x * w.tiles_y;
@@ -334,12 +357,13 @@ gsr_status gsr_workspace_size(gsr_context* ctx, const gsr_scene* scene, const gs
                               const gsr_options* opts, int64_t max_instances, size_t* bytes) {
   if (!bytes) return fail(ctx, GSR_ERR_INVALID_ARG, "NULL output");
   gsr_status st;
-  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
+  if ((st = validate_scene(ctx, scene)) || (st = validate_opts(ctx, opts)) ||
+      (st = validate_views(ctx, cams, V, tile_wl_of(opts))) ||
       (st = validate_records(ctx, scene, V)))
     return st;
   if (max_instances < 0) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances < 0");
   if (max_instances >= ((int64_t)1 << 30)) return fail(ctx, GSR_ERR_INVALID_ARG, "max_instances >= 2^30");
-  *bytes = bytes_for_instances(scene, cams, V, max_instances, opts->deterministic != 0);
+  *bytes = bytes_for_instances(scene, cams, V, tile_wl_of(opts), max_instances, opts->deterministic != 0);
   return GSR_OK;
 }
 
@@ -354,21 +378,23 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
                          FrameRecord** out) {
   gsr_status st;
   bool attached = false;
-  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
+  if ((st = validate_scene(ctx, scene)) || (st = validate_opts(ctx, opts)) ||
+      (st = validate_views(ctx, cams, V, tile_wl_of(opts))) ||
       (st = validate_records(ctx, scene, V)))
     return st;
   if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
   if (((uintptr_t)workspace & (kAlign - 1)) != 0) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   const bool fixed = opts->deterministic != 0;
-  int64_t cap = instances_for_bytes(scene, cams, V, ws_bytes, fixed);
+  const int wl = tile_wl_of(opts);
+  int64_t cap = instances_for_bytes(scene, cams, V, wl, ws_bytes, fixed);
   if (cap < 0) {
-    ctx->required = bytes_for_instances(scene, cams, V, 16 * (int64_t)scene->n + 1024, fixed);
+    ctx->required = bytes_for_instances(scene, cams, V, wl, 16 * (int64_t)scene->n + 1024, fixed);
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes < %zu needed before instances", ws_bytes,
-                bytes_for_instances(scene, cams, V, 0, fixed));
+                bytes_for_instances(scene, cams, V, wl, 0, fixed));
   }
   cap = std::min<int64_t>(cap, ((int64_t)1 << 30) - 1);
   Frame f;
-  const size_t total = plan_frame(scene, cams, V, cap, fixed, workspace, f);
+  const size_t total = plan_frame(scene, cams, V, wl, cap, fixed, workspace, f);
   f.split_len = ctx->split_len;
   f.split_len_bwd = ctx->split_len_bwd;
   f.radius_mode = opts->radius_mode;
@@ -383,7 +409,7 @@ gsr_status prepare_frame(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
   fr.precision = -1;
 
   ViewDev hv[GSR_MAX_VIEWS];
-  fill_views(cams, V, hv);
+  fill_views(cams, V, wl, hv);
   for (int v = 0; v < V; ++v) {
     fr.tile_base[v] = hv[v].tile_base;
     fr.pixel_base[v] = hv[v].pixel_base;
@@ -641,7 +667,8 @@ gsr_status backward_impl(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
                          const gsr_grads* grads, const gsr_stats* stats, const gsr::AdamDev* adam, void* stream) {
   if (!ctx) return GSR_ERR_INVALID_ARG;
   gsr_status st;
-  if ((st = validate_scene(ctx, scene)) || (st = validate_views(ctx, cams, V)) || (st = validate_opts(ctx, opts)) ||
+  if ((st = validate_scene(ctx, scene)) || (st = validate_opts(ctx, opts)) ||
+      (st = validate_views(ctx, cams, V, tile_wl_of(opts))) ||
       (st = validate_records(ctx, scene, V)))
     return st;
   if (!workspace) return fail(ctx, GSR_ERR_INVALID_ARG, "workspace is NULL");
@@ -658,7 +685,9 @@ gsr_status backward_impl(gsr_context* ctx, const gsr_scene* scene, const gsr_cam
     return fail(ctx, GSR_ERR_INVALID_ARG, "scene or views differ from the forward");
   {
     Frame chk;
-    const size_t total = plan_frame(scene, cams, V, f.inst_cap, f.grad2d_fx != nullptr, workspace, chk);
+    if (f.tile_wl != tile_wl_of(opts))
+      return fail(ctx, GSR_ERR_INVALID_ARG, "tile_width %d differs from the forward's", opts->tile_width);
+    const size_t total = plan_frame(scene, cams, V, f.tile_wl, f.inst_cap, f.grad2d_fx != nullptr, workspace, chk);
     if (chk.tiles != f.tiles || chk.pixels != f.pixels || chk.grad2d != f.grad2d || total > ws_bytes)
       return fail(ctx, GSR_ERR_INVALID_ARG, "cameras or workspace differ from the forward");
   }
@@ -768,7 +797,7 @@ gsr_status gsr_frame_inspect(gsr_context* ctx, const void* workspace, gsr_frame_
   if (h[gsr::kHdrError] & 2u) return fail(ctx, GSR_ERR_UNSUPPORTED, "the frame has 2^30 or more instances");
   if (h[gsr::kHdrError]) return fail(ctx, GSR_ERR_DEVICE, "a device-wide scan or sort wait gave up (frame aborted)");
   if (h[gsr::kHdrOverflow]) {
-    ctx->required = bytes_for_instances(&fr.scene, fr.cams, f.V, M + M / 8 + 1024, f.grad2d_fx != nullptr);
+    ctx->required = bytes_for_instances(&fr.scene, fr.cams, f.V, f.tile_wl, M + M / 8 + 1024, f.grad2d_fx != nullptr);
     return fail(ctx, GSR_ERR_WORKSPACE_TOO_SMALL, "frame has %lld instances, workspace holds %lld", (long long)M,
                 (long long)f.inst_cap);
   }

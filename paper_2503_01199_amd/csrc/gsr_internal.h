@@ -44,7 +44,7 @@ struct ViewDev {
   int32_t width, height;
   int32_t tiles_x, tiles_y;
   int32_t tile_base;      // first global tile id of the view
-  int32_t pad;
+  int32_t tile_wl;        // log2 of the tile width in pixels (tile height 256 >> tile_wl)
   int64_t pixel_base;     // first pixel of the view in the per-pixel arrays
 };
 
@@ -116,6 +116,7 @@ struct Frame {
   int32_t V, nclusters;
   int64_t tiles, pixels, inst_cap;
   int32_t tile_bits;
+  int32_t tile_wl;          // log2 of the tile width (gsr_options.tile_width)
   // device pointers (all inside the workspace)
   uint32_t* header;         // HeaderWord entries
   ViewDev* views;

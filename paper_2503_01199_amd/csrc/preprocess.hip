@@ -372,10 +372,11 @@ __global__ __launch_bounds__(kThreads) void k_preprocess_fwd(gsr_scene sc, const
       if (fx0 > fx1 || fy0 > fy1) {
         ok = false;
       } else {
-        x0 = (int)fx0 / GSR_TILE;
-        x1 = (int)fx1 / GSR_TILE;
-        y0 = (int)fy0 / GSR_TILE;
-        y1 = (int)fy1 / GSR_TILE;
+        const int hl = 8 - w.tile_wl;  // tiles 2^tile_wl wide, 2^hl high
+        x0 = (int)fx0 >> w.tile_wl;
+        x1 = (int)fx1 >> w.tile_wl;
+        y0 = (int)fy0 >> hl;
+        y1 = (int)fy1 >> hl;
       }
     }
     if (!ok) {

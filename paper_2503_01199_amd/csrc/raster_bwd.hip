@@ -170,13 +170,10 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
   const int lt = (int)gt - w.tile_base;
   const int tx = lt % w.tiles_x, ty = lt / w.tiles_x;
   const int lane = threadIdx.x;
-  const int px = tx * GSR_TILE + (lane & 15);
-  const int ys = ty * GSR_TILE + (lane >> 4);  // first row of the lane's whole-tile strip
-  const int py0 = ys + kStripStep * band;      // rows py0 + 4 j
-  const float pxc = (float)px + 0.5f;
-  const float pyc = (float)ys + kStripAnchor + 0.5f;
   float soff[NB], sg[NB];
-  strip_offsets<NB>(band, soff);
+  const LaneStrip q = lane_strip<NB>(w, tx, ty, band, lane, soff);
+  const int px = q.px, py0 = q.py0, step = q.step;  // rows py0 + step j
+  const float pxc = q.pxc, pyc = q.pyc;
   strip_sigmas<NB>(soff, sg);
   const int64_t plane = (int64_t)W * H;
   const float* g_img = dL.p[v];
@@ -194,8 +191,8 @@ __device__ __forceinline__ void raster_bwd_item(BwdBatch& bufA, BwdBatch& bufB, 
     last[j] = 0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) gI[j][ch] = 0.0f;
-    if (px < W && py0 + kStripStep * j < H) {
-      const int64_t o = (int64_t)(py0 + kStripStep * j) * W + px;
+    if (px < W && py0 + step * j < H) {
+      const int64_t o = (int64_t)(py0 + step * j) * W + px;
       const int64_t pp = w.pixel_base + o;
       last[j] = pix_last[pp];
       T[j] = pix_T[pp];

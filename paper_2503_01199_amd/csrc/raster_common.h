@@ -1,26 +1,27 @@
 // Per-wave arithmetic shared by the forward and backward raster kernels.
 //
-// Tile/thread mapping: one wave64 per 16x16 tile; lane l owns pixel column l % 16
-// and the 4-pixel vertical strip of rows l/16 + 4 j, j = 0..3 (the scanline of
-// App. A.2 runs along y, with a row step of kStripStep). Step j of every lane thus
-// covers the compact 16x4 band of rows 4j .. 4j+3, so an entry that blends no pixel
-// of a band skips that band wave-wide. A tile whose list is long is instead split
-// into its 4 bands, one wave each with one pixel per lane (NB = 1), so that the
-// longest lists do not set the kernel's duration. A band item evaluates its pixel
-// with the same strip anchor and row offset as the whole-tile walk, so every
-// pixel's arithmetic is the same whichever way its tile is scheduled (a batch of
-// frames may split other tiles than each frame alone, and the backward may walk
-// another schedule than the forward). Both kernels evaluate the exponent and alpha through
-// the functions below with an explicit operation sequence (the library is built
-// without FP contraction), so the backward re-derives exactly the forward's
-// blend decisions and transmittances.
+// Tile/thread mapping: one wave64 per tile of 256 pixels, TW = 2^tile_wl wide and
+// TH = 256 / TW high (16x16 by default); lane l owns pixel column l % TW and the
+// 4-pixel vertical strip of rows l / TW + S j, j = 0..3, with the row step
+// S = TH / 4 (the scanline of App. A.2 runs along y). Step j of every lane thus
+// covers the compact TW x S band of rows S j .. S j + S - 1 (16x4 in a 16x16 tile),
+// so an entry that blends no pixel of a band skips that band wave-wide. Tiles taller
+// than 16 rows (8x32, 4x64) are stacks of 16-row blocks walked the same way (S = 4;
+// band j is then row slab j of every block: lane_strip). A tile
+// whose list is long is instead split into its 4 bands, one wave each with one
+// pixel per lane (NB = 1), so that the longest lists do not set the kernel's
+// duration. A band item evaluates its pixel with the same strip anchor and row
+// offset as the whole-tile walk, so every pixel's arithmetic is the same whichever
+// way its tile is scheduled (a batch of frames may split other tiles than each
+// frame alone, and the backward may walk another schedule than the forward). Both
+// kernels evaluate the exponent and alpha through the functions below with an
+// explicit operation sequence (the library is built without FP contraction), so
+// the backward re-derives exactly the forward's blend decisions and transmittances.
 #pragma once
 
 #include "gsr_internal.h"
 
 namespace gsr {
-
-constexpr int kStripStep = 4;
 
 // Raster work items: (tile << 3) | code. kItemWhole (4) is the whole tile, 4
 // pixels per lane; codes 0..3 are band `code` of a tile split four ways, 1 pixel per
@@ -34,20 +35,36 @@ constexpr uint32_t kItemWhole = 4;
 constexpr uint32_t kItemHalf = 5;
 constexpr int64_t kSplitShare = 4;
 __host__ __device__ constexpr int64_t max_items(int64_t tiles) { return tiles + 3 * ((tiles + kSplitShare - 1) / kSplitShare); }
-// Row offsets s_j of the strip's pixels from its anchor, the centre row of the strip
-// (anchoring at the centre halves the largest offset, and so the extrapolation of the
-// scanline form, against anchoring at the first pixel). The exponent is evaluated at
-// the scaled offsets sigma_j = -2 s_j (strip_sigmas).
-constexpr float kStripOffset[4] = {-6.0f, -2.0f, 2.0f, 6.0f};
-constexpr float kStripAnchor = 6.0f;  // anchor row minus first row
+// A lane's pixels in a work item of a view's tile (tx, ty): column px, the rows
+// py0 + step j of its NB pixels (band `band` onwards), and the strip anchor, the
+// centre row of the lane's whole-tile strip (1.5 steps below its first row;
+// anchoring at the centre halves the largest offset, and so the extrapolation of
+// the scanline form, against anchoring at the first pixel). s[j] = step (band + j
+// - 3/2) is pixel j's row offset from the anchor (exact in FP32); the exponent is
+// evaluated at the scaled offsets sigma_j = -2 s_j (strip_sigmas).
+struct LaneStrip {
+  int px, py0, step;
+  float pxc, pyc;  // anchor pixel centre
+};
 
-// Row offsets from the strip anchor of the NB pixels a lane evaluates, in bands
-// band .. band + NB - 1: s = 4 b - 6 for band b (the whole strip when NB = 4).
 template <int NB>
-__device__ __forceinline__ void strip_offsets(int band, float s[NB]) {
+__device__ __forceinline__ LaneStrip lane_strip(const ViewDev& w, int tx, int ty, int band, int lane, float s[NB]) {
+  const int wl = w.tile_wl, hl = 8 - wl;
+  LaneStrip q;
+  // row step TH / 4, at most 4: a tile taller than 16 rows is a stack of 16-row
+  // blocks, lane row lr owning rows 16 (lr / 4) + lr % 4 + 4 j of it, so that no
+  // strip spans more than 13 rows (the scanline form extrapolates over +-6 rows at
+  // most, as in a 16x16 tile)
+  const int lr = lane >> wl;
+  q.step = hl > 4 ? 4 : 1 << (hl - 2);
+  q.px = (tx << wl) + (lane & ((1 << wl) - 1));
+  const int ys = (ty << hl) + (hl > 4 ? ((lr >> 2) << 4) + (lr & 3) : lr);  // first row of the lane's strip
+  q.py0 = ys + q.step * band;
+  q.pxc = (float)q.px + 0.5f;
+  q.pyc = (float)ys + 1.5f * (float)q.step + 0.5f;
 #pragma unroll
-  for (int j = 0; j < NB; ++j)
-    s[j] = NB == 4 ? kStripOffset[j] : (float)(kStripStep * (band + j)) - kStripAnchor;
+  for (int j = 0; j < NB; ++j) s[j] = (float)q.step * ((float)(band + j) - 1.5f);
+  return q;
 }
 
 template <int NB>

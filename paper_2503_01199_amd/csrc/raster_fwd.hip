@@ -52,13 +52,10 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
   const int lt = (int)gt - w.tile_base;
   const int tx = lt % w.tiles_x, ty = lt / w.tiles_x;
   const int lane = threadIdx.x;
-  const int px = tx * GSR_TILE + (lane & 15);
-  const int ys = ty * GSR_TILE + (lane >> 4);  // first row of the lane's whole-tile strip
-  const int py0 = ys + kStripStep * band;      // rows py0 + 4 j
-  const float pxc = (float)px + 0.5f;
-  const float pyc = (float)ys + kStripAnchor + 0.5f;
   float soff[NB], sg[NB];
-  strip_offsets<NB>(band, soff);
+  const LaneStrip q = lane_strip<NB>(w, tx, ty, band, lane, soff);
+  const int px = q.px, py0 = q.py0, step = q.step;  // rows py0 + step j
+  const float pxc = q.pxc, pyc = q.pyc;
   strip_sigmas<NB>(soff, sg);
 
   // A pixel blends an entry when alpha >= amin; amin is 1/255 while the pixel is
@@ -67,7 +64,7 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
   uint32_t last[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    amin[j] = ((px < W) && (py0 + kStripStep * j < H)) ? kAlphaMin : 2.0f;
+    amin[j] = ((px < W) && (py0 + step * j < H)) ? kAlphaMin : 2.0f;
     T[j] = 1.0f;
     cr[j] = cg[j] = cb[j] = 0.0f;
     last[j] = 0;
@@ -174,7 +171,7 @@ __device__ __forceinline__ void raster_fwd_item(FwdBatch& bufA, FwdBatch& bufB, 
   const int64_t plane = (int64_t)W * H;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    const int py = py0 + kStripStep * j;
+    const int py = py0 + step * j;
     if (py >= H) break;
     const int64_t o = (int64_t)py * W + px;
     img[o] = __builtin_fmaf(T[j], w.bg[0], cr[j]);

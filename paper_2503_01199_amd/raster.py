@@ -165,7 +165,7 @@ class Rasterizer:
 
     @staticmethod
     def options(precision=L.GSR_FP32, cluster_cull=True, stats=True, deterministic=False,
-                radius_mode=0, half_reduction=False) -> L.GsrOptions:
+                radius_mode=0, half_reduction=False, tile_width=0) -> L.GsrOptions:
         o = L.GsrOptions()
         o.precision = int(precision)
         o.cluster_cull = 1 if cluster_cull else 0
@@ -173,12 +173,14 @@ class Rasterizer:
         o.deterministic = 1 if deterministic else 0
         o.radius_mode = int(radius_mode)
         o.half_reduction = 1 if half_reduction else 0
+        o.tile_width = int(tile_width)
         return o
 
     # ------------------------------------------------------------------ forward / backward
     def forward(self, scene: SceneTensors, cameras, precision=L.GSR_FP32, cluster_cull=True, stats=True,
                 workspace: Workspace | None = None, images=None, check: bool = True,
-                deterministic: bool = False, radius_mode: int = 0, half_reduction: bool = False) -> Frame:
+                deterministic: bool = False, radius_mode: int = 0, half_reduction: bool = False,
+                tile_width: int = 0) -> Frame:
         """Renders the views. With check (the default) waits for the frame's counters
         and, when its instances did not fit the workspace, grows it and renders
         again; check=False returns right after enqueueing (info is then empty: call
@@ -186,10 +188,11 @@ class Rasterizer:
         deterministic: the frame's backward sums per-tile gradients in fixed point
         (bitwise reproducible gradients). radius_mode: 0 the exact alpha >= 1/255 tile
         membership, 1 the 3-sigma bound. half_reduction: the frame's backward reduces
-        colour and opacity gradients as packed FP16 pairs."""
+        colour and opacity gradients as packed FP16 pairs. tile_width: tiles of 256
+        pixels, that many wide (4, 8, 16, 32 or 64; 0: 16x16)."""
         V = len(cameras)
         cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
-        opts = self.options(precision, cluster_cull, stats, deterministic, radius_mode, half_reduction)
+        opts = self.options(precision, cluster_cull, stats, deterministic, radius_mode, half_reduction, tile_width)
         sc = scene.struct()
         ws = workspace if workspace is not None else self.default_workspace
         if images is None:
@@ -223,12 +226,12 @@ class Rasterizer:
 
     def prepare(self, scene: SceneTensors, cameras, cluster_cull=True, stats=True,
                 workspace: Workspace | None = None, stream=None, deterministic: bool = False,
-                radius_mode: int = 0) -> Frame:
+                radius_mode: int = 0, tile_width: int = 0) -> Frame:
         """Enqueues every stage before the raster (gsr_prepare) on `stream` (a
         torch.cuda.Stream; default the current stream); render with raster_batch."""
         V = len(cameras)
         cams = (L.GsrCamera * V)(*[camera_struct(c) for c in cameras])
-        opts = self.options(L.GSR_FP32, cluster_cull, stats, deterministic, radius_mode)
+        opts = self.options(L.GSR_FP32, cluster_cull, stats, deterministic, radius_mode, tile_width=tile_width)
         sc = scene.struct()
         ws = workspace if workspace is not None else Workspace(self.device)
         if ws.buf is None:
