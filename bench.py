@@ -55,9 +55,9 @@ TRAFFIC = {"k_raster_bwd": {"workload": "room-1000k-SH3-1600x1064",
                             "sources": ["paper_2503_01199_amd/csrc/raster_bwd.hip",
                                         "paper_2503_01199_amd/csrc/raster_common.h",
                                         "paper_2503_01199_amd/csrc/gsr_internal.h"],
-                            "sha1": "1f09376b809e9f7d137b8f29705c0032254bca4e",
-                            "fetch_kib": 70409.6, "write_kib": 99531.2,
-                            "valu_insts": 127857340, "valu_busy": 0.900, "valu_utilization": 0.7285}}
+                            "sha1": "d4d70c5a30764955ca5c714cffa9055acc75b3e0",
+                            "fetch_kib": 70280.3, "write_kib": 99531.2,
+                            "valu_insts": 127987504, "valu_busy": 0.936, "valu_utilization": 0.7288}}
 FETCH_SCALE = 1048576.0 / 524300.0
 WRITE_SCALE = 1.0
 FWD_FLOP_EVAL = 7
